@@ -1,0 +1,192 @@
+"""ctypes front end of the CPU FP64 reference (``libpp_oracle.so``).
+
+Test infrastructure only (test suite, smoke check, benchmark CPU-baseline leg).  It
+imports nothing from the HIP package; circuits and observables are passed as plain
+numpy arrays or duck-typed objects with the same fields as the seeded input generators
+produce (``n_qubits``, ``layers[m].gx/gz/theta/ex/ez/lam``, ``x/z/c``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+
+_u64p = C.POINTER(C.c_uint64)
+_f64p = C.POINTER(C.c_double)
+_u8p = C.POINTER(C.c_uint8)
+_i32p = C.POINTER(C.c_int)
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        path = _build.LIB
+        if not os.path.exists(path):
+            _build.build(force=True)
+        lib = C.CDLL(path)
+        lib.or_create.restype = C.c_void_p
+        lib.or_create.argtypes = [C.c_int, C.c_int64, _u64p, _u64p, _f64p, _u8p]
+        lib.or_clone.restype = C.c_void_p
+        lib.or_clone.argtypes = [C.c_void_p]
+        lib.or_free.argtypes = [C.c_void_p]
+        lib.or_size.restype = C.c_int64
+        lib.or_size.argtypes = [C.c_void_p]
+        lib.or_export.argtypes = [C.c_void_p, _u64p, _u64p, _f64p, _u8p]
+        lib.or_rotate.restype = C.c_int
+        lib.or_rotate.argtypes = [C.c_void_p, _u64p, _u64p, C.c_double, C.c_int]
+        lib.or_noise.argtypes = [C.c_void_p, C.c_int, _u64p, _u64p, _f64p, C.c_int, C.c_int, C.c_int]
+        lib.or_truncate.argtypes = [C.c_void_p, C.c_double, C.c_int64]
+        lib.or_apply_layer.argtypes = [C.c_void_p, C.c_int, _u64p, _u64p, _f64p, C.c_int, C.c_int,
+                                       _u64p, _u64p, _f64p, C.c_int, C.c_int, C.c_double, C.c_int64,
+                                       C.c_int, C.c_int]
+        lib.or_noise_canceling.restype = C.c_void_p
+        lib.or_noise_canceling.argtypes = [C.c_void_p, C.c_int, _i32p, _u64p, _u64p, _f64p, _i32p,
+                                           _u64p, _u64p, _f64p, C.c_double, C.c_int64, C.c_int, C.c_int]
+        lib.or_expectation.restype = C.c_double
+        lib.or_expectation.argtypes = [C.c_void_p, _u64p]
+        lib.or_norm2.restype = C.c_double
+        lib.or_norm2.argtypes = [C.c_void_p]
+        _LIB = lib
+    return _LIB
+
+
+def _p(a: Optional[np.ndarray], t):
+    if a is None:
+        return None
+    return a.ctypes.data_as(t)
+
+
+def _u64(a, w: int) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.uint64).reshape(-1, w))
+
+
+class OracleSum:
+    """A Pauli sum held by the CPU reference."""
+
+    def __init__(self, n_qubits: int, x, z, c, ord_=None, _handle=None):
+        self.n = int(n_qubits)
+        self.W = (self.n + 63) // 64
+        lib = _lib()
+        if _handle is not None:
+            self._h = _handle
+            return
+        x = _u64(x, self.W)
+        z = _u64(z, self.W)
+        c = np.ascontiguousarray(np.asarray(c, dtype=np.float64).reshape(-1))
+        o = None if ord_ is None else np.ascontiguousarray(np.asarray(ord_, dtype=np.uint8))
+        self._h = lib.or_create(self.n, c.shape[0], _p(x, _u64p), _p(z, _u64p), _p(c, _f64p), _p(o, _u8p))
+
+    @classmethod
+    def from_sum(cls, ps) -> "OracleSum":
+        return cls(ps.n_qubits, ps.x, ps.z, ps.c)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib().or_free(h)
+            self._h = None
+
+    def clone(self) -> "OracleSum":
+        return OracleSum(self.n, None, None, None, _handle=_lib().or_clone(self._h))
+
+    def __len__(self) -> int:
+        return int(_lib().or_size(self._h))
+
+    def export(self) -> Tuple[np.ndarray, np.ndarray, np.ndarray, np.ndarray]:
+        n = len(self)
+        x = np.zeros((n, self.W), np.uint64)
+        z = np.zeros((n, self.W), np.uint64)
+        c = np.zeros(n, np.float64)
+        o = np.zeros(n, np.uint8)
+        _lib().or_export(self._h, _p(x, _u64p), _p(z, _u64p), _p(c, _f64p), _p(o, _u8p))
+        return x, z, c, o
+
+    def rotate(self, rx, rz, theta: float, direction: int) -> bool:
+        rx = _u64(rx, self.W)
+        rz = _u64(rz, self.W)
+        return bool(_lib().or_rotate(self._h, _p(rx, _u64p), _p(rz, _u64p), float(theta), int(direction)))
+
+    def noise(self, ex, ez, lam, sign: int = 1, mode: int = 0, max_order: int = 2) -> None:
+        ex = _u64(ex, self.W)
+        ez = _u64(ez, self.W)
+        lam = np.ascontiguousarray(np.asarray(lam, np.float64))
+        _lib().or_noise(self._h, lam.shape[0], _p(ex, _u64p), _p(ez, _u64p), _p(lam, _f64p),
+                        int(sign), int(mode), int(max_order))
+
+    def truncate(self, eps: float, max_terms: int = 0) -> None:
+        _lib().or_truncate(self._h, float(eps), int(max_terms))
+
+    def apply_layer(self, layer, direction: int, with_gates: bool = True, with_noise: bool = True,
+                    noise_sign: int = 1, noise_after_gates: bool = True, eps: float = 0.0,
+                    max_terms: int = 0, mode: int = 0, max_order: int = 2) -> None:
+        W = self.W
+        ng = layer.n_gates if with_gates else 0
+        nk = layer.n_gen if with_noise else 0
+        gx = _u64(layer.gx, W) if ng else np.zeros((1, W), np.uint64)
+        gz = _u64(layer.gz, W) if ng else np.zeros((1, W), np.uint64)
+        th = np.ascontiguousarray(layer.theta, np.float64) if ng else np.zeros(1)
+        ex = _u64(layer.ex, W) if nk else np.zeros((1, W), np.uint64)
+        ez = _u64(layer.ez, W) if nk else np.zeros((1, W), np.uint64)
+        lam = np.ascontiguousarray(layer.lam, np.float64) if nk else np.zeros(1)
+        _lib().or_apply_layer(self._h, ng, _p(gx, _u64p), _p(gz, _u64p), _p(th, _f64p), int(direction),
+                              nk, _p(ex, _u64p), _p(ez, _u64p), _p(lam, _f64p), int(noise_sign),
+                              int(bool(noise_after_gates)), float(eps), int(max_terms), int(mode),
+                              int(max_order))
+
+    def expectation(self, basis=None) -> float:
+        b = None if basis is None else _u64(basis, self.W).reshape(-1)
+        return float(_lib().or_expectation(self._h, _p(b, _u64p)))
+
+    def norm2(self) -> float:
+        return float(_lib().or_norm2(self._h))
+
+    def as_dict(self):
+        x, z, c, o = self.export()
+        return {(tuple(int(v) for v in x[i]), tuple(int(v) for v in z[i]), int(o[i])): float(c[i])
+                for i in range(len(c))}
+
+
+def _circuit_arrays(circuit):
+    W = (circuit.n_qubits + 63) // 64
+    ng = np.array([l.n_gates for l in circuit.layers], dtype=np.int32)
+    nk = np.array([l.n_gen for l in circuit.layers], dtype=np.int32)
+
+    def cat(name, w):
+        parts = [np.asarray(getattr(l, name)).reshape(-1, w) if w else np.asarray(getattr(l, name)).reshape(-1)
+                 for l in circuit.layers]
+        arr = np.concatenate(parts) if parts else np.zeros((0, w) if w else 0)
+        if arr.size == 0:
+            arr = np.zeros((1, w) if w else 1, dtype=arr.dtype)
+        return np.ascontiguousarray(arr)
+
+    gx = cat("gx", W).astype(np.uint64)
+    gz = cat("gz", W).astype(np.uint64)
+    th = cat("theta", 0).astype(np.float64)
+    ex = cat("ex", W).astype(np.uint64)
+    ez = cat("ez", W).astype(np.uint64)
+    lam = cat("lam", 0).astype(np.float64)
+    return ng, nk, gx, gz, th, ex, ez, lam
+
+
+MODES = {"greedy": 0, "error_order": 1}
+
+
+def noise_canceling(circuit, observable, eps: float = 0.0, max_terms: int = 0,
+                    mode: str = "greedy", max_order: int = 2) -> OracleSum:
+    """O~ = D O for a layered circuit (see ``or_noise_canceling`` in pp_oracle.h)."""
+    obs = observable if isinstance(observable, OracleSum) else OracleSum.from_sum(observable)
+    ng, nk, gx, gz, th, ex, ez, lam = _circuit_arrays(circuit)
+    h = _lib().or_noise_canceling(obs._h, len(circuit.layers), _p(ng, _i32p), _p(gx, _u64p), _p(gz, _u64p),
+                                  _p(th, _f64p), _p(nk, _i32p), _p(ex, _u64p), _p(ez, _u64p), _p(lam, _f64p),
+                                  float(eps), int(max_terms), MODES[mode], int(max_order))
+    return OracleSum(circuit.n_qubits, None, None, None, _handle=h)
+
+
+def run_workload(wl) -> OracleSum:
+    return noise_canceling(wl.circuit, wl.observable, wl.eps, wl.max_terms, wl.mode, wl.max_order)
