@@ -1,0 +1,188 @@
+/*
+ * pp.h -- C ABI of the MI355X (gfx950) noise-canceling Pauli-propagation library.
+ *
+ * The library computes the noise-canceling observable O~ = D O,
+ * D = (C_ideal C_noisy^{-1})^dag, of Eddins et al., "Computing noise-canceling
+ * observables via Pauli propagation" (Section I.B, the trace identity
+ * <O> = Tr[D O rho] with rho = C_noisy |0><0|), by Heisenberg-picture Pauli
+ * propagation of a real-coefficient Pauli sum held on the GPU.  A caller drives it
+ * one circuit layer at a time (pp_apply_layer); the order of layers that realises D
+ * for a layered circuit is the caller's (the Python package provides it).
+ *
+ * Pauli strings.  A string on n qubits is two bit vectors x, z of W = ceil(n/64)
+ * little-endian uint64 words each (qubit q in word q/64, bit q%64); the operator is
+ * the Hermitian Pauli i^{|x&z|} X^x Z^z, so (x_q, z_q) = (1,1) is Y.  1 <= n <= 256.
+ * Host arrays of strings are row-major [count][W].
+ *
+ * Conventions for every entry point:
+ *  - Ownership: host arrays passed in are read during the call only; the caller keeps
+ *    them.  Device memory is owned by the library (allocated through the allocator
+ *    given to pp_ctx_create, else hipMalloc) and released by pp_destroy.
+ *  - Errors: every call returns a pp_status; no C++ exception crosses the ABI.  A
+ *    validation failure (PP_ERR_INVALID, PP_ERR_UNSUPPORTED) leaves the observable
+ *    unchanged.  PP_ERR_OOM or PP_ERR_DEVICE leaves it unusable (destroy it).
+ *    pp_last_error() returns a thread-local message for the last failure.
+ *  - Streams: all GPU work is enqueued on the context's stream.  pp_apply_layer and
+ *    pp_truncate synchronise that stream internally to read term counts (the arrays
+ *    are resized per layer); pp_size, pp_expectation and pp_export return host values
+ *    and therefore also synchronise.
+ *  - Threads: a context and its observables must be used by one host thread at a time;
+ *    different contexts may be driven concurrently from different threads.
+ */
+#ifndef PP_H
+#define PP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PP_OK = 0,
+  PP_ERR_INVALID = 1,      /* bad argument; nothing changed */
+  PP_ERR_OOM = 2,          /* device allocation failed; observable unusable */
+  PP_ERR_DEVICE = 3,       /* HIP runtime error; observable unusable */
+  PP_ERR_UNSUPPORTED = 4   /* valid but not supported by this build; nothing changed */
+} pp_status;
+
+/* Coefficient storage.  PP_F64: FP64 throughout.  PP_F32_KAHAN: FP32 coefficients in
+ * HBM; each rotation's cos/sin combination is evaluated in FP64 and rounded once,
+ * duplicate-string merges use compensated (Kahan) sums, inverse-noise scale factors
+ * are accumulated in FP64 and the expectation value is reduced in FP64. */
+typedef enum { PP_F64 = 0, PP_F32_KAHAN = 1 } pp_precision;
+
+/* Truncation mode.  PP_MODE_GREEDY: propagated noise absorption's greedy truncation
+ * (Section I.A): drop |c| < eps and keep at most max_terms of the largest |c|.
+ * PP_MODE_ERROR_ORDER: each term carries an error-order tag (uint8); every inverse
+ * Pauli-Lindblad layer multiplies a Pauli P by prod_{k: <P,E_k>=1} (1 + x_k),
+ * x_k = f_k - 1 with f_k the generator's inverse fidelity factor, and that product is
+ * expanded in powers of the x_k: a term of order o receives the degree-j elementary
+ * symmetric sum of its anticommuting x_k at order o + j, orders above max_order are
+ * dropped, and terms are merged by (string, order) (the expansion in the number of
+ * errors of Appendix C; the Euclid appendix's first-order form 1/f ~ 1 + eps). */
+typedef enum { PP_MODE_GREEDY = 0, PP_MODE_ERROR_ORDER = 1 } pp_mode;
+
+/* Direction of a gate layer.  PP_HEISENBERG: P -> U^dag P U = cos P + sin (i R P) for
+ * anticommuting P (backward rule of the Euclid appendix); gates are applied in reverse
+ * list order.  PP_FORWARD: P -> U P U^dag = cos P - sin (i R P) (Section I,
+ * Eq. evolve_gate); gates in list order.  U = exp(-i theta R / 2). */
+typedef enum { PP_HEISENBERG = 1, PP_FORWARD = -1 } pp_dir;
+
+typedef struct {
+  double eps;          /* drop |c| < eps after every non-Clifford gate (>= 0) */
+  int64_t max_terms;   /* after every layer keep at most this many (0 = no cap);
+                          ties in |c| go to the smaller canonical key */
+  int max_order;       /* PP_MODE_ERROR_ORDER: highest kept order (0..250) */
+} pp_trunc;
+
+/* One circuit layer.  Gates: n_gates Pauli rotations R_g (gx, gz: [n_gates][W]) with
+ * angles theta[g].  Angles within 1e-12 of a multiple of pi/2 are Clifford and use
+ * exact cos/sin in {0, +-1}; no threshold is applied after a Clifford gate.
+ * Noise: n_gen Pauli-Lindblad generators E_k (ex, ez: [n_gen][W]) with strengths
+ * lambda[k] >= 0 (Section I: the local channel applies E_k with probability
+ * p_k = (1 - e^{-2 lambda_k})/2).  noise_sign = +1 applies the inverse map
+ * (Eq. evolve_noise: an anticommuting P is multiplied by 1 - 2 q_k = e^{2 lambda_k});
+ * -1 applies the channel (factor e^{-2 lambda_k}).  noise_after_gates selects whether
+ * the noise map follows (1) or precedes (0) the gates.  Either count may be 0. */
+typedef struct {
+  int n_gates;
+  const uint64_t* gx;
+  const uint64_t* gz;
+  const double* theta;
+  int dir;                 /* pp_dir */
+  int n_gen;
+  const uint64_t* ex;
+  const uint64_t* ez;
+  const double* lambda;
+  int noise_sign;          /* +1 inverse map, -1 channel */
+  int noise_after_gates;   /* 1: gates then noise; 0: noise then gates */
+} pp_layer;
+
+typedef struct pp_ctx pp_ctx;
+typedef struct pp_obs pp_obs;
+
+/* Device allocator hooks (e.g. a framework's caching allocator).  alloc returns NULL
+ * on failure; release may be called with any pointer alloc returned. */
+typedef void* (*pp_alloc_fn)(size_t bytes, void* user);
+typedef void (*pp_release_fn)(void* ptr, void* user);
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream` (a
+ * hipStream_t; NULL = the null stream).  alloc/release may both be NULL (then
+ * hipMalloc/hipFree with an internal buffer cache).  *out receives the handle. */
+pp_status pp_ctx_create(int device, void* hip_stream, pp_alloc_fn alloc, pp_release_fn release,
+                        void* user, pp_ctx** out);
+void pp_ctx_destroy(pp_ctx* ctx);
+
+/* Create an observable O = sum_i coeff[i] P_i on the device (step "create": the host
+ * strings are copied, duplicated strings are summed and exact zeros dropped; Appendix B's
+ * accumulate-and-deduplicate).  n_terms >= 0; x, z: [n_terms][W] host arrays with no bits
+ * at or above n_qubits; coeff finite.  trunc configures every later pp_apply_layer. */
+pp_status pp_create_observable(pp_ctx* ctx, int n_qubits, int64_t n_terms, const uint64_t* x,
+                               const uint64_t* z, const double* coeff, pp_precision precision,
+                               pp_mode mode, pp_trunc trunc, pp_obs** out);
+
+/* Propagate through one layer (gates, then or preceded by, a Pauli-Lindblad map):
+ * rotation branching per gate with the cos/sin split (Eq. evolve_gate and its backward
+ * form), duplicate strings merged after every gate and |c| < eps dropped after every
+ * non-Clifford gate, the inverse-noise rescale by exp(2 noise_sign sum_{k anticommuting}
+ * lambda_k) (Eq. evolve_noise; in PP_MODE_ERROR_ORDER the expansion described above,
+ * followed by the eps threshold per (string, order)), then the max_terms cap. */
+pp_status pp_apply_layer(pp_obs* obs, const pp_layer* layer);
+
+/* Explicit greedy truncation: drop |c| < eps, then keep the max_terms largest |c|
+ * (0 = no cap; ties to the smaller canonical key).  E.g. the K_M leading terms of
+ * Section I.C's estimation step. */
+pp_status pp_truncate(pp_obs* obs, double eps, int64_t max_terms);
+
+/* <b| O |b> = sum over terms with x = 0 of c (-1)^{|z & b|} (Section I.B's <O> for a
+ * computational-basis state), reduced in FP64 on the device; basis: W host words, or
+ * NULL for |0...0>.  In PP_MODE_ERROR_ORDER all orders are summed. */
+pp_status pp_expectation(pp_obs* obs, const uint64_t* basis, double* out);
+
+/* Current number of terms (distinct (string, order) entries). */
+pp_status pp_size(pp_obs* obs, int64_t* out);
+
+/* Copy all terms to host arrays sized by pp_size: x, z [n][W], c [n] (FP64), ord [n]
+ * (0 in greedy mode), in canonical order: x words compared from word W-1 down, then z
+ * words likewise, then order.  Any output pointer may be NULL. */
+pp_status pp_export(pp_obs* obs, uint64_t* x, uint64_t* z, double* c, uint8_t* ord);
+
+void pp_destroy(pp_obs* obs);
+
+/* Thread-local message of the last failed call on this thread ("" if none). */
+const char* pp_last_error(void);
+
+/* ---- instrumentation (not part of the method) ---------------------------------------
+ * When enabled, every kernel launch of the context is bracketed by HIP events on the
+ * context's stream, and per-kernel-name totals (launch count, summed device time,
+ * summed algorithmic bytes) are accumulated until read.  pp_timing_read fills up to
+ * `cap` records and returns the number of distinct kernel names. */
+typedef struct {
+  char name[48];
+  int64_t launches;
+  double total_ms;
+  double algo_bytes;     /* bytes the method must move for the launches' work */
+  double items;          /* terms processed (term-updates for layer kernels) */
+} pp_kernel_stat;
+
+pp_status pp_timing_enable(pp_ctx* ctx, int enable);
+int pp_timing_read(pp_ctx* ctx, pp_kernel_stat* out, int cap, int reset);
+
+/* Per-layer counters of the last pp_apply_layer on this observable. */
+typedef struct {
+  int64_t n_in;            /* terms entering the layer */
+  int64_t n_out;           /* terms after the layer (after the cap) */
+  int64_t n_peak;          /* largest intermediate count */
+  int64_t n_fallback;      /* terms routed to the per-gate path */
+  int64_t n_capped;        /* terms removed by the cap */
+  double dropped_l1;       /* sum of |c| removed by thresholds and the cap */
+} pp_layer_stats;
+
+pp_status pp_last_layer_stats(pp_obs* obs, pp_layer_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PP_H */

@@ -1,0 +1,1298 @@
+// pp_api.hip -- host orchestration and the C ABI (include/pp.h) of the gfx950 library.
+//
+// Per layer (pp_apply_layer) the host classifies the gates, uploads them in application
+// order with their exact or libm cos/sin, and enqueues:
+//   * all-Clifford layer: one elementwise kernel (strings map one-to-one; no merging);
+//   * a run of X-type (z-preserving) or Z-type (x-preserving) rotations: group-hash radix
+//     passes, tile boundaries, then the fused LDS layer kernel (all gates of the run, the
+//     per-gate merge and threshold, and the noise map when it follows);
+//   * any other rotation: the same fused kernel with one gate, grouped by its pair key;
+//   * tiles that outgrow LDS: the per-gate path (expand, canonical sort, segmented sum);
+//   * the cap: radix select on |c| with ties ranked by canonical key, then compaction.
+#include "../../include/pp.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "pp_common.hpp"
+#include "pp_layer.hpp"
+#include "pp_misc.hpp"
+#include "pp_sort.hpp"
+
+using namespace pp;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Failure {
+  pp_status status;
+  std::string msg;
+};
+
+[[noreturn]] void throw_fail(pp_status s, const std::string& m) { throw Failure{s, m}; }
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) throw_fail(PP_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+inline uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+inline int ceil_log2(uint64_t v) { int k = 0; while ((1ULL << k) < v) ++k; return k; }
+inline int floor_log2(uint64_t v) { int k = 0; while ((2ULL << k) <= v) ++k; return k; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------------------------
+struct pp_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  pp_alloc_fn alloc = nullptr;
+  pp_release_fn release = nullptr;
+  void* user = nullptr;
+  uint64_t* pinned = nullptr;   // host-pinned scratch for counters
+  bool timing = false;
+  struct Pending {
+    std::string name;
+    hipEvent_t a, b;
+    double bytes, items;
+  };
+  std::vector<Pending> pending;
+  struct Acc {
+    int64_t launches = 0;
+    double ms = 0, bytes = 0, items = 0;
+  };
+  std::map<std::string, Acc> acc;
+  std::vector<hipEvent_t> evfree;
+
+  void* dalloc(size_t b) {
+    if (b == 0) b = 256;
+    void* p = nullptr;
+    if (alloc) {
+      p = alloc(b, user);
+    } else if (hipMalloc(&p, b) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+    if (!p) throw_fail(PP_ERR_OOM, "device allocation of " + std::to_string(b) + " bytes failed");
+    return p;
+  }
+  void dfree(void* p) {
+    if (!p) return;
+    if (release) release(p, user);
+    else (void)hipFree(p);
+  }
+  hipEvent_t ev() {
+    if (!evfree.empty()) {
+      hipEvent_t e = evfree.back();
+      evfree.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    return e;
+  }
+  // Enqueue `f` bracketed by events when timing is on.  Returns the pending index or -1.
+  template <class F>
+  int run(const char* name, double bytes, double items, F&& f) {
+    if (!timing) {
+      f();
+      return -1;
+    }
+    Pending p{name, ev(), ev(), bytes, items};
+    HIPCHK(hipEventRecord(p.a, stream));
+    f();
+    HIPCHK(hipEventRecord(p.b, stream));
+    pending.push_back(p);
+    return (int)pending.size() - 1;
+  }
+  void collect() {
+    if (pending.empty()) return;
+    HIPCHK(hipStreamSynchronize(stream));
+    for (auto& p : pending) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+      Acc& a = acc[p.name];
+      a.launches += 1;
+      a.ms += ms;
+      a.bytes += p.bytes;
+      a.items += p.items;
+      evfree.push_back(p.a);
+      evfree.push_back(p.b);
+    }
+    pending.clear();
+  }
+  void check_launch() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw_fail(PP_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+  }
+};
+
+namespace {
+
+struct Buf {
+  pp_ctx* ctx = nullptr;
+  void* p = nullptr;
+  size_t bytes = 0;
+  void ensure(size_t b) {
+    if (b <= bytes) return;
+    release();
+    const size_t nb = b + b / 4 + 256;
+    p = ctx->dalloc(nb);
+    bytes = nb;
+  }
+  void release() {
+    if (p) ctx->dfree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T>
+  T* as() const { return (T*)p; }
+};
+
+template <class CT, bool ORD>
+struct TBuf {
+  Buf mem;
+  uint64_t cap = 0;
+  int W = 1;
+  static size_t bytes_for(int W, uint64_t n) {
+    return (size_t)n * (16 * W + sizeof(CT) + (ORD ? 1 : 0)) + 1024;
+  }
+  void ensure(uint64_t n) {   // contents are NOT preserved
+    if (n <= cap) return;
+    const uint64_t nc = std::max<uint64_t>(n + n / 4, 4096);
+    mem.release();
+    mem.ensure(bytes_for(W, nc));
+    cap = nc;
+  }
+  Terms<CT> view() const {
+    Terms<CT> t;
+    char* b = (char*)mem.p;
+    t.x = (uint64_t*)b;
+    t.z = t.x + (size_t)W * cap;
+    t.c = (CT*)(t.z + (size_t)W * cap);
+    t.o = ORD ? (uint8_t*)(t.c + cap) : nullptr;
+    t.stride = cap;
+    return t;
+  }
+  void swap(TBuf& o) {
+    std::swap(mem.p, o.mem.p);
+    std::swap(mem.bytes, o.mem.bytes);
+    std::swap(cap, o.cap);
+  }
+};
+
+// Clifford test and cos/sin: multiples of pi/2 (within 1e-12 of the quotient) are exact.
+bool angle_cos_sin(double theta, double* c, double* s) {
+  const double q = theta / (M_PI / 2);
+  const double r = std::nearbyint(q);
+  if (std::fabs(q - r) < 1e-12) {
+    const long k = (((long)r) % 4 + 4) % 4;
+    const double cc[4] = {1.0, 0.0, -1.0, 0.0};
+    const double ss[4] = {0.0, 1.0, 0.0, -1.0};
+    *c = cc[k];
+    *s = ss[k];
+    return true;
+  }
+  *c = std::cos(theta);
+  *s = std::sin(theta);
+  return false;
+}
+
+enum GateKind { KIND_X = 0, KIND_Z = 1, KIND_OTHER = 2, KIND_NOISE = 3 };
+
+struct HostGate {
+  GateDev g;
+  int kind;
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// Observable
+// ---------------------------------------------------------------------------------------------
+struct EngineBase {
+  virtual ~EngineBase() = default;
+  virtual void create(int64_t n, const uint64_t* x, const uint64_t* z, const double* c) = 0;
+  virtual void apply_layer(const pp_layer* L) = 0;
+  virtual void truncate(double eps, int64_t cap) = 0;
+  virtual double expectation(const uint64_t* basis) = 0;
+  virtual void export_terms(uint64_t* x, uint64_t* z, double* c, uint8_t* o) = 0;
+  virtual uint64_t size() const = 0;
+};
+
+struct pp_obs {
+  pp_ctx* ctx = nullptr;
+  int n_qubits = 0;
+  int W = 1;
+  pp_precision prec = PP_F64;
+  pp_mode mode = PP_MODE_GREEDY;
+  pp_trunc trunc{0.0, 0, 2};
+  bool broken = false;
+  pp_layer_stats last{};
+  std::unique_ptr<EngineBase> eng;
+};
+
+namespace {
+
+template <int W, class CT, bool ORD>
+struct Engine final : EngineBase {
+  static constexpr int CAP = LayerCfg<W>::CAP;
+  static constexpr int BLOCK = LayerCfg<W>::BLOCK;
+  static constexpr double kTermBytes = 16.0 * W + sizeof(CT) + (ORD ? 1 : 0);
+
+  pp_obs* obs;
+  pp_ctx* ctx;
+  hipStream_t st;
+  uint64_t N = 0;
+  TBuf<CT, ORD> cur, alt, sa, sb;
+  TBuf<double, true> ta, tb;     // tie lists for the cap
+  Buf u32a, u32b, u32c, scan_scr, tiles, gates_d, sup_d, tab_d, dm_d, dval_d, cnt_d, ovf_d, partial_d, f64_d, span_d;
+  double growth[4] = {4.0, 4.0, 2.0, 3.0};
+
+  explicit Engine(pp_obs* o) : obs(o), ctx(o->ctx), st(o->ctx->stream) {
+    for (auto* t : {&cur, &alt, &sa, &sb}) { t->mem.ctx = ctx; t->W = W; }
+    for (auto* t : {&ta, &tb}) { t->mem.ctx = ctx; t->W = W; }
+    for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
+                   &partial_d, &f64_d, &span_d})
+      b->ctx = ctx;
+    cnt_d.ensure(256);
+    span_d.ensure(256);
+  }
+  ~Engine() override {
+    for (auto* t : {&cur, &alt, &sa, &sb}) t->mem.release();
+    for (auto* t : {&ta, &tb}) t->mem.release();
+    for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
+                   &partial_d, &f64_d, &span_d})
+      b->release();
+  }
+
+  uint64_t size() const override { return N; }
+
+  static dim3 grid1(uint64_t n, int b = 256) { return dim3((unsigned)std::max<uint64_t>(1, cdiv(n, b))); }
+
+  void sync() { HIPCHK(hipStreamSynchronize(st)); }
+
+  // ---- scans ---------------------------------------------------------------------------------
+  void scan_u32(uint32_t* data, uint64_t n) {
+    scan_scr.ensure(scan_scratch_words(n) * 4);
+    ctx->run("scan", 0, (double)n, [&] { exclusive_scan_u32(data, n, scan_scr.as<uint32_t>(), st); });
+    ctx->check_launch();
+  }
+
+  // ---- radix passes ----------------------------------------------------------------------------
+  template <class CT2, bool ORD2, class DS>
+  void radix_pass(TBuf<CT2, ORD2>& a, TBuf<CT2, ORD2>& b, uint64_t n, const DS& ds, int bits, const char* tag) {
+    const uint32_t nblocks = (uint32_t)cdiv(n, kSortTile);
+    const int bins = 1 << bits;
+    u32a.ensure((size_t)bins * nblocks * 4 + 64);
+    b.ensure(n);
+    const Terms<CT2> in = a.view(), out = b.view();
+    uint32_t* counts = u32a.as<uint32_t>();
+    ctx->run("radix_hist", 0, (double)n, [&] {
+      hipLaunchKernelGGL((k_radix_hist<W, CT2, DS>), dim3(nblocks), dim3(kSortBlock), 0, st, in, n, ds, bins,
+                         counts, nblocks);
+    });
+    ctx->check_launch();
+    scan_u32(counts, (uint64_t)bins * nblocks);
+    const double rec = 16.0 * W + sizeof(CT2) + (ORD2 ? 1 : 0);
+    ctx->run(tag, 2.0 * rec * n, (double)n, [&] {
+      hipLaunchKernelGGL((k_radix_scatter<W, CT2, ORD2, DS>), dim3(nblocks), dim3(kSortBlock), 0, st, in, out, n,
+                         ds, bits, (const uint32_t*)counts, nblocks);
+    });
+    ctx->check_launch();
+    a.swap(b);
+  }
+
+  // Sort by the low k bits of the group hash (result in a).
+  void hash_sort(TBuf<CT, ORD>& a, TBuf<CT, ORD>& b, uint64_t n, const GroupMask& gm, int k) {
+    const int passes = (k + kMaxDigitBits - 1) / kMaxDigitBits;
+    const int bits = (k + passes - 1) / passes;
+    for (int p = 0; p < passes; ++p) {
+      HashDigits<W> ds{gm, p * bits, bits};
+      radix_pass(a, b, n, ds, bits, "radix_scatter_hash");
+    }
+  }
+
+  // Canonical order: x words (word W-1 most significant), then z words, then order.  Digits
+  // whose bits are the same in every term are skipped.  Result in a.
+  template <class CT2, bool ORD2>
+  void canonical_sort(TBuf<CT2, ORD2>& a, TBuf<CT2, ORD2>& b, uint64_t n) {
+    if (n <= 1) return;
+    constexpr int NP = 2 * W + 1;
+    HIPCHK(hipMemsetAsync(span_d.p, 0, 8 * NP, st));
+    HIPCHK(hipMemsetAsync(span_d.as<unsigned long long>() + NP, 0xff, 8 * NP, st));
+    const Terms<CT2> t = a.view();
+    unsigned long long* oa = span_d.as<unsigned long long>();
+    const unsigned nb = (unsigned)std::min<uint64_t>(1024, cdiv(n, 256));
+    ctx->run("key_span", 0, (double)n, [&] {
+      hipLaunchKernelGGL((k_key_span<W, CT2, ORD2>), dim3(nb), dim3(256), 0, st, t, n, oa);
+    });
+    ctx->check_launch();
+    uint64_t span[2 * NP];
+    HIPCHK(hipMemcpyAsync(ctx->pinned, oa, 16 * NP, hipMemcpyDeviceToHost, st));
+    sync();
+    std::memcpy(span, ctx->pinned, 16 * NP);
+    // least significant first: order, z words 0..W-1, x words 0..W-1
+    std::vector<int> planes;
+    if (ORD2) planes.push_back(2 * W);
+    for (int w = 0; w < W; ++w) planes.push_back(W + w);
+    for (int w = 0; w < W; ++w) planes.push_back(w);
+    for (int p : planes) {
+      const uint64_t var = span[p] ^ span[NP + p];
+      if (!var) continue;
+      const int lo = __builtin_ctzll(var);
+      const int hi = 63 - __builtin_clzll(var);
+      const int width = hi - lo + 1;
+      const int passes = (width + kMaxDigitBits - 1) / kMaxDigitBits;
+      const int bits = (width + passes - 1) / passes;
+      for (int q = 0; q < passes; ++q) {
+        const int sh = lo + q * bits;
+        const int bb = std::min(bits, 64 - sh);
+        WordDigits<W> ds{p, sh, bb};
+        radix_pass(a, b, n, ds, bb, "radix_scatter_canon");
+      }
+    }
+  }
+
+  // On a canonically sorted buffer a: merge runs, drop zeros and |c| < thr; result in a.
+  uint64_t merge_sorted(TBuf<CT, ORD>& a, TBuf<CT, ORD>& b, uint64_t n, double thr, double* dropped_dev) {
+    if (n == 0) return 0;
+    u32b.ensure(n * 4 + 64);
+    u32c.ensure(n * 4 + 64);
+    uint32_t* keep = u32b.as<uint32_t>();
+    uint32_t* pos = u32c.as<uint32_t>();
+    const Terms<CT> t = a.view();
+    ctx->run("reduce_runs", 0, (double)n, [&] {
+      hipLaunchKernelGGL((k_reduce_runs<W, CT, ORD>), grid1(n), dim3(256), 0, st, t, n, thr, keep, dropped_dev);
+    });
+    ctx->check_launch();
+    HIPCHK(hipMemcpyAsync(pos, keep, n * 4, hipMemcpyDeviceToDevice, st));
+    scan_u32(pos, n);
+    uint32_t last_pos = 0, last_keep = 0;
+    HIPCHK(hipMemcpyAsync(ctx->pinned, pos + n - 1, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync((char*)ctx->pinned + 4, keep + n - 1, 4, hipMemcpyDeviceToHost, st));
+    sync();
+    std::memcpy(&last_pos, ctx->pinned, 4);
+    std::memcpy(&last_keep, (char*)ctx->pinned + 4, 4);
+    const uint64_t m = (uint64_t)last_pos + last_keep;
+    b.ensure(std::max<uint64_t>(m, 1));
+    const Terms<CT> o = b.view();
+    ctx->run("compact", 0, (double)n, [&] {
+      hipLaunchKernelGGL((k_compact<W, CT, ORD>), grid1(n), dim3(256), 0, st, t, o, n, (const uint32_t*)keep,
+                         (const uint32_t*)pos);
+    });
+    ctx->check_launch();
+    a.swap(b);
+    return m;
+  }
+
+  // Keep-flag compaction of cur (flags in u32b) -> cur.
+  uint64_t compact_cur(uint32_t* keep) {
+    u32c.ensure(N * 4 + 64);
+    uint32_t* pos = u32c.as<uint32_t>();
+    HIPCHK(hipMemcpyAsync(pos, keep, N * 4, hipMemcpyDeviceToDevice, st));
+    scan_u32(pos, N);
+    uint32_t lp = 0, lk = 0;
+    HIPCHK(hipMemcpyAsync(ctx->pinned, pos + N - 1, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync((char*)ctx->pinned + 4, keep + N - 1, 4, hipMemcpyDeviceToHost, st));
+    sync();
+    std::memcpy(&lp, ctx->pinned, 4);
+    std::memcpy(&lk, (char*)ctx->pinned + 4, 4);
+    const uint64_t m = (uint64_t)lp + lk;
+    alt.ensure(std::max<uint64_t>(m, 1));
+    const Terms<CT> in = cur.view(), out = alt.view();
+    const uint64_t n = N;
+    ctx->run("compact", 0, (double)n, [&] {
+      hipLaunchKernelGGL((k_compact<W, CT, ORD>), grid1(n), dim3(256), 0, st, in, out, n, (const uint32_t*)keep,
+                         (const uint32_t*)pos);
+    });
+    ctx->check_launch();
+    cur.swap(alt);
+    N = m;
+    return m;
+  }
+
+  // ---- gates and noise on the host --------------------------------------------------------------
+  std::vector<HostGate> prepare_gates(const pp_layer* L) {
+    std::vector<HostGate> out;
+    for (int i = 0; i < L->n_gates; ++i) {
+      const int g = L->dir == PP_HEISENBERG ? L->n_gates - 1 - i : i;
+      HostGate h{};
+      std::memset(&h.g, 0, sizeof h.g);
+      bool any_x = false, any_z = false;
+      int rr = 0;
+      for (int w = 0; w < W; ++w) {
+        h.g.m[w] = L->gx[(size_t)g * W + w];
+        h.g.m[W + w] = L->gz[(size_t)g * W + w];
+        any_x |= h.g.m[w] != 0;
+        any_z |= h.g.m[W + w] != 0;
+        rr += __builtin_popcountll(h.g.m[w] & h.g.m[W + w]);
+      }
+      double cs, sn;
+      h.g.clifford = angle_cos_sin(L->theta[g], &cs, &sn) ? 1 : 0;
+      h.g.cs = cs;
+      h.g.sn_dir = L->dir == PP_HEISENBERG ? sn : -sn;
+      h.g.rr_phase = rr & 3;
+      h.g.pivot_word = -1;
+      h.g.pivot_bit = 0;
+      for (int w = 0; w < 2 * W; ++w)
+        if (h.g.m[w]) {
+          h.g.pivot_word = w;
+          h.g.pivot_bit = __builtin_ctzll(h.g.m[w]);
+          break;
+        }
+      if (h.g.pivot_word < 0) { h.g.pivot_word = 0; h.g.pivot_bit = 0; }
+      h.kind = !any_z ? KIND_X : (!any_x ? KIND_Z : KIND_OTHER);
+      out.push_back(h);
+    }
+    return out;
+  }
+
+  struct HostNoise {
+    std::vector<SupportDev> sup;
+    std::vector<double> tab;
+    std::vector<uint64_t> dm;
+    std::vector<double> dval;
+    int np = 1;
+  };
+
+  // Decompose the generators by support (Section I's local Pauli-Lindblad channels are
+  // independent; their factors multiply, so the exponent or power sums add over supports).
+  HostNoise prepare_noise(const pp_layer* L, int mode, int max_order) {
+    HostNoise hn;
+    const int np = mode == PP_MODE_GREEDY ? 1 : std::max(1, max_order);
+    hn.np = np;
+    std::map<std::pair<int, int>, std::vector<int>> by_sup;
+    for (int k = 0; k < L->n_gen; ++k) {
+      std::vector<int> qs;
+      for (int w = 0; w < W && qs.size() <= 2; ++w) {
+        uint64_t s = L->ex[(size_t)k * W + w] | L->ez[(size_t)k * W + w];
+        while (s && qs.size() <= 2) {
+          qs.push_back(64 * w + __builtin_ctzll(s));
+          s &= s - 1;
+        }
+      }
+      if (qs.empty()) continue;   // identity generator commutes with everything
+      if (qs.size() <= 2) by_sup[{qs[0], qs.size() == 2 ? qs[1] : -1}].push_back(k);
+      else {
+        for (int w = 0; w < W; ++w) hn.dm.push_back(L->ex[(size_t)k * W + w]);
+        for (int w = 0; w < W; ++w) hn.dm.push_back(L->ez[(size_t)k * W + w]);
+        const double v = mode == PP_MODE_GREEDY ? L->lambda[k] : std::expm1(2.0 * L->noise_sign * L->lambda[k]);
+        double pw = 1.0;
+        for (int j = 0; j < np; ++j) {
+          pw = mode == PP_MODE_GREEDY ? v : pw * v;
+          hn.dval.push_back(pw);
+        }
+      }
+    }
+    auto bit = [&](const uint64_t* a, int k, int q) -> int { return (int)((a[(size_t)k * W + q / 64] >> (q % 64)) & 1ULL); };
+    for (auto& kv : by_sup) {
+      const int q0 = kv.first.first, q1 = kv.first.second;
+      SupportDev sd;
+      sd.w0 = (int16_t)(q0 / 64);
+      sd.b0 = (int16_t)(q0 % 64);
+      sd.w1 = (int16_t)(q1 < 0 ? -1 : q1 / 64);
+      sd.b1 = (int16_t)(q1 < 0 ? 0 : q1 % 64);
+      sd.table = (int32_t)hn.tab.size();
+      const int npat = q1 < 0 ? 4 : 16;
+      for (int pat = 0; pat < npat; ++pat) {
+        const int px0 = pat & 1, pz0 = (pat >> 1) & 1, px1 = (pat >> 2) & 1, pz1 = (pat >> 3) & 1;
+        std::vector<double> acc(np, 0.0);
+        for (int k : kv.second) {
+          int par = px0 * bit(L->ez, k, q0) + pz0 * bit(L->ex, k, q0);
+          if (q1 >= 0) par += px1 * bit(L->ez, k, q1) + pz1 * bit(L->ex, k, q1);
+          if (!(par & 1)) continue;
+          const double v = mode == PP_MODE_GREEDY ? L->lambda[k] : std::expm1(2.0 * L->noise_sign * L->lambda[k]);
+          double pw = 1.0;
+          for (int j = 0; j < np; ++j) {
+            pw = mode == PP_MODE_GREEDY ? v : pw * v;
+            acc[j] += pw;
+          }
+        }
+        for (int j = 0; j < np; ++j) hn.tab.push_back(acc[j]);
+      }
+      hn.sup.push_back(sd);
+    }
+    return hn;
+  }
+
+  NoiseDev upload_noise(const HostNoise& hn, int sign, int mode, int max_order) {
+    NoiseDev nd{};
+    nd.nsup = (int)hn.sup.size();
+    nd.ndirect = (int)(hn.dm.size() / (2 * W));
+    nd.sign = sign;
+    nd.mode = mode == PP_MODE_GREEDY ? 0 : 1;
+    nd.max_order = max_order;
+    sup_d.ensure(hn.sup.size() * sizeof(SupportDev) + 64);
+    tab_d.ensure(hn.tab.size() * 8 + 64);
+    dm_d.ensure(hn.dm.size() * 8 + 64);
+    dval_d.ensure(hn.dval.size() * 8 + 64);
+    if (!hn.sup.empty())
+      HIPCHK(hipMemcpyAsync(sup_d.p, hn.sup.data(), hn.sup.size() * sizeof(SupportDev), hipMemcpyHostToDevice, st));
+    if (!hn.tab.empty()) HIPCHK(hipMemcpyAsync(tab_d.p, hn.tab.data(), hn.tab.size() * 8, hipMemcpyHostToDevice, st));
+    if (!hn.dm.empty()) HIPCHK(hipMemcpyAsync(dm_d.p, hn.dm.data(), hn.dm.size() * 8, hipMemcpyHostToDevice, st));
+    if (!hn.dval.empty())
+      HIPCHK(hipMemcpyAsync(dval_d.p, hn.dval.data(), hn.dval.size() * 8, hipMemcpyHostToDevice, st));
+    nd.sup = sup_d.as<SupportDev>();
+    nd.tab = tab_d.as<double>();
+    nd.dm = dm_d.as<uint64_t>();
+    nd.dval = dval_d.as<double>();
+    // The uploads above are ordered on the stream before the kernels that read them; the
+    // host vectors are synchronous copies' sources, so wait for them before returning.
+    sync();
+    return nd;
+  }
+
+  // ---- per-gate path on a subset (sa holds m terms) ------------------------------------------
+  uint64_t per_gate(uint64_t m, const std::vector<GateDev>& gates, double eps, const NoiseDev* nd,
+                    double eps_noise, double* dropped_dev) {
+    for (const GateDev& G : gates) {
+      if (m == 0) break;
+      sb.ensure(2 * m);
+      const Terms<CT> in = sa.view(), out = sb.view();
+      ctx->run("expand_gate", 0, (double)m, [&] {
+        hipLaunchKernelGGL((k_expand_gate<W, CT, ORD>), grid1(m), dim3(256), 0, st, in, m, G, out);
+      });
+      ctx->check_launch();
+      sa.swap(sb);
+      canonical_sort(sa, sb, 2 * m);
+      m = merge_sorted(sa, sb, 2 * m, G.clifford ? 0.0 : eps, dropped_dev);
+    }
+    if (nd && m) {
+      if (nd->mode == 0) {
+        const Terms<CT> t = sa.view();
+        const NoiseDev ndv = *nd;
+        ctx->run("noise", 0, (double)m, [&] {
+          hipLaunchKernelGGL((k_noise_greedy<W, CT>), grid1(m), dim3(256), 0, st, t, m, ndv);
+        });
+        ctx->check_launch();
+      } else {
+        const uint64_t M1 = (uint64_t)nd->max_order + 1;
+        sb.ensure(m * M1);
+        const Terms<CT> in = sa.view(), out = sb.view();
+        const NoiseDev ndv = *nd;
+        ctx->run("expand_noise", 0, (double)m, [&] {
+          hipLaunchKernelGGL((k_expand_noise<W, CT, ORD>), grid1(m), dim3(256), 0, st, in, m, ndv, out);
+        });
+        ctx->check_launch();
+        sa.swap(sb);
+        canonical_sort(sa, sb, m * M1);
+        m = merge_sorted(sa, sb, m * M1, eps_noise, dropped_dev);
+      }
+    }
+    return m;
+  }
+
+  struct Counters {
+    unsigned long long out_count;
+    uint32_t ovf_count;
+    uint32_t peak;
+    double dropped;
+  };
+
+  // ---- grouped fused pass ---------------------------------------------------------------------
+  void grouped_pass(const std::vector<GateDev>& gates, const GroupMask& gm, int kind, double eps,
+                    const NoiseDev* nd, double eps_noise, pp_layer_stats& ls) {
+    if (N == 0) return;
+    const uint64_t n_in = N;
+    const double g = growth[kind];
+    uint64_t T = (uint64_t)std::max(16.0, std::min((double)CAP / 2, (double)CAP / g));
+    uint64_t ntiles;
+    if (N <= T) {
+      ntiles = 1;
+      tiles.ensure(64);
+      uint32_t h[2] = {0u, (uint32_t)N};
+      std::memcpy(ctx->pinned, h, 8);
+      HIPCHK(hipMemcpyAsync(tiles.p, ctx->pinned, 8, hipMemcpyHostToDevice, st));
+    } else {
+      const int k = std::min(40, std::max(8, ceil_log2(N) - floor_log2(T) + 4));
+      const int passes = (k + kMaxDigitBits - 1) / kMaxDigitBits;
+      const int kk = passes * ((k + passes - 1) / passes);
+      hash_sort(cur, alt, N, gm, kk);
+      ntiles = cdiv(N, T);
+      tiles.ensure((ntiles + 2) * 4);
+      const Terms<CT> t = cur.view();
+      const uint64_t kmask = kk >= 64 ? ~0ULL : ((1ULL << kk) - 1);
+      uint32_t* ts = tiles.as<uint32_t>();
+      const uint64_t n = N;
+      ctx->run("tiles", 0, (double)ntiles, [&] {
+        hipLaunchKernelGGL((k_tiles<W, CT>), grid1(ntiles + 1), dim3(256), 0, st, t, n, gm, kmask, T,
+                           (uint32_t)ntiles, ts);
+      });
+      ctx->check_launch();
+    }
+    gates_d.ensure(std::max<size_t>(1, gates.size()) * sizeof(GateDev) + 64);
+    if (!gates.empty())
+      HIPCHK(hipMemcpyAsync(gates_d.p, gates.data(), gates.size() * sizeof(GateDev), hipMemcpyHostToDevice, st));
+    const uint64_t out_cap = (uint64_t)((double)N * std::max(2.0, g) * 1.25) + 4 * CAP;
+    alt.ensure(out_cap);
+    ovf_d.ensure((ntiles + 2) * 4);
+    HIPCHK(hipMemsetAsync(cnt_d.p, 0, sizeof(Counters), st));
+    Counters* cd = cnt_d.as<Counters>();
+    LayerArgs<CT> a{};
+    a.in = cur.view();
+    a.out = alt.view();
+    a.out.stride = alt.cap;
+    a.tile_start = tiles.as<uint32_t>();
+    a.tile_list = nullptr;
+    a.gates = gates_d.as<GateDev>();
+    a.ngates = (int)gates.size();
+    a.eps = eps;
+    a.has_noise = nd ? 1 : 0;
+    if (nd) a.noise = *nd;
+    a.eps_noise = eps_noise;
+    a.out_count = &cd->out_count;
+    a.ovf_tiles = ovf_d.as<uint32_t>();
+    a.ovf_count = &cd->ovf_count;
+    a.dropped = &cd->dropped;
+    a.peak = &cd->peak;
+    // A term's bytes in and out of the layer (reads of every input term, writes of every
+    // output term) are the algorithmic traffic; the count of outputs is known afterwards.
+    const int pi = ctx->run("layer_fused", 0, (double)n_in, [&] {
+      hipLaunchKernelGGL((k_layer<W, CT, ORD>), dim3((unsigned)ntiles), dim3(BLOCK), 0, st, a);
+    });
+    ctx->check_launch();
+    Counters hc;
+    HIPCHK(hipMemcpyAsync(ctx->pinned, cd, sizeof(Counters), hipMemcpyDeviceToHost, st));
+    sync();
+    std::memcpy(&hc, ctx->pinned, sizeof hc);
+    uint64_t n_out = hc.out_count;
+    if (pi >= 0) ctx->pending[pi].bytes = kTermBytes * (double)(n_in + n_out);
+    ls.n_peak = std::max<int64_t>(ls.n_peak, (int64_t)n_out);
+    if (hc.ovf_count > 0) {
+      const uint32_t nov = hc.ovf_count;
+      std::vector<uint32_t> ov(nov), ts(ntiles + 1);
+      HIPCHK(hipMemcpyAsync(ov.data(), ovf_d.p, 4 * (size_t)nov, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(ts.data(), tiles.p, 4 * (ntiles + 1), hipMemcpyDeviceToHost, st));
+      sync();
+      std::vector<uint32_t> src, len;
+      std::vector<uint64_t> dst;
+      uint64_t m = 0;
+      bool out_ovf = false;
+      for (uint32_t v : ov) {
+        out_ovf |= (v & kOvfOutput) != 0;
+        const uint32_t t = v & ~kOvfOutput;
+        const uint32_t s0 = ts[t], s1 = ts[t + 1];
+        src.push_back(s0);
+        len.push_back(s1 - s0);
+        dst.push_back(m);
+        m += s1 - s0;
+      }
+      ls.n_fallback += (int64_t)m;
+      sa.ensure(std::max<uint64_t>(m, 1));
+      u32b.ensure(8 * (size_t)nov + 64);
+      u32c.ensure(8 * (size_t)nov + 64);
+      partial_d.ensure(8 * (size_t)nov + 64);
+      HIPCHK(hipMemcpyAsync(u32b.p, src.data(), 4 * (size_t)nov, hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(u32c.p, len.data(), 4 * (size_t)nov, hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(partial_d.p, dst.data(), 8 * (size_t)nov, hipMemcpyHostToDevice, st));
+      const Terms<CT> in = cur.view(), sub = sa.view();
+      const uint32_t *srcd = u32b.as<uint32_t>(), *lend = u32c.as<uint32_t>();
+      const uint64_t* dstd = partial_d.as<uint64_t>();
+      ctx->run("copy_ranges", 0, (double)m, [&] {
+        hipLaunchKernelGGL((k_copy_ranges<W, CT, ORD>), dim3(nov), dim3(256), 0, st, in, sub, srcd, lend, dstd,
+                           (int)nov);
+      });
+      ctx->check_launch();
+      sync();   // the range lists are host vectors
+      const uint64_t mm = per_gate(m, gates, eps, nd, eps_noise, &cd->dropped);
+      // append the per-gate results behind the fused output (grow keeping the prefix)
+      if (n_out + mm > alt.cap) {
+        sb.ensure(std::max<uint64_t>(n_out, 1));
+        const Terms<CT> from = alt.view(), to = sb.view();
+        if (n_out) {
+          ctx->run("copy", 0, (double)n_out, [&] {
+            hipLaunchKernelGGL((k_copy<W, CT, ORD>), grid1(n_out), dim3(256), 0, st, from, 0, to, 0, n_out);
+          });
+          ctx->check_launch();
+        }
+        alt.ensure(n_out + mm + 1);
+        const Terms<CT> back = alt.view(), hold = sb.view();
+        if (n_out) {
+          ctx->run("copy", 0, (double)n_out, [&] {
+            hipLaunchKernelGGL((k_copy<W, CT, ORD>), grid1(n_out), dim3(256), 0, st, hold, 0, back, 0, n_out);
+          });
+          ctx->check_launch();
+        }
+      }
+      if (mm) {
+        const Terms<CT> from = sa.view(), to = alt.view();
+        ctx->run("copy", 0, (double)mm, [&] {
+          hipLaunchKernelGGL((k_copy<W, CT, ORD>), grid1(mm), dim3(256), 0, st, from, 0, to, n_out, mm);
+        });
+        ctx->check_launch();
+      }
+      n_out += mm;
+      const double frac = (double)nov / (double)ntiles;
+      if (out_ovf || frac > 0.01) growth[kind] = std::min(256.0, growth[kind] * 2.0);
+    }
+    cur.swap(alt);
+    N = n_out;
+    const double obs_g = (double)n_out / (double)std::max<uint64_t>(1, n_in);
+    growth[kind] = std::min(256.0, std::max({2.0, 1.5 * obs_g, growth[kind] * 0.75}));
+    HIPCHK(hipMemcpyAsync(ctx->pinned, cd, sizeof(Counters), hipMemcpyDeviceToHost, st));
+    sync();
+    std::memcpy(&hc, ctx->pinned, sizeof hc);
+    ls.dropped_l1 += hc.dropped;
+    ls.n_peak = std::max<int64_t>(ls.n_peak, (int64_t)hc.peak);
+  }
+
+  // ---- create ----------------------------------------------------------------------------------
+  void create(int64_t n, const uint64_t* x, const uint64_t* z, const double* c) override {
+    N = 0;
+    if (n == 0) return;
+    const uint64_t un = (uint64_t)n;
+    sa.ensure(un);
+    std::vector<uint64_t> plane(un);
+    const Terms<CT> t = sa.view();
+    for (int w = 0; w < W; ++w) {
+      for (uint64_t i = 0; i < un; ++i) plane[i] = x[i * W + w];
+      HIPCHK(hipMemcpyAsync(t.x + (size_t)w * t.stride, plane.data(), un * 8, hipMemcpyHostToDevice, st));
+      sync();
+      for (uint64_t i = 0; i < un; ++i) plane[i] = z[i * W + w];
+      HIPCHK(hipMemcpyAsync(t.z + (size_t)w * t.stride, plane.data(), un * 8, hipMemcpyHostToDevice, st));
+      sync();
+    }
+    f64_d.ensure(un * 8 + 64);
+    HIPCHK(hipMemcpyAsync(f64_d.p, c, un * 8, hipMemcpyHostToDevice, st));
+    const double* src = f64_d.as<double>();
+    CT* dstc = t.c;
+    ctx->run("convert", 0, (double)un, [&] {
+      hipLaunchKernelGGL((k_from_f64<CT>), grid1(un), dim3(256), 0, st, src, dstc, un);
+    });
+    ctx->check_launch();
+    if (ORD) HIPCHK(hipMemsetAsync(t.o, 0, un, st));
+    sync();
+    canonical_sort(sa, sb, un);
+    const uint64_t m = merge_sorted(sa, sb, un, 0.0, nullptr);
+    cur.swap(sa);
+    N = m;
+  }
+
+  // ---- apply layer -----------------------------------------------------------------------------
+  void noise_step(const pp_layer* L, pp_layer_stats& ls) {
+    const int mode = obs->mode;
+    const int M = obs->trunc.max_order;
+    HostNoise hn = prepare_noise(L, mode, M);
+    NoiseDev nd = upload_noise(hn, L->noise_sign, mode, M);
+    if (N == 0) return;
+    if (mode == PP_MODE_GREEDY) {
+      const Terms<CT> t = cur.view();
+      const uint64_t n = N;
+      ctx->run("noise", 2.0 * kTermBytes * n, (double)n, [&] {
+        hipLaunchKernelGGL((k_noise_greedy<W, CT>), grid1(n), dim3(256), 0, st, t, n, nd);
+      });
+      ctx->check_launch();
+    } else {
+      GroupMask gm;
+      for (int w = 0; w < PP_MAXW; ++w) { gm.mx[w] = ~0ULL; gm.mz[w] = ~0ULL; }
+      grouped_pass({}, gm, KIND_NOISE, 0.0, &nd, obs->trunc.eps, ls);
+    }
+  }
+
+  void apply_layer(const pp_layer* L) override {
+    pp_layer_stats ls{};
+    ls.n_in = (int64_t)N;
+    const double eps = obs->trunc.eps;
+    const bool has_noise = L->n_gen > 0;
+    bool noise_done = false;
+    if (has_noise && !L->noise_after_gates) {
+      noise_step(L, ls);
+      noise_done = true;
+    }
+    std::vector<HostGate> hg = prepare_gates(L);
+    if (!hg.empty() && N > 0) {
+      bool all_cliff = true;
+      for (auto& h : hg) all_cliff &= h.g.clifford != 0;
+      const bool fuse_noise = has_noise && !noise_done && L->noise_after_gates;
+      if (all_cliff) {
+        std::vector<GateDev> gv;
+        for (auto& h : hg) gv.push_back(h.g);
+        gates_d.ensure(gv.size() * sizeof(GateDev) + 64);
+        HIPCHK(hipMemcpyAsync(gates_d.p, gv.data(), gv.size() * sizeof(GateDev), hipMemcpyHostToDevice, st));
+        NoiseDev nd{};
+        int with_noise = 0;
+        if (fuse_noise && obs->mode == PP_MODE_GREEDY) {
+          HostNoise hn = prepare_noise(L, obs->mode, obs->trunc.max_order);
+          nd = upload_noise(hn, L->noise_sign, obs->mode, obs->trunc.max_order);
+          with_noise = 1;
+          noise_done = true;
+        }
+        const Terms<CT> t = cur.view();
+        const uint64_t n = N;
+        const GateDev* gd = gates_d.as<GateDev>();
+        const int ng = (int)gv.size();
+        ctx->run("clifford_layer", 2.0 * kTermBytes * n, (double)n, [&] {
+          hipLaunchKernelGGL((k_clifford<W, CT, ORD>), grid1(n), dim3(256), 0, st, t, n, gd, ng, with_noise, nd);
+        });
+        ctx->check_launch();
+        sync();   // gv is a host vector
+      } else {
+        // split into runs of X-type, Z-type, and single general gates
+        size_t i = 0;
+        while (i < hg.size()) {
+          size_t j = i + 1;
+          const int kind = hg[i].kind;
+          if (kind != KIND_OTHER)
+            while (j < hg.size() && hg[j].kind == kind) ++j;
+          std::vector<GateDev> run;
+          for (size_t k = i; k < j; ++k) run.push_back(hg[k].g);
+          GroupMask gm;
+          for (int w = 0; w < PP_MAXW; ++w) { gm.mx[w] = 0; gm.mz[w] = 0; }
+          for (int w = 0; w < W; ++w) {
+            if (kind == KIND_X) { gm.mx[w] = 0; gm.mz[w] = ~0ULL; }
+            else if (kind == KIND_Z) { gm.mx[w] = ~0ULL; gm.mz[w] = 0; }
+            else { gm.mx[w] = ~0ULL; gm.mz[w] = ~0ULL; }
+          }
+          if (kind == KIND_OTHER) {   // pair key: clear the pivot bit
+            const int pw = run[0].pivot_word, pb = run[0].pivot_bit;
+            if (pw < W) gm.mx[pw] &= ~(1ULL << pb);
+            else gm.mz[pw - W] &= ~(1ULL << pb);
+          }
+          const bool last = j == hg.size();
+          NoiseDev nd{};
+          const NoiseDev* ndp = nullptr;
+          if (last && fuse_noise) {
+            HostNoise hn = prepare_noise(L, obs->mode, obs->trunc.max_order);
+            nd = upload_noise(hn, L->noise_sign, obs->mode, obs->trunc.max_order);
+            ndp = &nd;
+            noise_done = true;
+          }
+          grouped_pass(run, gm, kind, eps, ndp, eps, ls);
+          i = j;
+        }
+      }
+    }
+    if (has_noise && !noise_done) noise_step(L, ls);
+    const int64_t before_cap = (int64_t)N;
+    if (obs->trunc.max_terms > 0 && (int64_t)N > obs->trunc.max_terms) cap_select((uint64_t)obs->trunc.max_terms, ls);
+    ls.n_capped = before_cap - (int64_t)N;
+    ls.n_out = (int64_t)N;
+    ls.n_peak = std::max(ls.n_peak, std::max(ls.n_in, before_cap));
+    obs->last = ls;
+  }
+
+  // ---- cap -------------------------------------------------------------------------------------
+  void cap_select(uint64_t K, pp_layer_stats& ls) {
+    if (N <= K) return;
+    const int KB = sizeof(CT) == 8 ? 63 : 31;
+    uint64_t prefix = 0, pmask = 0, need = K, count_eq = 0;
+    u32a.ensure(2048 * 4 + 64);
+    uint32_t* hist = u32a.as<uint32_t>();
+    const CT* c = cur.view().c;
+    const uint64_t n = N;
+    int hi = KB;
+    std::vector<uint32_t> h(2048);
+    while (hi > 0) {
+      const int bits = std::min(11, hi);
+      const int shift = hi - bits;
+      const int bins = 1 << bits;
+      HIPCHK(hipMemsetAsync(hist, 0, bins * 4, st));
+      const unsigned nb = (unsigned)std::min<uint64_t>(2048, cdiv(n, 256));
+      ctx->run("cap_hist", sizeof(CT) * (double)n, (double)n, [&] {
+        hipLaunchKernelGGL((k_abs_hist<CT>), dim3(nb), dim3(256), 0, st, c, n, shift, bits, pmask, prefix, hist);
+      });
+      ctx->check_launch();
+      HIPCHK(hipMemcpyAsync(ctx->pinned, hist, bins * 4, hipMemcpyDeviceToHost, st));
+      sync();
+      std::memcpy(h.data(), ctx->pinned, bins * 4);
+      uint64_t cum = 0;
+      int d = bins - 1;
+      for (; d >= 0; --d) {
+        if (cum + h[d] >= need) break;
+        cum += h[d];
+      }
+      if (d < 0) d = 0;   // cannot happen while N > K
+      need -= cum;
+      prefix |= (uint64_t)d << shift;
+      pmask |= (uint64_t)(bins - 1) << shift;
+      count_eq = h[d];
+      hi = shift;
+    }
+    const uint64_t tau = prefix;
+    u32b.ensure(n * 4 + 64);
+    u32c.ensure(n * 4 + 64);
+    uint32_t* keep = u32b.as<uint32_t>();
+    uint32_t* tie = u32c.as<uint32_t>();
+    double* dd = &cnt_d.as<Counters>()->dropped;
+    HIPCHK(hipMemsetAsync(dd, 0, 8, st));
+    ctx->run("cap_flags", 0, (double)n, [&] {
+      hipLaunchKernelGGL((k_cap_flags<CT>), grid1(n), dim3(256), 0, st, c, n, tau, keep, tie, dd);
+    });
+    ctx->check_launch();
+    if (need >= count_eq) {
+      // every tied term is kept: keep = keep | tie
+      ctx->run("cap_flags", 0, (double)n, [&] {
+        hipLaunchKernelGGL(k_or_flags, grid1(n), dim3(256), 0, st, keep, (const uint32_t*)tie, n);
+      });
+      ctx->check_launch();
+    } else {
+      // rank the tied terms by canonical key; keep the first `need`
+      Buf posb;
+      posb.ctx = ctx;
+      posb.ensure(n * 4 + 64);
+      uint32_t* pos = posb.as<uint32_t>();
+      HIPCHK(hipMemcpyAsync(pos, tie, n * 4, hipMemcpyDeviceToDevice, st));
+      scan_u32(pos, n);
+      ta.ensure(count_eq + 1);
+      const Terms<CT> in = cur.view();
+      const Terms<double> tt = ta.view();
+      ctx->run("cap_ties", 0, (double)n, [&] {
+        hipLaunchKernelGGL((k_gather_ties<W, CT, ORD>), grid1(n), dim3(256), 0, st, in, n, (const uint32_t*)tie,
+                           (const uint32_t*)pos, tt);
+      });
+      ctx->check_launch();
+      canonical_sort(ta, tb, count_eq);
+      const double* idx = ta.view().c;
+      ctx->run("cap_ties", 0, (double)need, [&] {
+        hipLaunchKernelGGL((k_mark_ties<CT>), grid1(need), dim3(256), 0, st, idx, need, keep, n);
+      });
+      ctx->check_launch();
+      sync();
+      posb.release();
+    }
+    compact_cur(keep);
+    double dropped = 0.0;
+    HIPCHK(hipMemcpyAsync(ctx->pinned, dd, 8, hipMemcpyDeviceToHost, st));
+    sync();
+    std::memcpy(&dropped, ctx->pinned, 8);
+    ls.dropped_l1 += dropped;
+  }
+
+  void truncate(double eps, int64_t cap) override {
+    pp_layer_stats ls{};
+    if (N > 0 && eps > 0.0) {
+      u32b.ensure(N * 4 + 64);
+      uint32_t* keep = u32b.as<uint32_t>();
+      const CT* c = cur.view().c;
+      const uint64_t n = N;
+      ctx->run("threshold", 0, (double)n, [&] {
+        hipLaunchKernelGGL((k_threshold_flags<CT>), grid1(n), dim3(256), 0, st, c, n, eps, keep, (double*)nullptr);
+      });
+      ctx->check_launch();
+      compact_cur(keep);
+    }
+    if (cap > 0 && (int64_t)N > cap) cap_select((uint64_t)cap, ls);
+  }
+
+  double expectation(const uint64_t* basis) override {
+    GroupMask b;
+    for (int w = 0; w < PP_MAXW; ++w) { b.mx[w] = 0; b.mz[w] = 0; }
+    if (basis)
+      for (int w = 0; w < W; ++w) b.mz[w] = basis[w];
+    const unsigned nb = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(1024, cdiv(N, 256)));
+    partial_d.ensure(nb * 8 + 64);
+    double* part = partial_d.as<double>();
+    const Terms<CT> t = cur.view();
+    const uint64_t n = N;
+    double* outd = &cnt_d.as<Counters>()->dropped;
+    ctx->run("expectation", kTermBytes * n, (double)n, [&] {
+      hipLaunchKernelGGL((k_expect<W, CT>), dim3(nb), dim3(256), 0, st, t, n, b, part);
+      hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, st, (const double*)part, (int)nb, outd);
+    });
+    ctx->check_launch();
+    double v = 0.0;
+    HIPCHK(hipMemcpyAsync(ctx->pinned, outd, 8, hipMemcpyDeviceToHost, st));
+    sync();
+    std::memcpy(&v, ctx->pinned, 8);
+    return v;
+  }
+
+  void export_terms(uint64_t* x, uint64_t* z, double* c, uint8_t* o) override {
+    if (N == 0) return;
+    const uint64_t n = N;
+    sa.ensure(n);
+    {
+      const Terms<CT> from = cur.view(), to = sa.view();
+      ctx->run("copy", 0, (double)n, [&] {
+        hipLaunchKernelGGL((k_copy<W, CT, ORD>), grid1(n), dim3(256), 0, st, from, 0, to, 0, n);
+      });
+      ctx->check_launch();
+    }
+    canonical_sort(sa, sb, n);
+    const Terms<CT> t = sa.view();
+    std::vector<uint64_t> plane(n);
+    for (int w = 0; w < W; ++w) {
+      if (x) {
+        HIPCHK(hipMemcpyAsync(plane.data(), t.x + (size_t)w * t.stride, n * 8, hipMemcpyDeviceToHost, st));
+        sync();
+        for (uint64_t i = 0; i < n; ++i) x[i * W + w] = plane[i];
+      }
+      if (z) {
+        HIPCHK(hipMemcpyAsync(plane.data(), t.z + (size_t)w * t.stride, n * 8, hipMemcpyDeviceToHost, st));
+        sync();
+        for (uint64_t i = 0; i < n; ++i) z[i * W + w] = plane[i];
+      }
+    }
+    if (c) {
+      f64_d.ensure(n * 8 + 64);
+      double* d = f64_d.as<double>();
+      const CT* src = t.c;
+      ctx->run("convert", 0, (double)n, [&] {
+        hipLaunchKernelGGL((k_to_f64<CT>), grid1(n), dim3(256), 0, st, src, d, n);
+      });
+      ctx->check_launch();
+      HIPCHK(hipMemcpyAsync(c, d, n * 8, hipMemcpyDeviceToHost, st));
+      sync();
+    }
+    if (o) {
+      if (ORD) {
+        HIPCHK(hipMemcpyAsync(o, t.o, n, hipMemcpyDeviceToHost, st));
+        sync();
+      } else {
+        std::memset(o, 0, n);
+      }
+    }
+  }
+};
+
+template <int W>
+EngineBase* make_engine_w(pp_obs* o) {
+  const bool f32 = o->prec == PP_F32_KAHAN;
+  const bool ord = o->mode == PP_MODE_ERROR_ORDER;
+  if (!f32 && !ord) return new Engine<W, double, false>(o);
+  if (!f32 && ord) return new Engine<W, double, true>(o);
+  if (f32 && !ord) return new Engine<W, float, false>(o);
+  return new Engine<W, float, true>(o);
+}
+
+EngineBase* make_engine(pp_obs* o) {
+  switch (o->W) {
+    case 1: return make_engine_w<1>(o);
+    case 2: return make_engine_w<2>(o);
+    case 3: return make_engine_w<3>(o);
+    case 4: return make_engine_w<4>(o);
+  }
+  throw_fail(PP_ERR_UNSUPPORTED, "more than 256 qubits");
+}
+
+template <class F>
+pp_status guarded(F&& f) {
+  try {
+    f();
+    return PP_OK;
+  } catch (const Failure& e) {
+    g_last_error = e.msg;
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return PP_ERR_OOM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return PP_ERR_DEVICE;
+  }
+}
+
+bool strings_ok(int n_qubits, int W, int64_t n, const uint64_t* x, const uint64_t* z) {
+  const int top = n_qubits - 64 * (W - 1);
+  const uint64_t mask = top >= 64 ? ~0ULL : ((1ULL << top) - 1);
+  for (int64_t i = 0; i < n; ++i)
+    if ((x[(size_t)i * W + W - 1] & ~mask) || (z[(size_t)i * W + W - 1] & ~mask)) return false;
+  return true;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------------------------
+extern "C" {
+
+const char* pp_last_error(void) { return g_last_error.c_str(); }
+
+pp_status pp_ctx_create(int device, void* hip_stream, pp_alloc_fn alloc, pp_release_fn release, void* user,
+                        pp_ctx** out) {
+  if (!out) { g_last_error = "out is NULL"; return PP_ERR_INVALID; }
+  *out = nullptr;
+  if ((alloc == nullptr) != (release == nullptr)) {
+    g_last_error = "alloc and release must both be given or both be NULL";
+    return PP_ERR_INVALID;
+  }
+  return guarded([&] {
+    int count = 0;
+    HIPCHK(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) throw_fail(PP_ERR_INVALID, "device index out of range");
+    HIPCHK(hipSetDevice(device));
+    auto* c = new pp_ctx;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->alloc = alloc;
+    c->release = release;
+    c->user = user;
+    if (hipHostMalloc((void**)&c->pinned, 1 << 16, hipHostMallocDefault) != hipSuccess) {
+      delete c;
+      throw_fail(PP_ERR_OOM, "pinned host allocation failed");
+    }
+    *out = c;
+  });
+}
+
+void pp_ctx_destroy(pp_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& p : ctx->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+  for (auto e : ctx->evfree) (void)hipEventDestroy(e);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  delete ctx;
+}
+
+pp_status pp_create_observable(pp_ctx* ctx, int n_qubits, int64_t n_terms, const uint64_t* x, const uint64_t* z,
+                               const double* coeff, pp_precision precision, pp_mode mode, pp_trunc trunc,
+                               pp_obs** out) {
+  if (!out) { g_last_error = "out is NULL"; return PP_ERR_INVALID; }
+  *out = nullptr;
+  if (!ctx) { g_last_error = "ctx is NULL"; return PP_ERR_INVALID; }
+  if (n_qubits < 1 || n_qubits > 64 * PP_MAXW) { g_last_error = "n_qubits must be in 1..256"; return PP_ERR_INVALID; }
+  if (n_terms < 0 || n_terms >= (1LL << 31)) { g_last_error = "n_terms out of range"; return PP_ERR_INVALID; }
+  if (n_terms > 0 && (!x || !z || !coeff)) { g_last_error = "NULL term array"; return PP_ERR_INVALID; }
+  if (precision != PP_F64 && precision != PP_F32_KAHAN) { g_last_error = "bad precision"; return PP_ERR_INVALID; }
+  if (mode != PP_MODE_GREEDY && mode != PP_MODE_ERROR_ORDER) { g_last_error = "bad mode"; return PP_ERR_INVALID; }
+  if (!(trunc.eps >= 0.0) || !std::isfinite(trunc.eps)) { g_last_error = "eps must be finite and >= 0"; return PP_ERR_INVALID; }
+  if (trunc.max_terms < 0) { g_last_error = "max_terms must be >= 0"; return PP_ERR_INVALID; }
+  if (mode == PP_MODE_ERROR_ORDER && (trunc.max_order < 0 || trunc.max_order > kMaxPowerSums)) {
+    g_last_error = "max_order must be in 0..4 on the GPU";
+    return PP_ERR_UNSUPPORTED;
+  }
+  const int W = (n_qubits + 63) / 64;
+  if (n_terms > 0 && !strings_ok(n_qubits, W, n_terms, x, z)) { g_last_error = "string bits above n_qubits"; return PP_ERR_INVALID; }
+  for (int64_t i = 0; i < n_terms; ++i)
+    if (!std::isfinite(coeff[i])) { g_last_error = "non-finite coefficient"; return PP_ERR_INVALID; }
+  pp_obs* o = new pp_obs;
+  o->ctx = ctx;
+  o->n_qubits = n_qubits;
+  o->W = W;
+  o->prec = precision;
+  o->mode = mode;
+  o->trunc = trunc;
+  const pp_status s = guarded([&] {
+    HIPCHK(hipSetDevice(ctx->device));
+    o->eng.reset(make_engine(o));
+    o->eng->create(n_terms, x, z, coeff);
+  });
+  if (s != PP_OK) {
+    delete o;
+    return s;
+  }
+  *out = o;
+  return PP_OK;
+}
+
+pp_status pp_apply_layer(pp_obs* obs, const pp_layer* L) {
+  if (!obs || !L) { g_last_error = "NULL argument"; return PP_ERR_INVALID; }
+  if (obs->broken) { g_last_error = "observable is unusable after an earlier device error"; return PP_ERR_INVALID; }
+  if (L->n_gates < 0 || L->n_gen < 0) { g_last_error = "negative count"; return PP_ERR_INVALID; }
+  if (L->n_gates > 0 && (!L->gx || !L->gz || !L->theta)) { g_last_error = "NULL gate array"; return PP_ERR_INVALID; }
+  if (L->n_gen > 0 && (!L->ex || !L->ez || !L->lambda)) { g_last_error = "NULL noise array"; return PP_ERR_INVALID; }
+  if (L->n_gates > 0 && L->dir != PP_HEISENBERG && L->dir != PP_FORWARD) { g_last_error = "dir must be +1 or -1"; return PP_ERR_INVALID; }
+  if (L->n_gen > 0 && L->noise_sign != 1 && L->noise_sign != -1) { g_last_error = "noise_sign must be +1 or -1"; return PP_ERR_INVALID; }
+  for (int g = 0; g < L->n_gates; ++g)
+    if (!std::isfinite(L->theta[g])) { g_last_error = "non-finite angle"; return PP_ERR_INVALID; }
+  for (int k = 0; k < L->n_gen; ++k)
+    if (!(L->lambda[k] >= 0.0) || !std::isfinite(L->lambda[k])) { g_last_error = "lambda must be finite and >= 0"; return PP_ERR_INVALID; }
+  if (L->n_gates > 0 && !strings_ok(obs->n_qubits, obs->W, L->n_gates, L->gx, L->gz)) { g_last_error = "gate bits above n_qubits"; return PP_ERR_INVALID; }
+  if (L->n_gen > 0 && !strings_ok(obs->n_qubits, obs->W, L->n_gen, L->ex, L->ez)) { g_last_error = "generator bits above n_qubits"; return PP_ERR_INVALID; }
+  const pp_status s = guarded([&] {
+    HIPCHK(hipSetDevice(obs->ctx->device));
+    obs->eng->apply_layer(L);
+  });
+  if (s == PP_ERR_DEVICE || s == PP_ERR_OOM) obs->broken = true;
+  return s;
+}
+
+pp_status pp_truncate(pp_obs* obs, double eps, int64_t max_terms) {
+  if (!obs) { g_last_error = "NULL argument"; return PP_ERR_INVALID; }
+  if (obs->broken) { g_last_error = "observable is unusable after an earlier device error"; return PP_ERR_INVALID; }
+  if (!(eps >= 0.0) || !std::isfinite(eps) || max_terms < 0) { g_last_error = "bad truncation arguments"; return PP_ERR_INVALID; }
+  const pp_status s = guarded([&] {
+    HIPCHK(hipSetDevice(obs->ctx->device));
+    obs->eng->truncate(eps, max_terms);
+  });
+  if (s == PP_ERR_DEVICE || s == PP_ERR_OOM) obs->broken = true;
+  return s;
+}
+
+pp_status pp_expectation(pp_obs* obs, const uint64_t* basis, double* out) {
+  if (!obs || !out) { g_last_error = "NULL argument"; return PP_ERR_INVALID; }
+  if (obs->broken) { g_last_error = "observable is unusable after an earlier device error"; return PP_ERR_INVALID; }
+  if (basis && !strings_ok(obs->n_qubits, obs->W, 1, basis, basis)) { g_last_error = "basis bits above n_qubits"; return PP_ERR_INVALID; }
+  const pp_status s = guarded([&] {
+    HIPCHK(hipSetDevice(obs->ctx->device));
+    *out = obs->eng->expectation(basis);
+  });
+  if (s == PP_ERR_DEVICE || s == PP_ERR_OOM) obs->broken = true;
+  return s;
+}
+
+pp_status pp_size(pp_obs* obs, int64_t* out) {
+  if (!obs || !out) { g_last_error = "NULL argument"; return PP_ERR_INVALID; }
+  *out = (int64_t)obs->eng->size();
+  return PP_OK;
+}
+
+pp_status pp_export(pp_obs* obs, uint64_t* x, uint64_t* z, double* c, uint8_t* ord) {
+  if (!obs) { g_last_error = "NULL argument"; return PP_ERR_INVALID; }
+  if (obs->broken) { g_last_error = "observable is unusable after an earlier device error"; return PP_ERR_INVALID; }
+  const pp_status s = guarded([&] {
+    HIPCHK(hipSetDevice(obs->ctx->device));
+    obs->eng->export_terms(x, z, c, ord);
+  });
+  if (s == PP_ERR_DEVICE || s == PP_ERR_OOM) obs->broken = true;
+  return s;
+}
+
+void pp_destroy(pp_obs* obs) {
+  if (!obs) return;
+  (void)hipSetDevice(obs->ctx->device);
+  (void)hipStreamSynchronize(obs->ctx->stream);
+  delete obs;
+}
+
+pp_status pp_timing_enable(pp_ctx* ctx, int enable) {
+  if (!ctx) { g_last_error = "NULL argument"; return PP_ERR_INVALID; }
+  return guarded([&] {
+    ctx->collect();
+    ctx->timing = enable != 0;
+  });
+}
+
+int pp_timing_read(pp_ctx* ctx, pp_kernel_stat* out, int cap, int reset) {
+  if (!ctx) return -1;
+  int n = 0;
+  const pp_status s = guarded([&] {
+    ctx->collect();
+    for (auto& kv : ctx->acc) {
+      if (out && n < cap) {
+        pp_kernel_stat& k = out[n];
+        std::memset(&k, 0, sizeof k);
+        std::snprintf(k.name, sizeof k.name, "%s", kv.first.c_str());
+        k.launches = kv.second.launches;
+        k.total_ms = kv.second.ms;
+        k.algo_bytes = kv.second.bytes;
+        k.items = kv.second.items;
+      }
+      ++n;
+    }
+    if (reset) ctx->acc.clear();
+  });
+  return s == PP_OK ? n : -1;
+}
+
+pp_status pp_last_layer_stats(pp_obs* obs, pp_layer_stats* out) {
+  if (!obs || !out) { g_last_error = "NULL argument"; return PP_ERR_INVALID; }
+  *out = obs->last;
+  return PP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// pp_common.hpp -- shared device/host definitions of the gfx950 Pauli-propagation library.
+//
+// Term storage (HBM): structure of arrays with one plane per 64-bit word, so a wavefront's
+// load of one plane is 64 consecutive 8-byte words:
+//   x[w * stride + i], z[w * stride + i]   (w = 0..W-1)   Pauli bits of term i
+//   c[i]                                    coefficient (double, or float)
+//   o[i]                                    error-order tag (error-order mode only)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define PP_MAXW 4
+
+namespace pp {
+
+constexpr int kWave = 64;
+
+template <class CT>
+struct Terms {
+  uint64_t* x;      // [W][stride]
+  uint64_t* z;      // [W][stride]
+  CT* c;            // [stride]
+  uint8_t* o;       // [stride] or nullptr
+  uint64_t stride;  // plane stride (capacity)
+};
+
+// One rotation as the kernels see it.  m[0..W-1] = x mask, m[W..2W-1] = z mask.
+struct GateDev {
+  uint64_t m[2 * PP_MAXW];
+  double cs;          // cos(theta) (exact for Clifford angles)
+  double sn_dir;      // +sin(theta) for U^dag P U, -sin(theta) for U P U^dag
+  int pivot_word;     // word (0..2W-1) of the lowest set bit of m; pair leader has it clear
+  int pivot_bit;
+  int rr_phase;       // |x_R & z_R| mod 4
+  int clifford;       // 1: exact angle, no threshold afterwards
+};
+
+// Noise of one layer, decomposed by generator support on the host:
+//  * `nsup` supports of one or two qubits, each with a table over the 4 or 16 local
+//    Pauli patterns giving, for the generators on that support that anticommute with
+//    the pattern, sum(lambda) (greedy mode) or sum(x_k) and sum(x_k^2) (error-order
+//    mode, x_k = f_k - 1);
+//  * `ndirect` generators with larger support, tested one by one.
+struct SupportDev {
+  int16_t w0, b0, w1, b1;   // word/bit of the two qubits (w1 < 0: single qubit)
+  int32_t table;            // offset into the value table
+};
+
+struct NoiseDev {
+  int nsup;
+  int ndirect;
+  int sign;                 // +1 inverse map, -1 channel
+  int mode;                 // 0 greedy, 1 error order
+  int max_order;
+  const SupportDev* sup;
+  const double* tab;        // greedy: 1 value per pattern; error order: 2 values per pattern
+  const uint64_t* dm;       // direct generators: [ndirect][2W]
+  const double* dval;       // greedy: lambda; error order: (x_k, x_k^2) pairs
+};
+
+__device__ __forceinline__ int popc64(uint64_t v) { return __popcll(v); }
+
+__device__ __host__ __forceinline__ uint64_t mix64(uint64_t v) {
+  v ^= v >> 31;
+  v *= 0x7fb5d329728ea185ULL;
+  v ^= v >> 27;
+  v *= 0x81dadef4bc2dd44dULL;
+  v ^= v >> 33;
+  return v;
+}
+
+// Group hash: the bits of (x & mx, z & mz) that a layer's gates can never change.
+template <int W>
+__device__ __forceinline__ uint64_t group_hash(const uint64_t* xs, const uint64_t* zs,
+                                               const uint64_t* mx, const uint64_t* mz) {
+  uint64_t h = 0x243f6a8885a308d3ULL;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    h = mix64(h ^ (xs[w] & mx[w]));
+    h = mix64(h + (zs[w] & mz[w]));
+  }
+  return h;
+}
+
+struct GroupMask {
+  uint64_t mx[PP_MAXW];
+  uint64_t mz[PP_MAXW];
+};
+
+}  // namespace pp

@@ -1,0 +1,324 @@
+// pp_misc.hpp -- per-gate path, segmented merge, cap selection, expectation (gfx950).
+#pragma once
+
+#include "pp_common.hpp"
+#include "pp_layer.hpp"
+#include "pp_sort.hpp"
+
+namespace pp {
+
+// ------------------------------------------------------------------------------------------
+// Per-gate path (tiles that outgrow LDS, and general gates): every term writes two slots --
+// itself (cos part, or unchanged if it commutes) and its sin child (or a zero placeholder) --
+// then a canonical sort and a segmented sum merge equal strings.
+// ------------------------------------------------------------------------------------------
+template <int W, class CT, bool ORD>
+__global__ void k_expand_gate(Terms<CT> in, uint64_t n, GateDev G, Terms<CT> out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t kx[W], kz[W], m[2 * W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) { kx[w] = in.x[w * in.stride + i]; kz[w] = in.z[w * in.stride + i]; }
+#pragma unroll
+  for (int w = 0; w < 2 * W; ++w) m[w] = G.m[w];
+  const double c = (double)in.c[i];
+  const uint8_t o = ORD ? in.o[i] : 0;
+  const uint64_t a = 2 * i, b = 2 * i + 1;
+  double ca = c, cb = 0.0;
+  uint64_t bx[W], bz[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) { bx[w] = kx[w]; bz[w] = kz[w]; }
+  if (anticommutes<W>(kx, kz, m)) {
+    ca = c * G.cs;
+    if (G.sn_dir != 0.0) {
+      const bool neg = irp_negative<W>(kx, kz, m, G.rr_phase);
+      cb = (neg ? -c : c) * G.sn_dir;
+#pragma unroll
+      for (int w = 0; w < W; ++w) { bx[w] = kx[w] ^ m[w]; bz[w] = kz[w] ^ m[W + w]; }
+    }
+  }
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    out.x[w * out.stride + a] = kx[w];
+    out.z[w * out.stride + a] = kz[w];
+    out.x[w * out.stride + b] = bx[w];
+    out.z[w * out.stride + b] = bz[w];
+  }
+  out.c[a] = (CT)ca;
+  out.c[b] = (CT)cb;
+  if (ORD) { out.o[a] = o; out.o[b] = o; }
+}
+
+// Error-order noise for the per-gate path: term (P, o) writes M+1 slots (P, o+j, c e_j) for
+// o + j <= M and zero placeholders otherwise.
+template <int W, class CT, bool ORD>
+__global__ void k_expand_noise(Terms<CT> in, uint64_t n, NoiseDev nd, Terms<CT> out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int M = nd.max_order;
+  uint64_t kx[W], kz[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) { kx[w] = in.x[w * in.stride + i]; kz[w] = in.z[w * in.stride + i]; }
+  const double c = (double)in.c[i];
+  const int o = ORD ? in.o[i] : 0;
+  double p[kMaxPowerSums], e[kMaxPowerSums + 1];
+  noise_sums<W>(kx, kz, nd, M, p);
+  elementary_from_power(p, M, e);
+  for (int j = 0; j <= M; ++j) {
+    const uint64_t s = i * (uint64_t)(M + 1) + j;
+#pragma unroll
+    for (int w = 0; w < W; ++w) { out.x[w * out.stride + s] = kx[w]; out.z[w * out.stride + s] = kz[w]; }
+    const bool ok = o + j <= M;
+    out.c[s] = (CT)(ok ? c * e[j] : 0.0);
+    if (ORD) out.o[s] = (uint8_t)(ok ? o + j : o);
+  }
+}
+
+template <int W, class CT, bool ORD>
+__device__ __forceinline__ bool same_term(const Terms<CT>& t, uint64_t a, uint64_t b) {
+  bool eq = true;
+#pragma unroll
+  for (int w = 0; w < W; ++w)
+    eq = eq && t.x[w * t.stride + a] == t.x[w * t.stride + b] && t.z[w * t.stride + a] == t.z[w * t.stride + b];
+  if (ORD) eq = eq && t.o[a] == t.o[b];
+  return eq;
+}
+
+// On a sorted array: the first entry of each run of equal (string, order) sums its run
+// (compensated in FP32), stores the sum in place and flags it if nonzero and |sum| >= thr.
+template <int W, class CT, bool ORD>
+__global__ void k_reduce_runs(Terms<CT> t, uint64_t n, double thr, uint32_t* keep, double* dropped) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (i > 0 && same_term<W, CT, ORD>(t, i, i - 1)) { keep[i] = 0; return; }
+  double s;
+  if (sizeof(CT) == 8) {
+    s = (double)t.c[i];
+    for (uint64_t j = i + 1; j < n && same_term<W, CT, ORD>(t, i, j); ++j) s += (double)t.c[j];
+  } else {
+    float sum = (float)t.c[i], comp = 0.0f;   // Kahan summation in FP32
+    for (uint64_t j = i + 1; j < n && same_term<W, CT, ORD>(t, i, j); ++j) {
+      const float y = (float)t.c[j] - comp;
+      const float tt = sum + y;
+      comp = (tt - sum) - y;
+      sum = tt;
+    }
+    s = (double)sum;
+  }
+  t.c[i] = (CT)s;
+  const bool k = s != 0.0 && !(fabs(s) < thr);
+  keep[i] = k ? 1u : 0u;
+  if (!k && s != 0.0 && dropped) atomicAdd(dropped, fabs(s));
+}
+
+// keep flags from a threshold on |c| (exact zeros always dropped)
+template <class CT>
+__global__ void k_threshold_flags(const CT* c, uint64_t n, double thr, uint32_t* keep, double* dropped) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = (double)c[i];
+  const bool k = v != 0.0 && !(fabs(v) < thr);
+  keep[i] = k ? 1u : 0u;
+  if (!k && v != 0.0 && dropped) atomicAdd(dropped, fabs(v));
+}
+
+// out[pos[i]] = in[i] for keep[i]; pos = exclusive scan of keep (kept in a separate array).
+template <int W, class CT, bool ORD>
+__global__ void k_compact(Terms<CT> in, Terms<CT> out, uint64_t n, const uint32_t* keep, const uint32_t* pos) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !keep[i]) return;
+  const uint64_t j = pos[i];
+  if (j >= out.stride) return;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    out.x[w * out.stride + j] = in.x[w * in.stride + i];
+    out.z[w * out.stride + j] = in.z[w * in.stride + i];
+  }
+  out.c[j] = in.c[i];
+  if (ORD) out.o[j] = in.o[i];
+}
+
+// Copy terms [src, src+len) of `in` to `out` at dst (ranges from a list).
+template <int W, class CT, bool ORD>
+__global__ void k_copy_ranges(Terms<CT> in, Terms<CT> out, const uint32_t* src, const uint32_t* len,
+                              const uint64_t* dst, int nranges) {
+  const int r = blockIdx.x;
+  if (r >= nranges) return;
+  for (uint32_t k = threadIdx.x; k < len[r]; k += blockDim.x) {
+    const uint64_t i = (uint64_t)src[r] + k;
+    const uint64_t j = dst[r] + k;
+    if (j >= out.stride) return;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      out.x[w * out.stride + j] = in.x[w * in.stride + i];
+      out.z[w * out.stride + j] = in.z[w * in.stride + i];
+    }
+    out.c[j] = in.c[i];
+    if (ORD) out.o[j] = in.o[i];
+  }
+}
+
+template <int W, class CT, bool ORD>
+__global__ void k_copy(Terms<CT> in, uint64_t i0, Terms<CT> out, uint64_t j0, uint64_t n) {
+  const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const uint64_t i = i0 + k, j = j0 + k;
+  if (j >= out.stride) return;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    out.x[w * out.stride + j] = in.x[w * in.stride + i];
+    out.z[w * out.stride + j] = in.z[w * in.stride + i];
+  }
+  out.c[j] = in.c[i];
+  if (ORD) out.o[j] = in.o[i];
+}
+
+// OR and AND of every key plane (to find which digit ranges of the canonical key vary).
+template <int W, class CT, bool ORD>
+__global__ void k_key_span(Terms<CT> t, uint64_t n, unsigned long long* or_and /*[2][2W+1]*/) {
+  constexpr int NP = 2 * W + 1;
+  uint64_t vo[NP], va[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) { vo[p] = 0; va[p] = ~0ULL; }
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const uint64_t a = t.x[w * t.stride + i], b = t.z[w * t.stride + i];
+      vo[w] |= a; va[w] &= a;
+      vo[W + w] |= b; va[W + w] &= b;
+    }
+    const uint64_t o = ORD ? t.o[i] : 0;
+    vo[2 * W] |= o; va[2 * W] &= o;
+  }
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    uint64_t a = vo[p], b = va[p];
+    for (int d = 32; d >= 1; d >>= 1) {
+      a |= __shfl_xor(a, d, 64);
+      b &= __shfl_xor(b, d, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      atomicOr(&or_and[p], (unsigned long long)a);
+      atomicAnd(&or_and[NP + p], (unsigned long long)b);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Cap: radix select on |c| bits, most significant digit first.
+// ------------------------------------------------------------------------------------------
+template <class CT>
+__device__ __forceinline__ uint64_t abs_key(CT v) {
+  return coef_bits<CT>(v) & (sizeof(CT) == 8 ? 0x7fffffffffffffffULL : 0x7fffffffULL);
+}
+
+template <class CT>
+__global__ void __launch_bounds__(256) k_abs_hist(const CT* c, uint64_t n, int shift, int bits,
+                                                  uint64_t pmask, uint64_t prefix, uint32_t* hist) {
+  __shared__ uint32_t h[2048];
+  const int bins = 1 << bits;
+  for (int b = threadIdx.x; b < bins; b += 256) h[b] = 0;
+  __syncthreads();
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+    const uint64_t k = abs_key<CT>(c[i]);
+    if ((k & pmask) == prefix) atomicAdd(&h[(k >> shift) & (uint64_t)(bins - 1)], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < bins; b += 256)
+    if (h[b]) atomicAdd(&hist[b], h[b]);
+}
+
+// keep: |c| > tau, or |c| == tau and marked; ties flagged for the tie-break list
+template <class CT>
+__global__ void k_cap_flags(const CT* c, uint64_t n, uint64_t tau, uint32_t* keep, uint32_t* tie, double* dropped) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t k = abs_key<CT>(c[i]);
+  keep[i] = k > tau ? 1u : 0u;
+  tie[i] = k == tau ? 1u : 0u;
+  if (k < tau && dropped) atomicAdd(dropped, fabs((double)c[i]));
+}
+
+// Gather tied terms' keys with their index stored as the coefficient (double).
+template <int W, class CT, bool ORD>
+__global__ void k_gather_ties(Terms<CT> in, uint64_t n, const uint32_t* tie, const uint32_t* pos, Terms<double> out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !tie[i]) return;
+  const uint64_t j = pos[i];
+  if (j >= out.stride) return;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    out.x[w * out.stride + j] = in.x[w * in.stride + i];
+    out.z[w * out.stride + j] = in.z[w * in.stride + i];
+  }
+  out.c[j] = (double)i;
+  out.o[j] = ORD ? in.o[i] : 0;
+}
+
+template <class CT>
+__global__ void k_mark_ties(const double* idx, uint64_t r, uint32_t* keep, uint64_t n) {
+  const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= r) return;
+  const uint64_t i = (uint64_t)idx[j];
+  if (i < n) keep[i] = 1u;
+}
+
+// ------------------------------------------------------------------------------------------
+// Expectation <b|O|b>: per-block FP64 partial sums, then one block in fixed order.
+// ------------------------------------------------------------------------------------------
+template <int W, class CT>
+__global__ void __launch_bounds__(256) k_expect(Terms<CT> t, uint64_t n, GroupMask basis, double* partial) {
+  __shared__ double s[4];
+  double acc = 0.0;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+    bool diag = true;
+    int par = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      diag = diag && t.x[w * t.stride + i] == 0;
+      par += __popcll(t.z[w * t.stride + i] & basis.mz[w]);
+    }
+    if (diag) {
+      const double v = (double)t.c[i];
+      acc += (par & 1) ? -v : v;
+    }
+  }
+  for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = (s[0] + s[1]) + (s[2] + s[3]);
+}
+
+__global__ void k_sum_partials(const double* partial, int nb, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double a = 0.0;
+    for (int i = 0; i < nb; ++i) a += partial[i];
+    *out = a;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Conversions for FP32 storage.
+// ------------------------------------------------------------------------------------------
+template <class CT>
+__global__ void k_from_f64(const double* src, CT* dst, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (CT)src[i];
+}
+template <class CT>
+__global__ void k_to_f64(const CT* src, double* dst, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (double)src[i];
+}
+
+__global__ void k_or_flags(uint32_t* a, const uint32_t* b, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] |= b[i];
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+}  // namespace pp

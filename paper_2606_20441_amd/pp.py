@@ -1,0 +1,304 @@
+"""ctypes binding of ``libpp.so`` (C ABI in ``include/pp.h``).
+
+Argument marshalling only: every step of the propagation runs in the library's HIP
+kernels.  PyTorch supplies the HIP stream and, optionally, device memory through its
+caching allocator.  Loading fails loudly if the library was not built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpp.so")
+
+PP_OK, PP_ERR_INVALID, PP_ERR_OOM, PP_ERR_DEVICE, PP_ERR_UNSUPPORTED = 0, 1, 2, 3, 4
+PP_F64, PP_F32_KAHAN = 0, 1
+PP_MODE_GREEDY, PP_MODE_ERROR_ORDER = 0, 1
+PP_HEISENBERG, PP_FORWARD = 1, -1
+
+PRECISIONS = {"f64": PP_F64, "f32k": PP_F32_KAHAN}
+MODES = {"greedy": PP_MODE_GREEDY, "error_order": PP_MODE_ERROR_ORDER}
+
+
+class PPError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"pp status {status}: {msg}")
+        self.status = status
+
+
+class pp_trunc(C.Structure):
+    _fields_ = [("eps", C.c_double), ("max_terms", C.c_int64), ("max_order", C.c_int)]
+
+
+_u64p = C.POINTER(C.c_uint64)
+_f64p = C.POINTER(C.c_double)
+_u8p = C.POINTER(C.c_uint8)
+
+
+class pp_layer(C.Structure):
+    _fields_ = [("n_gates", C.c_int), ("gx", _u64p), ("gz", _u64p), ("theta", _f64p), ("dir", C.c_int),
+                ("n_gen", C.c_int), ("ex", _u64p), ("ez", _u64p), ("lambda_", _f64p),
+                ("noise_sign", C.c_int), ("noise_after_gates", C.c_int)]
+
+
+class pp_kernel_stat(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("total_ms", C.c_double),
+                ("algo_bytes", C.c_double), ("items", C.c_double)]
+
+
+class pp_layer_stats(C.Structure):
+    _fields_ = [("n_in", C.c_int64), ("n_out", C.c_int64), ("n_peak", C.c_int64), ("n_fallback", C.c_int64),
+                ("n_capped", C.c_int64), ("dropped_l1", C.c_double)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+_lib = None
+_lib_lock = threading.Lock()
+
+EXPORTED = ["pp_ctx_create", "pp_ctx_destroy", "pp_create_observable", "pp_apply_layer", "pp_truncate",
+            "pp_expectation", "pp_size", "pp_export", "pp_destroy", "pp_last_error", "pp_timing_enable",
+            "pp_timing_read", "pp_last_layer_stats"]
+
+
+def lib():
+    """Load ``libpp.so`` (raises if it has not been built)."""
+    global _lib
+    with _lib_lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2606_20441_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        L.pp_last_error.restype = C.c_char_p
+        L.pp_ctx_create.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]
+        L.pp_ctx_create.restype = C.c_int
+        L.pp_ctx_destroy.argtypes = [C.c_void_p]
+        L.pp_create_observable.argtypes = [C.c_void_p, C.c_int, C.c_int64, _u64p, _u64p, _f64p, C.c_int, C.c_int,
+                                           pp_trunc, C.POINTER(C.c_void_p)]
+        L.pp_create_observable.restype = C.c_int
+        L.pp_apply_layer.argtypes = [C.c_void_p, C.POINTER(pp_layer)]
+        L.pp_apply_layer.restype = C.c_int
+        L.pp_truncate.argtypes = [C.c_void_p, C.c_double, C.c_int64]
+        L.pp_truncate.restype = C.c_int
+        L.pp_expectation.argtypes = [C.c_void_p, _u64p, _f64p]
+        L.pp_expectation.restype = C.c_int
+        L.pp_size.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+        L.pp_size.restype = C.c_int
+        L.pp_export.argtypes = [C.c_void_p, _u64p, _u64p, _f64p, _u8p]
+        L.pp_export.restype = C.c_int
+        L.pp_destroy.argtypes = [C.c_void_p]
+        L.pp_timing_enable.argtypes = [C.c_void_p, C.c_int]
+        L.pp_timing_enable.restype = C.c_int
+        L.pp_timing_read.argtypes = [C.c_void_p, C.POINTER(pp_kernel_stat), C.c_int, C.c_int]
+        L.pp_timing_read.restype = C.c_int
+        L.pp_last_layer_stats.argtypes = [C.c_void_p, C.POINTER(pp_layer_stats)]
+        L.pp_last_layer_stats.restype = C.c_int
+        _lib = L
+        return L
+
+
+def _check(status: int):
+    if status != PP_OK:
+        raise PPError(status, lib().pp_last_error().decode())
+
+
+def _ptr(a: Optional[np.ndarray], t):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+def _words(a, w: int) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.uint64).reshape(-1, w))
+
+
+class Context:
+    """A device, a HIP stream and (optionally) PyTorch's caching allocator."""
+
+    def __init__(self, device: int = 0, stream=None, torch_allocator: bool = True):
+        import torch
+        self.device = device
+        self._torch_stream = stream if stream is not None else torch.cuda.current_stream(device)
+        handle = C.c_void_p(self._torch_stream.cuda_stream)
+        self._alloc_cb = None
+        self._release_cb = None
+        if torch_allocator:
+            dev = torch.device("cuda", device)
+            st = self._torch_stream
+
+            def _alloc(nbytes, _user):
+                try:
+                    return int(torch.cuda.caching_allocator_alloc(int(nbytes), dev, st))
+                except Exception:
+                    return None
+
+            def _release(p, _user):
+                torch.cuda.caching_allocator_delete(int(p))
+
+            self._alloc_cb = ALLOC_FN(_alloc)
+            self._release_cb = RELEASE_FN(_release)
+        out = C.c_void_p()
+        a = C.cast(self._alloc_cb, C.c_void_p) if self._alloc_cb else None
+        r = C.cast(self._release_cb, C.c_void_p) if self._release_cb else None
+        _check(lib().pp_ctx_create(device, handle, a, r, None, C.byref(out)))
+        self._h = out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pp_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def timing(self, enable: bool = True):
+        _check(lib().pp_timing_enable(self._h, int(enable)))
+
+    def timing_read(self, reset: bool = True) -> List[dict]:
+        n = lib().pp_timing_read(self._h, None, 0, 0)
+        if n < 0:
+            raise PPError(PP_ERR_DEVICE, lib().pp_last_error().decode())
+        arr = (pp_kernel_stat * max(n, 1))()
+        lib().pp_timing_read(self._h, arr, n, int(reset))
+        return [dict(name=arr[i].name.decode(), launches=int(arr[i].launches), total_ms=float(arr[i].total_ms),
+                     algo_bytes=float(arr[i].algo_bytes), items=float(arr[i].items)) for i in range(n)]
+
+
+class Observable:
+    """A Pauli sum resident on the device (``pp_obs``)."""
+
+    def __init__(self, ctx: Context, n_qubits: int, x, z, c, precision: str = "f64", mode: str = "greedy",
+                 eps: float = 0.0, max_terms: int = 0, max_order: int = 2):
+        self.ctx = ctx
+        self.n = int(n_qubits)
+        self.W = (self.n + 63) // 64
+        self.mode = mode
+        xw = _words(x, self.W)
+        zw = _words(z, self.W)
+        cc = np.ascontiguousarray(np.asarray(c, dtype=np.float64).reshape(-1))
+        out = C.c_void_p()
+        tr = pp_trunc(float(eps), int(max_terms), int(max_order))
+        _check(lib().pp_create_observable(ctx._h, self.n, cc.shape[0], _ptr(xw, _u64p), _ptr(zw, _u64p),
+                                          _ptr(cc, _f64p), PRECISIONS[precision], MODES[mode], tr, C.byref(out)))
+        self._h = out
+
+    @classmethod
+    def from_sum(cls, ctx: Context, ps, **kw) -> "Observable":
+        return cls(ctx, ps.n_qubits, ps.x, ps.z, ps.c, **kw)
+
+    def destroy(self):
+        if getattr(self, "_h", None):
+            lib().pp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def apply_layer(self, layer, direction: int = PP_HEISENBERG, with_gates: bool = True, with_noise: bool = True,
+                    noise_sign: int = 1, noise_after_gates: bool = True):
+        W = self.W
+        ng = layer.n_gates if with_gates else 0
+        nk = layer.n_gen if with_noise else 0
+        keep = []
+        L = pp_layer()
+        L.n_gates = ng
+        L.dir = int(direction)
+        if ng:
+            gx, gz = _words(layer.gx, W), _words(layer.gz, W)
+            th = np.ascontiguousarray(layer.theta, np.float64)
+            keep += [gx, gz, th]
+            L.gx, L.gz, L.theta = _ptr(gx, _u64p), _ptr(gz, _u64p), _ptr(th, _f64p)
+        L.n_gen = nk
+        if nk:
+            ex, ez = _words(layer.ex, W), _words(layer.ez, W)
+            lam = np.ascontiguousarray(layer.lam, np.float64)
+            keep += [ex, ez, lam]
+            L.ex, L.ez, L.lambda_ = _ptr(ex, _u64p), _ptr(ez, _u64p), _ptr(lam, _f64p)
+        L.noise_sign = int(noise_sign)
+        L.noise_after_gates = int(bool(noise_after_gates))
+        _check(lib().pp_apply_layer(self._h, C.byref(L)))
+        del keep
+
+    def truncate(self, eps: float, max_terms: int = 0):
+        _check(lib().pp_truncate(self._h, float(eps), int(max_terms)))
+
+    def expectation(self, basis=None) -> float:
+        out = C.c_double()
+        b = None if basis is None else _words(basis, self.W).reshape(-1)
+        _check(lib().pp_expectation(self._h, _ptr(b, _u64p), C.byref(out)))
+        return float(out.value)
+
+    def __len__(self) -> int:
+        out = C.c_int64()
+        _check(lib().pp_size(self._h, C.byref(out)))
+        return int(out.value)
+
+    def export(self):
+        n = len(self)
+        x = np.zeros((n, self.W), np.uint64)
+        z = np.zeros((n, self.W), np.uint64)
+        c = np.zeros(n, np.float64)
+        o = np.zeros(n, np.uint8)
+        if n:
+            _check(lib().pp_export(self._h, _ptr(x, _u64p), _ptr(z, _u64p), _ptr(c, _f64p), _ptr(o, _u8p)))
+        return x, z, c, o
+
+    def as_dict(self):
+        x, z, c, o = self.export()
+        return {(tuple(int(v) for v in x[i]), tuple(int(v) for v in z[i]), int(o[i])): float(c[i])
+                for i in range(len(c))}
+
+    def last_layer_stats(self) -> dict:
+        s = pp_layer_stats()
+        _check(lib().pp_last_layer_stats(self._h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in pp_layer_stats._fields_}
+
+
+def noise_canceling(ctx: Context, circuit, observable, eps: float = 0.0, max_terms: int = 0,
+                    mode: str = "greedy", max_order: int = 2, precision: str = "f64",
+                    on_layer=None) -> Observable:
+    """O~ = D O with D = (C_ideal C_noisy^{-1})^dag (Section I.B of the paper).
+
+    For a circuit of layers m = 1..M (gates G_m, then Pauli-Lindblad channel N_m),
+    C_ideal C_noisy^{-1} = G_M..G_2 N_1^{-1} G_2^{-1} N_2^{-1} .. G_M^{-1} N_M^{-1} (the first
+    layer's gates cancel).  Its adjoint applied to O therefore walks backward through
+    G_M .. G_2 without noise (U^dag P U), applies N_1^{-1}, then for m = 2..M goes forward
+    through G_m (U P U^dag) followed by N_m^{-1}.
+    """
+    obs = Observable.from_sum(ctx, observable, precision=precision, mode=mode, eps=eps, max_terms=max_terms,
+                              max_order=max_order)
+    layers = circuit.layers
+    M = len(layers)
+    step = 0
+    for m in range(M - 1, 0, -1):
+        obs.apply_layer(layers[m], PP_HEISENBERG, with_noise=False)
+        if on_layer:
+            on_layer(step, "backward", m, obs)
+        step += 1
+    obs.apply_layer(layers[0], PP_FORWARD, with_gates=False, noise_sign=1)
+    if on_layer:
+        on_layer(step, "noise", 0, obs)
+    step += 1
+    for m in range(1, M):
+        obs.apply_layer(layers[m], PP_FORWARD, noise_sign=1, noise_after_gates=True)
+        if on_layer:
+            on_layer(step, "forward", m, obs)
+        step += 1
+    return obs
+
+
+def run_workload(ctx: Context, wl, precision: Optional[str] = None, on_layer=None) -> Observable:
+    return noise_canceling(ctx, wl.circuit, wl.observable, wl.eps, wl.max_terms, wl.mode, wl.max_order,
+                           precision or wl.precision, on_layer=on_layer)
