@@ -255,13 +255,16 @@ struct Engine final : EngineBase {
   pp_ctx* ctx;
   hipStream_t st;
   uint64_t N = 0;
-  TBuf<CT, ORD> cur, alt, sa, sb;
+  TBuf<CT, ORD> cur, alt, sa, sb, tmp;
+  double tau = 0.0;   // smallest |c| kept by the most recent cap that removed terms
   TBuf<double, true> ta, tb;     // tie lists for the cap
   Buf u32a, u32b, u32c, scan_scr, tiles, gates_d, sup_d, tab_d, dm_d, dval_d, cnt_d, ovf_d, partial_d, f64_d, span_d;
   double growth[4] = {4.0, 4.0, 2.0, 3.0};
+  double tile_target[4] = {CAP / 3.0, CAP / 3.0, CAP / 3.0, CAP / 4.0};
+  uint64_t last_ntiles = 1, last_ovf_tiles = 0;
 
   explicit Engine(pp_obs* o) : obs(o), ctx(o->ctx), st(o->ctx->stream) {
-    for (auto* t : {&cur, &alt, &sa, &sb}) { t->mem.ctx = ctx; t->W = W; }
+    for (auto* t : {&cur, &alt, &sa, &sb, &tmp}) { t->mem.ctx = ctx; t->W = W; }
     for (auto* t : {&ta, &tb}) { t->mem.ctx = ctx; t->W = W; }
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
                    &partial_d, &f64_d, &span_d})
@@ -270,7 +273,7 @@ struct Engine final : EngineBase {
     span_d.ensure(256);
   }
   ~Engine() override {
-    for (auto* t : {&cur, &alt, &sa, &sb}) t->mem.release();
+    for (auto* t : {&cur, &alt, &sa, &sb, &tmp}) t->mem.release();
     for (auto* t : {&ta, &tb}) t->mem.release();
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
                    &partial_d, &f64_d, &span_d})
@@ -280,6 +283,8 @@ struct Engine final : EngineBase {
   uint64_t size() const override { return N; }
 
   static dim3 grid1(uint64_t n, int b = 256) { return dim3((unsigned)std::max<uint64_t>(1, cdiv(n, b))); }
+  // bounded grid for grid-stride kernels that reduce per block
+  static dim3 gridb(uint64_t n) { return dim3((unsigned)std::min<uint64_t>(2048, std::max<uint64_t>(1, cdiv(n, 256)))); }
 
   void sync() { HIPCHK(hipStreamSynchronize(st)); }
 
@@ -374,7 +379,7 @@ struct Engine final : EngineBase {
     uint32_t* pos = u32c.as<uint32_t>();
     const Terms<CT> t = a.view();
     ctx->run("reduce_runs", 0, (double)n, [&] {
-      hipLaunchKernelGGL((k_reduce_runs<W, CT, ORD>), grid1(n), dim3(256), 0, st, t, n, thr, keep, dropped_dev);
+      hipLaunchKernelGGL((k_reduce_runs<W, CT, ORD>), gridb(n), dim3(256), 0, st, t, n, thr, keep, dropped_dev);
     });
     ctx->check_launch();
     HIPCHK(hipMemcpyAsync(pos, keep, n * 4, hipMemcpyDeviceToDevice, st));
@@ -531,6 +536,7 @@ struct Engine final : EngineBase {
     NoiseDev nd{};
     nd.nsup = (int)hn.sup.size();
     nd.ndirect = (int)(hn.dm.size() / (2 * W));
+    nd.ntab = (int)hn.tab.size();
     nd.sign = sign;
     nd.mode = mode == PP_MODE_GREEDY ? 0 : 1;
     nd.max_order = max_order;
@@ -554,6 +560,21 @@ struct Engine final : EngineBase {
     return nd;
   }
 
+  // Greedy-mode rescale, elementwise, support tables staged in LDS.
+  void noise_greedy(const Terms<CT>& t, uint64_t n, const NoiseDev& nd, const char* name) {
+    if (n == 0) return;
+    const size_t lds = noise_lds_bytes(nd.ntab, nd.nsup);
+    if (lds > 160 * 1024) throw_fail(PP_ERR_UNSUPPORTED, "noise tables exceed LDS");
+    if (lds > kNoiseLdsMax)
+      HIPCHK(hipFuncSetAttribute((const void*)k_noise_greedy<W, CT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds));
+    const unsigned nb = (unsigned)std::min<uint64_t>(cdiv(n, 256), 4096);
+    ctx->run(name, 2.0 * kTermBytes * n, (double)n, [&] {
+      hipLaunchKernelGGL((k_noise_greedy<W, CT>), dim3(nb), dim3(256), lds, st, t, n, nd);
+    });
+    ctx->check_launch();
+  }
+
   // ---- per-gate path on a subset (sa holds m terms) ------------------------------------------
   uint64_t per_gate(uint64_t m, const std::vector<GateDev>& gates, double eps, const NoiseDev* nd,
                     double eps_noise, double* dropped_dev) {
@@ -571,12 +592,7 @@ struct Engine final : EngineBase {
     }
     if (nd && m) {
       if (nd->mode == 0) {
-        const Terms<CT> t = sa.view();
-        const NoiseDev ndv = *nd;
-        ctx->run("noise", 0, (double)m, [&] {
-          hipLaunchKernelGGL((k_noise_greedy<W, CT>), grid1(m), dim3(256), 0, st, t, m, ndv);
-        });
-        ctx->check_launch();
+        noise_greedy(sa.view(), m, *nd, "noise");
       } else {
         const uint64_t M1 = (uint64_t)nd->max_order + 1;
         sb.ensure(m * M1);
@@ -602,64 +618,60 @@ struct Engine final : EngineBase {
   };
 
   // ---- grouped fused pass ---------------------------------------------------------------------
-  void grouped_pass(const std::vector<GateDev>& gates, const GroupMask& gm, int kind, double eps,
-                    const NoiseDev* nd, double eps_noise, pp_layer_stats& ls) {
-    if (N == 0) return;
-    const uint64_t n_in = N;
-    const double g = growth[kind];
-    uint64_t T = (uint64_t)std::max(16.0, std::min((double)CAP / 2, (double)CAP / g));
+  // One level: run the fused kernel over `m` terms of `src` with tile target T, appending the
+  // survivors to `alt` at out_count; the inputs of tiles that overflowed (LDS or output
+  // space) are gathered into `ovf`.  Returns their count.
+  uint64_t fused_level(TBuf<CT, ORD>& src, uint64_t m, uint64_t T, const GroupMask& gm, int ngates, int kind,
+                       bool any_nc, double thr, const NoiseDev* nd, double thr_noise, TBuf<CT, ORD>& dst,
+                       uint64_t& out_count, TBuf<CT, ORD>& ovf, bool& out_full, pp_layer_stats& ls) {
     uint64_t ntiles;
-    if (N <= T) {
+    if (m <= T) {
       ntiles = 1;
       tiles.ensure(64);
-      uint32_t h[2] = {0u, (uint32_t)N};
+      uint32_t h[2] = {0u, (uint32_t)m};
       std::memcpy(ctx->pinned, h, 8);
       HIPCHK(hipMemcpyAsync(tiles.p, ctx->pinned, 8, hipMemcpyHostToDevice, st));
     } else {
-      const int k = std::min(40, std::max(8, ceil_log2(N) - floor_log2(T) + 4));
+      const int k = std::min(40, std::max(8, ceil_log2(m) - floor_log2(T) + 4));
       const int passes = (k + kMaxDigitBits - 1) / kMaxDigitBits;
       const int kk = passes * ((k + passes - 1) / passes);
-      hash_sort(cur, alt, N, gm, kk);
-      ntiles = cdiv(N, T);
+      hash_sort(src, tmp, m, gm, kk);
+      ntiles = cdiv(m, T);
       tiles.ensure((ntiles + 2) * 4);
-      const Terms<CT> t = cur.view();
+      const Terms<CT> t = src.view();
       const uint64_t kmask = kk >= 64 ? ~0ULL : ((1ULL << kk) - 1);
       uint32_t* ts = tiles.as<uint32_t>();
-      const uint64_t n = N;
       ctx->run("tiles", 0, (double)ntiles, [&] {
-        hipLaunchKernelGGL((k_tiles<W, CT>), grid1(ntiles + 1), dim3(256), 0, st, t, n, gm, kmask, T,
+        hipLaunchKernelGGL((k_tiles<W, CT>), grid1(ntiles + 1), dim3(256), 0, st, t, m, gm, kmask, T,
                            (uint32_t)ntiles, ts);
       });
       ctx->check_launch();
     }
-    gates_d.ensure(std::max<size_t>(1, gates.size()) * sizeof(GateDev) + 64);
-    if (!gates.empty())
-      HIPCHK(hipMemcpyAsync(gates_d.p, gates.data(), gates.size() * sizeof(GateDev), hipMemcpyHostToDevice, st));
-    const uint64_t out_cap = (uint64_t)((double)N * std::max(2.0, g) * 1.25) + 4 * CAP;
-    alt.ensure(out_cap);
     ovf_d.ensure((ntiles + 2) * 4);
-    HIPCHK(hipMemsetAsync(cnt_d.p, 0, sizeof(Counters), st));
+    Counters hc0{};
+    hc0.out_count = out_count;
+    std::memcpy((char*)ctx->pinned + 256, &hc0, sizeof hc0);
+    HIPCHK(hipMemcpyAsync(cnt_d.p, (char*)ctx->pinned + 256, sizeof(Counters), hipMemcpyHostToDevice, st));
     Counters* cd = cnt_d.as<Counters>();
     LayerArgs<CT> a{};
-    a.in = cur.view();
-    a.out = alt.view();
-    a.out.stride = alt.cap;
+    a.in = src.view();
+    a.out = dst.view();
     a.tile_start = tiles.as<uint32_t>();
     a.tile_list = nullptr;
     a.gates = gates_d.as<GateDev>();
-    a.ngates = (int)gates.size();
-    a.eps = eps;
+    a.ngates = ngates;
+    a.eps = thr;
+    a.gate_kind = kind == KIND_OTHER ? 2 : (kind == KIND_Z ? 1 : 0);
+    a.any_nonclifford = any_nc ? 1 : 0;
     a.has_noise = nd ? 1 : 0;
     if (nd) a.noise = *nd;
-    a.eps_noise = eps_noise;
+    a.eps_noise = thr_noise;
     a.out_count = &cd->out_count;
     a.ovf_tiles = ovf_d.as<uint32_t>();
     a.ovf_count = &cd->ovf_count;
     a.dropped = &cd->dropped;
     a.peak = &cd->peak;
-    // A term's bytes in and out of the layer (reads of every input term, writes of every
-    // output term) are the algorithmic traffic; the count of outputs is known afterwards.
-    const int pi = ctx->run("layer_fused", 0, (double)n_in, [&] {
+    const int pi = ctx->run("layer_fused", 0, (double)m, [&] {
       hipLaunchKernelGGL((k_layer<W, CT, ORD>), dim3((unsigned)ntiles), dim3(BLOCK), 0, st, a);
     });
     ctx->check_launch();
@@ -667,85 +679,179 @@ struct Engine final : EngineBase {
     HIPCHK(hipMemcpyAsync(ctx->pinned, cd, sizeof(Counters), hipMemcpyDeviceToHost, st));
     sync();
     std::memcpy(&hc, ctx->pinned, sizeof hc);
-    uint64_t n_out = hc.out_count;
-    if (pi >= 0) ctx->pending[pi].bytes = kTermBytes * (double)(n_in + n_out);
-    ls.n_peak = std::max<int64_t>(ls.n_peak, (int64_t)n_out);
+    last_ntiles = ntiles;
+    last_ovf_tiles = hc.ovf_count;
+    const uint64_t written = hc.out_count - out_count;
+    out_count = hc.out_count;
+    ls.dropped_l1 += hc.dropped;
+    ls.n_peak = std::max<int64_t>(ls.n_peak, (int64_t)hc.peak);
+    uint64_t mo = 0;
+    std::vector<uint32_t> src_r, len_r;
+    std::vector<uint64_t> dst_r;
     if (hc.ovf_count > 0) {
       const uint32_t nov = hc.ovf_count;
       std::vector<uint32_t> ov(nov), ts(ntiles + 1);
       HIPCHK(hipMemcpyAsync(ov.data(), ovf_d.p, 4 * (size_t)nov, hipMemcpyDeviceToHost, st));
       HIPCHK(hipMemcpyAsync(ts.data(), tiles.p, 4 * (ntiles + 1), hipMemcpyDeviceToHost, st));
       sync();
-      std::vector<uint32_t> src, len;
-      std::vector<uint64_t> dst;
-      uint64_t m = 0;
-      bool out_ovf = false;
       for (uint32_t v : ov) {
-        out_ovf |= (v & kOvfOutput) != 0;
+        out_full |= (v & kOvfOutput) != 0;
         const uint32_t t = v & ~kOvfOutput;
-        const uint32_t s0 = ts[t], s1 = ts[t + 1];
-        src.push_back(s0);
-        len.push_back(s1 - s0);
-        dst.push_back(m);
-        m += s1 - s0;
+        src_r.push_back(ts[t]);
+        len_r.push_back(ts[t + 1] - ts[t]);
+        dst_r.push_back(mo);
+        mo += ts[t + 1] - ts[t];
       }
-      ls.n_fallback += (int64_t)m;
-      sa.ensure(std::max<uint64_t>(m, 1));
+      ovf.ensure(std::max<uint64_t>(mo, 1));
       u32b.ensure(8 * (size_t)nov + 64);
       u32c.ensure(8 * (size_t)nov + 64);
       partial_d.ensure(8 * (size_t)nov + 64);
-      HIPCHK(hipMemcpyAsync(u32b.p, src.data(), 4 * (size_t)nov, hipMemcpyHostToDevice, st));
-      HIPCHK(hipMemcpyAsync(u32c.p, len.data(), 4 * (size_t)nov, hipMemcpyHostToDevice, st));
-      HIPCHK(hipMemcpyAsync(partial_d.p, dst.data(), 8 * (size_t)nov, hipMemcpyHostToDevice, st));
-      const Terms<CT> in = cur.view(), sub = sa.view();
+      HIPCHK(hipMemcpyAsync(u32b.p, src_r.data(), 4 * (size_t)nov, hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(u32c.p, len_r.data(), 4 * (size_t)nov, hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(partial_d.p, dst_r.data(), 8 * (size_t)nov, hipMemcpyHostToDevice, st));
+      const Terms<CT> in = src.view(), sub = ovf.view();
       const uint32_t *srcd = u32b.as<uint32_t>(), *lend = u32c.as<uint32_t>();
       const uint64_t* dstd = partial_d.as<uint64_t>();
-      ctx->run("copy_ranges", 0, (double)m, [&] {
+      ctx->run("copy_ranges", 0, (double)mo, [&] {
         hipLaunchKernelGGL((k_copy_ranges<W, CT, ORD>), dim3(nov), dim3(256), 0, st, in, sub, srcd, lend, dstd,
                            (int)nov);
       });
       ctx->check_launch();
       sync();   // the range lists are host vectors
-      const uint64_t mm = per_gate(m, gates, eps, nd, eps_noise, &cd->dropped);
-      // append the per-gate results behind the fused output (grow keeping the prefix)
-      if (n_out + mm > alt.cap) {
-        sb.ensure(std::max<uint64_t>(n_out, 1));
-        const Terms<CT> from = alt.view(), to = sb.view();
-        if (n_out) {
-          ctx->run("copy", 0, (double)n_out, [&] {
-            hipLaunchKernelGGL((k_copy<W, CT, ORD>), grid1(n_out), dim3(256), 0, st, from, 0, to, 0, n_out);
-          });
-          ctx->check_launch();
-        }
-        alt.ensure(n_out + mm + 1);
-        const Terms<CT> back = alt.view(), hold = sb.view();
-        if (n_out) {
-          ctx->run("copy", 0, (double)n_out, [&] {
-            hipLaunchKernelGGL((k_copy<W, CT, ORD>), grid1(n_out), dim3(256), 0, st, hold, 0, back, 0, n_out);
-          });
-          ctx->check_launch();
-        }
-      }
-      if (mm) {
-        const Terms<CT> from = sa.view(), to = alt.view();
-        ctx->run("copy", 0, (double)mm, [&] {
-          hipLaunchKernelGGL((k_copy<W, CT, ORD>), grid1(mm), dim3(256), 0, st, from, 0, to, n_out, mm);
-        });
-        ctx->check_launch();
-      }
-      n_out += mm;
-      const double frac = (double)nov / (double)ntiles;
-      if (out_ovf || frac > 0.01) growth[kind] = std::min(256.0, growth[kind] * 2.0);
     }
+    // A term's bytes in and out of the layer are the algorithmic traffic of the launch.
+    if (pi >= 0) ctx->pending[pi].bytes = kTermBytes * (double)((m - mo) + written);
+    return mo;
+  }
+
+  // Grow `b` to hold `need` terms, keeping its first `keep` terms (staged through tmp).
+  void grow_keep(TBuf<CT, ORD>& b, uint64_t need, uint64_t keep) {
+    if (need <= b.cap) return;
+    tmp.ensure(std::max<uint64_t>(keep, 1));
+    if (keep) {
+      const Terms<CT> from = b.view(), to = tmp.view();
+      ctx->run("copy", 0, (double)keep, [&] {
+        hipLaunchKernelGGL((k_copy<W, CT, ORD>), grid1(keep), dim3(256), 0, st, from, 0, to, 0, keep);
+      });
+      ctx->check_launch();
+    }
+    b.ensure(need);
+    if (keep) {
+      const Terms<CT> from = tmp.view(), to = b.view();
+      ctx->run("copy", 0, (double)keep, [&] {
+        hipLaunchKernelGGL((k_copy<W, CT, ORD>), grid1(keep), dim3(256), 0, st, from, 0, to, 0, keep);
+      });
+      ctx->check_launch();
+    }
+  }
+
+  void append(TBuf<CT, ORD>& dst, uint64_t& count, TBuf<CT, ORD>& src, uint64_t m) {
+    if (!m) return;
+    grow_keep(dst, count + m + 1, count);
+    const Terms<CT> from = src.view(), to = dst.view();
+    const uint64_t oc = count;
+    ctx->run("copy", 0, (double)m, [&] {
+      hipLaunchKernelGGL((k_copy<W, CT, ORD>), grid1(m), dim3(256), 0, st, from, 0, to, oc, m);
+    });
+    ctx->check_launch();
+    count += m;
+  }
+
+  // Group mask of the bits a run of gates cannot change: X-type gates keep z and every x bit
+  // outside the union of their x masks; Z-type likewise with x and z exchanged; a general
+  // gate keeps all but its pivot bit.
+  GroupMask invariant_mask(const std::vector<GateDev>& gates, int kind) const {
+    GroupMask gm;
+    for (int w = 0; w < PP_MAXW; ++w) { gm.mx[w] = ~0ULL; gm.mz[w] = ~0ULL; }
+    if (kind == KIND_X) {
+      for (const GateDev& g : gates)
+        for (int w = 0; w < W; ++w) gm.mx[w] &= ~g.m[w];
+    } else if (kind == KIND_Z) {
+      for (const GateDev& g : gates)
+        for (int w = 0; w < W; ++w) gm.mz[w] &= ~g.m[W + w];
+    } else if (kind == KIND_OTHER) {
+      for (const GateDev& g : gates) {
+        if (g.pivot_word < W) gm.mx[g.pivot_word] &= ~(1ULL << g.pivot_bit);
+        else gm.mz[g.pivot_word - W] &= ~(1ULL << g.pivot_bit);
+      }
+    }
+    return gm;
+  }
+
+  // Propagate the m terms of `src` through `gates` (one kind; noise `nd` after them) and
+  // append the results to dst.  Tiles that outgrow LDS are retried with smaller tiles; the
+  // terms that still do not fit go through the gates in two halves, each grouped by its own
+  // (finer) invariant mask, recursively.  `src` is consumed.
+  void run_groups(TBuf<CT, ORD>& src, uint64_t m, const std::vector<GateDev>& gates, int kind, double thr,
+                  const NoiseDev* nd, double thr_noise, TBuf<CT, ORD>& dst, uint64_t& dst_count, int depth,
+                  pp_layer_stats& ls) {
+    if (m == 0) return;
+    bool any_nc = false;
+    for (const GateDev& g : gates) any_nc |= g.clifford == 0;
+    gates_d.ensure(std::max<size_t>(1, gates.size()) * sizeof(GateDev) + 64);
+    if (!gates.empty()) {
+      HIPCHK(hipMemcpyAsync(gates_d.p, gates.data(), gates.size() * sizeof(GateDev), hipMemcpyHostToDevice, st));
+      sync();
+    }
+    const GroupMask gm = invariant_mask(gates, kind);
+    uint64_t T = (uint64_t)std::max(4.0, std::min((double)CAP / 2, depth == 0 ? tile_target[kind] : CAP / 3.0));
+    TBuf<CT, ORD> ov_a, ov_b;
+    for (auto* t : {&ov_a, &ov_b}) { t->mem.ctx = ctx; t->W = W; }
+    TBuf<CT, ORD>* in = &src;
+    uint64_t mi = m;
+    for (int level = 0; level < 2 && mi > 0; ++level) {
+      TBuf<CT, ORD>& ovf = level == 0 ? ov_a : ov_b;
+      bool out_full = false;
+      const uint64_t mo = fused_level(*in, mi, T, gm, (int)gates.size(), kind, any_nc, thr, nd, thr_noise, dst,
+                                      dst_count, ovf, out_full, ls);
+      if (level > 0 || depth > 0) ls.n_fallback += (int64_t)mi;
+      if (mo && out_full) grow_keep(dst, std::max<uint64_t>(2 * dst.cap, dst_count + mo * 16), dst_count);
+      if (level == 0 && depth == 0) {
+        const double frac = (double)last_ovf_tiles / (double)std::max<uint64_t>(1, last_ntiles);
+        if (frac > 0.05) tile_target[kind] = std::max(8.0, tile_target[kind] * 0.5);
+        else if (frac < 0.01) tile_target[kind] = std::min((double)CAP / 2, tile_target[kind] * 1.25);
+      }
+      in = &ovf;
+      mi = mo;
+      T = std::max<uint64_t>(4, T / 16);
+    }
+    if (mi > 0) {
+      if (gates.size() >= 2 && depth < 8) {
+        // groups too large for LDS under all these gates: split the gate list in two
+        const size_t h = gates.size() / 2;
+        std::vector<GateDev> g1(gates.begin(), gates.begin() + h), g2(gates.begin() + h, gates.end());
+        TBuf<CT, ORD> mid;
+        mid.mem.ctx = ctx;
+        mid.W = W;
+        uint64_t mm = 0;
+        mid.ensure(mi * 2 + 1);
+        run_groups(*in, mi, g1, kind, thr, nullptr, thr_noise, mid, mm, depth + 1, ls);
+        run_groups(mid, mm, g2, kind, thr, nd, thr_noise, dst, dst_count, depth + 1, ls);
+        mid.mem.release();
+      } else {
+        // last resort (a single gate's pairs cannot outgrow LDS; kept for safety)
+        ls.n_fallback += (int64_t)mi;
+        if (in != &sa) sa.swap(*in);
+        const uint64_t mm = per_gate(mi, gates, thr, nd, thr_noise, &cnt_d.as<Counters>()->dropped);
+        append(dst, dst_count, sa, mm);
+      }
+    }
+    ov_a.mem.release();
+    ov_b.mem.release();
+  }
+
+  void grouped_pass(const std::vector<GateDev>& gates, const GroupMask& /*unused*/, int kind, double thr,
+                    const NoiseDev* nd, double thr_noise, pp_layer_stats& ls) {
+    if (N == 0) return;
+    const uint64_t n_in = N;
+    const double g = growth[kind];
+    alt.ensure((uint64_t)((double)N * std::max(2.0, g) * 2.0) + 4 * CAP);
+    uint64_t out_count = 0;
+    run_groups(cur, N, gates, kind, thr, nd, thr_noise, alt, out_count, 0, ls);
     cur.swap(alt);
-    N = n_out;
-    const double obs_g = (double)n_out / (double)std::max<uint64_t>(1, n_in);
+    N = out_count;
+    const double obs_g = (double)N / (double)std::max<uint64_t>(1, n_in);
     growth[kind] = std::min(256.0, std::max({2.0, 1.5 * obs_g, growth[kind] * 0.75}));
-    HIPCHK(hipMemcpyAsync(ctx->pinned, cd, sizeof(Counters), hipMemcpyDeviceToHost, st));
-    sync();
-    std::memcpy(&hc, ctx->pinned, sizeof hc);
-    ls.dropped_l1 += hc.dropped;
-    ls.n_peak = std::max<int64_t>(ls.n_peak, (int64_t)hc.peak);
   }
 
   // ---- create ----------------------------------------------------------------------------------
@@ -788,23 +894,19 @@ struct Engine final : EngineBase {
     NoiseDev nd = upload_noise(hn, L->noise_sign, mode, M);
     if (N == 0) return;
     if (mode == PP_MODE_GREEDY) {
-      const Terms<CT> t = cur.view();
-      const uint64_t n = N;
-      ctx->run("noise", 2.0 * kTermBytes * n, (double)n, [&] {
-        hipLaunchKernelGGL((k_noise_greedy<W, CT>), grid1(n), dim3(256), 0, st, t, n, nd);
-      });
-      ctx->check_launch();
+      noise_greedy(cur.view(), N, nd, "noise");
     } else {
       GroupMask gm;
       for (int w = 0; w < PP_MAXW; ++w) { gm.mx[w] = ~0ULL; gm.mz[w] = ~0ULL; }
-      grouped_pass({}, gm, KIND_NOISE, 0.0, &nd, obs->trunc.eps, ls);
+      grouped_pass({}, gm, KIND_NOISE, 0.0, &nd, std::max(obs->trunc.eps, tau), ls);
     }
   }
 
   void apply_layer(const pp_layer* L) override {
     pp_layer_stats ls{};
     ls.n_in = (int64_t)N;
-    const double eps = obs->trunc.eps;
+    // threshold after every non-Clifford gate: max(eps, tau) (tau: the most recent cap's cut)
+    const double eps = std::max(obs->trunc.eps, tau);
     const bool has_noise = L->n_gen > 0;
     bool noise_done = false;
     if (has_noise && !L->noise_after_gates) {
@@ -833,8 +935,14 @@ struct Engine final : EngineBase {
         const uint64_t n = N;
         const GateDev* gd = gates_d.as<GateDev>();
         const int ng = (int)gv.size();
+        const size_t lds = ng * sizeof(GateDev) + (with_noise ? noise_lds_bytes(nd.ntab, nd.nsup) : 0);
+        if (lds > 160 * 1024) throw_fail(PP_ERR_UNSUPPORTED, "gate and noise tables exceed LDS");
+        if (lds > kNoiseLdsMax)
+          HIPCHK(hipFuncSetAttribute((const void*)k_clifford<W, CT, ORD>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        const unsigned nb = (unsigned)std::min<uint64_t>(cdiv(n, 256), 4096);
         ctx->run("clifford_layer", 2.0 * kTermBytes * n, (double)n, [&] {
-          hipLaunchKernelGGL((k_clifford<W, CT, ORD>), grid1(n), dim3(256), 0, st, t, n, gd, ng, with_noise, nd);
+          hipLaunchKernelGGL((k_clifford<W, CT, ORD>), dim3(nb), dim3(256), lds, st, t, n, gd, ng, with_noise, nd);
         });
         ctx->check_launch();
         sync();   // gv is a host vector
@@ -863,7 +971,7 @@ struct Engine final : EngineBase {
           const bool last = j == hg.size();
           NoiseDev nd{};
           const NoiseDev* ndp = nullptr;
-          if (last && fuse_noise) {
+          if (last && fuse_noise && obs->mode == PP_MODE_ERROR_ORDER) {
             HostNoise hn = prepare_noise(L, obs->mode, obs->trunc.max_order);
             nd = upload_noise(hn, L->noise_sign, obs->mode, obs->trunc.max_order);
             ndp = &nd;
@@ -884,7 +992,19 @@ struct Engine final : EngineBase {
   }
 
   // ---- cap -------------------------------------------------------------------------------------
-  void cap_select(uint64_t K, pp_layer_stats& ls) {
+  static double coef_from_bits_host(uint64_t b) {
+    if (sizeof(CT) == 8) {
+      double v;
+      std::memcpy(&v, &b, 8);
+      return v;
+    }
+    const uint32_t u = (uint32_t)b;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return (double)f;
+  }
+
+  void cap_select(uint64_t K, pp_layer_stats& ls, bool layer_cap = true) {
     if (N <= K) return;
     const int KB = sizeof(CT) == 8 ? 63 : 31;
     uint64_t prefix = 0, pmask = 0, need = K, count_eq = 0;
@@ -920,7 +1040,8 @@ struct Engine final : EngineBase {
       count_eq = h[d];
       hi = shift;
     }
-    const uint64_t tau = prefix;
+    const uint64_t tau_key = prefix;
+    if (layer_cap) tau = coef_from_bits_host(tau_key);
     u32b.ensure(n * 4 + 64);
     u32c.ensure(n * 4 + 64);
     uint32_t* keep = u32b.as<uint32_t>();
@@ -928,7 +1049,7 @@ struct Engine final : EngineBase {
     double* dd = &cnt_d.as<Counters>()->dropped;
     HIPCHK(hipMemsetAsync(dd, 0, 8, st));
     ctx->run("cap_flags", 0, (double)n, [&] {
-      hipLaunchKernelGGL((k_cap_flags<CT>), grid1(n), dim3(256), 0, st, c, n, tau, keep, tie, dd);
+      hipLaunchKernelGGL((k_cap_flags<CT>), gridb(n), dim3(256), 0, st, c, n, tau_key, keep, tie, dd);
     });
     ctx->check_launch();
     if (need >= count_eq) {
@@ -978,12 +1099,12 @@ struct Engine final : EngineBase {
       const CT* c = cur.view().c;
       const uint64_t n = N;
       ctx->run("threshold", 0, (double)n, [&] {
-        hipLaunchKernelGGL((k_threshold_flags<CT>), grid1(n), dim3(256), 0, st, c, n, eps, keep, (double*)nullptr);
+        hipLaunchKernelGGL((k_threshold_flags<CT>), gridb(n), dim3(256), 0, st, c, n, eps, keep, (double*)nullptr);
       });
       ctx->check_launch();
       compact_cur(keep);
     }
-    if (cap > 0 && (int64_t)N > cap) cap_select((uint64_t)cap, ls);
+    if (cap > 0 && (int64_t)N > cap) cap_select((uint64_t)cap, ls, false);
   }
 
   double expectation(const uint64_t* basis) override {

@@ -50,6 +50,7 @@ struct SupportDev {
 struct NoiseDev {
   int nsup;
   int ndirect;
+  int ntab;                 // doubles in `tab`
   int sign;                 // +1 inverse map, -1 channel
   int mode;                 // 0 greedy, 1 error order
   int max_order;

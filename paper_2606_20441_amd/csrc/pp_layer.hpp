@@ -41,6 +41,8 @@ struct LayerArgs {
   const GateDev* gates;         // in application order
   int ngates;
   double eps;                   // threshold after each non-Clifford gate (0: none)
+  int gate_kind;                // 0 X-type run, 1 Z-type run, 2 general gate
+  int any_nonclifford;          // the gate list holds a non-Clifford gate
   int has_noise;
   NoiseDev noise;
   double eps_noise;             // threshold after the noise expansion (error-order mode)
@@ -131,15 +133,16 @@ __global__ void __launch_bounds__(LayerCfg<W>::BLOCK) k_layer(LayerArgs<CT> a) {
   constexpr int H = 2 * CAP;
   constexpr int R = CAP / BLOCK;
   constexpr uint32_t EMPTY = 0xffffffffu;
-  constexpr uint16_t P_NONE = 0xffff, P_KEEP = 0xfffe, P_SCALE = 0xfffd;
 
   __shared__ uint64_t sx[W][CAP];
   __shared__ uint64_t sz[W][CAP];
   __shared__ CT sc[CAP];
   __shared__ uint8_t so[ORD ? CAP : 1];
   __shared__ uint32_t hidx[H];
-  __shared__ uint16_t part[CAP];
-  __shared__ uint32_t s_new, s_ovf;
+  __shared__ uint32_t s_cnt[3];      // appends of gate g land in s_cnt[g % 3]
+  __shared__ uint32_t s_dead[3];     // entries zeroed by gate g
+  __shared__ uint32_t s_ovf;
+  __shared__ unsigned long long s_or[2 * W];
   __shared__ uint32_t stmp[BLOCK / 64];
   __shared__ unsigned long long s_base;
   __shared__ double s_drop[BLOCK / 64];
@@ -184,43 +187,72 @@ __global__ void __launch_bounds__(LayerCfg<W>::BLOCK) k_layer(LayerArgs<CT> a) {
     }
     return EMPTY;
   };
-  auto insert = [&](uint32_t i) {
-    uint64_t kx[W], kz[W];
-#pragma unroll
-    for (int w = 0; w < W; ++w) { kx[w] = sx[w][i]; kz[w] = sz[w][i]; }
-    uint32_t h = slot_of(kx, kz, ORD ? so[i] : 0u);
+  auto insert_key = [&](uint32_t i, const uint64_t* kx, const uint64_t* kz, uint32_t o) {
+    uint32_t h = slot_of(kx, kz, o);
     for (int probe = 0; probe < H; ++probe) {
       if (atomicCAS(&hidx[h], EMPTY, i) == EMPTY) return;
       h = (h + 1) & (H - 1);
     }
+  };
+  auto insert = [&](uint32_t i) {
+    uint64_t kx[W], kz[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) { kx[w] = sx[w][i]; kz[w] = sz[w][i]; }
+    insert_key(i, kx, kz, ORD ? so[i] : 0u);
   };
   auto load_key = [&](uint32_t i, uint64_t* kx, uint64_t* kz) {
 #pragma unroll
     for (int w = 0; w < W; ++w) { kx[w] = sx[w][i]; kz[w] = sz[w][i]; }
   };
 
-  // ---- load the tile ----------------------------------------------------------------------
+  // ---- load the tile -----------------------------------------------------------------------
+  uint64_t lor[2 * W];
+#pragma unroll
+  for (int w = 0; w < 2 * W; ++w) lor[w] = 0;
   for (uint32_t i = tid; i < n0; i += BLOCK) {
 #pragma unroll
     for (int w = 0; w < W; ++w) {
-      sx[w][i] = a.in.x[w * a.in.stride + t0 + i];
-      sz[w][i] = a.in.z[w * a.in.stride + t0 + i];
+      const uint64_t xv = a.in.x[w * a.in.stride + t0 + i];
+      const uint64_t zv = a.in.z[w * a.in.stride + t0 + i];
+      sx[w][i] = xv;
+      sz[w][i] = zv;
+      lor[w] |= xv;
+      lor[W + w] |= zv;
     }
     sc[i] = a.in.c[t0 + i];
     if (ORD) so[i] = a.in.o[t0 + i];
   }
   for (uint32_t j = tid; j < (uint32_t)H; j += BLOCK) hidx[j] = EMPTY;
-  if (tid == 0) { s_new = 0; s_ovf = 0; }
+  if (tid < 2 * W) s_or[tid] = 0;
+  if (tid < 3) { s_cnt[tid] = 0; s_dead[tid] = 0; }
+  if (tid == 0) s_ovf = 0;
   __syncthreads();
+#pragma unroll
+  for (int w = 0; w < 2 * W; ++w) {
+    uint64_t v = lor[w];
+    for (int d = 32; d >= 1; d >>= 1) v |= __shfl_xor(v, d, 64);
+    if ((tid & 63) == 0 && v) atomicOr(&s_or[w], (unsigned long long)v);
+  }
   for (uint32_t i = tid; i < n0; i += BLOCK) insert(i);
   __syncthreads();
+  // x bits and z bits present anywhere in the tile: a gate R can only act on the tile if
+  // (x_any & z_R) | (z_any & x_R) is nonzero.  Gates keep the group's invariant bits, so
+  // for X-type (Z-type) runs the z (x) part of this mask stays exact; otherwise it is
+  // refreshed below after every gate that moved bits.
+  uint64_t orx[W], orz[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) { orx[w] = s_or[w]; orz[w] = s_or[W + w]; }
 
   uint32_t n = n0;
   uint32_t peak = n0;
+  uint32_t dead = 0;
   double dropped = 0.0;
+  bool thresholded_all = false;
+  int gi = 0;   // processed-gate counter (rotates the shared counters)
 
-  // Compaction of entries [0, nn) keeping those with keep(c) true; rebuilds the hash index.
-  auto compact = [&](uint32_t nn, double thr) -> uint32_t {
+  // Compaction of entries [0, nn) keeping c != 0 and !(|c| < thr); optionally rebuilds the
+  // hash index.  Uniform call.
+  auto compact = [&](uint32_t nn, double thr, bool rebuild) -> uint32_t {
     uint64_t rx[R][W], rz[R][W];
     CT rc[R];
     uint8_t ro[R];
@@ -253,9 +285,11 @@ __global__ void __launch_bounds__(LayerCfg<W>::BLOCK) k_layer(LayerArgs<CT> a) {
         ++pos;
       }
     }
-    for (uint32_t j = tid; j < (uint32_t)H; j += BLOCK) hidx[j] = EMPTY;
-    __syncthreads();
-    for (uint32_t i = tid; i < total; i += BLOCK) insert(i);
+    if (rebuild) {
+      for (uint32_t j = tid; j < (uint32_t)H; j += BLOCK) hidx[j] = EMPTY;
+      __syncthreads();
+      for (uint32_t i = tid; i < total; i += BLOCK) insert(i);
+    }
     __syncthreads();
     return total;
   };
@@ -267,75 +301,111 @@ __global__ void __launch_bounds__(LayerCfg<W>::BLOCK) k_layer(LayerArgs<CT> a) {
     }
   };
 
-  // ---- gates -------------------------------------------------------------------------------
+  // The threshold after the first non-Clifford gate also reaches terms that gate left alone
+  // (later ones cannot fall below it: magnitudes change only where a gate acts).
+  auto threshold_all = [&]() {
+    thresholded_all = true;
+    if (!(a.eps > 0.0)) return;
+    int nd = 0;
+    for (int r = 0; r < R; ++r) {
+      const uint32_t i = (uint32_t)r * BLOCK + tid;
+      if (i >= n) break;
+      const double v = (double)sc[i];
+      if (v != 0.0 && fabs(v) < a.eps) {
+        dropped += fabs(v);
+        sc[i] = (CT)0.0;
+        ++nd;
+      }
+    }
+    if (__syncthreads_or(nd)) dead += 1;   // barrier; zeros now exist, so compaction may run
+  };
+
+  // ---- gates: one pass and one barrier per gate ------------------------------------------------
   for (int g = 0; g < a.ngates; ++g) {
     uint64_t m[2 * W];
 #pragma unroll
     for (int w = 0; w < 2 * W; ++w) m[w] = a.gates[g].m[w];
+    const bool clifford = a.gates[g].clifford != 0;
+    uint64_t touch = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) touch |= (orx[w] & m[W + w]) | (orz[w] & m[w]);
+    if (!touch) {   // no entry of this tile anticommutes with the gate
+      if (!clifford && !thresholded_all) threshold_all();
+      continue;
+    }
     const double cs = a.gates[g].cs;
     const double snd = a.gates[g].sn_dir;
     const int pw = a.gates[g].pivot_word;
     const int pb = a.gates[g].pivot_bit;
     const int rrp = a.gates[g].rr_phase;
-    const bool clifford = a.gates[g].clifford != 0;
-
-    // Phase 1: classify and look up partners (the hash index is read-only here).
+    const double thr = clifford ? 0.0 : a.eps;
+    const int slot = gi % 3;
+    // keep room: at most n appends can happen in this gate
+    if (n + n > (uint32_t)CAP && dead > 0) {
+      n = compact(n, 0.0, true);
+      dead = 0;
+    }
+    if (tid == 0) { s_cnt[(gi + 1) % 3] = 0; s_dead[(gi + 1) % 3] = 0; }
+    ++gi;
     for (int r = 0; r < R; ++r) {
       const uint32_t i = (uint32_t)r * BLOCK + tid;
       if (i >= n) break;
       uint64_t kx[W], kz[W];
       load_key(i, kx, kz);
-      uint16_t pv;
-      if (!anticommutes<W>(kx, kz, m)) {
-        pv = P_KEEP;
-      } else if (snd == 0.0) {
-        pv = P_SCALE;
-      } else {
-#pragma unroll
-        for (int w = 0; w < W; ++w) { kx[w] ^= m[w]; kz[w] ^= m[W + w]; }
-        const uint32_t p = lookup(kx, kz, ORD ? so[i] : 0u);
-        pv = p == EMPTY ? P_NONE : (uint16_t)p;
-      }
-      part[i] = pv;
-    }
-    __syncthreads();
-    // Phase 2: new coefficients; a pair is updated by its member with the pivot bit clear,
-    // a term without partner writes its cos part and appends its sin child.
-    for (int r = 0; r < R; ++r) {
-      const uint32_t i = (uint32_t)r * BLOCK + tid;
-      if (i >= n) break;
-      const uint16_t pv = part[i];
-      if (pv == P_KEEP) continue;
+      if (!anticommutes<W>(kx, kz, m)) continue;
       const double c = (double)sc[i];
-      if (pv == P_SCALE) {
+      if (snd == 0.0) {   // sin = 0: the Pauli is only scaled (Clifford, |cos| = 1)
         sc[i] = (CT)(c * cs);
         continue;
       }
-      uint64_t kx[W], kz[W];
-      load_key(i, kx, kz);
-      const bool neg_i = irp_negative<W>(kx, kz, m, rrp);
-      if (pv == P_NONE) {
-        const double child = (neg_i ? -c : c) * snd;
-        sc[i] = (CT)(c * cs);
-        const uint32_t j = n + atomicAdd(&s_new, 1u);
-        if (j < (uint32_t)CAP) {
+      uint64_t qx[W], qz[W];
 #pragma unroll
-          for (int w = 0; w < W; ++w) { sx[w][j] = kx[w] ^ m[w]; sz[w][j] = kz[w] ^ m[W + w]; }
-          if (ORD) so[j] = so[i];
-          sc[j] = (CT)child;
+      for (int w = 0; w < W; ++w) { qx[w] = kx[w] ^ m[w]; qz[w] = kz[w] ^ m[W + w]; }
+      const uint32_t oi = ORD ? so[i] : 0u;
+      const uint32_t p = lookup(qx, qz, oi);
+      const bool neg_i = irp_negative<W>(kx, kz, m, rrp);
+      if (p == EMPTY) {
+        if (c == 0.0) continue;
+        double ni = c * cs;
+        const double child = (neg_i ? -c : c) * snd;
+        if (ni == 0.0 || fabs(ni) < thr) {
+          dropped += fabs(ni);
+          ni = 0.0;
+          atomicAdd(&s_dead[slot], 1u);
+        }
+        sc[i] = (CT)ni;
+        if (!(fabs(child) < thr) && child != 0.0) {
+          const uint32_t j = n + atomicAdd(&s_cnt[slot], 1u);
+          if (j < (uint32_t)CAP) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) { sx[w][j] = qx[w]; sz[w][j] = qz[w]; }
+            if (ORD) so[j] = (uint8_t)oi;
+            sc[j] = (CT)child;
+            __threadfence_block();
+            insert_key(j, qx, qz, oi);
+          } else {
+            s_ovf = 1;
+          }
         } else {
-          s_ovf = 1;
+          dropped += fabs(child);
         }
       } else {
-        const uint64_t piv = W == 1 && pw == 0 ? kx[0] : (pw < W ? pick<W>(kx, pw) : pick<W>(kz, pw - W));
+        const uint64_t piv = pw < W ? pick<W>(kx, pw) : pick<W>(kz, pw - W);
         if ((piv >> pb) & 1u) continue;   // the partner leads this pair
-        const uint32_t p = pv;
-        uint64_t qx[W], qz[W];
-        load_key(p, qx, qz);
         const bool neg_p = irp_negative<W>(qx, qz, m, rrp);
         const double cp = (double)sc[p];
-        const double ni = c * cs + (neg_p ? -cp : cp) * snd;
-        const double np = cp * cs + (neg_i ? -c : c) * snd;
+        double ni = c * cs + (neg_p ? -cp : cp) * snd;
+        double np = cp * cs + (neg_i ? -c : c) * snd;
+        if (fabs(ni) < thr || ni == 0.0) {
+          dropped += fabs(ni);
+          if (c != 0.0) atomicAdd(&s_dead[slot], 1u);
+          ni = 0.0;
+        }
+        if (fabs(np) < thr || np == 0.0) {
+          dropped += fabs(np);
+          if (cp != 0.0) atomicAdd(&s_dead[slot], 1u);
+          np = 0.0;
+        }
         sc[i] = (CT)ni;
         sc[p] = (CT)np;
       }
@@ -345,28 +415,18 @@ __global__ void __launch_bounds__(LayerCfg<W>::BLOCK) k_layer(LayerArgs<CT> a) {
       overflow_exit();
       return;
     }
-    const uint32_t added = s_new;
-    const uint32_t nn = n + added;
-    // Phase 3: drop exact zeros always, |c| < eps after non-Clifford gates.
-    const double thr = clifford ? 0.0 : a.eps;
-    bool any_drop = false;
-    for (int r = 0; r < R; ++r) {
-      const uint32_t i = (uint32_t)r * BLOCK + tid;
-      if (i >= nn) break;
-      const double v = (double)sc[i];
-      if (v == 0.0 || fabs(v) < thr) any_drop = true;
-    }
-    const int drop = __syncthreads_or(any_drop ? 1 : 0);
-    if (tid == 0) s_new = 0;
-    peak = nn > peak ? nn : peak;
-    if (drop) {
-      n = compact(nn, thr);
-    } else {
-      for (uint32_t i = n + tid; i < nn; i += BLOCK) insert(i);
-      __syncthreads();
-      n = nn;
+    n += s_cnt[slot];
+    dead += s_dead[slot];
+    peak = n > peak ? n : peak;
+    if (!clifford && !thresholded_all) threshold_all();
+    if (a.gate_kind == 2) {
+      // a general gate moves both x and z bits: refresh the OR masks from the live entries
+#pragma unroll
+      for (int w = 0; w < W; ++w) { orx[w] |= m[w]; orz[w] |= m[W + w]; }
     }
   }
+
+  if (a.any_nonclifford && !thresholded_all) threshold_all();
 
   // ---- noise -------------------------------------------------------------------------------
   if (a.has_noise) {
@@ -375,16 +435,20 @@ __global__ void __launch_bounds__(LayerCfg<W>::BLOCK) k_layer(LayerArgs<CT> a) {
       for (int r = 0; r < R; ++r) {
         const uint32_t i = (uint32_t)r * BLOCK + tid;
         if (i >= n) break;
+        const double c = (double)sc[i];
+        if (c == 0.0) continue;
         uint64_t kx[W], kz[W];
         load_key(i, kx, kz);
         double p[kMaxPowerSums];
         noise_sums<W>(kx, kz, nd, 1, p);
-        const double f = exp(2.0 * nd.sign * p[0]);
-        sc[i] = (CT)((double)sc[i] * f);
+        sc[i] = (CT)(c * exp(2.0 * nd.sign * p[0]));
       }
       __syncthreads();
     } else if (ORD) {
       const int M = nd.max_order;
+      __syncthreads();
+      if (tid == 0) s_cnt[0] = 0;
+      __syncthreads();
       for (int r = 0; r < R; ++r) {
         const uint32_t i = (uint32_t)r * BLOCK + tid;
         if (i >= n) break;
@@ -400,17 +464,24 @@ __global__ void __launch_bounds__(LayerCfg<W>::BLOCK) k_layer(LayerArgs<CT> a) {
         elementary_from_power(p, M, e);
         uint32_t idx[kMaxPowerSums + 1];
         double val[kMaxPowerSums + 1];
-        for (int o = 0; o <= M; ++o) {
-          idx[o] = (uint32_t)o < oi ? EMPTY : lookup(kx, kz, (uint32_t)o);
-          val[o] = idx[o] == EMPTY ? 0.0 : (double)sc[idx[o]];
+#pragma unroll
+        for (int o = 0; o <= kMaxPowerSums; ++o) {
+          idx[o] = EMPTY;
+          val[o] = 0.0;
+          if (o <= M && (uint32_t)o >= oi) {
+            idx[o] = lookup(kx, kz, (uint32_t)o);
+            val[o] = idx[o] == EMPTY ? 0.0 : (double)sc[idx[o]];
+          }
         }
-        for (int o = M; o >= 0; --o) {
+#pragma unroll
+        for (int o = kMaxPowerSums; o >= 0; --o) {
+          if (o > M) continue;
           double acc = 0.0;
           for (int j = 0; j <= o; ++j) acc += val[o - j] * e[j];
           if (idx[o] != EMPTY) {
             sc[idx[o]] = (CT)acc;
           } else if (acc != 0.0) {
-            const uint32_t j = n + atomicAdd(&s_new, 1u);
+            const uint32_t j = n + atomicAdd(&s_cnt[0], 1u);
             if (j < (uint32_t)CAP) {
 #pragma unroll
               for (int w = 0; w < W; ++w) { sx[w][j] = kx[w]; sz[w][j] = kz[w]; }
@@ -427,14 +498,15 @@ __global__ void __launch_bounds__(LayerCfg<W>::BLOCK) k_layer(LayerArgs<CT> a) {
         overflow_exit();
         return;
       }
-      const uint32_t nn = n + s_new;
-      peak = nn > peak ? nn : peak;
+      n += s_cnt[0];
+      peak = n > peak ? n : peak;
       __syncthreads();
-      n = compact(nn, a.eps_noise);
+      n = compact(n, a.eps_noise, false);
     }
   }
 
-  // ---- write out ---------------------------------------------------------------------------
+  // ---- pack the live entries and write them out ---------------------------------------------
+  n = compact(n, 0.0, false);
   if (tid == 0) {
     unsigned long long old = *((volatile unsigned long long*)a.out_count);
     unsigned long long got = ~0ULL;
@@ -445,7 +517,6 @@ __global__ void __launch_bounds__(LayerCfg<W>::BLOCK) k_layer(LayerArgs<CT> a) {
     }
     s_base = got;
   }
-  // block-reduce the dropped mass
   {
     double v = dropped;
 #pragma unroll
@@ -453,12 +524,6 @@ __global__ void __launch_bounds__(LayerCfg<W>::BLOCK) k_layer(LayerArgs<CT> a) {
     if ((tid & 63) == 0) s_drop[tid >> 6] = v;
   }
   __syncthreads();
-  if (tid == 0) {
-    double v = 0.0;
-    for (int w = 0; w < BLOCK / 64; ++w) v += s_drop[w];
-    if (v != 0.0) atomicAdd(a.dropped, v);
-    atomicMax(a.peak, peak);
-  }
   const unsigned long long base = s_base;
   if (base == ~0ULL) {
     if (tid == 0) {
@@ -466,6 +531,12 @@ __global__ void __launch_bounds__(LayerCfg<W>::BLOCK) k_layer(LayerArgs<CT> a) {
       a.ovf_tiles[k] = tile | kOvfOutput;
     }
     return;
+  }
+  if (tid == 0) {
+    double v = 0.0;
+    for (int w = 0; w < BLOCK / 64; ++w) v += s_drop[w];
+    if (v != 0.0) atomicAdd(a.dropped, v);
+    atomicMax(a.peak, peak);
   }
   for (uint32_t i = tid; i < n; i += BLOCK) {
     const uint64_t j = base + i;
@@ -505,52 +576,91 @@ __global__ void k_tiles(Terms<CT> t, uint64_t n, GroupMask gm, uint64_t kmask, u
 // ------------------------------------------------------------------------------------------
 // Elementwise kernels.
 // ------------------------------------------------------------------------------------------
+// Bytes of LDS a noise descriptor needs when staged (table, then supports).
+inline size_t noise_lds_bytes(int ntab, int nsup) {
+  return (size_t)ntab * sizeof(double) + (size_t)nsup * sizeof(SupportDev);
+}
+constexpr size_t kNoiseLdsMax = 64 * 1024;
+
+// Greedy-mode rescale with the support tables staged in LDS: the exponent is a sum of one
+// table value per support (one or two qubits) plus the generators with larger support.
+template <int W>
+__device__ __forceinline__ double noise_exponent_lds(const uint64_t* px, const uint64_t* pz, const double* stab,
+                                                     const SupportDev* ssup, const NoiseDev& nd) {
+  double acc = 0.0;
+  for (int s = 0; s < nd.nsup; ++s) {
+    const SupportDev sp = ssup[s];
+    uint32_t pat = (uint32_t)((pick<W>(px, sp.w0) >> sp.b0) & 1u) | (uint32_t)(((pick<W>(pz, sp.w0) >> sp.b0) & 1u) << 1);
+    if (sp.w1 >= 0)
+      pat |= (uint32_t)(((pick<W>(px, sp.w1) >> sp.b1) & 1u) << 2) | (uint32_t)(((pick<W>(pz, sp.w1) >> sp.b1) & 1u) << 3);
+    acc += stab[sp.table + pat];   // pattern 0 (identity on the support) holds 0
+  }
+  for (int d = 0; d < nd.ndirect; ++d) {
+    const uint64_t* m = nd.dm + (size_t)d * 2 * W;
+    if (anticommutes<W>(px, pz, m)) acc += nd.dval[d];
+  }
+  return acc;
+}
+
+__device__ __forceinline__ void stage_noise(const NoiseDev& nd, double* stab, SupportDev* ssup) {
+  for (int j = threadIdx.x; j < nd.ntab; j += blockDim.x) stab[j] = nd.tab[j];
+  for (int j = threadIdx.x; j < nd.nsup; j += blockDim.x) ssup[j] = nd.sup[j];
+}
+
 // A layer made only of Clifford rotations maps every string to one string (no merging):
-// apply the gates in order in registers, optionally followed by the greedy-mode rescale.
+// apply the gates (staged in LDS) in order in registers, optionally followed by the
+// greedy-mode rescale (tables staged in dynamic LDS after the gates).
 template <int W, class CT, bool ORD>
-__global__ void k_clifford(Terms<CT> t, uint64_t n, const GateDev* gates, int ngates, int has_noise,
-                           NoiseDev nd) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  uint64_t kx[W], kz[W];
+__global__ void __launch_bounds__(256) k_clifford(Terms<CT> t, uint64_t n, const GateDev* gates, int ngates,
+                                                  int has_noise, NoiseDev nd) {
+  extern __shared__ double dsm[];
+  GateDev* sg = (GateDev*)dsm;
+  double* stab = (double*)(sg + ngates);
+  SupportDev* ssup = (SupportDev*)(stab + (has_noise ? nd.ntab : 0));
+  for (int j = threadIdx.x; j < ngates; j += blockDim.x) sg[j] = gates[j];
+  if (has_noise) stage_noise(nd, stab, ssup);
+  __syncthreads();
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t kx[W], kz[W];
 #pragma unroll
-  for (int w = 0; w < W; ++w) { kx[w] = t.x[w * t.stride + i]; kz[w] = t.z[w * t.stride + i]; }
-  double c = (double)t.c[i];
-  for (int g = 0; g < ngates; ++g) {
-    uint64_t m[2 * W];
+    for (int w = 0; w < W; ++w) { kx[w] = t.x[w * t.stride + i]; kz[w] = t.z[w * t.stride + i]; }
+    double c = (double)t.c[i];
+    for (int g = 0; g < ngates; ++g) {
+      uint64_t m[2 * W];
 #pragma unroll
-    for (int w = 0; w < 2 * W; ++w) m[w] = gates[g].m[w];
-    if (!anticommutes<W>(kx, kz, m)) continue;
-    const double snd = gates[g].sn_dir;
-    if (snd == 0.0) {
-      c = c * gates[g].cs;
-    } else {
-      const bool neg = irp_negative<W>(kx, kz, m, gates[g].rr_phase);
-      c = (neg ? -c : c) * snd;
+      for (int w = 0; w < 2 * W; ++w) m[w] = sg[g].m[w];
+      if (!anticommutes<W>(kx, kz, m)) continue;
+      const double snd = sg[g].sn_dir;
+      if (snd == 0.0) {
+        c = c * sg[g].cs;
+      } else {
+        const bool neg = irp_negative<W>(kx, kz, m, sg[g].rr_phase);
+        c = (neg ? -c : c) * snd;
 #pragma unroll
-      for (int w = 0; w < W; ++w) { kx[w] ^= m[w]; kz[w] ^= m[W + w]; }
+        for (int w = 0; w < W; ++w) { kx[w] ^= m[w]; kz[w] ^= m[W + w]; }
+      }
     }
-  }
-  if (has_noise) {
-    double p[kMaxPowerSums];
-    noise_sums<W>(kx, kz, nd, 1, p);
-    c = c * exp(2.0 * nd.sign * p[0]);
-  }
+    if (has_noise) c = c * exp(2.0 * nd.sign * noise_exponent_lds<W>(kx, kz, stab, ssup, nd));
 #pragma unroll
-  for (int w = 0; w < W; ++w) { t.x[w * t.stride + i] = kx[w]; t.z[w * t.stride + i] = kz[w]; }
-  t.c[i] = (CT)c;
+    for (int w = 0; w < W; ++w) { t.x[w * t.stride + i] = kx[w]; t.z[w * t.stride + i] = kz[w]; }
+    t.c[i] = (CT)c;
+  }
 }
 
 template <int W, class CT>
-__global__ void k_noise_greedy(Terms<CT> t, uint64_t n, NoiseDev nd) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  uint64_t kx[W], kz[W];
+__global__ void __launch_bounds__(256) k_noise_greedy(Terms<CT> t, uint64_t n, NoiseDev nd) {
+  extern __shared__ double dsm[];
+  double* stab = dsm;
+  SupportDev* ssup = (SupportDev*)(stab + nd.ntab);
+  stage_noise(nd, stab, ssup);
+  __syncthreads();
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t kx[W], kz[W];
 #pragma unroll
-  for (int w = 0; w < W; ++w) { kx[w] = t.x[w * t.stride + i]; kz[w] = t.z[w * t.stride + i]; }
-  double p[kMaxPowerSums];
-  noise_sums<W>(kx, kz, nd, 1, p);
-  t.c[i] = (CT)((double)t.c[i] * exp(2.0 * nd.sign * p[0]));
+    for (int w = 0; w < W; ++w) { kx[w] = t.x[w * t.stride + i]; kz[w] = t.z[w * t.stride + i]; }
+    const double c = (double)t.c[i];
+    t.c[i] = (CT)(c * exp(2.0 * nd.sign * noise_exponent_lds<W>(kx, kz, stab, ssup, nd)));
+  }
 }
 
 }  // namespace pp

@@ -74,6 +74,19 @@ __global__ void k_expand_noise(Terms<CT> in, uint64_t n, NoiseDev nd, Terms<CT> 
   }
 }
 
+// Sum `v` over the (256-thread) block and add it to *dst once per block (dst may be null).
+// Kernels using it run a grid-stride loop over a bounded grid, so the atomics stay few.
+__device__ __forceinline__ void add_dropped(double v, double* dst) {
+  __shared__ double part[4];
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0 && dst) {
+    const double t = (part[0] + part[1]) + (part[2] + part[3]);
+    if (t != 0.0) atomicAdd(dst, t);
+  }
+}
+
 template <int W, class CT, bool ORD>
 __device__ __forceinline__ bool same_term(const Terms<CT>& t, uint64_t a, uint64_t b) {
   bool eq = true;
@@ -84,13 +97,9 @@ __device__ __forceinline__ bool same_term(const Terms<CT>& t, uint64_t a, uint64
   return eq;
 }
 
-// On a sorted array: the first entry of each run of equal (string, order) sums its run
-// (compensated in FP32), stores the sum in place and flags it if nonzero and |sum| >= thr.
 template <int W, class CT, bool ORD>
-__global__ void k_reduce_runs(Terms<CT> t, uint64_t n, double thr, uint32_t* keep, double* dropped) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (i > 0 && same_term<W, CT, ORD>(t, i, i - 1)) { keep[i] = 0; return; }
+__device__ __forceinline__ double reduce_run(Terms<CT>& t, uint64_t n, uint64_t i, double thr, uint32_t* keep) {
+  if (i > 0 && same_term<W, CT, ORD>(t, i, i - 1)) { keep[i] = 0; return 0.0; }
   double s;
   if (sizeof(CT) == 8) {
     s = (double)t.c[i];
@@ -108,18 +117,31 @@ __global__ void k_reduce_runs(Terms<CT> t, uint64_t n, double thr, uint32_t* kee
   t.c[i] = (CT)s;
   const bool k = s != 0.0 && !(fabs(s) < thr);
   keep[i] = k ? 1u : 0u;
-  if (!k && s != 0.0 && dropped) atomicAdd(dropped, fabs(s));
+  return k ? 0.0 : fabs(s);
+}
+
+
+// On a sorted array: the first entry of each run of equal (string, order) sums its run
+// (compensated in FP32), stores the sum in place and flags it if nonzero and |sum| >= thr.
+template <int W, class CT, bool ORD>
+__global__ void k_reduce_runs(Terms<CT> t, uint64_t n, double thr, uint32_t* keep, double* dropped) {
+  double lost = 0.0;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    lost += reduce_run<W, CT, ORD>(t, n, i, thr, keep);
+  add_dropped(lost, dropped);
 }
 
 // keep flags from a threshold on |c| (exact zeros always dropped)
 template <class CT>
 __global__ void k_threshold_flags(const CT* c, uint64_t n, double thr, uint32_t* keep, double* dropped) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double v = (double)c[i];
-  const bool k = v != 0.0 && !(fabs(v) < thr);
-  keep[i] = k ? 1u : 0u;
-  if (!k && v != 0.0 && dropped) atomicAdd(dropped, fabs(v));
+  double lost = 0.0;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const double v = (double)c[i];
+    const bool k = v != 0.0 && !(fabs(v) < thr);
+    keep[i] = k ? 1u : 0u;
+    lost += k ? 0.0 : fabs(v);
+  }
+  add_dropped(lost, dropped);
 }
 
 // out[pos[i]] = in[i] for keep[i]; pos = exclusive scan of keep (kept in a separate array).
@@ -231,12 +253,14 @@ __global__ void __launch_bounds__(256) k_abs_hist(const CT* c, uint64_t n, int s
 // keep: |c| > tau, or |c| == tau and marked; ties flagged for the tie-break list
 template <class CT>
 __global__ void k_cap_flags(const CT* c, uint64_t n, uint64_t tau, uint32_t* keep, uint32_t* tie, double* dropped) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint64_t k = abs_key<CT>(c[i]);
-  keep[i] = k > tau ? 1u : 0u;
-  tie[i] = k == tau ? 1u : 0u;
-  if (k < tau && dropped) atomicAdd(dropped, fabs((double)c[i]));
+  double lost = 0.0;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = abs_key<CT>(c[i]);
+    keep[i] = k > tau ? 1u : 0u;
+    tie[i] = k == tau ? 1u : 0u;
+    lost += k < tau ? fabs((double)c[i]) : 0.0;
+  }
+  add_dropped(lost, dropped);
 }
 
 // Gather tied terms' keys with their index stored as the coefficient (double).
