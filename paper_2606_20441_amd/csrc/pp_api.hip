@@ -28,6 +28,10 @@
 
 using namespace pp;
 
+#ifndef PP_LEVEL0_WAVE
+#define PP_LEVEL0_WAVE 1   // first attempt with one-wavefront tiles (else 1024-thread tiles)
+#endif
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -211,6 +215,28 @@ bool angle_cos_sin(double theta, double* c, double* s) {
 
 enum GateKind { KIND_X = 0, KIND_Z = 1, KIND_OTHER = 2, KIND_NOISE = 3 };
 
+// Tables of the linear key hash.  Every key bit gets a pseudo-random 32-bit word; the table
+// entry of (plane, byte, value) is the XOR of the words of the bits set in `value`, so the
+// hash of a key is the XOR of its bits' words -- a GF(2)-linear map.
+const std::vector<uint32_t>& hash_tables() {
+  static const std::vector<uint32_t> t = [] {
+    std::vector<uint32_t> v(kHashTabWords);
+    for (int pb = 0; pb < 2 * PP_MAXW * 8; ++pb) {   // (plane, byte) position
+      uint32_t basis[8];
+      for (int i = 0; i < 8; ++i)
+        basis[i] = (uint32_t)(mix64(0x243f6a8885a308d3ULL * (uint64_t)(pb * 8 + i + 1)) >> 32);
+      for (int val = 0; val < 256; ++val) {
+        uint32_t h = 0;
+        for (int i = 0; i < 8; ++i)
+          if (val >> i & 1) h ^= basis[i];
+        v[(size_t)pb * 256 + val] = h;
+      }
+    }
+    return v;
+  }();
+  return t;
+}
+
 struct HostGate {
   GateDev g;
   int kind;
@@ -258,25 +284,27 @@ struct Engine final : EngineBase {
   TBuf<CT, ORD> cur, alt, sa, sb, tmp;
   double tau = 0.0;   // smallest |c| kept by the most recent cap that removed terms
   TBuf<double, true> ta, tb;     // tie lists for the cap
-  Buf u32a, u32b, u32c, scan_scr, tiles, gates_d, sup_d, tab_d, dm_d, dval_d, cnt_d, ovf_d, partial_d, f64_d, span_d;
+  Buf u32a, u32b, u32c, scan_scr, tiles, gates_d, sup_d, tab_d, dm_d, dval_d, cnt_d, ovf_d, partial_d, f64_d, span_d, htab_d;
   double growth[4] = {4.0, 4.0, 2.0, 3.0};
-  double tile_target[4] = {CAP / 3.0, CAP / 3.0, CAP / 3.0, CAP / 4.0};
+  double tile_target[4] = {80.0, 80.0, 80.0, 64.0};   // level-0 (one-wavefront) tile targets
   uint64_t last_ntiles = 1, last_ovf_tiles = 0;
 
   explicit Engine(pp_obs* o) : obs(o), ctx(o->ctx), st(o->ctx->stream) {
     for (auto* t : {&cur, &alt, &sa, &sb, &tmp}) { t->mem.ctx = ctx; t->W = W; }
     for (auto* t : {&ta, &tb}) { t->mem.ctx = ctx; t->W = W; }
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
-                   &partial_d, &f64_d, &span_d})
+                   &partial_d, &f64_d, &span_d, &htab_d})
       b->ctx = ctx;
     cnt_d.ensure(256);
     span_d.ensure(256);
+    htab_d.ensure(kHashTabWords * 4);
+    HIPCHK(hipMemcpy(htab_d.p, hash_tables().data(), kHashTabWords * 4, hipMemcpyHostToDevice));
   }
   ~Engine() override {
     for (auto* t : {&cur, &alt, &sa, &sb, &tmp}) t->mem.release();
     for (auto* t : {&ta, &tb}) t->mem.release();
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
-                   &partial_d, &f64_d, &span_d})
+                   &partial_d, &f64_d, &span_d, &htab_d})
       b->release();
   }
 
@@ -459,6 +487,30 @@ struct Engine final : EngineBase {
         }
       if (h.g.pivot_word < 0) { h.g.pivot_word = 0; h.g.pivot_bit = 0; }
       h.kind = !any_z ? KIND_X : (!any_x ? KIND_Z : KIND_OTHER);
+      // bit-level forms for X on one qubit and Z Z on two qubits
+      int nx = 0, nz = 0;
+      for (int w = 0; w < W; ++w) { nx += __builtin_popcountll(h.g.m[w]); nz += __builtin_popcountll(h.g.m[W + w]); }
+      h.g.type = GATE_GENERIC;
+      h.g.w0 = h.g.b0 = h.g.w1 = h.g.b1 = 0;
+      if (nx == 1 && nz == 0) {
+        h.g.type = GATE_X1;
+        for (int w = 0; w < W; ++w)
+          if (h.g.m[w]) { h.g.w0 = w; h.g.b0 = __builtin_ctzll(h.g.m[w]); }
+      } else if (nx == 0 && nz == 2) {
+        h.g.type = GATE_ZZ;
+        int found = 0;
+        for (int w = 0; w < W; ++w) {
+          uint64_t v = h.g.m[W + w];
+          while (v) {
+            const int b = __builtin_ctzll(v);
+            v &= v - 1;
+            if (found == 0) { h.g.w0 = w; h.g.b0 = b; }
+            else { h.g.w1 = w; h.g.b1 = b; }
+            ++found;
+          }
+        }
+      }
+      h.g.hash = lin_hash<W>(h.g.m, h.g.m + W, hash_tables().data());
       out.push_back(h);
     }
     return out;
@@ -615,6 +667,7 @@ struct Engine final : EngineBase {
     uint32_t ovf_count;
     uint32_t peak;
     double dropped;
+    unsigned long long out_fail;
   };
 
   // ---- grouped fused pass ---------------------------------------------------------------------
@@ -623,7 +676,8 @@ struct Engine final : EngineBase {
   // space) are gathered into `ovf`.  Returns their count.
   uint64_t fused_level(TBuf<CT, ORD>& src, uint64_t m, uint64_t T, const GroupMask& gm, int ngates, int kind,
                        bool any_nc, double thr, const NoiseDev* nd, double thr_noise, TBuf<CT, ORD>& dst,
-                       uint64_t& out_count, TBuf<CT, ORD>& ovf, bool& out_full, pp_layer_stats& ls) {
+                       uint64_t& out_count, TBuf<CT, ORD>& ovf, bool& out_full, pp_layer_stats& ls,
+                       bool small) {
     uint64_t ntiles;
     if (m <= T) {
       ntiles = 1;
@@ -650,6 +704,7 @@ struct Engine final : EngineBase {
     ovf_d.ensure((ntiles + 2) * 4);
     Counters hc0{};
     hc0.out_count = out_count;
+    hc0.out_fail = ~0ULL;
     std::memcpy((char*)ctx->pinned + 256, &hc0, sizeof hc0);
     HIPCHK(hipMemcpyAsync(cnt_d.p, (char*)ctx->pinned + 256, sizeof(Counters), hipMemcpyHostToDevice, st));
     Counters* cd = cnt_d.as<Counters>();
@@ -666,13 +721,20 @@ struct Engine final : EngineBase {
     a.has_noise = nd ? 1 : 0;
     if (nd) a.noise = *nd;
     a.eps_noise = thr_noise;
+    a.htab = htab_d.as<uint32_t>();
     a.out_count = &cd->out_count;
+    a.out_fail = &cd->out_fail;
     a.ovf_tiles = ovf_d.as<uint32_t>();
     a.ovf_count = &cd->ovf_count;
     a.dropped = &cd->dropped;
     a.peak = &cd->peak;
-    const int pi = ctx->run("layer_fused", 0, (double)m, [&] {
-      hipLaunchKernelGGL((k_layer<W, CT, ORD>), dim3((unsigned)ntiles), dim3(BLOCK), 0, st, a);
+    const int pi = ctx->run(small ? "layer_fused_wave" : "layer_fused_block", 0, (double)m, [&] {
+      if (small)
+        hipLaunchKernelGGL((k_layer<W, CT, ORD, SmallCfg<W>::CAP, SmallCfg<W>::BLOCK, SmallCfg<W>::GATES>),
+                           dim3((unsigned)ntiles), dim3(SmallCfg<W>::BLOCK), 0, st, a);
+      else
+        hipLaunchKernelGGL((k_layer<W, CT, ORD, LayerCfg<W>::CAP, LayerCfg<W>::BLOCK, LayerCfg<W>::GATES>),
+                           dim3((unsigned)ntiles), dim3(LayerCfg<W>::BLOCK), 0, st, a);
     });
     ctx->check_launch();
     Counters hc;
@@ -681,8 +743,9 @@ struct Engine final : EngineBase {
     std::memcpy(&hc, ctx->pinned, sizeof hc);
     last_ntiles = ntiles;
     last_ovf_tiles = hc.ovf_count;
-    const uint64_t written = hc.out_count - out_count;
-    out_count = hc.out_count;
+    const uint64_t end = std::min<uint64_t>(hc.out_count, hc.out_fail);   // valid prefix
+    const uint64_t written = end - out_count;
+    out_count = end;
     ls.dropped_l1 += hc.dropped;
     ls.n_peak = std::max<int64_t>(ls.n_peak, (int64_t)hc.peak);
     uint64_t mo = 0;
@@ -759,7 +822,7 @@ struct Engine final : EngineBase {
 
   // Group mask of the bits a run of gates cannot change: X-type gates keep z and every x bit
   // outside the union of their x masks; Z-type likewise with x and z exchanged; a general
-  // gate keeps all but its pivot bit.
+  // gate keeps every bit outside its x and z masks.
   GroupMask invariant_mask(const std::vector<GateDev>& gates, int kind) const {
     GroupMask gm;
     for (int w = 0; w < PP_MAXW; ++w) { gm.mx[w] = ~0ULL; gm.mz[w] = ~0ULL; }
@@ -770,10 +833,12 @@ struct Engine final : EngineBase {
       for (const GateDev& g : gates)
         for (int w = 0; w < W; ++w) gm.mz[w] &= ~g.m[W + w];
     } else if (kind == KIND_OTHER) {
-      for (const GateDev& g : gates) {
-        if (g.pivot_word < W) gm.mx[g.pivot_word] &= ~(1ULL << g.pivot_bit);
-        else gm.mz[g.pivot_word - W] &= ~(1ULL << g.pivot_bit);
-      }
+      // a general rotation flips every bit of its own x and z masks
+      for (const GateDev& g : gates)
+        for (int w = 0; w < W; ++w) {
+          gm.mx[w] &= ~g.m[w];
+          gm.mz[w] &= ~g.m[W + w];
+        }
     }
     return gm;
   }
@@ -794,26 +859,32 @@ struct Engine final : EngineBase {
       sync();
     }
     const GroupMask gm = invariant_mask(gates, kind);
-    uint64_t T = (uint64_t)std::max(4.0, std::min((double)CAP / 2, depth == 0 ? tile_target[kind] : CAP / 3.0));
-    TBuf<CT, ORD> ov_a, ov_b;
-    for (auto* t : {&ov_a, &ov_b}) { t->mem.ctx = ctx; t->W = W; }
+    TBuf<CT, ORD> ov_a, ov_b, ov_c;
+    for (auto* t : {&ov_a, &ov_b, &ov_c}) { t->mem.ctx = ctx; t->W = W; }
     TBuf<CT, ORD>* in = &src;
     uint64_t mi = m;
-    for (int level = 0; level < 2 && mi > 0; ++level) {
-      TBuf<CT, ORD>& ovf = level == 0 ? ov_a : ov_b;
+    // level 0: one-wavefront tiles; levels 1, 2: 1024-thread tiles, the second with small
+    // targets (one hash class per tile)
+    for (int level = 0; level < 3 && mi > 0; ++level) {
+      TBuf<CT, ORD>& ovf = level == 0 ? ov_a : (level == 1 ? ov_b : ov_c);
+      const bool small = level == 0 && PP_LEVEL0_WAVE;
+      uint64_t T;
+      if (level == 0 && small) T = (uint64_t)std::max(4.0, std::min((double)SmallCfg<W>::CAP / 2, tile_target[kind]));
+      else if (level == 0) T = CAP / 3;
+      else if (level == 1) T = CAP / 3;
+      else T = 256;
       bool out_full = false;
       const uint64_t mo = fused_level(*in, mi, T, gm, (int)gates.size(), kind, any_nc, thr, nd, thr_noise, dst,
-                                      dst_count, ovf, out_full, ls);
+                                      dst_count, ovf, out_full, ls, small);
       if (level > 0 || depth > 0) ls.n_fallback += (int64_t)mi;
       if (mo && out_full) grow_keep(dst, std::max<uint64_t>(2 * dst.cap, dst_count + mo * 16), dst_count);
       if (level == 0 && depth == 0) {
         const double frac = (double)last_ovf_tiles / (double)std::max<uint64_t>(1, last_ntiles);
-        if (frac > 0.05) tile_target[kind] = std::max(8.0, tile_target[kind] * 0.5);
-        else if (frac < 0.01) tile_target[kind] = std::min((double)CAP / 2, tile_target[kind] * 1.25);
+        if (frac > 0.10) tile_target[kind] = std::max(16.0, tile_target[kind] * 0.75);
+        else if (frac < 0.02) tile_target[kind] = std::min((double)SmallCfg<W>::CAP / 2, tile_target[kind] * 1.2);
       }
       in = &ovf;
       mi = mo;
-      T = std::max<uint64_t>(4, T / 16);
     }
     if (mi > 0) {
       if (gates.size() >= 2 && depth < 8) {
@@ -838,6 +909,7 @@ struct Engine final : EngineBase {
     }
     ov_a.mem.release();
     ov_b.mem.release();
+    ov_c.mem.release();
   }
 
   void grouped_pass(const std::vector<GateDev>& gates, const GroupMask& /*unused*/, int kind, double thr,

@@ -26,16 +26,6 @@ struct Terms {
 };
 
 // One rotation as the kernels see it.  m[0..W-1] = x mask, m[W..2W-1] = z mask.
-struct GateDev {
-  uint64_t m[2 * PP_MAXW];
-  double cs;          // cos(theta) (exact for Clifford angles)
-  double sn_dir;      // +sin(theta) for U^dag P U, -sin(theta) for U P U^dag
-  int pivot_word;     // word (0..2W-1) of the lowest set bit of m; pair leader has it clear
-  int pivot_bit;
-  int rr_phase;       // |x_R & z_R| mod 4
-  int clifford;       // 1: exact angle, no threshold afterwards
-};
-
 // Noise of one layer, decomposed by generator support on the host:
 //  * `nsup` supports of one or two qubits, each with a table over the 4 or 16 local
 //    Pauli patterns giving, for the generators on that support that anticommute with
@@ -69,6 +59,38 @@ __device__ __host__ __forceinline__ uint64_t mix64(uint64_t v) {
   v *= 0x81dadef4bc2dd44dULL;
   v ^= v >> 33;
   return v;
+}
+
+enum GateType { GATE_GENERIC = 0, GATE_X1 = 1, GATE_ZZ = 2 };
+
+struct GateDev {
+  uint64_t m[2 * PP_MAXW];
+  double cs;          // cos(theta) (exact for Clifford angles)
+  double sn_dir;      // +sin(theta) for U^dag P U, -sin(theta) for U P U^dag
+  int pivot_word;     // word (0..2W-1) of the lowest set bit of m; pair leader has it clear
+  int pivot_bit;
+  int rr_phase;       // |x_R & z_R| mod 4
+  int clifford;       // 1: exact angle, no threshold afterwards
+  int type;           // GATE_X1: R = X on qubit (w0,b0); GATE_ZZ: R = Z Z on (w0,b0), (w1,b1)
+  int w0, b0, w1, b1; // for GATE_ZZ (w0,b0) is the lower qubit (the pivot)
+  uint32_t hash;      // linear key hash of the flip mask (x = m[0..W), z = m[W..2W))
+};
+
+// GF(2)-linear 32-bit hash of a Pauli key: XOR of one table word per key byte.  Linear, so
+// the hash of P xor R is hash(P) xor hash(R): a partner's hash costs one XOR.
+constexpr int kHashTabWords = 2 * PP_MAXW * 8 * 256;   // [plane][byte][value]; z planes at PP_MAXW
+template <int W>
+__device__ __host__ __forceinline__ uint32_t lin_hash(const uint64_t* kx, const uint64_t* kz, const uint32_t* tab) {
+  uint32_t h = 0;
+  for (int w = 0; w < W; ++w)
+    for (int k = 0; k < 8; ++k) {
+      h ^= tab[((w * 8) + k) * 256 + (uint32_t)((kx[w] >> (8 * k)) & 255u)];
+      h ^= tab[(((PP_MAXW + w) * 8) + k) * 256 + (uint32_t)((kz[w] >> (8 * k)) & 255u)];
+    }
+  return h;
+}
+__device__ __host__ __forceinline__ uint32_t ord_hash(uint32_t o) {
+  return o ? (uint32_t)(mix64(0x5851f42d4c957f2dULL + o) >> 32) : 0u;
 }
 
 // Group hash: the bits of (x & mx, z & mz) that a layer's gates can never change.

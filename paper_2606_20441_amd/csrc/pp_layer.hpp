@@ -16,18 +16,20 @@
 #include "pp_common.hpp"
 #include "pp_sort.hpp"
 
+#include <type_traits>
+
 namespace pp {
 
 template <int W>
 struct LayerCfg;
 template <>
-struct LayerCfg<1> { static constexpr int CAP = 4096, BLOCK = 512; };
+struct LayerCfg<1> { static constexpr int CAP = 4096, BLOCK = 1024, GATES = 64; };
 template <>
-struct LayerCfg<2> { static constexpr int CAP = 2048, BLOCK = 512; };
+struct LayerCfg<2> { static constexpr int CAP = 2048, BLOCK = 1024, GATES = 64; };
 template <>
-struct LayerCfg<3> { static constexpr int CAP = 2048, BLOCK = 512; };
+struct LayerCfg<3> { static constexpr int CAP = 2048, BLOCK = 1024, GATES = 32; };
 template <>
-struct LayerCfg<4> { static constexpr int CAP = 1024, BLOCK = 256; };
+struct LayerCfg<4> { static constexpr int CAP = 1024, BLOCK = 512, GATES = 64; };
 
 constexpr int kMaxPowerSums = 4;   // error-order mode supports max_order <= 4
 constexpr uint32_t kOvfOutput = 0x80000000u;   // overflow-list flag: output space, not LDS
@@ -46,12 +48,43 @@ struct LayerArgs {
   int has_noise;
   NoiseDev noise;
   double eps_noise;             // threshold after the noise expansion (error-order mode)
+  const uint32_t* htab;          // linear-hash tables (kHashTabWords)
   unsigned long long* out_count;
+  unsigned long long* out_fail;  // smallest start refused for lack of output space
   uint32_t* ovf_tiles;
   uint32_t* ovf_count;
   double* dropped;              // sum of |c| removed by thresholds
   unsigned int* peak;           // largest live count seen in a tile
 };
+
+// Compact per-W gate record staged in LDS by the fused kernel.
+template <int W>
+struct GateC {
+  uint64_t m[2 * W];
+  double cs, sn_dir;
+  uint32_t hash;
+  int16_t type, clifford, pivot_word, pivot_bit, rr_phase, w0, b0, w1, b1, pad;
+};
+template <int W>
+__device__ __forceinline__ GateC<W> to_compact(const GateDev& g) {
+  GateC<W> c;
+#pragma unroll
+  for (int w = 0; w < 2 * W; ++w) c.m[w] = w < W ? g.m[w] : g.m[W + (w - W)];
+  c.cs = g.cs;
+  c.sn_dir = g.sn_dir;
+  c.hash = g.hash;
+  c.type = (int16_t)g.type;
+  c.clifford = (int16_t)g.clifford;
+  c.pivot_word = (int16_t)g.pivot_word;
+  c.pivot_bit = (int16_t)g.pivot_bit;
+  c.rr_phase = (int16_t)g.rr_phase;
+  c.w0 = (int16_t)g.w0;
+  c.b0 = (int16_t)g.b0;
+  c.w1 = (int16_t)g.w1;
+  c.b1 = (int16_t)g.b1;
+  c.pad = 0;
+  return c;
+}
 
 // ------------------------------------------------------------------------------------------
 // Pauli helpers on register copies of a key.
@@ -126,10 +159,14 @@ __device__ __forceinline__ void elementary_from_power(const double* p, int M, do
 // ------------------------------------------------------------------------------------------
 // The fused layer kernel.
 // ------------------------------------------------------------------------------------------
-template <int W, class CT, bool ORD>
-__global__ void __launch_bounds__(LayerCfg<W>::BLOCK) k_layer(LayerArgs<CT> a) {
-  constexpr int CAP = LayerCfg<W>::CAP;
-  constexpr int BLOCK = LayerCfg<W>::BLOCK;
+// Two shapes of the same kernel: one wavefront with a 256-entry table (first attempt: many
+// small tiles, barriers are wavefront-local, tiles skip the gates none of their terms sees)
+// and a 1024-thread workgroup with the LayerCfg table (tiles whose groups outgrow 256).
+template <int W>
+struct SmallCfg { static constexpr int CAP = 256, BLOCK = 64, GATES = 64; };
+
+template <int W, class CT, bool ORD, int CAP, int BLOCK, int GATES>
+__global__ void __launch_bounds__(BLOCK) k_layer(LayerArgs<CT> a) {
   constexpr int H = 2 * CAP;
   constexpr int R = CAP / BLOCK;
   constexpr uint32_t EMPTY = 0xffffffffu;
@@ -137,15 +174,17 @@ __global__ void __launch_bounds__(LayerCfg<W>::BLOCK) k_layer(LayerArgs<CT> a) {
   __shared__ uint64_t sx[W][CAP];
   __shared__ uint64_t sz[W][CAP];
   __shared__ CT sc[CAP];
+  __shared__ uint32_t sh[CAP];       // linear hash of each entry's string (order not included)
   __shared__ uint8_t so[ORD ? CAP : 1];
-  __shared__ uint32_t hidx[H];
-  __shared__ uint32_t s_cnt[3];      // appends of gate g land in s_cnt[g % 3]
-  __shared__ uint32_t s_dead[3];     // entries zeroed by gate g
+  __shared__ uint32_t hidx[H];       // (16-bit fingerprint << 16) | entry index, or EMPTY
+  __shared__ uint32_t s_cnt[3];      // appends of processed gate k land in s_cnt[k % 3]
+  __shared__ uint32_t s_dead[3];     // entries zeroed by processed gate k
   __shared__ uint32_t s_ovf;
   __shared__ unsigned long long s_or[2 * W];
   __shared__ uint32_t stmp[BLOCK / 64];
   __shared__ unsigned long long s_base;
   __shared__ double s_drop[BLOCK / 64];
+  __shared__ GateC<W> sgate[GATES];   // a chunk of the gate list
 
   const int tid = threadIdx.x;
   const uint32_t tile = a.tile_list ? a.tile_list[blockIdx.x] : blockIdx.x;
@@ -161,15 +200,11 @@ __global__ void __launch_bounds__(LayerCfg<W>::BLOCK) k_layer(LayerArgs<CT> a) {
     return;
   }
 
-  auto slot_of = [&](const uint64_t* kx, const uint64_t* kz, uint32_t o) -> uint32_t {
-    uint64_t h = 0x9e3779b97f4a7c15ULL * (o + 1);
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-      h = (h ^ kx[w]) * 0xff51afd7ed558ccdULL;
-      h = (h ^ kz[w]) * 0xc4ceb9fe1a85ec53ULL;
-    }
-    return (uint32_t)(h >> 40) & (H - 1);
-  };
+  // Slot = low bits of the full hash, fingerprint = its high 16 bits (kept in the slot so
+  // most probes are resolved without reading the stored key).
+  auto full_hash = [](uint32_t hs, uint32_t o) -> uint32_t { return ORD ? hs ^ ord_hash(o) : hs; };
+  auto slot_of = [](uint32_t fh) -> uint32_t { return fh & (uint32_t)(H - 1); };
+  auto fp_of = [](uint32_t fh) -> uint32_t { return fh >> 16; };
   auto same_key = [&](uint32_t idx, const uint64_t* kx, const uint64_t* kz, uint32_t o) -> bool {
     bool eq = true;
 #pragma unroll
@@ -177,29 +212,33 @@ __global__ void __launch_bounds__(LayerCfg<W>::BLOCK) k_layer(LayerArgs<CT> a) {
     if (ORD) eq = eq && so[idx] == o;
     return eq;
   };
-  auto lookup = [&](const uint64_t* kx, const uint64_t* kz, uint32_t o) -> uint32_t {
-    uint32_t h = slot_of(kx, kz, o);
+  // Resolve a probe sequence whose first slot value v was already read.
+  auto resolve = [&](uint32_t s, uint32_t fp, uint32_t v, const uint64_t* kx, const uint64_t* kz,
+                     uint32_t o) -> uint32_t {
     for (int probe = 0; probe < H; ++probe) {
-      const uint32_t idx = hidx[h];
-      if (idx == EMPTY) return EMPTY;
-      if (same_key(idx, kx, kz, o)) return idx;
-      h = (h + 1) & (H - 1);
+      if (v == EMPTY) return EMPTY;
+      if ((v >> 16) == fp) {
+        const uint32_t idx = v & 0xffffu;
+        if (same_key(idx, kx, kz, o)) return idx;
+      }
+      s = (s + 1) & (H - 1);
+      v = hidx[s];
     }
     return EMPTY;
   };
-  auto insert_key = [&](uint32_t i, const uint64_t* kx, const uint64_t* kz, uint32_t o) {
-    uint32_t h = slot_of(kx, kz, o);
+  auto lookup_h = [&](uint32_t fh, const uint64_t* kx, const uint64_t* kz, uint32_t o) -> uint32_t {
+    const uint32_t s = slot_of(fh);
+    return resolve(s, fp_of(fh), hidx[s], kx, kz, o);
+  };
+  auto insert_h = [&](uint32_t i, uint32_t fh) {
+    uint32_t s = slot_of(fh);
+    const uint32_t v = (fp_of(fh) << 16) | i;
     for (int probe = 0; probe < H; ++probe) {
-      if (atomicCAS(&hidx[h], EMPTY, i) == EMPTY) return;
-      h = (h + 1) & (H - 1);
+      if (atomicCAS(&hidx[s], EMPTY, v) == EMPTY) return;
+      s = (s + 1) & (H - 1);
     }
   };
-  auto insert = [&](uint32_t i) {
-    uint64_t kx[W], kz[W];
-#pragma unroll
-    for (int w = 0; w < W; ++w) { kx[w] = sx[w][i]; kz[w] = sz[w][i]; }
-    insert_key(i, kx, kz, ORD ? so[i] : 0u);
-  };
+  auto insert = [&](uint32_t i) { insert_h(i, full_hash(sh[i], ORD ? (uint32_t)so[i] : 0u)); };
   auto load_key = [&](uint32_t i, uint64_t* kx, uint64_t* kz) {
 #pragma unroll
     for (int w = 0; w < W; ++w) { kx[w] = sx[w][i]; kz[w] = sz[w][i]; }
@@ -210,17 +249,19 @@ __global__ void __launch_bounds__(LayerCfg<W>::BLOCK) k_layer(LayerArgs<CT> a) {
 #pragma unroll
   for (int w = 0; w < 2 * W; ++w) lor[w] = 0;
   for (uint32_t i = tid; i < n0; i += BLOCK) {
+    uint64_t kx[W], kz[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) {
-      const uint64_t xv = a.in.x[w * a.in.stride + t0 + i];
-      const uint64_t zv = a.in.z[w * a.in.stride + t0 + i];
-      sx[w][i] = xv;
-      sz[w][i] = zv;
-      lor[w] |= xv;
-      lor[W + w] |= zv;
+      kx[w] = a.in.x[w * a.in.stride + t0 + i];
+      kz[w] = a.in.z[w * a.in.stride + t0 + i];
+      sx[w][i] = kx[w];
+      sz[w][i] = kz[w];
+      lor[w] |= kx[w];
+      lor[W + w] |= kz[w];
     }
     sc[i] = a.in.c[t0 + i];
     if (ORD) so[i] = a.in.o[t0 + i];
+    sh[i] = lin_hash<W>(kx, kz, a.htab);
   }
   for (uint32_t j = tid; j < (uint32_t)H; j += BLOCK) hidx[j] = EMPTY;
   if (tid < 2 * W) s_or[tid] = 0;
@@ -236,9 +277,8 @@ __global__ void __launch_bounds__(LayerCfg<W>::BLOCK) k_layer(LayerArgs<CT> a) {
   for (uint32_t i = tid; i < n0; i += BLOCK) insert(i);
   __syncthreads();
   // x bits and z bits present anywhere in the tile: a gate R can only act on the tile if
-  // (x_any & z_R) | (z_any & x_R) is nonzero.  Gates keep the group's invariant bits, so
-  // for X-type (Z-type) runs the z (x) part of this mask stays exact; otherwise it is
-  // refreshed below after every gate that moved bits.
+  // (x_any & z_R) | (z_any & x_R) is nonzero.  X-type (Z-type) runs never change z (x),
+  // so the half of this mask those gates test stays exact; a general gate is alone in its run.
   uint64_t orx[W], orz[W];
 #pragma unroll
   for (int w = 0; w < W; ++w) { orx[w] = s_or[w]; orz[w] = s_or[W + w]; }
@@ -250,12 +290,30 @@ __global__ void __launch_bounds__(LayerCfg<W>::BLOCK) k_layer(LayerArgs<CT> a) {
   bool thresholded_all = false;
   int gi = 0;   // processed-gate counter (rotates the shared counters)
 
+  // Keys and hashes of the entries this thread owns (entry i belongs to thread i % BLOCK).
+  uint64_t rkx[R][W], rkz[R][W];
+  uint32_t rko[R], rh[R];
+  auto reload = [&](uint32_t lo, uint32_t hi) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t i = (uint32_t)r * BLOCK + tid;
+      if (i >= lo && i < hi) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) { rkx[r][w] = sx[w][i]; rkz[r][w] = sz[w][i]; }
+        rko[r] = ORD ? so[i] : 0u;
+        rh[r] = sh[i];
+      }
+    }
+  };
+  reload(0, n);
+
   // Compaction of entries [0, nn) keeping c != 0 and !(|c| < thr); optionally rebuilds the
   // hash index.  Uniform call.
   auto compact = [&](uint32_t nn, double thr, bool rebuild) -> uint32_t {
     uint64_t rx[R][W], rz[R][W];
     CT rc[R];
     uint8_t ro[R];
+    uint32_t rhh[R];
     bool keep[R];
     uint32_t cnt = 0;
 #pragma unroll
@@ -267,6 +325,7 @@ __global__ void __launch_bounds__(LayerCfg<W>::BLOCK) k_layer(LayerArgs<CT> a) {
         for (int w = 0; w < W; ++w) { rx[r][w] = sx[w][i]; rz[r][w] = sz[w][i]; }
         rc[r] = sc[i];
         ro[r] = ORD ? so[i] : 0;
+        rhh[r] = sh[i];
         const double v = (double)rc[r];
         keep[r] = v != 0.0 && !(fabs(v) < thr);
         if (!keep[r]) dropped += fabs(v);
@@ -282,6 +341,7 @@ __global__ void __launch_bounds__(LayerCfg<W>::BLOCK) k_layer(LayerArgs<CT> a) {
         for (int w = 0; w < W; ++w) { sx[w][pos] = rx[r][w]; sz[w][pos] = rz[r][w]; }
         sc[pos] = rc[r];
         if (ORD) so[pos] = ro[r];
+        sh[pos] = rhh[r];
         ++pos;
       }
     }
@@ -307,125 +367,229 @@ __global__ void __launch_bounds__(LayerCfg<W>::BLOCK) k_layer(LayerArgs<CT> a) {
     thresholded_all = true;
     if (!(a.eps > 0.0)) return;
     int nd = 0;
+#pragma unroll
     for (int r = 0; r < R; ++r) {
       const uint32_t i = (uint32_t)r * BLOCK + tid;
-      if (i >= n) break;
-      const double v = (double)sc[i];
-      if (v != 0.0 && fabs(v) < a.eps) {
-        dropped += fabs(v);
-        sc[i] = (CT)0.0;
-        ++nd;
+      if (i < n) {
+        const double v = (double)sc[i];
+        if (v != 0.0 && fabs(v) < a.eps) {
+          dropped += fabs(v);
+          sc[i] = (CT)0.0;
+          ++nd;
+        }
       }
     }
     if (__syncthreads_or(nd)) dead += 1;   // barrier; zeros now exist, so compaction may run
   };
 
-  // ---- gates: one pass and one barrier per gate ------------------------------------------------
-  for (int g = 0; g < a.ngates; ++g) {
+  // One gate over the tile: stage 1 tests anticommutation and prefetches the partner's first
+  // slot, stage 2 resolves and updates (a pair by its member with the pivot bit clear), stage
+  // 3 appends the sin children of terms without partner.  TYPE selects the bit-level forms
+  // of the test, the flip and the sign of i R P for single-qubit X and for Z Z rotations.
+  auto gate_pass = [&](auto type_tag, const GateC<W>& G, uint32_t nn) {
+    constexpr int TYPE = decltype(type_tag)::value;
     uint64_t m[2 * W];
 #pragma unroll
-    for (int w = 0; w < 2 * W; ++w) m[w] = a.gates[g].m[w];
-    const bool clifford = a.gates[g].clifford != 0;
-    uint64_t touch = 0;
+    for (int w = 0; w < 2 * W; ++w) m[w] = G.m[w];
+    const double cs = G.cs;
+    const double snd = G.sn_dir;
+    const double thr = G.clifford ? 0.0 : a.eps;
+    const uint32_t ghash = G.hash;
+    const int w0 = G.w0, b0 = G.b0, w1 = G.w1, b1 = G.b1;
+    const int slot = (gi - 1) % 3;
+    auto anti_of = [&](const uint64_t* kx, const uint64_t* kz) -> bool {
+      if constexpr (TYPE == GATE_X1) return (pick<W>(kz, w0) >> b0) & 1u;
+      else if constexpr (TYPE == GATE_ZZ) return ((pick<W>(kx, w0) >> b0) ^ (pick<W>(kx, w1) >> b1)) & 1u;
+      else return anticommutes<W>(kx, kz, m);
+    };
+    auto flip = [&](const uint64_t* kx, const uint64_t* kz, uint64_t* qx, uint64_t* qz) {
 #pragma unroll
-    for (int w = 0; w < W; ++w) touch |= (orx[w] & m[W + w]) | (orz[w] & m[w]);
-    if (!touch) {   // no entry of this tile anticommutes with the gate
-      if (!clifford && !thresholded_all) threshold_all();
-      continue;
-    }
-    const double cs = a.gates[g].cs;
-    const double snd = a.gates[g].sn_dir;
-    const int pw = a.gates[g].pivot_word;
-    const int pb = a.gates[g].pivot_bit;
-    const int rrp = a.gates[g].rr_phase;
-    const double thr = clifford ? 0.0 : a.eps;
-    const int slot = gi % 3;
-    // keep room: at most n appends can happen in this gate
-    if (n + n > (uint32_t)CAP && dead > 0) {
-      n = compact(n, 0.0, true);
-      dead = 0;
-    }
-    if (tid == 0) { s_cnt[(gi + 1) % 3] = 0; s_dead[(gi + 1) % 3] = 0; }
-    ++gi;
+      for (int w = 0; w < W; ++w) { qx[w] = kx[w]; qz[w] = kz[w]; }
+      if constexpr (TYPE == GATE_X1) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) if (w == w0) qx[w] ^= 1ULL << b0;
+      } else if constexpr (TYPE == GATE_ZZ) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          if (w == w0) qz[w] ^= 1ULL << b0;
+          if (w == w1) qz[w] ^= 1ULL << b1;
+        }
+      } else {
+#pragma unroll
+        for (int w = 0; w < W; ++w) { qx[w] ^= m[w]; qz[w] ^= m[W + w]; }
+      }
+    };
+    // sign of i R P = -Q for an anticommuting P (see irp_negative for the general rule):
+    // X_j: negative iff P has X or Y... i.e. x_j = 1 (Y -> Z);  Z_a Z_b: negative iff the
+    // qubit carrying x has z = 0 there.
+    auto neg_of = [&](const uint64_t* kx, const uint64_t* kz) -> bool {
+      if constexpr (TYPE == GATE_X1) return (pick<W>(kx, w0) >> b0) & 1u;
+      else if constexpr (TYPE == GATE_ZZ) {
+        const bool xa = (pick<W>(kx, w0) >> b0) & 1u;
+        const uint64_t zq = xa ? (pick<W>(kz, w0) >> b0) : (pick<W>(kz, w1) >> b1);
+        return (zq & 1u) == 0;
+      } else return irp_negative<W>(kx, kz, m, G.rr_phase);
+    };
+    auto is_leader = [&](const uint64_t* kx, const uint64_t* kz) -> bool {
+      if constexpr (TYPE == GATE_X1) return ((pick<W>(kx, w0) >> b0) & 1u) == 0;
+      else if constexpr (TYPE == GATE_ZZ) return ((pick<W>(kz, w0) >> b0) & 1u) == 0;
+      else {
+        const uint64_t piv = G.pivot_word < W ? pick<W>(kx, G.pivot_word) : pick<W>(kz, G.pivot_word - W);
+        return ((piv >> G.pivot_bit) & 1u) == 0;
+      }
+    };
+
+    bool act[R];
+    uint32_t hs[R], hf[R], hv[R];
+    double cv[R];
+#pragma unroll
     for (int r = 0; r < R; ++r) {
       const uint32_t i = (uint32_t)r * BLOCK + tid;
-      if (i >= n) break;
-      uint64_t kx[W], kz[W];
-      load_key(i, kx, kz);
-      if (!anticommutes<W>(kx, kz, m)) continue;
-      const double c = (double)sc[i];
+      act[r] = false;
+      if ((uint32_t)r * BLOCK >= nn) continue;   // uniform: the whole round is empty
+      act[r] = i < nn && anti_of(rkx[r], rkz[r]);
+      hs[r] = 0; hf[r] = 0; hv[r] = EMPTY; cv[r] = 0.0;
+      if (act[r]) {
+        cv[r] = (double)sc[i];
+        if (snd != 0.0) {
+          const uint32_t fh = full_hash(rh[r] ^ ghash, rko[r]);
+          hs[r] = slot_of(fh);
+          hf[r] = fp_of(fh);
+          hv[r] = hidx[hs[r]];
+        }
+      }
+    }
+    bool app[R];
+    double childv[R];
+    uint32_t zeroed = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      app[r] = false;
+      childv[r] = 0.0;
+      if (!act[r]) continue;
+      const uint32_t i = (uint32_t)r * BLOCK + tid;
+      const double c = cv[r];
       if (snd == 0.0) {   // sin = 0: the Pauli is only scaled (Clifford, |cos| = 1)
         sc[i] = (CT)(c * cs);
         continue;
       }
       uint64_t qx[W], qz[W];
-#pragma unroll
-      for (int w = 0; w < W; ++w) { qx[w] = kx[w] ^ m[w]; qz[w] = kz[w] ^ m[W + w]; }
-      const uint32_t oi = ORD ? so[i] : 0u;
-      const uint32_t p = lookup(qx, qz, oi);
-      const bool neg_i = irp_negative<W>(kx, kz, m, rrp);
+      flip(rkx[r], rkz[r], qx, qz);
+      const uint32_t p = resolve(hs[r], hf[r], hv[r], qx, qz, rko[r]);
       if (p == EMPTY) {
         if (c == 0.0) continue;
+        const bool neg_i = neg_of(rkx[r], rkz[r]);
         double ni = c * cs;
         const double child = (neg_i ? -c : c) * snd;
         if (ni == 0.0 || fabs(ni) < thr) {
           dropped += fabs(ni);
           ni = 0.0;
-          atomicAdd(&s_dead[slot], 1u);
+          ++zeroed;
         }
         sc[i] = (CT)ni;
         if (!(fabs(child) < thr) && child != 0.0) {
-          const uint32_t j = n + atomicAdd(&s_cnt[slot], 1u);
-          if (j < (uint32_t)CAP) {
-#pragma unroll
-            for (int w = 0; w < W; ++w) { sx[w][j] = qx[w]; sz[w][j] = qz[w]; }
-            if (ORD) so[j] = (uint8_t)oi;
-            sc[j] = (CT)child;
-            __threadfence_block();
-            insert_key(j, qx, qz, oi);
-          } else {
-            s_ovf = 1;
-          }
+          app[r] = true;
+          childv[r] = child;
         } else {
           dropped += fabs(child);
         }
       } else {
-        const uint64_t piv = pw < W ? pick<W>(kx, pw) : pick<W>(kz, pw - W);
-        if ((piv >> pb) & 1u) continue;   // the partner leads this pair
-        const bool neg_p = irp_negative<W>(qx, qz, m, rrp);
+        if (!is_leader(rkx[r], rkz[r])) continue;   // the partner leads this pair
+        const bool neg_i = neg_of(rkx[r], rkz[r]);
+        const bool neg_p = neg_of(qx, qz);
         const double cp = (double)sc[p];
         double ni = c * cs + (neg_p ? -cp : cp) * snd;
         double np = cp * cs + (neg_i ? -c : c) * snd;
         if (fabs(ni) < thr || ni == 0.0) {
           dropped += fabs(ni);
-          if (c != 0.0) atomicAdd(&s_dead[slot], 1u);
+          if (c != 0.0) ++zeroed;
           ni = 0.0;
         }
         if (fabs(np) < thr || np == 0.0) {
           dropped += fabs(np);
-          if (cp != 0.0) atomicAdd(&s_dead[slot], 1u);
+          if (cp != 0.0) ++zeroed;
           np = 0.0;
         }
         sc[i] = (CT)ni;
         sc[p] = (CT)np;
       }
     }
+    // stage 3: one shared-counter atomic per wavefront for its queued children
+    const uint64_t lt = lanemask_lt();
+    const int lane = tid & 63;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if ((uint32_t)r * BLOCK >= nn) continue;
+      const uint64_t bal = __ballot(app[r]);
+      if (bal == 0) continue;
+      const int leader = __ffsll((unsigned long long)bal) - 1;
+      uint32_t base = 0;
+      if (lane == leader) base = atomicAdd(&s_cnt[slot], (uint32_t)__popcll(bal));
+      base = __shfl(base, leader, 64);
+      if (app[r]) {
+        const uint32_t j = nn + base + (uint32_t)__popcll(bal & lt);
+        if (j < (uint32_t)CAP) {
+          uint64_t qx[W], qz[W];
+          flip(rkx[r], rkz[r], qx, qz);
+#pragma unroll
+          for (int w = 0; w < W; ++w) { sx[w][j] = qx[w]; sz[w][j] = qz[w]; }
+          if (ORD) so[j] = (uint8_t)rko[r];
+          sc[j] = (CT)childv[r];
+          const uint32_t hq = rh[r] ^ ghash;
+          sh[j] = hq;
+          __threadfence_block();
+          insert_h(j, full_hash(hq, rko[r]));
+        } else {
+          s_ovf = 1;
+        }
+      }
+    }
+    uint32_t zs = zeroed;
+    for (int d = 32; d >= 1; d >>= 1) zs += __shfl_xor(zs, d, 64);
+    if (lane == 0 && zs) atomicAdd(&s_dead[slot], zs);
+  };
+
+  // ---- gates: one pass and one barrier per gate ------------------------------------------------
+  for (int g = 0; g < a.ngates; ++g) {
+    if (g % GATES == 0) {   // stage the next chunk of gate records
+      __syncthreads();
+      const int cnt = a.ngates - g < GATES ? a.ngates - g : GATES;
+      for (int j = tid; j < cnt; j += BLOCK) sgate[j] = to_compact<W>(a.gates[g + j]);
+      __syncthreads();
+    }
+    const GateC<W> G = sgate[g % GATES];
+    const bool clifford = G.clifford != 0;
+    uint64_t touch = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) touch |= (orx[w] & G.m[W + w]) | (orz[w] & G.m[w]);
+    if (!touch) {   // no entry of this tile anticommutes with the gate
+      if (!clifford && !thresholded_all) threshold_all();
+      continue;
+    }
+    // reclaim zeroed slots when the table is filling up and enough of them are dead
+    if (n > (uint32_t)(3 * CAP / 4) && dead * 8 > n) {
+      n = compact(n, 0.0, true);
+      dead = 0;
+      reload(0, n);
+    }
+    const int slot = gi % 3;
+    if (tid == 0) { s_cnt[(gi + 1) % 3] = 0; s_dead[(gi + 1) % 3] = 0; }
+    ++gi;
+    if (G.type == GATE_X1) gate_pass(std::integral_constant<int, GATE_X1>{}, G, n);
+    else if (G.type == GATE_ZZ) gate_pass(std::integral_constant<int, GATE_ZZ>{}, G, n);
+    else gate_pass(std::integral_constant<int, GATE_GENERIC>{}, G, n);
     __syncthreads();
     if (s_ovf) {
       overflow_exit();
       return;
     }
+    const uint32_t n_old = n;
     n += s_cnt[slot];
     dead += s_dead[slot];
     peak = n > peak ? n : peak;
+    if (n > n_old) reload(n_old, n);
     if (!clifford && !thresholded_all) threshold_all();
-    if (a.gate_kind == 2) {
-      // a general gate moves both x and z bits: refresh the OR masks from the live entries
-#pragma unroll
-      for (int w = 0; w < W; ++w) { orx[w] |= m[w]; orz[w] |= m[W + w]; }
-    }
   }
-
   if (a.any_nonclifford && !thresholded_all) threshold_all();
 
   // ---- noise -------------------------------------------------------------------------------
@@ -455,9 +619,10 @@ __global__ void __launch_bounds__(LayerCfg<W>::BLOCK) k_layer(LayerArgs<CT> a) {
         uint64_t kx[W], kz[W];
         load_key(i, kx, kz);
         const uint32_t oi = so[i];
+        const uint32_t hstr = sh[i];
         bool leader = true;
         for (uint32_t o = 0; o < oi && leader; ++o)
-          if (lookup(kx, kz, o) != EMPTY) leader = false;
+          if (lookup_h(full_hash(hstr, o), kx, kz, o) != EMPTY) leader = false;
         if (!leader) continue;
         double p[kMaxPowerSums], e[kMaxPowerSums + 1];
         noise_sums<W>(kx, kz, nd, M, p);
@@ -469,7 +634,7 @@ __global__ void __launch_bounds__(LayerCfg<W>::BLOCK) k_layer(LayerArgs<CT> a) {
           idx[o] = EMPTY;
           val[o] = 0.0;
           if (o <= M && (uint32_t)o >= oi) {
-            idx[o] = lookup(kx, kz, (uint32_t)o);
+            idx[o] = lookup_h(full_hash(hstr, (uint32_t)o), kx, kz, (uint32_t)o);
             val[o] = idx[o] == EMPTY ? 0.0 : (double)sc[idx[o]];
           }
         }
@@ -487,6 +652,7 @@ __global__ void __launch_bounds__(LayerCfg<W>::BLOCK) k_layer(LayerArgs<CT> a) {
               for (int w = 0; w < W; ++w) { sx[w][j] = kx[w]; sz[w][j] = kz[w]; }
               so[j] = (uint8_t)o;
               sc[j] = (CT)acc;
+              sh[j] = hstr;
             } else {
               s_ovf = 1;
             }
@@ -508,14 +674,16 @@ __global__ void __launch_bounds__(LayerCfg<W>::BLOCK) k_layer(LayerArgs<CT> a) {
   // ---- pack the live entries and write them out ---------------------------------------------
   n = compact(n, 0.0, false);
   if (tid == 0) {
-    unsigned long long old = *((volatile unsigned long long*)a.out_count);
-    unsigned long long got = ~0ULL;
-    while (old + n <= a.out.stride) {
-      const unsigned long long prev = atomicCAS(a.out_count, old, old + n);
-      if (prev == old) { got = old; break; }
-      old = prev;
+    // One fetch-add per tile.  Ranges are handed out in order, so when the buffer runs out
+    // every tile from the first that does not fit on is refused; the host keeps the prefix
+    // below the smallest refused start (out_fail) and retries the refused tiles.
+    const unsigned long long old = n ? atomicAdd(a.out_count, (unsigned long long)n) : 0ULL;
+    if (old + n <= a.out.stride) {
+      s_base = old;
+    } else {
+      s_base = ~0ULL;
+      atomicMin(a.out_fail, old);
     }
-    s_base = got;
   }
   {
     double v = dropped;

@@ -63,6 +63,28 @@ RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 _lib = None
 _lib_lock = threading.Lock()
 
+# Live handles, released before interpreter shutdown tears PyTorch down (the library may
+# call back into PyTorch's allocator while releasing device memory).
+import atexit
+import weakref
+
+_live_obs = weakref.WeakSet()
+_live_ctx = weakref.WeakSet()
+
+
+@atexit.register
+def _release_all():
+    for o in list(_live_obs):
+        try:
+            o.destroy()
+        except Exception:
+            pass
+    for c in list(_live_ctx):
+        try:
+            c.close()
+        except Exception:
+            pass
+
 EXPORTED = ["pp_ctx_create", "pp_ctx_destroy", "pp_create_observable", "pp_apply_layer", "pp_truncate",
             "pp_expectation", "pp_size", "pp_export", "pp_destroy", "pp_last_error", "pp_timing_enable",
             "pp_timing_read", "pp_last_layer_stats"]
@@ -148,9 +170,13 @@ class Context:
         r = C.cast(self._release_cb, C.c_void_p) if self._release_cb else None
         _check(lib().pp_ctx_create(device, handle, a, r, None, C.byref(out)))
         self._h = out
+        self._obs = weakref.WeakSet()
+        _live_ctx.add(self)
 
     def close(self):
         if getattr(self, "_h", None):
+            for o in list(getattr(self, "_obs", ())):
+                o.destroy()
             lib().pp_ctx_destroy(self._h)
             self._h = None
 
@@ -190,6 +216,8 @@ class Observable:
         _check(lib().pp_create_observable(ctx._h, self.n, cc.shape[0], _ptr(xw, _u64p), _ptr(zw, _u64p),
                                           _ptr(cc, _f64p), PRECISIONS[precision], MODES[mode], tr, C.byref(out)))
         self._h = out
+        ctx._obs.add(self)
+        _live_obs.add(self)
 
     @classmethod
     def from_sum(cls, ctx: Context, ps, **kw) -> "Observable":
