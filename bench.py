@@ -26,6 +26,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM traffic of the fused layer kernel, taken from FETCH_SIZE / WRITE_SIZE counter runs and
+# scaled by the same counters read on a plain device copy of known size.  The figure is
+# reported only while the kernel sources still hash to the value recorded with it.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_layer_fused_wave_tfim7x8_pna.md")
+KERNEL_SOURCES = ["paper_2606_20441_amd/csrc/pp_layer.hpp", "paper_2606_20441_amd/csrc/pp_common.hpp",
+                  "paper_2606_20441_amd/csrc/pp_api.hip"]
 
 
 def log(*a):
@@ -76,7 +82,46 @@ def run_gpu(ctx, wl, precision, steps, warmup, layers_verbose=False):
     return dict(seconds=t1 - t0, updates=total_upd, expectation=res[0], terms=res[1], kernels=kstats)
 
 
-def roofline(kstats, term_bytes):
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel: str, precision: str):
+    """HBM bytes per launch recorded for `kernel` at `precision`, or None when absent or stale."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    src = kernel_source_hash()
+    for line in text.splitlines():
+        # machine-readable lines: "traffic: <kernel> <precision> <bytes per launch> <source hash>"
+        if line.startswith("traffic:"):
+            parts = line.split()
+            if len(parts) == 5 and parts[1] == kernel and parts[2] == precision and parts[4] == src:
+                return float(parts[3])
+    return None
+
+
+def copy_probe(nbytes: int, reps: int = 5):
+    """A plain device-to-device copy of known size: the calibration run for the HBM counters."""
+    import torch
+    n = nbytes // 4
+    a = torch.arange(n, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    assert bool((b[-1] == n - 1).item())
+    log(f"copy probe: {reps} copies of {n * 4} bytes")
+
+
+def roofline(kstats, term_bytes, precision="f64"):
     timed = [k for k in kstats if k["total_ms"] > 0]
     total = sum(k["total_ms"] for k in timed)
     dom = max(timed, key=lambda k: k["total_ms"])
@@ -85,8 +130,11 @@ def roofline(kstats, term_bytes):
     avg_ms = pick["total_ms"] / pick["launches"]
     per_launch_bytes = pick["algo_bytes"] / pick["launches"]
     achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    traffic = recorded_traffic(pick["name"], precision)
     out = {"bound": "hbm", "kernel": pick["name"], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+           "traffic": None if traffic is None else round(traffic),
+           "algo_bytes_per_launch": round(per_launch_bytes),
            "share_of_device_time": round(pick["total_ms"] / total, 3),
            "avg_launch_ms": round(avg_ms, 4), "launches": pick["launches"]}
     if fused is not None and fused is not pick:
@@ -110,14 +158,21 @@ def cpu_baseline(wl, budget_s=15.0):
     t0 = time.perf_counter()
     upd = 0
     done = 0
+    last = prev = 0.0
     for m, d, g, nz in calls:
         n_in = len(s)
+        spent = time.perf_counter() - t0
+        # stop before a call whose predicted time (the last call's, grown by the last ratio)
+        # would take the sample past twice the budget
+        predicted = last * max(1.0, last / prev) if prev > 0 else last
+        if done and (spent > budget_s or spent + predicted > 2.0 * budget_s):
+            break
+        t_call = time.perf_counter()
         s.apply_layer(c.layers[m], d, with_gates=g, with_noise=nz, eps=wl.eps, max_terms=wl.max_terms,
                       mode=mode, max_order=wl.max_order)
+        prev, last = last, time.perf_counter() - t_call
         upd += n_in
         done += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
     dt = time.perf_counter() - t0
     return {"value": round(upd / dt, 1), "unit": "term-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"first {done} of {len(calls)} layer calls of the same propagation ({upd} term-updates, {dt:.1f} s)"}
@@ -133,6 +188,8 @@ def main():
     ap.add_argument("--layers", action="store_true", help="print per-layer counts of the first warmup step")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -145,6 +202,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     pp.lib()
     wl = W.named_workload(args.workload)
     ctx = pp.Context(0)
@@ -156,7 +216,7 @@ def main():
         r = run_gpu(ctx, wl, prec, args.steps, args.warmup, layers_verbose=args.layers)
         tb = 16 * Wd + (8 if prec == "f64" else 4) + (1 if wl.mode == "error_order" else 0)
         r["term_bytes"] = tb
-        r["roofline"] = roofline(r["kernels"], tb)
+        r["roofline"] = roofline(r["kernels"], tb, prec)
         results[prec] = r
         log(f"   {r['updates'] / r['seconds']:.4g} term-updates/s, {1e3 * r['seconds'] / args.steps:.1f} ms/step, "
             f"<O> = {r['expectation']!r}, {r['terms']} terms")
