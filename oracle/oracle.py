@@ -50,8 +50,6 @@ def _lib():
                                            _u64p, _u64p, _f64p, C.c_double, C.c_int64, C.c_int, C.c_int]
         lib.or_expectation.restype = C.c_double
         lib.or_expectation.argtypes = [C.c_void_p, _u64p]
-        lib.or_tau.restype = C.c_double
-        lib.or_tau.argtypes = [C.c_void_p]
         lib.or_norm2.restype = C.c_double
         lib.or_norm2.argtypes = [C.c_void_p]
         _LIB = lib
@@ -144,9 +142,6 @@ class OracleSum:
     def expectation(self, basis=None) -> float:
         b = None if basis is None else _u64(basis, self.W).reshape(-1)
         return float(_lib().or_expectation(self._h, _p(b, _u64p)))
-
-    def tau(self) -> float:
-        return float(_lib().or_tau(self._h))
 
     def norm2(self) -> float:
         return float(_lib().or_norm2(self._h))

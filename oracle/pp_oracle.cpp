@@ -77,7 +77,6 @@ struct or_sum {
   int n = 0;
   int W = 0;
   Map m;
-  double tau = 0.0;   // smallest |c| kept by the most recent layer cap that removed terms
 };
 
 namespace {
@@ -264,17 +263,16 @@ void apply_layer(or_sum* s, int n_gates, const uint64_t* gx, const uint64_t* gz,
                  int noise_sign, int noise_after_gates, double eps, int64_t max_terms, int mode,
                  int max_order) {
   const int W = s->W;
-  // Truncation of intermediate results (Section I.A): |c| below the threshold is dropped
-  // after every non-Clifford gate, and after each layer only the max_terms largest terms
-  // are kept.  Reading used here: the threshold is max(eps, tau), where tau is the smallest
-  // magnitude kept by the most recent cap that removed terms, so terms too small to have
-  // survived that selection are not regrown inside the next layer (memory stays a small
-  // multiple of max_terms without a global selection after every gate).
-  const double thr = std::max(eps, s->tau);
+  // Truncation of intermediate results (Section I.A): terms with |c| < eps are dropped and
+  // at most max_terms of the largest |c| are kept.  Reading used here: both are applied
+  // after every non-Clifford gate (merge, then threshold, then cap), and in the error-order
+  // mode also after the noise layer.  Clifford gates and the greedy mode's inverse noise
+  // never lower a magnitude, so nothing is truncated after them.
+  const bool truncating = eps > 0.0 || max_terms > 0;
   auto do_noise = [&]() {
     if (n_gen <= 0) return;
     noise(s, n_gen, ex, ez, lambda, noise_sign, mode, max_order);
-    if (mode == 1 && thr > 0.0) threshold(s->m, thr);
+    if (mode == 1 && truncating) truncate(s, eps, max_terms);
   };
   if (!noise_after_gates) do_noise();
   // A layer's gates are in time order.  U^dag P U for U = U_G ... U_1 conjugates by U_G
@@ -282,15 +280,9 @@ void apply_layer(or_sum* s, int n_gates, const uint64_t* gx, const uint64_t* gz,
   for (int i = 0; i < n_gates; ++i) {
     const int g = dir == 1 ? n_gates - 1 - i : i;
     const int clifford = rotate(s, gx + (size_t)g * W, gz + (size_t)g * W, theta[g], dir);
-    if (!clifford && thr > 0.0) threshold(s->m, thr);
+    if (!clifford && truncating) truncate(s, eps, max_terms);
   }
   if (noise_after_gates) do_noise();
-  if (max_terms > 0 && (int64_t)s->m.size() > max_terms) {
-    truncate(s, 0.0, max_terms);
-    double smallest = INFINITY;
-    for (const auto& kv : s->m) smallest = std::min(smallest, std::fabs(kv.second));
-    s->tau = smallest;
-  }
 }
 
 }  // namespace
@@ -408,8 +400,6 @@ double or_expectation(const or_sum* s, const uint64_t* basis) {
   }
   return (double)acc;
 }
-
-double or_tau(const or_sum* s) { return s->tau; }
 
 double or_norm2(const or_sum* s) {
   long double acc = 0.0L;

@@ -62,10 +62,9 @@ void    or_truncate(or_sum* s, double eps, int64_t max_terms);
 
 /* One circuit layer with the truncation schedule of the propagation:
  *   [noise if !noise_after_gates] ; gates (dir = +1: reverse list order, U^dag P U;
- *   dir = -1: list order, U P U^dag), threshold after every non-Clifford gate ;
- *   [noise if noise_after_gates] (threshold afterwards in mode 1) ; cap.
- * The threshold is max(eps, tau), tau = the smallest |c| kept by the most recent cap of
- * this sum that removed terms (0 before any).  n_gates or n_gen may be 0. */
+ *   dir = -1: list order, U P U^dag), after every non-Clifford gate: drop |c| < eps, then
+ *   keep the max_terms largest (max_terms > 0) ; [noise if noise_after_gates].  In mode 1
+ *   the same truncation follows the noise.  n_gates or n_gen may be 0. */
 void    or_apply_layer(or_sum* s, int n_gates, const uint64_t* gx, const uint64_t* gz,
                        const double* theta, int dir, int n_gen, const uint64_t* ex,
                        const uint64_t* ez, const double* lambda, int noise_sign,
@@ -85,8 +84,6 @@ or_sum* or_noise_canceling(const or_sum* obs, int n_layers, const int* n_gates,
 
 /* <b| S |b> = sum over terms with x = 0 of c (-1)^{|z & b|}; basis = W words or NULL (|0>). */
 double  or_expectation(const or_sum* s, const uint64_t* basis);
-/* tau of the threshold rule above. */
-double  or_tau(const or_sum* s);
 /* Sum of c^2 (the Pauli 2-norm squared, invariant under unitary conjugation). */
 double  or_norm2(const or_sum* s);
 

@@ -361,3 +361,54 @@ def test_expectation_against_matrices(oracle_lib):
 def test_create_merges_duplicates(oracle_lib):
     s = oracle_lib.OracleSum(3, [[1], [1], [2]], [[0], [0], [2]], [0.5, -0.5, 0.25])
     assert s.as_dict() == {((2,), (2,), 0): 0.25}
+
+
+# --------------------------------------------------------------------------------------
+# Truncation schedule of one layer: threshold and cap after every non-Clifford gate only
+# (a Clifford gate between them is never followed by a truncation), checked against a
+# dense brute force of each gate followed by a plain sort.
+# --------------------------------------------------------------------------------------
+def test_layer_truncation_schedule_against_brute_force(oracle_lib):
+    B = _brute()
+    n = 4
+    ps = W.random_pauli_sum(n, 40, seed=31, allow_duplicates=False)
+    gates = [("X", (0,), 0.7), ("ZZ", (0, 1), -math.pi / 2), ("X", (1,), 0.4), ("ZZ", (2, 3), 0.9),
+             ("X", (3,), math.pi / 2), ("Y", (2,), 1.1)]
+    gx, gz = [], []
+    for p, qs, _ in gates:
+        ops = {q: (p if p != "ZZ" else "Z") for q in qs}
+        x, z = W.pauli_masks(n, ops)
+        gx.append(x)
+        gz.append(z)
+    theta = [t for _, _, t in gates]
+
+    class _L:
+        pass
+    L = _L()
+    L.n_gates, L.n_gen = len(gates), 0
+    L.gx, L.gz, L.theta = np.array(gx), np.array(gz), np.array(theta)
+    L.ex = L.ez = L.lam = None
+    for direction in (+1, -1):
+        for eps, cap in [(0.02, 0), (0.0, 30), (0.01, 25)]:
+            s = oracle_lib.OracleSum.from_sum(ps)
+            s.apply_layer(L, direction, with_noise=False, eps=eps, max_terms=cap)
+            # brute force: dense conjugation per gate, then threshold and cap by a sort
+            m = B.pauli_sum_matrix(n, ps.x, ps.z, ps.c)
+            cur = None
+            order = range(len(gates)) if direction == -1 else reversed(range(len(gates)))
+            for g in order:
+                R = B.PauliOp(n, gx[g], gz[g])
+                m = B.conj_forward(m, R, theta[g]) if direction == -1 else B.conj_backward(m, R, theta[g])
+                cur = {k: v.real for k, v in B.pauli_decompose(m, n, 1e-14).items()}
+                clifford = abs(theta[g] / (math.pi / 2) - round(theta[g] / (math.pi / 2))) < 1e-12
+                if not clifford:
+                    cur = {k: v for k, v in cur.items() if abs(v) >= eps}
+                    if cap and len(cur) > cap:
+                        ranked = sorted(cur.items(), key=lambda kv: (-abs(kv[1]), kv[0][0], kv[0][1]))
+                        cur = dict(ranked[:cap])
+                    m = sum((v * B.PauliOp(n, xm, zm).matrix() for (xm, zm), v in cur.items()),
+                            np.zeros((1 << n, 1 << n), complex))
+            got = {(k[0][0], k[1][0]): v for k, v in s.as_dict().items()}
+            assert set(got) == set(cur), (direction, eps, cap)
+            for k in cur:
+                assert abs(got[k] - cur[k]) < 1e-12
