@@ -72,14 +72,15 @@ typedef enum { PP_HEISENBERG = 1, PP_FORWARD = -1 } pp_dir;
 
 typedef struct {
   double eps;          /* drop |c| < eps after every non-Clifford gate (>= 0) */
-  int64_t max_terms;   /* after every layer keep at most this many (0 = no cap);
-                          ties in |c| go to the smaller canonical key */
+  int64_t max_terms;   /* after every non-Clifford gate (after the eps threshold) keep at
+                          most this many of the largest |c| (0 = no cap); ties in |c| go
+                          to the smaller canonical key (Section I.A's K_O) */
   int max_order;       /* PP_MODE_ERROR_ORDER: highest kept order (0..250) */
 } pp_trunc;
 
 /* One circuit layer.  Gates: n_gates Pauli rotations R_g (gx, gz: [n_gates][W]) with
  * angles theta[g].  Angles within 1e-12 of a multiple of pi/2 are Clifford and use
- * exact cos/sin in {0, +-1}; no threshold is applied after a Clifford gate.
+ * exact cos/sin in {0, +-1}; nothing is truncated after a Clifford gate.
  * Noise: n_gen Pauli-Lindblad generators E_k (ex, ez: [n_gen][W]) with strengths
  * lambda[k] >= 0 (Section I: the local channel applies E_k with probability
  * p_k = (1 - e^{-2 lambda_k})/2).  noise_sign = +1 applies the inverse map
@@ -125,10 +126,12 @@ pp_status pp_create_observable(pp_ctx* ctx, int n_qubits, int64_t n_terms, const
 
 /* Propagate through one layer (gates, then or preceded by, a Pauli-Lindblad map):
  * rotation branching per gate with the cos/sin split (Eq. evolve_gate and its backward
- * form), duplicate strings merged after every gate and |c| < eps dropped after every
- * non-Clifford gate, the inverse-noise rescale by exp(2 noise_sign sum_{k anticommuting}
- * lambda_k) (Eq. evolve_noise; in PP_MODE_ERROR_ORDER the expansion described above,
- * followed by the eps threshold per (string, order)), then the max_terms cap. */
+ * form), duplicate strings merged after every gate, and after every non-Clifford gate
+ * |c| < eps dropped and then the max_terms cap (Section I.A's truncation of intermediate
+ * results); the inverse-noise rescale by exp(2 noise_sign sum_{k anticommuting} lambda_k)
+ * (Eq. evolve_noise), not followed by a truncation in PP_MODE_GREEDY; in
+ * PP_MODE_ERROR_ORDER the expansion described above, followed by the eps threshold per
+ * (string, order) and the max_terms cap. */
 pp_status pp_apply_layer(pp_obs* obs, const pp_layer* layer);
 
 /* Explicit greedy truncation: drop |c| < eps, then keep the max_terms largest |c|
@@ -173,10 +176,10 @@ int pp_timing_read(pp_ctx* ctx, pp_kernel_stat* out, int cap, int reset);
 /* Per-layer counters of the last pp_apply_layer on this observable. */
 typedef struct {
   int64_t n_in;            /* terms entering the layer */
-  int64_t n_out;           /* terms after the layer (after the cap) */
+  int64_t n_out;           /* terms after the layer */
   int64_t n_peak;          /* largest intermediate count */
   int64_t n_fallback;      /* terms routed to the per-gate path */
-  int64_t n_capped;        /* terms removed by the cap */
+  int64_t n_capped;        /* terms removed by the caps of this layer */
   double dropped_l1;       /* sum of |c| removed by thresholds and the cap */
 } pp_layer_stats;
 

@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "pp_common.hpp"
+#include "pp_gate.hpp"
 #include "pp_layer.hpp"
 #include "pp_misc.hpp"
 #include "pp_sort.hpp"
@@ -282,9 +283,10 @@ struct Engine final : EngineBase {
   hipStream_t st;
   uint64_t N = 0;
   TBuf<CT, ORD> cur, alt, sa, sb, tmp;
-  double tau = 0.0;   // smallest |c| kept by the most recent cap that removed terms
+  uint64_t run_bound = 0;   // upper bound of the live count after any gate of the current run
   TBuf<double, true> ta, tb;     // tie lists for the cap
-  Buf u32a, u32b, u32c, scan_scr, tiles, gates_d, sup_d, tab_d, dm_d, dval_d, cnt_d, ovf_d, partial_d, f64_d, span_d, htab_d;
+  Buf u32a, u32b, u32c, scan_scr, tiles, gates_d, sup_d, tab_d, fidx_d, dm_d, dval_d, cnt_d, ovf_d, partial_d, f64_d, span_d, htab_d;
+  Buf hp_a, hp_b, tr_s0, tr_l0, tr_s1, tr_l1, g1_d, g1_ovf, g1_base, g1_drop;   // per-gate tile path
   double growth[4] = {4.0, 4.0, 2.0, 3.0};
   double tile_target[4] = {80.0, 80.0, 80.0, 64.0};   // level-0 (one-wavefront) tile targets
   uint64_t last_ntiles = 1, last_ovf_tiles = 0;
@@ -292,19 +294,20 @@ struct Engine final : EngineBase {
   explicit Engine(pp_obs* o) : obs(o), ctx(o->ctx), st(o->ctx->stream) {
     for (auto* t : {&cur, &alt, &sa, &sb, &tmp}) { t->mem.ctx = ctx; t->W = W; }
     for (auto* t : {&ta, &tb}) { t->mem.ctx = ctx; t->W = W; }
-    for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
-                   &partial_d, &f64_d, &span_d, &htab_d})
+    for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &fidx_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
+                   &partial_d, &f64_d, &span_d, &htab_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_drop})
       b->ctx = ctx;
     cnt_d.ensure(256);
     span_d.ensure(256);
     htab_d.ensure(kHashTabWords * 4);
-    HIPCHK(hipMemcpy(htab_d.p, hash_tables().data(), kHashTabWords * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpyAsync(htab_d.p, hash_tables().data(), kHashTabWords * 4, hipMemcpyHostToDevice, st));
+    sync();
   }
   ~Engine() override {
     for (auto* t : {&cur, &alt, &sa, &sb, &tmp}) t->mem.release();
     for (auto* t : {&ta, &tb}) t->mem.release();
-    for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
-                   &partial_d, &f64_d, &span_d, &htab_d})
+    for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &fidx_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
+                   &partial_d, &f64_d, &span_d, &htab_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_drop})
       b->release();
   }
 
@@ -519,63 +522,151 @@ struct Engine final : EngineBase {
   struct HostNoise {
     std::vector<SupportDev> sup;
     std::vector<double> tab;
+    std::vector<uint16_t> fidx;
     std::vector<uint64_t> dm;
     std::vector<double> dval;
     int np = 1;
   };
 
-  // Decompose the generators by support (Section I's local Pauli-Lindblad channels are
-  // independent; their factors multiply, so the exponent or power sums add over supports).
+  // The support (one or two qubits) of generator k, or {-2,-2} for a larger one and
+  // {-1,-1} for the identity.
+  std::pair<int, int> gen_support(const pp_layer* L, int k) const {
+    std::vector<int> qs;
+    for (int w = 0; w < W && qs.size() <= 2; ++w) {
+      uint64_t s = L->ex[(size_t)k * W + w] | L->ez[(size_t)k * W + w];
+      while (s && qs.size() <= 2) {
+        qs.push_back(64 * w + __builtin_ctzll(s));
+        s &= s - 1;
+      }
+    }
+    if (qs.empty()) return {-1, -1};
+    if (qs.size() > 2) return {-2, -2};
+    return {qs[0], qs.size() == 2 ? qs[1] : -1};
+  }
+
+  // Fidelity factor 1 - 2q of one generator (Eq. evolve_noise): the local channel applies
+  // E with p = (1 - e^{-2 lambda})/2; the inverse map negates lambda (sign = +1).
+  static double fidelity_factor(double lambda, int sign) {
+    const double q = (1.0 - std::exp(2.0 * sign * lambda)) / 2.0;
+    return 1.0 - 2.0 * q;
+  }
+
+  // Generator tables.  Greedy mode: each string's factor is the product of its
+  // anticommuting generators' fidelity factors in list order (see noise_factor); supports
+  // are kept in list order with per-pattern factor slots when every generator acts on one
+  // or two qubits and each support's generators are contiguous in the list, and otherwise
+  // every generator is handled directly, in list order.  Error-order mode: per support and
+  // pattern, the power sums of x_k = f_k - 1 = e^{2 sign lambda_k} - 1 over its anticommuting generators (the
+  // supports' independent channels multiply, so power sums add over supports).
   HostNoise prepare_noise(const pp_layer* L, int mode, int max_order) {
     HostNoise hn;
     const int np = mode == PP_MODE_GREEDY ? 1 : std::max(1, max_order);
     hn.np = np;
-    std::map<std::pair<int, int>, std::vector<int>> by_sup;
-    for (int k = 0; k < L->n_gen; ++k) {
-      std::vector<int> qs;
-      for (int w = 0; w < W && qs.size() <= 2; ++w) {
-        uint64_t s = L->ex[(size_t)k * W + w] | L->ez[(size_t)k * W + w];
-        while (s && qs.size() <= 2) {
-          qs.push_back(64 * w + __builtin_ctzll(s));
-          s &= s - 1;
-        }
-      }
-      if (qs.empty()) continue;   // identity generator commutes with everything
-      if (qs.size() <= 2) by_sup[{qs[0], qs.size() == 2 ? qs[1] : -1}].push_back(k);
-      else {
-        for (int w = 0; w < W; ++w) hn.dm.push_back(L->ex[(size_t)k * W + w]);
-        for (int w = 0; w < W; ++w) hn.dm.push_back(L->ez[(size_t)k * W + w]);
-        const double v = mode == PP_MODE_GREEDY ? L->lambda[k] : std::expm1(2.0 * L->noise_sign * L->lambda[k]);
-        double pw = 1.0;
-        for (int j = 0; j < np; ++j) {
-          pw = mode == PP_MODE_GREEDY ? v : pw * v;
-          hn.dval.push_back(pw);
-        }
-      }
-    }
     auto bit = [&](const uint64_t* a, int k, int q) -> int { return (int)((a[(size_t)k * W + q / 64] >> (q % 64)) & 1ULL); };
-    for (auto& kv : by_sup) {
-      const int q0 = kv.first.first, q1 = kv.first.second;
-      SupportDev sd;
+    auto anti_pat = [&](int k, int q0, int q1, int pat) -> bool {
+      const int px0 = pat & 1, pz0 = (pat >> 1) & 1, px1 = (pat >> 2) & 1, pz1 = (pat >> 3) & 1;
+      int par = px0 * bit(L->ez, k, q0) + pz0 * bit(L->ex, k, q0);
+      if (q1 >= 0) par += px1 * bit(L->ez, k, q1) + pz1 * bit(L->ex, k, q1);
+      return (par & 1) != 0;
+    };
+    auto add_direct = [&](int k, const std::vector<double>& vals) {
+      for (int w = 0; w < W; ++w) hn.dm.push_back(L->ex[(size_t)k * W + w]);
+      for (int w = 0; w < W; ++w) hn.dm.push_back(L->ez[(size_t)k * W + w]);
+      for (double v : vals) hn.dval.push_back(v);
+    };
+    auto make_sup = [&](int q0, int q1) {
+      SupportDev sd{};
       sd.w0 = (int16_t)(q0 / 64);
       sd.b0 = (int16_t)(q0 % 64);
       sd.w1 = (int16_t)(q1 < 0 ? -1 : q1 / 64);
       sd.b1 = (int16_t)(q1 < 0 ? 0 : q1 % 64);
       sd.table = (int32_t)hn.tab.size();
+      return sd;
+    };
+    if (mode == PP_MODE_GREEDY) {
+      std::vector<std::pair<int, int>> order;
+      std::vector<std::vector<int>> groups;
+      std::map<std::pair<int, int>, int> seen;
+      bool tabled = true;
+      for (int k = 0; k < L->n_gen && tabled; ++k) {
+        const auto sup = gen_support(L, k);
+        if (sup.first == -1) continue;             // the identity commutes with everything
+        if (sup.first == -2) { tabled = false; break; }
+        if (order.empty() || order.back() != sup) {
+          if (seen.count(sup)) { tabled = false; break; }
+          seen[sup] = (int)order.size();
+          order.push_back(sup);
+          groups.emplace_back();
+        }
+        groups.back().push_back(k);
+      }
+      if (!tabled) {
+        for (int k = 0; k < L->n_gen; ++k)
+          if (gen_support(L, k).first != -1) add_direct(k, {fidelity_factor(L->lambda[k], L->noise_sign)});
+        return hn;
+      }
+      // tab: one factor per tabled generator, then 1.0 (the padding target)
+      std::vector<int> slot_of(L->n_gen, -1);
+      for (auto& gk : groups)
+        for (int k : gk) {
+          slot_of[k] = (int)hn.tab.size();
+          hn.tab.push_back(fidelity_factor(L->lambda[k], L->noise_sign));
+        }
+      const int one = (int)hn.tab.size();
+      hn.tab.push_back(1.0);
+      if (one > 65535) throw_fail(PP_ERR_UNSUPPORTED, "more than 65535 noise generators in one layer");
+      for (size_t si = 0; si < order.size(); ++si) {
+        const int q0 = order[si].first, q1 = order[si].second;
+        const int npat = q1 < 0 ? 4 : 16;
+        int slots = 1;
+        for (int pat = 1; pat < npat; ++pat) {
+          int cnt = 0;
+          for (int k : groups[si]) cnt += anti_pat(k, q0, q1, pat);
+          slots = std::max(slots, cnt);
+        }
+        SupportDev sd = make_sup(q0, q1);
+        sd.table = (int32_t)hn.fidx.size();
+        sd.nslot = (int16_t)slots;
+        for (int pat = 0; pat < npat; ++pat) {
+          int used = 0;
+          if (pat)
+            for (int k : groups[si])
+              if (anti_pat(k, q0, q1, pat)) {
+                hn.fidx.push_back((uint16_t)slot_of[k]);
+                ++used;
+              }
+          for (; used < slots; ++used) hn.fidx.push_back((uint16_t)one);
+        }
+        hn.sup.push_back(sd);
+      }
+      return hn;
+    }
+    std::map<std::pair<int, int>, std::vector<int>> by_sup;
+    for (int k = 0; k < L->n_gen; ++k) {
+      const auto sup = gen_support(L, k);
+      if (sup.first == -1) continue;
+      const double v = std::expm1(2.0 * L->noise_sign * L->lambda[k]);   // x_k = f_k - 1
+      if (sup.first == -2) {
+        std::vector<double> pw(np);
+        double a = 1.0;
+        for (int j = 0; j < np; ++j) pw[j] = (a *= v);
+        add_direct(k, pw);
+        continue;
+      }
+      by_sup[sup].push_back(k);
+    }
+    for (auto& kv : by_sup) {
+      const int q0 = kv.first.first, q1 = kv.first.second;
+      SupportDev sd = make_sup(q0, q1);
+      sd.nslot = 0;
       const int npat = q1 < 0 ? 4 : 16;
       for (int pat = 0; pat < npat; ++pat) {
-        const int px0 = pat & 1, pz0 = (pat >> 1) & 1, px1 = (pat >> 2) & 1, pz1 = (pat >> 3) & 1;
         std::vector<double> acc(np, 0.0);
         for (int k : kv.second) {
-          int par = px0 * bit(L->ez, k, q0) + pz0 * bit(L->ex, k, q0);
-          if (q1 >= 0) par += px1 * bit(L->ez, k, q1) + pz1 * bit(L->ex, k, q1);
-          if (!(par & 1)) continue;
-          const double v = mode == PP_MODE_GREEDY ? L->lambda[k] : std::expm1(2.0 * L->noise_sign * L->lambda[k]);
-          double pw = 1.0;
-          for (int j = 0; j < np; ++j) {
-            pw = mode == PP_MODE_GREEDY ? v : pw * v;
-            acc[j] += pw;
-          }
+          if (!anti_pat(k, q0, q1, pat)) continue;
+          const double v = std::expm1(2.0 * L->noise_sign * L->lambda[k]);   // x_k = f_k - 1
+          double a = 1.0;
+          for (int j = 0; j < np; ++j) acc[j] += (a *= v);
         }
         for (int j = 0; j < np; ++j) hn.tab.push_back(acc[j]);
       }
@@ -589,21 +680,26 @@ struct Engine final : EngineBase {
     nd.nsup = (int)hn.sup.size();
     nd.ndirect = (int)(hn.dm.size() / (2 * W));
     nd.ntab = (int)hn.tab.size();
+    nd.nidx = (int)hn.fidx.size();
     nd.sign = sign;
     nd.mode = mode == PP_MODE_GREEDY ? 0 : 1;
     nd.max_order = max_order;
     sup_d.ensure(hn.sup.size() * sizeof(SupportDev) + 64);
     tab_d.ensure(hn.tab.size() * 8 + 64);
+    fidx_d.ensure(hn.fidx.size() * 2 + 64);
     dm_d.ensure(hn.dm.size() * 8 + 64);
     dval_d.ensure(hn.dval.size() * 8 + 64);
     if (!hn.sup.empty())
       HIPCHK(hipMemcpyAsync(sup_d.p, hn.sup.data(), hn.sup.size() * sizeof(SupportDev), hipMemcpyHostToDevice, st));
     if (!hn.tab.empty()) HIPCHK(hipMemcpyAsync(tab_d.p, hn.tab.data(), hn.tab.size() * 8, hipMemcpyHostToDevice, st));
+    if (!hn.fidx.empty())
+      HIPCHK(hipMemcpyAsync(fidx_d.p, hn.fidx.data(), hn.fidx.size() * 2, hipMemcpyHostToDevice, st));
     if (!hn.dm.empty()) HIPCHK(hipMemcpyAsync(dm_d.p, hn.dm.data(), hn.dm.size() * 8, hipMemcpyHostToDevice, st));
     if (!hn.dval.empty())
       HIPCHK(hipMemcpyAsync(dval_d.p, hn.dval.data(), hn.dval.size() * 8, hipMemcpyHostToDevice, st));
     nd.sup = sup_d.as<SupportDev>();
     nd.tab = tab_d.as<double>();
+    nd.fidx = fidx_d.as<uint16_t>();
     nd.dm = dm_d.as<uint64_t>();
     nd.dval = dval_d.as<double>();
     // The uploads above are ordered on the stream before the kernels that read them; the
@@ -615,7 +711,7 @@ struct Engine final : EngineBase {
   // Greedy-mode rescale, elementwise, support tables staged in LDS.
   void noise_greedy(const Terms<CT>& t, uint64_t n, const NoiseDev& nd, const char* name) {
     if (n == 0) return;
-    const size_t lds = noise_lds_bytes(nd.ntab, nd.nsup);
+    const size_t lds = noise_lds_bytes(nd);
     if (lds > 160 * 1024) throw_fail(PP_ERR_UNSUPPORTED, "noise tables exceed LDS");
     if (lds > kNoiseLdsMax)
       HIPCHK(hipFuncSetAttribute((const void*)k_noise_greedy<W, CT>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -629,7 +725,8 @@ struct Engine final : EngineBase {
 
   // ---- per-gate path on a subset (sa holds m terms) ------------------------------------------
   uint64_t per_gate(uint64_t m, const std::vector<GateDev>& gates, double eps, const NoiseDev* nd,
-                    double eps_noise, double* dropped_dev) {
+                    double eps_noise, double* dropped_dev, uint64_t* peak_out = nullptr) {
+    uint64_t gate_peak = m;
     for (const GateDev& G : gates) {
       if (m == 0) break;
       sb.ensure(2 * m);
@@ -641,7 +738,9 @@ struct Engine final : EngineBase {
       sa.swap(sb);
       canonical_sort(sa, sb, 2 * m);
       m = merge_sorted(sa, sb, 2 * m, G.clifford ? 0.0 : eps, dropped_dev);
+      gate_peak = std::max(gate_peak, m);
     }
+    if (peak_out) *peak_out = gate_peak;
     if (nd && m) {
       if (nd->mode == 0) {
         noise_greedy(sa.view(), m, *nd, "noise");
@@ -668,6 +767,7 @@ struct Engine final : EngineBase {
     uint32_t peak;
     double dropped;
     unsigned long long out_fail;
+    unsigned long long peak_sum;
   };
 
   // ---- grouped fused pass ---------------------------------------------------------------------
@@ -728,6 +828,7 @@ struct Engine final : EngineBase {
     a.ovf_count = &cd->ovf_count;
     a.dropped = &cd->dropped;
     a.peak = &cd->peak;
+    a.peak_sum = &cd->peak_sum;
     const int pi = ctx->run(small ? "layer_fused_wave" : "layer_fused_block", 0, (double)m, [&] {
       if (small)
         hipLaunchKernelGGL((k_layer<W, CT, ORD, SmallCfg<W>::CAP, SmallCfg<W>::BLOCK, SmallCfg<W>::GATES>),
@@ -748,6 +849,7 @@ struct Engine final : EngineBase {
     out_count = end;
     ls.dropped_l1 += hc.dropped;
     ls.n_peak = std::max<int64_t>(ls.n_peak, (int64_t)hc.peak);
+    run_bound += hc.peak_sum;
     uint64_t mo = 0;
     std::vector<uint32_t> src_r, len_r;
     std::vector<uint64_t> dst_r;
@@ -903,7 +1005,9 @@ struct Engine final : EngineBase {
         // last resort (a single gate's pairs cannot outgrow LDS; kept for safety)
         ls.n_fallback += (int64_t)mi;
         if (in != &sa) sa.swap(*in);
-        const uint64_t mm = per_gate(mi, gates, thr, nd, thr_noise, &cnt_d.as<Counters>()->dropped);
+        uint64_t gp = 0;
+        const uint64_t mm = per_gate(mi, gates, thr, nd, thr_noise, &cnt_d.as<Counters>()->dropped, &gp);
+        run_bound += gp;
         append(dst, dst_count, sa, mm);
       }
     }
@@ -912,18 +1016,365 @@ struct Engine final : EngineBase {
     ov_c.mem.release();
   }
 
-  void grouped_pass(const std::vector<GateDev>& gates, const GroupMask& /*unused*/, int kind, double thr,
-                    const NoiseDev* nd, double thr_noise, pp_layer_stats& ls) {
+  // One run of gates of one kind.  Truncation follows every non-Clifford gate: the threshold
+  // inside the kernels, the cap (when set) as a device-wide selection.  All gates of the run
+  // go through one fused pass when the cap cannot bind: the pass reports an upper bound of
+  // the live count after every gate, and if that bound stays within the cap, every
+  // per-gate cap was a no-op.  Otherwise the run is redone one gate at a time, with the cap
+  // after each non-Clifford gate.  Returns false if the noise `nd` was not applied (the
+  // caller applies it after the run).
+  bool grouped_pass(const std::vector<GateDev>& gates, int kind, double thr, const NoiseDev* nd,
+                    double thr_noise, pp_layer_stats& ls) {
+    if (N == 0) return true;
+    const int64_t cap = obs->trunc.max_terms;
+    bool any_nc = false;
+    for (const GateDev& g : gates) any_nc |= g.clifford == 0;
+    const bool capped = cap > 0 && any_nc;
+    // a sum already at half the cap nearly always outgrows it at some gate
+    if (!capped || (int64_t)N * 2 <= cap) {
+      const uint64_t n_in = N;
+      const double g = growth[kind];
+      alt.ensure((uint64_t)((double)N * std::max(2.0, g) * 2.0) + 4 * CAP);
+      uint64_t out_count = 0;
+      run_bound = 0;
+      run_groups(cur, N, gates, kind, thr, nd, thr_noise, alt, out_count, 0, ls);
+      if (!capped || run_bound <= (uint64_t)cap) {
+        cur.swap(alt);
+        N = out_count;
+        const double obs_g = (double)N / (double)std::max<uint64_t>(1, n_in);
+        growth[kind] = std::min(256.0, std::max({2.0, 1.5 * obs_g, growth[kind] * 0.75}));
+        return true;
+      }
+      ls.n_fallback += (int64_t)N;   // the fused result is discarded; cur still holds the input
+    }
+    gate_by_gate(gates, kind, thr, (uint64_t)cap, ls);
+    return nd == nullptr;
+  }
+
+  // ---- gate by gate over persistent tiles --------------------------------------------------------
+  struct G1Counters {
+    uint32_t ovf_count;
+    uint32_t big_count;
+  };
+  static constexpr uint64_t kG1Target = 96;     // terms per one-wavefront tile when tiling
+  static constexpr uint32_t kG1Big = 160;       // a tile above this may outgrow 256 at the next gate
+  uint64_t g1_ntiles = 0;
+
+  // Group the terms by the run's invariant bits, cut them into tiles of whole groups and
+  // compute the per-term hash plane (cur must be dense).
+  void g1_tile(const GroupMask& gm) {
+    const uint64_t m = N;
+    const uint64_t T = kG1Target;
+    const int k = std::min(40, std::max(8, ceil_log2(std::max<uint64_t>(m, 2)) - floor_log2(T) + 4));
+    const int passes = (k + kMaxDigitBits - 1) / kMaxDigitBits;
+    const int kk = passes * ((k + passes - 1) / passes);
+    hash_sort(cur, tmp, m, gm, kk);
+    const uint64_t ntiles = std::max<uint64_t>(1, cdiv(m, T));
+    tiles.ensure((ntiles + 2) * 4);
+    const Terms<CT> t = cur.view();
+    const uint64_t kmask = kk >= 64 ? ~0ULL : ((1ULL << kk) - 1);
+    uint32_t* ts = tiles.as<uint32_t>();
+    ctx->run("tiles", 0, (double)ntiles, [&] {
+      hipLaunchKernelGGL((k_tiles<W, CT>), grid1(ntiles + 1), dim3(256), 0, st, t, m, gm, kmask, T, (uint32_t)ntiles,
+                         ts);
+    });
+    ctx->check_launch();
+    tr_s0.ensure(ntiles * 4 + 64);
+    tr_l0.ensure(ntiles * 4 + 64);
+    uint32_t *s0 = tr_s0.as<uint32_t>(), *l0 = tr_l0.as<uint32_t>();
+    hipLaunchKernelGGL(k_tile_ranges, grid1(ntiles), dim3(256), 0, st, (const uint32_t*)ts, (uint32_t)ntiles, s0, l0);
+    ctx->check_launch();
+    hp_a.ensure(cur.cap * 4 + 64);
+    uint32_t* hp = hp_a.as<uint32_t>();
+    const uint32_t* ht = htab_d.as<uint32_t>();
+    ctx->run("hash_plane", 0, (double)m, [&] {
+      hipLaunchKernelGGL((k_hash_plane<W, CT>), grid1(m), dim3(256), 0, st, t, m, ht, hp);
+    });
+    ctx->check_launch();
+    g1_ntiles = ntiles;
+  }
+
+  // Output bases of the tiles for the next gate: exclusive prefix of 2 * len.  Returns the
+  // total (the extent of the output buffer).
+  uint64_t g1_bases(const uint32_t* len, uint64_t ntiles) {
+    g1_base.ensure(ntiles * 4 + 64);
+    uint32_t* b = g1_base.as<uint32_t>();
+    hipLaunchKernelGGL(k_double_len, grid1(ntiles), dim3(256), 0, st, len, (uint32_t)ntiles, b);
+    ctx->check_launch();
+    uint32_t last = 0;
+    HIPCHK(hipMemcpyAsync(ctx->pinned, b + ntiles - 1, 4, hipMemcpyDeviceToHost, st));
+    scan_u32(b, ntiles);
+    uint32_t lastb = 0;
+    HIPCHK(hipMemcpyAsync((char*)ctx->pinned + 4, b + ntiles - 1, 4, hipMemcpyDeviceToHost, st));
+    sync();
+    std::memcpy(&last, ctx->pinned, 4);
+    std::memcpy(&lastb, (char*)ctx->pinned + 4, 4);
+    return (uint64_t)lastb + last;
+  }
+
+  // The cut of the cap at K: |c| keys with (key & mask) >= prefix are kept.  Returns false
+  // when the K-th largest value is tied with terms that must be dropped (the caller then
+  // needs the exact tie-break by key).
+  bool cap_cut(uint64_t K, uint64_t n, uint64_t& prefix_out, uint64_t& mask_out) {
+    const int KB = sizeof(CT) == 8 ? 63 : 31;
+    uint64_t prefix = 0, pmask = 0, need = K, count_eq = 0;
+    u32a.ensure(2048 * 4 + 64);
+    uint32_t* hist = u32a.as<uint32_t>();
+    const CT* c = cur.view().c;
+    int hi = KB;
+    std::vector<uint32_t> h(2048);
+    while (hi > 0) {
+      const int bits = std::min(11, hi);
+      const int shift = hi - bits;
+      const int bins = 1 << bits;
+      HIPCHK(hipMemsetAsync(hist, 0, bins * 4, st));
+      const unsigned nb = (unsigned)std::min<uint64_t>(2048, cdiv(n, 256));
+      ctx->run("cap_hist", sizeof(CT) * (double)n, (double)n, [&] {
+        hipLaunchKernelGGL((k_abs_hist<CT>), dim3(nb), dim3(256), 0, st, c, n, shift, bits, pmask, prefix, hist);
+      });
+      ctx->check_launch();
+      HIPCHK(hipMemcpyAsync(ctx->pinned, hist, bins * 4, hipMemcpyDeviceToHost, st));
+      sync();
+      std::memcpy(h.data(), ctx->pinned, bins * 4);
+      uint64_t cum = 0;
+      int d = bins - 1;
+      for (; d >= 0; --d) {
+        if (cum + h[d] >= need) break;
+        cum += h[d];
+      }
+      if (d < 0) d = 0;
+      need -= cum;
+      prefix |= (uint64_t)d << shift;
+      pmask |= (uint64_t)(bins - 1) << shift;
+      count_eq = h[d];
+      hi = shift;
+      if (need == count_eq) break;
+    }
+    prefix_out = prefix;
+    mask_out = pmask;
+    return need == count_eq;
+  }
+
+  // Drop the terms below a pending cut (and exact zeros) from cur.
+  void apply_cut(uint64_t key, uint64_t mask, pp_layer_stats& ls) {
     if (N == 0) return;
-    const uint64_t n_in = N;
-    const double g = growth[kind];
-    alt.ensure((uint64_t)((double)N * std::max(2.0, g) * 2.0) + 4 * CAP);
-    uint64_t out_count = 0;
-    run_groups(cur, N, gates, kind, thr, nd, thr_noise, alt, out_count, 0, ls);
-    cur.swap(alt);
-    N = out_count;
-    const double obs_g = (double)N / (double)std::max<uint64_t>(1, n_in);
-    growth[kind] = std::min(256.0, std::max({2.0, 1.5 * obs_g, growth[kind] * 0.75}));
+    u32b.ensure(N * 4 + 64);
+    uint32_t* keep = u32b.as<uint32_t>();
+    double* dd = &cnt_d.as<Counters>()->dropped;
+    HIPCHK(hipMemsetAsync(dd, 0, 8, st));
+    const CT* c = cur.view().c;
+    const uint64_t n = N;
+    ctx->run("cut_flags", 0, (double)n, [&] {
+      hipLaunchKernelGGL((k_cut_keep<CT>), gridb(n), dim3(256), 0, st, c, n, key, mask, keep, dd);
+    });
+    ctx->check_launch();
+    compact_cur(keep);
+    double dropped = 0.0;
+    HIPCHK(hipMemcpyAsync(ctx->pinned, dd, 8, hipMemcpyDeviceToHost, st));
+    sync();
+    std::memcpy(&dropped, ctx->pinned, 8);
+    ls.dropped_l1 += dropped;
+  }
+
+  // The pending cut on the m terms of sa (result in sa); returns the survivors' count.
+  uint64_t cut_subset(uint64_t m, uint64_t key, uint64_t mask) {
+    if (m == 0) return 0;
+    u32b.ensure(m * 4 + 64);
+    u32c.ensure(m * 4 + 64);
+    uint32_t* keep = u32b.as<uint32_t>();
+    uint32_t* pos = u32c.as<uint32_t>();
+    const CT* c = sa.view().c;
+    ctx->run("cut_flags", 0, (double)m, [&] {
+      hipLaunchKernelGGL((k_cut_keep<CT>), gridb(m), dim3(256), 0, st, c, m, key, mask, keep, (double*)nullptr);
+    });
+    ctx->check_launch();
+    HIPCHK(hipMemcpyAsync(pos, keep, m * 4, hipMemcpyDeviceToDevice, st));
+    scan_u32(pos, m);
+    uint32_t lp = 0, lk = 0;
+    HIPCHK(hipMemcpyAsync(ctx->pinned, pos + m - 1, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync((char*)ctx->pinned + 4, keep + m - 1, 4, hipMemcpyDeviceToHost, st));
+    sync();
+    std::memcpy(&lp, ctx->pinned, 4);
+    std::memcpy(&lk, (char*)ctx->pinned + 4, 4);
+    const uint64_t k = (uint64_t)lp + lk;
+    sb.ensure(std::max<uint64_t>(k, 1));
+    const Terms<CT> in = sa.view(), out = sb.view();
+    ctx->run("compact", 0, (double)m, [&] {
+      hipLaunchKernelGGL((k_compact<W, CT, ORD>), grid1(m), dim3(256), 0, st, in, out, m, (const uint32_t*)keep,
+                         (const uint32_t*)pos);
+    });
+    ctx->check_launch();
+    sa.swap(sb);
+    return k;
+  }
+
+  template <int CAPK, int BLOCKK>
+  void g1_launch(const Gate1Args<CT>& a, unsigned nblocks, bool small) {
+    ctx->run(small ? "gate_tile_wave" : "gate_tile_block", 0, (double)nblocks, [&] {
+      hipLaunchKernelGGL((k_gate1<W, CT, ORD, CAPK, BLOCKK>), dim3(nblocks), dim3(BLOCKK), 0, st, a);
+    });
+    ctx->check_launch();
+  }
+
+  // Apply `gates` one at a time with the cap after each non-Clifford gate (Section I.A's
+  // truncation of intermediate results, taken after every such gate).  The terms are tiled
+  // once by the run's invariant bits; each gate is one pass over the tiles.  Between gates
+  // the buffer holds each tile in its own region (2x its input), unused slots at c = 0, and
+  // the cut of the last gate is applied when the next pass loads the tile.
+  void gate_by_gate(const std::vector<GateDev>& gates, int kind, double eps, uint64_t cap, pp_layer_stats& ls) {
+    const GroupMask gm = invariant_mask(gates, kind);
+    bool has_cut = false, need_tiles = true;
+    uint64_t cut_key = 0, cut_mask = 0;
+    uint64_t extent = N;      // slots of cur that hold terms or zeros
+    uint64_t out_extent = 0;  // slots the next pass writes
+    g1_d.ensure(sizeof(G1Counters) + 64);
+    g1_drop.ensure(kDropSlots * 8 + 64);
+    G1Counters* cd = g1_d.as<G1Counters>();
+    double* dropd = g1_drop.as<double>();
+    auto densify = [&]() {   // apply a pending cut and squeeze out the unused slots
+      N = extent;
+      apply_cut(has_cut ? cut_key : 0, has_cut ? cut_mask : 0, ls);
+      has_cut = false;
+      extent = N;
+    };
+    for (size_t gi = 0; gi < gates.size() && N > 0; ++gi) {
+      const GateDev& G = gates[gi];
+      if (need_tiles) {
+        if (extent != N || has_cut) densify();
+        if (N == 0) break;
+        g1_tile(gm);
+        out_extent = g1_bases(tr_l0.as<uint32_t>(), g1_ntiles);
+        need_tiles = false;
+      }
+      const uint64_t ntiles = g1_ntiles;
+      alt.ensure(out_extent + 64);
+      hp_b.ensure(alt.cap * 4 + 64);
+      tr_s1.ensure(ntiles * 4 + 64);
+      tr_l1.ensure(ntiles * 4 + 64);
+      g1_ovf.ensure(ntiles * 4 + 64);
+      HIPCHK(hipMemsetAsync(cd, 0, sizeof(G1Counters), st));
+      HIPCHK(hipMemsetAsync(dropd, 0, kDropSlots * 8, st));
+      Gate1Args<CT> a{};
+      a.in = cur.view();
+      a.out = alt.view();
+      a.hin = hp_a.as<uint32_t>();
+      a.hout = hp_b.as<uint32_t>();
+      a.t_start = tr_s0.as<uint32_t>();
+      a.t_len = tr_l0.as<uint32_t>();
+      a.t_list = nullptr;
+      a.o_base = g1_base.as<uint32_t>();
+      a.o_start = tr_s1.as<uint32_t>();
+      a.o_len = tr_l1.as<uint32_t>();
+      a.zero_on_ovf = 0;
+      a.g = G;
+      a.eps = G.clifford ? 0.0 : eps;
+      a.has_cut = has_cut ? 1 : 0;
+      a.cut_key = cut_key;
+      a.cut_mask = cut_mask;
+      a.ovf_tiles = g1_ovf.as<uint32_t>();
+      a.ovf_count = &cd->ovf_count;
+      a.dropped = dropd;
+      a.big_count = &cd->big_count;
+      a.big_hint = kG1Big;
+      g1_launch<SmallCfg<W>::CAP, SmallCfg<W>::BLOCK>(a, (unsigned)ntiles, true);
+      G1Counters hc;
+      HIPCHK(hipMemcpyAsync(ctx->pinned, cd, sizeof hc, hipMemcpyDeviceToHost, st));
+      sync();
+      std::memcpy(&hc, ctx->pinned, sizeof hc);
+      uint64_t giant_terms = 0;
+      if (hc.ovf_count > 0) {
+        // tiles too large for one wavefront: the 1024-thread shape, on the same ranges
+        const uint32_t nov = hc.ovf_count;
+        Gate1Args<CT> b = a;
+        u32c.ensure(4 * (size_t)nov + 64);
+        u32b.ensure(4 * (size_t)nov + 64);
+        HIPCHK(hipMemcpyAsync(u32c.p, g1_ovf.p, 4 * (size_t)nov, hipMemcpyDeviceToDevice, st));
+        b.t_list = u32c.as<uint32_t>();
+        b.ovf_tiles = u32b.as<uint32_t>();
+        b.zero_on_ovf = 1;
+        HIPCHK(hipMemsetAsync(cd, 0, sizeof(G1Counters), st));
+        g1_launch<LayerCfg<W>::CAP, LayerCfg<W>::BLOCK>(b, nov, false);
+        G1Counters hb;
+        HIPCHK(hipMemcpyAsync(ctx->pinned, cd, sizeof hb, hipMemcpyDeviceToHost, st));
+        sync();
+        std::memcpy(&hb, ctx->pinned, sizeof hb);
+        hc.big_count += hb.big_count;
+        if (hb.ovf_count > 0) {
+          // groups too large for LDS that the gate touches: the sort-based path, on their terms
+          const uint32_t n2 = hb.ovf_count;
+          std::vector<uint32_t> o2(n2), ts(ntiles), tl(ntiles);
+          HIPCHK(hipMemcpyAsync(o2.data(), u32b.p, 4 * (size_t)n2, hipMemcpyDeviceToHost, st));
+          HIPCHK(hipMemcpyAsync(ts.data(), tr_s0.p, 4 * ntiles, hipMemcpyDeviceToHost, st));
+          HIPCHK(hipMemcpyAsync(tl.data(), tr_l0.p, 4 * ntiles, hipMemcpyDeviceToHost, st));
+          sync();
+          std::vector<uint32_t> src_r, len_r;
+          std::vector<uint64_t> dst_r;
+          uint64_t mo = 0;
+          for (uint32_t v : o2) {
+            src_r.push_back(ts[v]);
+            len_r.push_back(tl[v]);
+            dst_r.push_back(mo);
+            mo += tl[v];
+          }
+          sa.ensure(std::max<uint64_t>(mo, 1));
+          u32c.ensure(8 * (size_t)n2 + 64);
+          partial_d.ensure(8 * (size_t)n2 + 64);
+          u32b.ensure(8 * (size_t)n2 + 64);
+          HIPCHK(hipMemcpyAsync(u32b.p, src_r.data(), 4 * (size_t)n2, hipMemcpyHostToDevice, st));
+          HIPCHK(hipMemcpyAsync(u32c.p, len_r.data(), 4 * (size_t)n2, hipMemcpyHostToDevice, st));
+          HIPCHK(hipMemcpyAsync(partial_d.p, dst_r.data(), 8 * (size_t)n2, hipMemcpyHostToDevice, st));
+          const Terms<CT> in = cur.view(), sub = sa.view();
+          const uint32_t *srcd = u32b.as<uint32_t>(), *lend = u32c.as<uint32_t>();
+          const uint64_t* dstd = partial_d.as<uint64_t>();
+          ctx->run("copy_ranges", 0, (double)mo, [&] {
+            hipLaunchKernelGGL((k_copy_ranges<W, CT, ORD>), dim3(n2), dim3(256), 0, st, in, sub, srcd, lend, dstd,
+                               (int)n2);
+          });
+          ctx->check_launch();
+          sync();
+          uint64_t mm = mo;
+          if (has_cut) mm = cut_subset(mm, cut_key, cut_mask);   // the pending cut, on this subset
+          ls.n_fallback += (int64_t)mm;
+          mm = per_gate(mm, {G}, G.clifford ? 0.0 : eps, nullptr, 0.0, &dropd[0]);
+          uint64_t oc = out_extent;
+          append(alt, oc, sa, mm);
+          giant_terms = mm;
+          out_extent = oc;
+          need_tiles = true;   // these terms are no longer laid out by tile
+        }
+      }
+      std::vector<double> dsl(kDropSlots);
+      HIPCHK(hipMemcpyAsync(dsl.data(), dropd, kDropSlots * 8, hipMemcpyDeviceToHost, st));
+      cur.swap(alt);
+      std::swap(hp_a, hp_b);
+      std::swap(tr_s0, tr_s1);
+      std::swap(tr_l0, tr_l1);
+      extent = out_extent;
+      // live terms, and the output bases of the next gate
+      const uint64_t next_extent = g1_bases(tr_l0.as<uint32_t>(), ntiles);
+      for (double v : dsl) ls.dropped_l1 += v;
+      N = next_extent / 2 + giant_terms;
+      out_extent = next_extent;
+      ls.n_peak = std::max<int64_t>(ls.n_peak, (int64_t)N);
+      has_cut = false;
+      if (!G.clifford && cap > 0 && N > cap) {
+        uint64_t key = 0, mask = 0;
+        if (cap_cut(cap, extent, key, mask)) {
+          has_cut = true;
+          cut_key = key;
+          cut_mask = mask;
+          ls.n_capped += (int64_t)(N - cap);
+        } else {
+          densify();   // exact ties at the cut: rank them by key on the dense array
+          cap_select(cap, ls);
+          extent = N;
+          need_tiles = true;
+        }
+      }
+      // regroup when the cut has left the tiles small on average
+      if (N < ntiles * kG1Target / 4) need_tiles = true;
+    }
+    if (has_cut || extent != N) densify();
   }
 
   // ---- create ----------------------------------------------------------------------------------
@@ -970,15 +1421,18 @@ struct Engine final : EngineBase {
     } else {
       GroupMask gm;
       for (int w = 0; w < PP_MAXW; ++w) { gm.mx[w] = ~0ULL; gm.mz[w] = ~0ULL; }
-      grouped_pass({}, gm, KIND_NOISE, 0.0, &nd, std::max(obs->trunc.eps, tau), ls);
+      grouped_pass({}, KIND_NOISE, 0.0, &nd, obs->trunc.eps, ls);
+      // error-order mode: the noise is followed by the threshold (in the pass) and the cap
+      if (obs->trunc.max_terms > 0 && (int64_t)N > obs->trunc.max_terms)
+        cap_select((uint64_t)obs->trunc.max_terms, ls);
     }
   }
 
   void apply_layer(const pp_layer* L) override {
     pp_layer_stats ls{};
     ls.n_in = (int64_t)N;
-    // threshold after every non-Clifford gate: max(eps, tau) (tau: the most recent cap's cut)
-    const double eps = std::max(obs->trunc.eps, tau);
+    // threshold (and cap) after every non-Clifford gate
+    const double eps = obs->trunc.eps;
     const bool has_noise = L->n_gen > 0;
     bool noise_done = false;
     if (has_noise && !L->noise_after_gates) {
@@ -1007,7 +1461,7 @@ struct Engine final : EngineBase {
         const uint64_t n = N;
         const GateDev* gd = gates_d.as<GateDev>();
         const int ng = (int)gv.size();
-        const size_t lds = ng * sizeof(GateDev) + (with_noise ? noise_lds_bytes(nd.ntab, nd.nsup) : 0);
+        const size_t lds = ng * sizeof(GateDev) + (with_noise ? noise_lds_bytes(nd) : 0);
         if (lds > 160 * 1024) throw_fail(PP_ERR_UNSUPPORTED, "gate and noise tables exceed LDS");
         if (lds > kNoiseLdsMax)
           HIPCHK(hipFuncSetAttribute((const void*)k_clifford<W, CT, ORD>,
@@ -1049,17 +1503,16 @@ struct Engine final : EngineBase {
             ndp = &nd;
             noise_done = true;
           }
-          grouped_pass(run, gm, kind, eps, ndp, eps, ls);
+          if (!grouped_pass(run, kind, eps, ndp, eps, ls)) noise_done = false;
+          else if (ndp && obs->trunc.max_terms > 0 && (int64_t)N > obs->trunc.max_terms)
+            cap_select((uint64_t)obs->trunc.max_terms, ls);   // the cap after the fused noise
           i = j;
         }
       }
     }
     if (has_noise && !noise_done) noise_step(L, ls);
-    const int64_t before_cap = (int64_t)N;
-    if (obs->trunc.max_terms > 0 && (int64_t)N > obs->trunc.max_terms) cap_select((uint64_t)obs->trunc.max_terms, ls);
-    ls.n_capped = before_cap - (int64_t)N;
     ls.n_out = (int64_t)N;
-    ls.n_peak = std::max(ls.n_peak, std::max(ls.n_in, before_cap));
+    ls.n_peak = std::max(ls.n_peak, std::max(ls.n_in, ls.n_out));
     obs->last = ls;
   }
 
@@ -1076,7 +1529,7 @@ struct Engine final : EngineBase {
     return (double)f;
   }
 
-  void cap_select(uint64_t K, pp_layer_stats& ls, bool layer_cap = true) {
+  void cap_select(uint64_t K, pp_layer_stats& ls) {
     if (N <= K) return;
     const int KB = sizeof(CT) == 8 ? 63 : 31;
     uint64_t prefix = 0, pmask = 0, need = K, count_eq = 0;
@@ -1111,9 +1564,10 @@ struct Engine final : EngineBase {
       pmask |= (uint64_t)(bins - 1) << shift;
       count_eq = h[d];
       hi = shift;
+      if (need == count_eq) break;   // the whole bucket is kept: the cut is its lower edge
     }
     const uint64_t tau_key = prefix;
-    if (layer_cap) tau = coef_from_bits_host(tau_key);
+    const uint64_t before = N;
     u32b.ensure(n * 4 + 64);
     u32c.ensure(n * 4 + 64);
     uint32_t* keep = u32b.as<uint32_t>();
@@ -1121,7 +1575,7 @@ struct Engine final : EngineBase {
     double* dd = &cnt_d.as<Counters>()->dropped;
     HIPCHK(hipMemsetAsync(dd, 0, 8, st));
     ctx->run("cap_flags", 0, (double)n, [&] {
-      hipLaunchKernelGGL((k_cap_flags<CT>), gridb(n), dim3(256), 0, st, c, n, tau_key, keep, tie, dd);
+      hipLaunchKernelGGL((k_cap_flags<CT>), gridb(n), dim3(256), 0, st, c, n, tau_key, pmask, keep, tie, dd);
     });
     ctx->check_launch();
     if (need >= count_eq) {
@@ -1161,6 +1615,7 @@ struct Engine final : EngineBase {
     sync();
     std::memcpy(&dropped, ctx->pinned, 8);
     ls.dropped_l1 += dropped;
+    ls.n_capped += (int64_t)(before - N);
   }
 
   void truncate(double eps, int64_t cap) override {
@@ -1176,7 +1631,7 @@ struct Engine final : EngineBase {
       ctx->check_launch();
       compact_cur(keep);
     }
-    if (cap > 0 && (int64_t)N > cap) cap_select((uint64_t)cap, ls, false);
+    if (cap > 0 && (int64_t)N > cap) cap_select((uint64_t)cap, ls);
   }
 
   double expectation(const uint64_t* basis) override {
@@ -1184,11 +1639,43 @@ struct Engine final : EngineBase {
     for (int w = 0; w < PP_MAXW; ++w) { b.mx[w] = 0; b.mz[w] = 0; }
     if (basis)
       for (int w = 0; w < W; ++w) b.mz[w] = basis[w];
-    const unsigned nb = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(1024, cdiv(N, 256)));
+    // Only diagonal strings contribute.  They are gathered and put in canonical order
+    // first, so the FP64 sum runs in an order fixed by the term set alone, and the value
+    // does not depend on where earlier kernels happened to place each term.
+    uint64_t n = 0;
+    if (N > 0) {
+      u32b.ensure(N * 4 + 64);
+      u32c.ensure(N * 4 + 64);
+      uint32_t* keep = u32b.as<uint32_t>();
+      uint32_t* pos = u32c.as<uint32_t>();
+      const Terms<CT> all = cur.view();
+      const uint64_t nall = N;
+      ctx->run("diag_flags", 0, (double)nall, [&] {
+        hipLaunchKernelGGL((k_diag_flags<W, CT>), grid1(nall), dim3(256), 0, st, all, nall, keep);
+      });
+      ctx->check_launch();
+      HIPCHK(hipMemcpyAsync(pos, keep, nall * 4, hipMemcpyDeviceToDevice, st));
+      scan_u32(pos, nall);
+      uint32_t lp = 0, lk = 0;
+      HIPCHK(hipMemcpyAsync(ctx->pinned, pos + nall - 1, 4, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync((char*)ctx->pinned + 4, keep + nall - 1, 4, hipMemcpyDeviceToHost, st));
+      sync();
+      std::memcpy(&lp, ctx->pinned, 4);
+      std::memcpy(&lk, (char*)ctx->pinned + 4, 4);
+      n = (uint64_t)lp + lk;
+      sa.ensure(std::max<uint64_t>(n, 1));
+      const Terms<CT> dg = sa.view();
+      ctx->run("compact", 0, (double)nall, [&] {
+        hipLaunchKernelGGL((k_compact<W, CT, ORD>), grid1(nall), dim3(256), 0, st, all, dg, nall,
+                           (const uint32_t*)keep, (const uint32_t*)pos);
+      });
+      ctx->check_launch();
+      canonical_sort(sa, sb, n);
+    }
+    const unsigned nb = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(1024, cdiv(n, 256)));
     partial_d.ensure(nb * 8 + 64);
     double* part = partial_d.as<double>();
-    const Terms<CT> t = cur.view();
-    const uint64_t n = N;
+    const Terms<CT> t = sa.view();
     double* outd = &cnt_d.as<Counters>()->dropped;
     ctx->run("expectation", kTermBytes * n, (double)n, [&] {
       hipLaunchKernelGGL((k_expect<W, CT>), dim3(nb), dim3(256), 0, st, t, n, b, part);

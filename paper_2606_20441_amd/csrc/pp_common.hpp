@@ -35,19 +35,23 @@ struct Terms {
 struct SupportDev {
   int16_t w0, b0, w1, b1;   // word/bit of the two qubits (w1 < 0: single qubit)
   int32_t table;            // offset into the value table
+  int16_t nslot;            // greedy mode: factor slots per pattern
+  int16_t pad;
 };
 
 struct NoiseDev {
   int nsup;
   int ndirect;
   int ntab;                 // doubles in `tab`
+  int nidx;                 // greedy mode: entries of `fidx`
   int sign;                 // +1 inverse map, -1 channel
   int mode;                 // 0 greedy, 1 error order
   int max_order;
   const SupportDev* sup;
-  const double* tab;        // greedy: 1 value per pattern; error order: 2 values per pattern
+  const double* tab;        // greedy: one fidelity factor per generator, then 1.0; error order: max_order power sums per pattern
+  const uint16_t* fidx;     // greedy: per support and pattern, nslot indices into tab (padding: the 1.0)
   const uint64_t* dm;       // direct generators: [ndirect][2W]
-  const double* dval;       // greedy: lambda; error order: (x_k, x_k^2) pairs
+  const double* dval;       // greedy: fidelity factor; error order: max_order powers of x_k
 };
 
 __device__ __forceinline__ int popc64(uint64_t v) { return __popcll(v); }

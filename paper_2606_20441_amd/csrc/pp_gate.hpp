@@ -1,0 +1,395 @@
+// pp_gate.hpp -- one rotation over persistent tiles, with the truncation of the previous
+// gate applied on load (gfx950).
+//
+// When the cap (keep the largest K_O terms, Section I.A) binds after every non-Clifford
+// gate, each gate needs a device-wide selection before the next one can start.  The
+// terms are grouped once per run of gates by a hash of the bits no gate of the run changes,
+// and cut into tiles of whole groups.  Every gate is then one pass over the same tiles:
+// a workgroup loads its tile, drops the terms below the previous gate's cut, pairs each
+// anticommuting string with its partner through an LDS hash table, applies the cos/sin
+// branching (Section I, Eq. evolve_gate, and the Euclid appendix's backward rule), drops
+// |c| < eps, and writes its survivors back as one contiguous range, which is the same
+// tile at the next gate.  A per-term 32-bit hash (GF(2)-linear in the string, so a
+// partner's hash is one XOR away) travels with the terms.
+#pragma once
+
+#include "pp_common.hpp"
+#include "pp_layer.hpp"
+#include "pp_misc.hpp"
+
+namespace pp {
+
+constexpr int kDropSlots = 64;   // spread accumulators: one address per workgroup is a serial queue
+
+template <class CT>
+struct Gate1Args {
+  Terms<CT> in;
+  Terms<CT> out;
+  const uint32_t* hin;          // per-term hash of `in`
+  uint32_t* hout;               // per-term hash of `out`
+  const uint32_t* t_start;      // tile ranges in `in`
+  const uint32_t* t_len;
+  const uint32_t* t_list;       // optional: blockIdx.x -> tile
+  const uint32_t* o_base;       // start of each tile's output region (2 * t_len slots)
+  uint32_t* o_start;            // tile ranges in `out` (same tile index)
+  uint32_t* o_len;
+  int zero_on_ovf;              // a tile that does not fit zeroes its region (nobody retries it here)
+  GateDev g;
+  double eps;                   // threshold after the gate (0: none)
+  int has_cut;                  // drop terms whose (|c| key & cut_mask) < cut_key on load
+  uint64_t cut_key;
+  uint64_t cut_mask;
+  uint32_t* ovf_tiles;          // tiles that did not fit in LDS
+  uint32_t* ovf_count;
+  double* dropped;              // [kDropSlots]: sum of |c| removed (cut and threshold)
+  uint32_t* big_count;          // tiles whose output exceeds big_hint terms
+  uint32_t big_hint;
+};
+
+// A tile handed to another path: its output region is left empty (c = 0, length 0).
+template <class CT>
+__device__ void zero_region(const Gate1Args<CT>& a, uint32_t tile, uint32_t n0) {
+  const uint64_t base = a.o_base[tile];
+  if (threadIdx.x == 0) {
+    a.o_start[tile] = (uint32_t)base;
+    a.o_len[tile] = 0;
+  }
+  for (uint64_t i = base + threadIdx.x; i < base + 2ULL * n0; i += blockDim.x) a.out.c[i] = (CT)0;
+}
+
+// A tile copied through with only the pending cut applied (order kept).
+template <int W, class CT, bool ORD, int BLOCK>
+__device__ void pass_through(const Gate1Args<CT>& a, uint32_t tile, uint32_t t0, uint32_t n0) {
+  constexpr int NW = BLOCK / 64;
+  __shared__ uint32_t p_wsum[NW];
+  __shared__ double p_drop[NW];
+  const int tid = threadIdx.x, lane = tid & 63;
+  auto keep = [&](uint64_t src) {
+    const CT v = a.in.c[src];
+    return v != (CT)0 && !(a.has_cut && (abs_key<CT>(v) & a.cut_mask) < a.cut_key);
+  };
+  // count survivors per contiguous chunk of the tile
+  const uint32_t chunk = (n0 + BLOCK - 1) / BLOCK;
+  const uint32_t lo = tid * chunk < n0 ? tid * chunk : n0;
+  const uint32_t hi = lo + chunk < n0 ? lo + chunk : n0;
+  uint32_t cnt = 0;
+  double lost = 0.0;
+  for (uint32_t i = lo; i < hi; ++i) {
+    if (keep((uint64_t)t0 + i)) ++cnt;
+    else lost += fabs((double)a.in.c[(uint64_t)t0 + i]);
+  }
+  uint32_t incl = cnt;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t v = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += v;
+  }
+  for (int d = 32; d >= 1; d >>= 1) lost += __shfl_xor(lost, d, 64);
+  if (lane == 63) p_wsum[tid >> 6] = incl;
+  if (lane == 0) p_drop[tid >> 6] = lost;
+  __syncthreads();
+  uint32_t before = 0, total = 0;
+  for (int w = 0; w < NW; ++w) {
+    before += (w < (tid >> 6)) ? p_wsum[w] : 0u;
+    total += p_wsum[w];
+  }
+  const uint64_t base = a.o_base[tile];
+  if (tid == 0) {
+    a.o_start[tile] = (uint32_t)base;
+    a.o_len[tile] = total;
+    double v = 0.0;
+    for (int w = 0; w < NW; ++w) v += p_drop[w];
+    if (v != 0.0) atomicAdd(&a.dropped[blockIdx.x % kDropSlots], v);
+    if (total > a.big_hint) atomicAdd(a.big_count, 1u);
+  }
+  for (uint64_t i = base + total + tid; i < base + 2ULL * n0; i += BLOCK) a.out.c[i] = (CT)0;
+  uint64_t dst = base + before + incl - cnt;
+  for (uint32_t i = lo; i < hi; ++i) {
+    const uint64_t src = (uint64_t)t0 + i;
+    if (!keep(src)) continue;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      a.out.x[w * a.out.stride + dst] = a.in.x[w * a.in.stride + src];
+      a.out.z[w * a.out.stride + dst] = a.in.z[w * a.in.stride + src];
+    }
+    a.out.c[dst] = a.in.c[src];
+    if (ORD) a.out.o[dst] = a.in.o[src];
+    a.hout[dst] = a.hin[src];
+    ++dst;
+  }
+}
+
+template <int W, class CT, bool ORD, int CAP, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
+  constexpr int R = CAP / BLOCK;
+  constexpr int H = 2 * CAP;
+  constexpr int NW = BLOCK / 64;
+  constexpr uint32_t EMPTY = 0xffffffffu;
+  __shared__ uint64_t sx[W][CAP];
+  __shared__ uint64_t sz[W][CAP];
+  __shared__ CT sc[CAP];
+  __shared__ uint32_t sh[CAP];
+  __shared__ uint8_t so[ORD ? CAP : 1];
+  __shared__ uint32_t hidx[H];
+  __shared__ uint32_t s_new, s_ovf;
+  __shared__ uint32_t s_wsum[NW];
+  __shared__ double s_drop[NW];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const uint32_t tile = a.t_list ? a.t_list[blockIdx.x] : blockIdx.x;
+  const uint32_t t0 = a.t_start[tile];
+  const uint32_t n0 = a.t_len[tile];
+  if (n0 > (uint32_t)CAP) {
+    // Too large for LDS.  If no term of the tile anticommutes with the gate, the tile
+    // passes through unchanged apart from the pending cut; otherwise it is reported.
+    __shared__ uint32_t s_any;
+    if (tid == 0) s_any = 0;
+    __syncthreads();
+    bool any = false;
+    for (uint32_t i = tid; i < n0 && !any; i += BLOCK) {
+      uint64_t kx[W], kz[W], mm[2 * W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        kx[w] = a.in.x[w * a.in.stride + t0 + i];
+        kz[w] = a.in.z[w * a.in.stride + t0 + i];
+      }
+#pragma unroll
+      for (int w = 0; w < 2 * W; ++w) mm[w] = a.g.m[w];
+      any = anticommutes<W>(kx, kz, mm) != 0;
+    }
+    if (any) s_any = 1;
+    __syncthreads();
+    if (s_any || BLOCK < 256) {
+      if (tid == 0) a.ovf_tiles[atomicAdd(a.ovf_count, 1u)] = tile;
+      if (a.zero_on_ovf) zero_region(a, tile, n0);
+      return;
+    }
+    pass_through<W, CT, ORD, BLOCK>(a, tile, t0, n0);
+    return;
+  }
+  for (int j = tid; j < H; j += BLOCK) hidx[j] = EMPTY;
+  if (tid == 0) { s_new = 0; s_ovf = 0; }
+  __syncthreads();
+
+  uint64_t m[2 * W];
+#pragma unroll
+  for (int w = 0; w < 2 * W; ++w) m[w] = a.g.m[w];
+  const double cs = a.g.cs, snd = a.g.sn_dir;
+  const uint32_t gh = a.g.hash;
+  const int pw = a.g.pivot_word, pb = a.g.pivot_bit;
+
+  // ---- load, cut, insert -----------------------------------------------------------------------
+  double lost = 0.0;
+  uint64_t rkx[R][W], rkz[R][W];
+  uint32_t rh[R];
+  double rc[R];
+  uint32_t ro[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t i = (uint32_t)r * BLOCK + tid;
+    rc[r] = 0.0;
+    rh[r] = 0;
+    ro[r] = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) { rkx[r][w] = 0; rkz[r][w] = 0; }
+    if (i >= n0) continue;
+    const uint64_t src = (uint64_t)t0 + i;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      rkx[r][w] = a.in.x[w * a.in.stride + src];
+      rkz[r][w] = a.in.z[w * a.in.stride + src];
+      sx[w][i] = rkx[r][w];
+      sz[w][i] = rkz[r][w];
+    }
+    const CT cv = a.in.c[src];
+    double c = (double)cv;
+    if (c != 0.0 && a.has_cut && (abs_key<CT>(cv) & a.cut_mask) < a.cut_key) {
+      lost += fabs(c);
+      c = 0.0;
+    }
+    rc[r] = c;
+    rh[r] = a.hin[src];
+    sh[i] = rh[r];
+    if (ORD) { ro[r] = a.in.o[src]; so[i] = (uint8_t)ro[r]; }
+    sc[i] = (CT)c;
+    if (c != 0.0) {
+      uint32_t slot = (rh[r] ^ (ro[r] * 0x9e3779b9u)) & (H - 1);
+      while (atomicCAS(&hidx[slot], EMPTY, i) != EMPTY) slot = (slot + 1) & (H - 1);
+    }
+  }
+  __syncthreads();
+
+  // ---- the gate ----------------------------------------------------------------------------------
+  const bool nonclifford = cs != 0.0 && snd != 0.0;
+  const double thr = a.eps;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t i = (uint32_t)r * BLOCK + tid;
+    if (i >= n0 || rc[r] == 0.0) continue;
+    if (!anticommutes<W>(rkx[r], rkz[r], m)) continue;
+    const double ci = rc[r];
+    if (snd == 0.0) {            // cos = +-1, sin = 0: a sign, no branching
+      sc[i] = (CT)(ci * cs);
+      continue;
+    }
+    const bool neg_i = irp_negative<W>(rkx[r], rkz[r], m, a.g.rr_phase);
+    uint64_t qx[W], qz[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) { qx[w] = rkx[r][w] ^ m[w]; qz[w] = rkz[r][w] ^ m[W + w]; }
+    if (cs == 0.0) {             // sin = +-1: P -> +-iRP in place (a permutation of strings)
+#pragma unroll
+      for (int w = 0; w < W; ++w) { sx[w][i] = qx[w]; sz[w][i] = qz[w]; }
+      sh[i] = rh[r] ^ gh;
+      sc[i] = (CT)((neg_i ? -ci : ci) * snd);
+      continue;
+    }
+    // non-Clifford: find the partner string (same order tag) in the tile
+    const uint32_t hq = rh[r] ^ gh;
+    uint32_t slot = (hq ^ (ro[r] * 0x9e3779b9u)) & (H - 1);
+    uint32_t j = EMPTY;
+    for (;;) {
+      const uint32_t k = hidx[slot];
+      if (k == EMPTY) break;
+      if (sh[k] == hq) {
+        bool eq = !ORD || so[k] == ro[r];
+#pragma unroll
+        for (int w = 0; w < W; ++w) eq = eq && sx[w][k] == qx[w] && sz[w][k] == qz[w];
+        if (eq) { j = k; break; }
+      }
+      slot = (slot + 1) & (H - 1);
+    }
+    if (j != EMPTY) {
+      // both present: the member with the pivot bit clear updates the pair
+      const uint64_t pv = pw < W ? pick<W>(rkx[r], pw) : pick<W>(rkz[r], pw - W);
+      if ((pv >> pb) & 1ULL) continue;
+      const double cj = (double)sc[j];
+      const bool neg_j = irp_negative<W>(qx, qz, m, a.g.rr_phase);
+      double ni = ci * cs + (neg_j ? -cj : cj) * snd;
+      double nj = cj * cs + (neg_i ? -ci : ci) * snd;
+      if (fabs(ni) < thr || ni == 0.0) { lost += fabs(ni); ni = 0.0; }
+      if (fabs(nj) < thr || nj == 0.0) { lost += fabs(nj); nj = 0.0; }
+      sc[i] = (CT)ni;
+      sc[j] = (CT)nj;
+    } else {
+      double ni = ci * cs;
+      const double nq = (neg_i ? -ci : ci) * snd;
+      if (fabs(ni) < thr || ni == 0.0) { lost += fabs(ni); ni = 0.0; }
+      sc[i] = (CT)ni;
+      if (fabs(nq) < thr || nq == 0.0) {
+        lost += fabs(nq);
+      } else {
+        const uint32_t k = n0 + atomicAdd(&s_new, 1u);
+        if (k < (uint32_t)CAP) {
+#pragma unroll
+          for (int w = 0; w < W; ++w) { sx[w][k] = qx[w]; sz[w][k] = qz[w]; }
+          sh[k] = hq;
+          if (ORD) so[k] = (uint8_t)ro[r];
+          sc[k] = (CT)nq;
+        } else {
+          s_ovf = 1;
+        }
+      }
+    }
+  }
+  (void)nonclifford;
+  __syncthreads();
+  if (s_ovf) {
+    if (tid == 0) a.ovf_tiles[atomicAdd(a.ovf_count, 1u)] = tile;
+    if (a.zero_on_ovf) zero_region(a, tile, n0);
+    return;
+  }
+  const uint32_t n = n0 + s_new;
+
+  // ---- compact and write -----------------------------------------------------------------------
+  // thread tid owns entries [tid * R, tid * R + R): contiguous ranks keep the tile's order
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t i = (uint32_t)tid * R + r;
+    cnt += (i < n && sc[i] != (CT)0) ? 1u : 0u;
+  }
+  uint32_t incl = cnt;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t v = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += v;
+  }
+  double lsum = lost;
+  for (int d = 32; d >= 1; d >>= 1) lsum += __shfl_xor(lsum, d, 64);
+  if (lane == 63) s_wsum[tid >> 6] = incl;
+  if (lane == 0) s_drop[tid >> 6] = lsum;
+  __syncthreads();
+  uint32_t before = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    before += (w < (tid >> 6)) ? s_wsum[w] : 0u;
+    total += s_wsum[w];
+  }
+  // the tile's output region holds 2 * n0 slots (a gate at most doubles a tile); unused
+  // slots get a zero coefficient so that sweeps over the whole buffer skip them
+  const uint64_t base = a.o_base[tile];
+  if (tid == 0) {
+    a.o_start[tile] = (uint32_t)base;
+    a.o_len[tile] = total;
+    if (total > a.big_hint) atomicAdd(a.big_count, 1u);
+    double v = 0.0;
+    for (int w = 0; w < NW; ++w) v += s_drop[w];
+    if (v != 0.0) atomicAdd(&a.dropped[blockIdx.x % kDropSlots], v);
+  }
+  for (uint64_t i = base + total + tid; i < base + 2ULL * n0; i += BLOCK) a.out.c[i] = (CT)0;
+  uint32_t rank = before + incl - cnt;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t i = (uint32_t)tid * R + r;
+    if (i >= n || sc[i] == (CT)0) continue;
+    const uint64_t dst = base + rank++;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      a.out.x[w * a.out.stride + dst] = sx[w][i];
+      a.out.z[w * a.out.stride + dst] = sz[w][i];
+    }
+    a.out.c[dst] = sc[i];
+    if (ORD) a.out.o[dst] = so[i];
+    a.hout[dst] = sh[i];
+  }
+}
+
+// Per-term linear hash of the string (order tag not included).
+template <int W, class CT>
+__global__ void k_hash_plane(Terms<CT> t, uint64_t n, const uint32_t* htab, uint32_t* h) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t kx[W], kz[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) { kx[w] = t.x[w * t.stride + i]; kz[w] = t.z[w * t.stride + i]; }
+  h[i] = lin_hash<W>(kx, kz, htab);
+}
+
+// v[t] = 2 * len[t] (output region sizes; an exclusive scan turns them into bases).
+__global__ void k_double_len(const uint32_t* len, uint32_t ntiles, uint32_t* v) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < ntiles) v[t] = 2u * len[t];
+}
+
+// Tile ranges from tile starts ([ntiles + 1] prefix form).
+__global__ void k_tile_ranges(const uint32_t* starts, uint32_t ntiles, uint32_t* start, uint32_t* len) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  start[t] = starts[t];
+  len[t] = starts[t + 1] - starts[t];
+}
+
+// keep[i] = the term survives the pending cut (and is not an exact zero).
+template <class CT>
+__global__ void k_cut_keep(const CT* c, uint64_t n, uint64_t cut_key, uint64_t cut_mask, uint32_t* keep,
+                           double* dropped) {
+  double lost = 0.0;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const CT v = c[i];
+    const bool k = v != (CT)0 && (abs_key<CT>(v) & cut_mask) >= cut_key;
+    keep[i] = k ? 1u : 0u;
+    if (!k) lost += fabs((double)v);
+  }
+  add_dropped(lost, dropped);
+}
+
+}  // namespace pp

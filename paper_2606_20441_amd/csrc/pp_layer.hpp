@@ -55,6 +55,7 @@ struct LayerArgs {
   uint32_t* ovf_count;
   double* dropped;              // sum of |c| removed by thresholds
   unsigned int* peak;           // largest live count seen in a tile
+  unsigned long long* peak_sum; // sum over tiles of each tile's largest live count during the gates
 };
 
 // Compact per-W gate record staged in LDS by the fused kernel.
@@ -147,6 +148,32 @@ __device__ __forceinline__ void noise_sums(const uint64_t* px, const uint64_t* p
   }
 }
 
+// Greedy-mode factor of a string: the product, over the generators that anticommute with
+// it, of their fidelity factors 1 - 2q_k (Eq. evolve_noise), multiplied one at a time in
+// generator-list order.  Supports are listed in that order with their generators'
+// factor indices in per-pattern slots (padding points at a 1.0, an exact no-op);
+// generators handled directly come after them.
+template <int W>
+__device__ __forceinline__ double noise_factor(const uint64_t* px, const uint64_t* pz, const double* tab,
+                                               const uint16_t* fidx, const SupportDev* sup, const NoiseDev& nd) {
+  double prod = 1.0;
+  for (int s = 0; s < nd.nsup; ++s) {
+    const SupportDev sp = sup[s];
+    uint32_t pat = (uint32_t)((pick<W>(px, sp.w0) >> sp.b0) & 1u) | (uint32_t)(((pick<W>(pz, sp.w0) >> sp.b0) & 1u) << 1);
+    if (sp.w1 >= 0)
+      pat |= (uint32_t)(((pick<W>(px, sp.w1) >> sp.b1) & 1u) << 2) | (uint32_t)(((pick<W>(pz, sp.w1) >> sp.b1) & 1u) << 3);
+    if (pat) {
+      const uint16_t* f = fidx + sp.table + (size_t)pat * sp.nslot;
+      for (int j = 0; j < sp.nslot; ++j) prod *= tab[f[j]];
+    }
+  }
+  for (int d = 0; d < nd.ndirect; ++d) {
+    const uint64_t* m = nd.dm + (size_t)d * 2 * W;
+    if (anticommutes<W>(px, pz, m)) prod *= nd.dval[d];
+  }
+  return prod;
+}
+
 // Elementary symmetric sums e_0..e_M of the anticommuting x_k from power sums (Newton).
 __device__ __forceinline__ void elementary_from_power(const double* p, int M, double* e) {
   e[0] = 1.0;
@@ -179,6 +206,8 @@ __global__ void __launch_bounds__(BLOCK) k_layer(LayerArgs<CT> a) {
   __shared__ uint32_t hidx[H];       // (16-bit fingerprint << 16) | entry index, or EMPTY
   __shared__ uint32_t s_cnt[3];      // appends of processed gate k land in s_cnt[k % 3]
   __shared__ uint32_t s_dead[3];     // entries zeroed by processed gate k
+  __shared__ int s_ldelta[3];        // change of the live count by processed gate k (appends aside)
+  __shared__ uint32_t s_tdrop;       // entries zeroed by the tile-wide threshold (cumulative)
   __shared__ uint32_t s_ovf;
   __shared__ unsigned long long s_or[2 * W];
   __shared__ uint32_t stmp[BLOCK / 64];
@@ -265,8 +294,8 @@ __global__ void __launch_bounds__(BLOCK) k_layer(LayerArgs<CT> a) {
   }
   for (uint32_t j = tid; j < (uint32_t)H; j += BLOCK) hidx[j] = EMPTY;
   if (tid < 2 * W) s_or[tid] = 0;
-  if (tid < 3) { s_cnt[tid] = 0; s_dead[tid] = 0; }
-  if (tid == 0) s_ovf = 0;
+  if (tid < 3) { s_cnt[tid] = 0; s_dead[tid] = 0; s_ldelta[tid] = 0; }
+  if (tid == 0) { s_ovf = 0; s_tdrop = 0; }
   __syncthreads();
 #pragma unroll
   for (int w = 0; w < 2 * W; ++w) {
@@ -285,6 +314,9 @@ __global__ void __launch_bounds__(BLOCK) k_layer(LayerArgs<CT> a) {
 
   uint32_t n = n0;
   uint32_t peak = n0;
+  uint32_t live_peak = n0;   // largest count of live entries after any gate
+  int64_t live = n0;         // entries with c != 0 (exact: every change is counted)
+  uint32_t tdrop_seen = 0;
   uint32_t dead = 0;
   double dropped = 0.0;
   bool thresholded_all = false;
@@ -379,7 +411,12 @@ __global__ void __launch_bounds__(BLOCK) k_layer(LayerArgs<CT> a) {
         }
       }
     }
+    int ndw = nd;
+    for (int d = 32; d >= 1; d >>= 1) ndw += __shfl_xor(ndw, d, 64);
+    if ((tid & 63) == 0 && ndw) atomicAdd(&s_tdrop, (uint32_t)ndw);
     if (__syncthreads_or(nd)) dead += 1;   // barrier; zeros now exist, so compaction may run
+    live -= (int64_t)(s_tdrop - tdrop_seen);
+    tdrop_seen = s_tdrop;
   };
 
   // One gate over the tile: stage 1 tests anticommutation and prefetches the partner's first
@@ -462,6 +499,7 @@ __global__ void __launch_bounds__(BLOCK) k_layer(LayerArgs<CT> a) {
     bool app[R];
     double childv[R];
     uint32_t zeroed = 0;
+    int dl = 0;   // live-count change from updates in place
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       app[r] = false;
@@ -485,6 +523,7 @@ __global__ void __launch_bounds__(BLOCK) k_layer(LayerArgs<CT> a) {
           dropped += fabs(ni);
           ni = 0.0;
           ++zeroed;
+          --dl;
         }
         sc[i] = (CT)ni;
         if (!(fabs(child) < thr) && child != 0.0) {
@@ -510,6 +549,7 @@ __global__ void __launch_bounds__(BLOCK) k_layer(LayerArgs<CT> a) {
           if (cp != 0.0) ++zeroed;
           np = 0.0;
         }
+        dl += (ni != 0.0) - (c != 0.0) + (np != 0.0) - (cp != 0.0);
         sc[i] = (CT)ni;
         sc[p] = (CT)np;
       }
@@ -547,6 +587,8 @@ __global__ void __launch_bounds__(BLOCK) k_layer(LayerArgs<CT> a) {
     uint32_t zs = zeroed;
     for (int d = 32; d >= 1; d >>= 1) zs += __shfl_xor(zs, d, 64);
     if (lane == 0 && zs) atomicAdd(&s_dead[slot], zs);
+    for (int d = 32; d >= 1; d >>= 1) dl += __shfl_xor(dl, d, 64);
+    if (lane == 0 && dl) atomicAdd(&s_ldelta[slot], dl);
   };
 
   // ---- gates: one pass and one barrier per gate ------------------------------------------------
@@ -573,7 +615,7 @@ __global__ void __launch_bounds__(BLOCK) k_layer(LayerArgs<CT> a) {
       reload(0, n);
     }
     const int slot = gi % 3;
-    if (tid == 0) { s_cnt[(gi + 1) % 3] = 0; s_dead[(gi + 1) % 3] = 0; }
+    if (tid == 0) { s_cnt[(gi + 1) % 3] = 0; s_dead[(gi + 1) % 3] = 0; s_ldelta[(gi + 1) % 3] = 0; }
     ++gi;
     if (G.type == GATE_X1) gate_pass(std::integral_constant<int, GATE_X1>{}, G, n);
     else if (G.type == GATE_ZZ) gate_pass(std::integral_constant<int, GATE_ZZ>{}, G, n);
@@ -586,9 +628,11 @@ __global__ void __launch_bounds__(BLOCK) k_layer(LayerArgs<CT> a) {
     const uint32_t n_old = n;
     n += s_cnt[slot];
     dead += s_dead[slot];
+    live += (int64_t)s_cnt[slot] + s_ldelta[slot];
     peak = n > peak ? n : peak;
     if (n > n_old) reload(n_old, n);
     if (!clifford && !thresholded_all) threshold_all();
+    live_peak = live > (int64_t)live_peak ? (uint32_t)live : live_peak;
   }
   if (a.any_nonclifford && !thresholded_all) threshold_all();
 
@@ -603,9 +647,7 @@ __global__ void __launch_bounds__(BLOCK) k_layer(LayerArgs<CT> a) {
         if (c == 0.0) continue;
         uint64_t kx[W], kz[W];
         load_key(i, kx, kz);
-        double p[kMaxPowerSums];
-        noise_sums<W>(kx, kz, nd, 1, p);
-        sc[i] = (CT)(c * exp(2.0 * nd.sign * p[0]));
+        sc[i] = (CT)(c * noise_factor<W>(kx, kz, nd.tab, nd.fidx, nd.sup, nd));
       }
       __syncthreads();
     } else if (ORD) {
@@ -705,6 +747,7 @@ __global__ void __launch_bounds__(BLOCK) k_layer(LayerArgs<CT> a) {
     for (int w = 0; w < BLOCK / 64; ++w) v += s_drop[w];
     if (v != 0.0) atomicAdd(a.dropped, v);
     atomicMax(a.peak, peak);
+    if (a.peak_sum) atomicAdd(a.peak_sum, (unsigned long long)live_peak);
   }
   for (uint32_t i = tid; i < n; i += BLOCK) {
     const uint64_t j = base + i;
@@ -745,32 +788,15 @@ __global__ void k_tiles(Terms<CT> t, uint64_t n, GroupMask gm, uint64_t kmask, u
 // Elementwise kernels.
 // ------------------------------------------------------------------------------------------
 // Bytes of LDS a noise descriptor needs when staged (table, then supports).
-inline size_t noise_lds_bytes(int ntab, int nsup) {
-  return (size_t)ntab * sizeof(double) + (size_t)nsup * sizeof(SupportDev);
+inline size_t noise_lds_bytes(const NoiseDev& nd) {
+  return (size_t)nd.ntab * sizeof(double) + (size_t)nd.nsup * sizeof(SupportDev) +
+         (((size_t)nd.nidx * sizeof(uint16_t) + 15) & ~(size_t)15);
 }
 constexpr size_t kNoiseLdsMax = 64 * 1024;
 
-// Greedy-mode rescale with the support tables staged in LDS: the exponent is a sum of one
-// table value per support (one or two qubits) plus the generators with larger support.
-template <int W>
-__device__ __forceinline__ double noise_exponent_lds(const uint64_t* px, const uint64_t* pz, const double* stab,
-                                                     const SupportDev* ssup, const NoiseDev& nd) {
-  double acc = 0.0;
-  for (int s = 0; s < nd.nsup; ++s) {
-    const SupportDev sp = ssup[s];
-    uint32_t pat = (uint32_t)((pick<W>(px, sp.w0) >> sp.b0) & 1u) | (uint32_t)(((pick<W>(pz, sp.w0) >> sp.b0) & 1u) << 1);
-    if (sp.w1 >= 0)
-      pat |= (uint32_t)(((pick<W>(px, sp.w1) >> sp.b1) & 1u) << 2) | (uint32_t)(((pick<W>(pz, sp.w1) >> sp.b1) & 1u) << 3);
-    acc += stab[sp.table + pat];   // pattern 0 (identity on the support) holds 0
-  }
-  for (int d = 0; d < nd.ndirect; ++d) {
-    const uint64_t* m = nd.dm + (size_t)d * 2 * W;
-    if (anticommutes<W>(px, pz, m)) acc += nd.dval[d];
-  }
-  return acc;
-}
-
-__device__ __forceinline__ void stage_noise(const NoiseDev& nd, double* stab, SupportDev* ssup) {
+// LDS layout of a staged noise descriptor: tab (doubles), supports, factor indices.
+__device__ __forceinline__ void stage_noise(const NoiseDev& nd, double* stab, SupportDev* ssup, uint16_t* sidx) {
+  for (int j = threadIdx.x; j < nd.nidx; j += blockDim.x) sidx[j] = nd.fidx[j];
   for (int j = threadIdx.x; j < nd.ntab; j += blockDim.x) stab[j] = nd.tab[j];
   for (int j = threadIdx.x; j < nd.nsup; j += blockDim.x) ssup[j] = nd.sup[j];
 }
@@ -785,8 +811,9 @@ __global__ void __launch_bounds__(256) k_clifford(Terms<CT> t, uint64_t n, const
   GateDev* sg = (GateDev*)dsm;
   double* stab = (double*)(sg + ngates);
   SupportDev* ssup = (SupportDev*)(stab + (has_noise ? nd.ntab : 0));
+  uint16_t* sidx = (uint16_t*)(ssup + (has_noise ? nd.nsup : 0));
   for (int j = threadIdx.x; j < ngates; j += blockDim.x) sg[j] = gates[j];
-  if (has_noise) stage_noise(nd, stab, ssup);
+  if (has_noise) stage_noise(nd, stab, ssup, sidx);
   __syncthreads();
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
     uint64_t kx[W], kz[W];
@@ -808,7 +835,7 @@ __global__ void __launch_bounds__(256) k_clifford(Terms<CT> t, uint64_t n, const
         for (int w = 0; w < W; ++w) { kx[w] ^= m[w]; kz[w] ^= m[W + w]; }
       }
     }
-    if (has_noise) c = c * exp(2.0 * nd.sign * noise_exponent_lds<W>(kx, kz, stab, ssup, nd));
+    if (has_noise) c = c * noise_factor<W>(kx, kz, stab, sidx, ssup, nd);
 #pragma unroll
     for (int w = 0; w < W; ++w) { t.x[w * t.stride + i] = kx[w]; t.z[w * t.stride + i] = kz[w]; }
     t.c[i] = (CT)c;
@@ -820,14 +847,15 @@ __global__ void __launch_bounds__(256) k_noise_greedy(Terms<CT> t, uint64_t n, N
   extern __shared__ double dsm[];
   double* stab = dsm;
   SupportDev* ssup = (SupportDev*)(stab + nd.ntab);
-  stage_noise(nd, stab, ssup);
+  uint16_t* sidx = (uint16_t*)(ssup + nd.nsup);
+  stage_noise(nd, stab, ssup, sidx);
   __syncthreads();
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
     uint64_t kx[W], kz[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) { kx[w] = t.x[w * t.stride + i]; kz[w] = t.z[w * t.stride + i]; }
     const double c = (double)t.c[i];
-    t.c[i] = (CT)(c * exp(2.0 * nd.sign * noise_exponent_lds<W>(kx, kz, stab, ssup, nd)));
+    t.c[i] = (CT)(c * noise_factor<W>(kx, kz, stab, sidx, ssup, nd));
   }
 }
 

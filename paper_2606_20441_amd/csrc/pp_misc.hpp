@@ -250,12 +250,14 @@ __global__ void __launch_bounds__(256) k_abs_hist(const CT* c, uint64_t n, int s
     if (h[b]) atomicAdd(&hist[b], h[b]);
 }
 
-// keep: |c| > tau, or |c| == tau and marked; ties flagged for the tie-break list
+// keep: |c| > tau, or |c| == tau and marked; ties flagged for the tie-break list.  Only the
+// key bits in pmask take part (the selection may stop at a bucket that is kept whole).
 template <class CT>
-__global__ void k_cap_flags(const CT* c, uint64_t n, uint64_t tau, uint32_t* keep, uint32_t* tie, double* dropped) {
+__global__ void k_cap_flags(const CT* c, uint64_t n, uint64_t tau, uint64_t pmask, uint32_t* keep, uint32_t* tie,
+                            double* dropped) {
   double lost = 0.0;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t k = abs_key<CT>(c[i]);
+    const uint64_t k = abs_key<CT>(c[i]) & pmask;
     keep[i] = k > tau ? 1u : 0u;
     tie[i] = k == tau ? 1u : 0u;
     lost += k < tau ? fabs((double)c[i]) : 0.0;
@@ -311,6 +313,17 @@ __global__ void __launch_bounds__(256) k_expect(Terms<CT> t, uint64_t n, GroupMa
   if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0) partial[blockIdx.x] = (s[0] + s[1]) + (s[2] + s[3]);
+}
+
+// keep[i] = 1 for diagonal strings (x = 0): the only ones with a nonzero <b|P|b>.
+template <int W, class CT>
+__global__ void k_diag_flags(Terms<CT> t, uint64_t n, uint32_t* keep) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t any = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) any |= t.x[w * t.stride + i];
+  keep[i] = any == 0;
 }
 
 __global__ void k_sum_partials(const double* partial, int nb, double* out) {

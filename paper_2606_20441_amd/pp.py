@@ -143,24 +143,39 @@ def _words(a, w: int) -> np.ndarray:
 class Context:
     """A device, a HIP stream and (optionally) PyTorch's caching allocator."""
 
-    def __init__(self, device: int = 0, stream=None, torch_allocator: bool = True):
+    def __init__(self, device: int = 0, stream=None, torch_allocator: bool = True,
+                 limit_bytes: Optional[int] = None):
+        """`limit_bytes` (torch allocator only) caps the device bytes this context may hold at
+        once; an allocation beyond it fails, and the library reports PP_ERR_OOM."""
         import torch
         self.device = device
         self._torch_stream = stream if stream is not None else torch.cuda.current_stream(device)
         handle = C.c_void_p(self._torch_stream.cuda_stream)
         self._alloc_cb = None
         self._release_cb = None
+        self.limit_bytes = limit_bytes
+        self.live_bytes = 0
+        self.peak_bytes = 0
+        self._sizes = {}
         if torch_allocator:
             dev = torch.device("cuda", device)
             st = self._torch_stream
 
             def _alloc(nbytes, _user):
+                nbytes = int(nbytes)
+                if self.limit_bytes is not None and self.live_bytes + nbytes > self.limit_bytes:
+                    return None
                 try:
-                    return int(torch.cuda.caching_allocator_alloc(int(nbytes), dev, st))
+                    p = int(torch.cuda.caching_allocator_alloc(nbytes, dev, st))
                 except Exception:
                     return None
+                self._sizes[p] = nbytes
+                self.live_bytes += nbytes
+                self.peak_bytes = max(self.peak_bytes, self.live_bytes)
+                return p
 
             def _release(p, _user):
+                self.live_bytes -= self._sizes.pop(int(p), 0)
                 torch.cuda.caching_allocator_delete(int(p))
 
             self._alloc_cb = ALLOC_FN(_alloc)
