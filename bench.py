@@ -178,6 +178,23 @@ def cpu_baseline(wl, budget_s=15.0):
             "sample": f"first {done} of {len(calls)} layer calls of the same propagation ({upd} term-updates, {dt:.1f} s)"}
 
 
+def run_serving(n_requests: int, rate_hz: float, n_slots: int, warmup: int):
+    """The serving form: a seeded Poisson stream of mixed propagation requests replayed
+    against the wall clock; latency is arrival to result."""
+    from paper_2606_20441_amd import serve, workloads as W
+    reqs = W.serving_stream(n_requests + warmup, rate_hz=rate_hz)
+    srv = serve.Server(n_slots=n_slots, hbm_budget_bytes=200 * 10**9)
+    try:
+        out = srv.run(reqs)
+    finally:
+        srv.close()
+    measured = [r for r in out if r.rid >= warmup]
+    s = serve.summarize(measured, rate_hz)
+    s.update({"slots": n_slots, "warmup_requests": warmup, "hbm_budget_bytes": 200 * 10**9,
+              "peak_reserved_bytes": srv.sched.peak_reserved, "peak_running": srv.sched.peak_running})
+    return s
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,6 +205,11 @@ def main():
     ap.add_argument("--layers", action="store_true", help="print per-layer counts of the first warmup step")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--serve-requests", type=int, default=0,
+                    help="also run the serving stream with this many measured requests")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-warmup", type=int, default=10)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration) and exit")
     args = ap.parse_args()
@@ -256,6 +278,10 @@ def main():
                          "expectation": f["expectation"],
                          "abs_err_vs_f64_gpu": abs(f["expectation"] - r["expectation"]),
                          "roofline": f["roofline"]}
+    if args.serve_requests > 0:
+        log(f"== serving: {args.serve_requests} requests at {args.serve_rate:g}/s, {args.serve_slots} slots")
+        line["serving"] = run_serving(args.serve_requests, args.serve_rate, args.serve_slots, args.serve_warmup)
+        log(f"   {line['serving']}")
     if not args.no_cpu:
         log("== CPU reference sample")
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
