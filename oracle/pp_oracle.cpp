@@ -225,7 +225,7 @@ void noise(or_sum* s, int n_gen, const uint64_t* ex, const uint64_t* ez, const d
     e[0] = 1.0;
     for (int k = 0; k < n_gen; ++k) {
       if (!anticommutes(p, ex + (size_t)k * W, ez + (size_t)k * W, W)) continue;
-      const double xk = f[k] - 1.0;
+      const double xk = std::expm1(2.0 * sign * lambda[k]);   // f_k - 1 without cancellation
       for (int j = jmax; j >= 1; --j) e[j] += e[j - 1] * xk;
     }
     for (int j = 0; j <= jmax; ++j) {
