@@ -285,17 +285,20 @@ struct Engine final : EngineBase {
   TBuf<CT, ORD> cur, alt, sa, sb, tmp;
   uint64_t run_bound = 0;   // upper bound of the live count after any gate of the current run
   TBuf<double, true> ta, tb;     // tie lists for the cap
+  TBuf<CT, ORD> gb;              // boundary candidates of a cap
   Buf u32a, u32b, u32c, scan_scr, tiles, gates_d, sup_d, tab_d, fidx_d, dm_d, dval_d, cnt_d, ovf_d, partial_d, f64_d, span_d, htab_d;
   Buf hp_a, hp_b, tr_s0, tr_l0, tr_s1, tr_l1, g1_d, g1_ovf, g1_base, g1_drop;   // per-gate tile path
+  Buf rl0, rl1, ovl1, ovl2, tf_flag, tf_pos, tf_list, g1_io;
   double growth[4] = {4.0, 4.0, 2.0, 3.0};
   double tile_target[4] = {80.0, 80.0, 80.0, 64.0};   // level-0 (one-wavefront) tile targets
   uint64_t last_ntiles = 1, last_ovf_tiles = 0;
 
   explicit Engine(pp_obs* o) : obs(o), ctx(o->ctx), st(o->ctx->stream) {
-    for (auto* t : {&cur, &alt, &sa, &sb, &tmp}) { t->mem.ctx = ctx; t->W = W; }
+    for (auto* t : {&cur, &alt, &sa, &sb, &tmp, &gb}) { t->mem.ctx = ctx; t->W = W; }
     for (auto* t : {&ta, &tb}) { t->mem.ctx = ctx; t->W = W; }
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &fidx_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
-                   &partial_d, &f64_d, &span_d, &htab_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_drop})
+                   &partial_d, &f64_d, &span_d, &htab_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_drop, &rl0, &rl1, &ovl1, &ovl2,
+                   &tf_flag, &tf_pos, &tf_list, &g1_io})
       b->ctx = ctx;
     cnt_d.ensure(256);
     span_d.ensure(256);
@@ -304,10 +307,11 @@ struct Engine final : EngineBase {
     sync();
   }
   ~Engine() override {
-    for (auto* t : {&cur, &alt, &sa, &sb, &tmp}) t->mem.release();
+    for (auto* t : {&cur, &alt, &sa, &sb, &tmp, &gb}) t->mem.release();
     for (auto* t : {&ta, &tb}) t->mem.release();
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &fidx_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
-                   &partial_d, &f64_d, &span_d, &htab_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_drop})
+                   &partial_d, &f64_d, &span_d, &htab_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_drop, &rl0, &rl1, &ovl1, &ovl2,
+                   &tf_flag, &tf_pos, &tf_list, &g1_io})
       b->release();
   }
 
@@ -770,6 +774,38 @@ struct Engine final : EngineBase {
     unsigned long long peak_sum;
   };
 
+  // Tile starts ts[0..ntiles] over the m terms of `src` (sorted by the class hash): tile t
+  // starts at the first class boundary at or after t * T.
+  void make_tiles(const TBuf<CT, ORD>& src, uint64_t m, const GroupMask& gm, uint64_t kmask, uint64_t T,
+                  uint64_t ntiles, uint32_t* ts) {
+    tf_flag.ensure(m * 4 + 64);
+    tf_pos.ensure(m * 4 + 64);
+    tf_list.ensure(m * 4 + 64);
+    uint32_t *flag = tf_flag.as<uint32_t>(), *pos = tf_pos.as<uint32_t>(), *lst = tf_list.as<uint32_t>();
+    const Terms<CT> t = src.view();
+    ctx->run("tiles", 0, (double)m, [&] {
+      hipLaunchKernelGGL((k_class_flags<W, CT>), grid1(m), dim3(256), 0, st, t, m, gm, kmask, flag);
+    });
+    ctx->check_launch();
+    HIPCHK(hipMemcpyAsync(pos, flag, m * 4, hipMemcpyDeviceToDevice, st));
+    scan_u32(pos, m);
+    uint32_t lp = 0, lk = 0;
+    HIPCHK(hipMemcpyAsync(ctx->pinned, pos + m - 1, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync((char*)ctx->pinned + 4, flag + m - 1, 4, hipMemcpyDeviceToHost, st));
+    hipLaunchKernelGGL(k_scatter_flagged, grid1(m), dim3(256), 0, st, (const uint32_t*)flag, (const uint32_t*)pos, m,
+                       lst);
+    ctx->check_launch();
+    sync();
+    std::memcpy(&lp, ctx->pinned, 4);
+    std::memcpy(&lk, (char*)ctx->pinned + 4, 4);
+    const uint32_t nb = lp + lk;
+    ctx->run("tiles", 0, (double)ntiles, [&] {
+      hipLaunchKernelGGL(k_tile_starts, grid1(ntiles + 1), dim3(256), 0, st, (const uint32_t*)lst, nb, m, T,
+                         (uint32_t)ntiles, ts);
+    });
+    ctx->check_launch();
+  }
+
   // ---- grouped fused pass ---------------------------------------------------------------------
   // One level: run the fused kernel over `m` terms of `src` with tile target T, appending the
   // survivors to `alt` at out_count; the inputs of tiles that overflowed (LDS or output
@@ -795,11 +831,8 @@ struct Engine final : EngineBase {
       const Terms<CT> t = src.view();
       const uint64_t kmask = kk >= 64 ? ~0ULL : ((1ULL << kk) - 1);
       uint32_t* ts = tiles.as<uint32_t>();
-      ctx->run("tiles", 0, (double)ntiles, [&] {
-        hipLaunchKernelGGL((k_tiles<W, CT>), grid1(ntiles + 1), dim3(256), 0, st, t, m, gm, kmask, T,
-                           (uint32_t)ntiles, ts);
-      });
-      ctx->check_launch();
+      (void)t;
+      make_tiles(src, m, gm, kmask, T, ntiles, ts);
     }
     ovf_d.ensure((ntiles + 2) * 4);
     Counters hc0{};
@@ -1053,9 +1086,11 @@ struct Engine final : EngineBase {
 
   // ---- gate by gate over persistent tiles --------------------------------------------------------
   struct G1Counters {
-    uint32_t ovf_count;
+    uint32_t nlist[2];   // routed tiles: small, larger
+    uint32_t ovf[3];     // tiles reported by the one-wavefront, 256-thread and 1024-thread shapes
     uint32_t big_count;
   };
+  static constexpr uint32_t kG1SmallMax = 128;   // tiles up to this size start in one wavefront
   static constexpr uint64_t kG1Target = 96;     // terms per one-wavefront tile when tiling
   static constexpr uint32_t kG1Big = 160;       // a tile above this may outgrow 256 at the next gate
   uint64_t g1_ntiles = 0;
@@ -1074,11 +1109,7 @@ struct Engine final : EngineBase {
     const Terms<CT> t = cur.view();
     const uint64_t kmask = kk >= 64 ? ~0ULL : ((1ULL << kk) - 1);
     uint32_t* ts = tiles.as<uint32_t>();
-    ctx->run("tiles", 0, (double)ntiles, [&] {
-      hipLaunchKernelGGL((k_tiles<W, CT>), grid1(ntiles + 1), dim3(256), 0, st, t, m, gm, kmask, T, (uint32_t)ntiles,
-                         ts);
-    });
-    ctx->check_launch();
+    make_tiles(cur, m, gm, kmask, T, ntiles, ts);
     tr_s0.ensure(ntiles * 4 + 64);
     tr_l0.ensure(ntiles * 4 + 64);
     uint32_t *s0 = tr_s0.as<uint32_t>(), *l0 = tr_l0.as<uint32_t>();
@@ -1112,10 +1143,23 @@ struct Engine final : EngineBase {
     return (uint64_t)lastb + last;
   }
 
-  // The cut of the cap at K: |c| keys with (key & mask) >= prefix are kept.  Returns false
-  // when the K-th largest value is tied with terms that must be dropped (the caller then
-  // needs the exact tie-break by key).
-  bool cap_cut(uint64_t K, uint64_t n, uint64_t& prefix_out, uint64_t& mask_out) {
+  static uint64_t abs_key_host(CT v) {
+    if (sizeof(CT) == 8) {
+      uint64_t b;
+      std::memcpy(&b, &v, 8);
+      return b & 0x7fffffffffffffffULL;
+    }
+    uint32_t b;
+    std::memcpy(&b, &v, 4);
+    return b & 0x7fffffffU;
+  }
+
+  // The cut of a cap at K over the first n slots of cur (zeros are empty slots): radix
+  // select on the |c| bits narrows the K-th largest to a bucket of few candidates, which
+  // are gathered and ranked exactly on the host by (|c| descending, canonical key
+  // ascending); the K-th of that order is the boundary term.
+  CutDev cap_cut(uint64_t K, uint64_t n) {
+    constexpr uint32_t kGather = 4096;
     const int KB = sizeof(CT) == 8 ? 63 : 31;
     uint64_t prefix = 0, pmask = 0, need = K, count_eq = 0;
     u32a.ensure(2048 * 4 + 64);
@@ -1148,24 +1192,67 @@ struct Engine final : EngineBase {
       pmask |= (uint64_t)(bins - 1) << shift;
       count_eq = h[d];
       hi = shift;
-      if (need == count_eq) break;
+      if (count_eq <= kGather) break;
     }
-    prefix_out = prefix;
-    mask_out = pmask;
-    return need == count_eq;
+    // gather the bucket and rank it
+    gb.ensure(std::max<uint64_t>(count_eq, 1));
+    u32a.ensure(2048 * 4 + 64);
+    uint32_t* cntd = u32a.as<uint32_t>();
+    HIPCHK(hipMemsetAsync(cntd, 0, 4, st));
+    const Terms<CT> t = cur.view(), g = gb.view();
+    const uint64_t gcap = gb.cap;
+    ctx->run("cap_gather", 0, (double)n, [&] {
+      hipLaunchKernelGGL((k_gather_bucket<W, CT, ORD>), grid1(n), dim3(256), 0, st, t, n, pmask, prefix, g, gcap,
+                         cntd);
+    });
+    ctx->check_launch();
+    const uint64_t m = count_eq;
+    std::vector<uint64_t> gx(m * W), gz(m * W);
+    std::vector<CT> gc(m);
+    std::vector<uint8_t> go(m, 0);
+    for (int w = 0; w < W; ++w) {
+      HIPCHK(hipMemcpyAsync(gx.data() + (size_t)w * m, g.x + (size_t)w * g.stride, m * 8, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(gz.data() + (size_t)w * m, g.z + (size_t)w * g.stride, m * 8, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipMemcpyAsync(gc.data(), g.c, m * sizeof(CT), hipMemcpyDeviceToHost, st));
+    if (ORD) HIPCHK(hipMemcpyAsync(go.data(), g.o, m, hipMemcpyDeviceToHost, st));
+    sync();
+    std::vector<uint32_t> idx(m);
+    for (uint32_t i = 0; i < m; ++i) idx[i] = i;
+    auto before = [&](uint32_t a, uint32_t b) {   // a precedes b in the cap order
+      const uint64_t ka = abs_key_host(gc[a]), kb = abs_key_host(gc[b]);
+      if (ka != kb) return ka > kb;
+      for (int w = W - 1; w >= 0; --w)
+        if (gx[(size_t)w * m + a] != gx[(size_t)w * m + b]) return gx[(size_t)w * m + a] < gx[(size_t)w * m + b];
+      for (int w = W - 1; w >= 0; --w)
+        if (gz[(size_t)w * m + a] != gz[(size_t)w * m + b]) return gz[(size_t)w * m + a] < gz[(size_t)w * m + b];
+      return go[a] < go[b];
+    };
+    if (need < 1 || need > m) throw_fail(PP_ERR_DEVICE, "cap selection lost its boundary");
+    std::nth_element(idx.begin(), idx.begin() + (need - 1), idx.end(), before);
+    const uint32_t bi = idx[need - 1];
+    CutDev cut{};
+    cut.has = 1;
+    cut.val = abs_key_host(gc[bi]);
+    for (int w = 0; w < W; ++w) {
+      cut.x[w] = gx[(size_t)w * m + bi];
+      cut.z[w] = gz[(size_t)w * m + bi];
+    }
+    cut.o = go[bi];
+    return cut;
   }
 
-  // Drop the terms below a pending cut (and exact zeros) from cur.
-  void apply_cut(uint64_t key, uint64_t mask, pp_layer_stats& ls) {
+  // Drop the terms a cut removes (and exact zeros) from cur (N slots).
+  void apply_cut(const CutDev& cut, pp_layer_stats& ls) {
     if (N == 0) return;
     u32b.ensure(N * 4 + 64);
     uint32_t* keep = u32b.as<uint32_t>();
     double* dd = &cnt_d.as<Counters>()->dropped;
     HIPCHK(hipMemsetAsync(dd, 0, 8, st));
-    const CT* c = cur.view().c;
+    const Terms<CT> t = cur.view();
     const uint64_t n = N;
     ctx->run("cut_flags", 0, (double)n, [&] {
-      hipLaunchKernelGGL((k_cut_keep<CT>), gridb(n), dim3(256), 0, st, c, n, key, mask, keep, dd);
+      hipLaunchKernelGGL((k_cut_keep<W, CT, ORD>), gridb(n), dim3(256), 0, st, t, n, cut, keep, dd);
     });
     ctx->check_launch();
     compact_cur(keep);
@@ -1177,15 +1264,15 @@ struct Engine final : EngineBase {
   }
 
   // The pending cut on the m terms of sa (result in sa); returns the survivors' count.
-  uint64_t cut_subset(uint64_t m, uint64_t key, uint64_t mask) {
+  uint64_t cut_subset(uint64_t m, const CutDev& cut) {
     if (m == 0) return 0;
     u32b.ensure(m * 4 + 64);
     u32c.ensure(m * 4 + 64);
     uint32_t* keep = u32b.as<uint32_t>();
     uint32_t* pos = u32c.as<uint32_t>();
-    const CT* c = sa.view().c;
+    const Terms<CT> ts = sa.view();
     ctx->run("cut_flags", 0, (double)m, [&] {
-      hipLaunchKernelGGL((k_cut_keep<CT>), gridb(m), dim3(256), 0, st, c, m, key, mask, keep, (double*)nullptr);
+      hipLaunchKernelGGL((k_cut_keep<W, CT, ORD>), gridb(m), dim3(256), 0, st, ts, m, cut, keep, (double*)nullptr);
     });
     ctx->check_launch();
     HIPCHK(hipMemcpyAsync(pos, keep, m * 4, hipMemcpyDeviceToDevice, st));
@@ -1208,12 +1295,27 @@ struct Engine final : EngineBase {
     return k;
   }
 
+  // One launch of the gate pass; its algorithmic bytes (terms loaded and written by the
+  // tiles it completed, times the term size) are read back when timing is on.
   template <int CAPK, int BLOCKK>
-  void g1_launch(const Gate1Args<CT>& a, unsigned nblocks, bool small) {
-    ctx->run(small ? "gate_tile_wave" : "gate_tile_block", 0, (double)nblocks, [&] {
+  void g1_launch(Gate1Args<CT> a, unsigned nblocks, int shape) {
+    static const char* names[3] = {"gate_tile_wave", "gate_tile_256", "gate_tile_1024"};
+    g1_io.ensure(2 * kDropSlots * 8 + 64);
+    unsigned long long* io = g1_io.as<unsigned long long>();
+    a.io = io;
+    if (ctx->timing) HIPCHK(hipMemsetAsync(io, 0, 2 * kDropSlots * 8, st));
+    const int pi = ctx->run(names[shape], 0, (double)nblocks, [&] {
       hipLaunchKernelGGL((k_gate1<W, CT, ORD, CAPK, BLOCKK>), dim3(nblocks), dim3(BLOCKK), 0, st, a);
     });
     ctx->check_launch();
+    if (pi >= 0) {
+      std::vector<unsigned long long> h(2 * kDropSlots);
+      HIPCHK(hipMemcpyAsync(h.data(), io, h.size() * 8, hipMemcpyDeviceToHost, st));
+      sync();
+      double terms = 0.0;
+      for (unsigned long long v : h) terms += (double)v;
+      ctx->pending[pi].bytes = kTermBytes * terms;
+    }
   }
 
   // Apply `gates` one at a time with the cap after each non-Clifford gate (Section I.A's
@@ -1223,8 +1325,8 @@ struct Engine final : EngineBase {
   // the cut of the last gate is applied when the next pass loads the tile.
   void gate_by_gate(const std::vector<GateDev>& gates, int kind, double eps, uint64_t cap, pp_layer_stats& ls) {
     const GroupMask gm = invariant_mask(gates, kind);
-    bool has_cut = false, need_tiles = true;
-    uint64_t cut_key = 0, cut_mask = 0;
+    bool need_tiles = true;
+    CutDev cut{};   // the pending cut (cut.has = 0: none)
     uint64_t extent = N;      // slots of cur that hold terms or zeros
     uint64_t out_extent = 0;  // slots the next pass writes
     g1_d.ensure(sizeof(G1Counters) + 64);
@@ -1233,14 +1335,14 @@ struct Engine final : EngineBase {
     double* dropd = g1_drop.as<double>();
     auto densify = [&]() {   // apply a pending cut and squeeze out the unused slots
       N = extent;
-      apply_cut(has_cut ? cut_key : 0, has_cut ? cut_mask : 0, ls);
-      has_cut = false;
+      apply_cut(cut, ls);
+      cut.has = 0;
       extent = N;
     };
     for (size_t gi = 0; gi < gates.size() && N > 0; ++gi) {
       const GateDev& G = gates[gi];
       if (need_tiles) {
-        if (extent != N || has_cut) densify();
+        if (extent != N || cut.has) densify();
         if (N == 0) break;
         g1_tile(gm);
         out_extent = g1_bases(tr_l0.as<uint32_t>(), g1_ntiles);
@@ -1251,9 +1353,21 @@ struct Engine final : EngineBase {
       hp_b.ensure(alt.cap * 4 + 64);
       tr_s1.ensure(ntiles * 4 + 64);
       tr_l1.ensure(ntiles * 4 + 64);
-      g1_ovf.ensure(ntiles * 4 + 64);
+      for (Buf* b : {&rl0, &rl1, &g1_ovf, &ovl1, &ovl2}) b->ensure(ntiles * 4 + 64);
       HIPCHK(hipMemsetAsync(cd, 0, sizeof(G1Counters), st));
       HIPCHK(hipMemsetAsync(dropd, 0, kDropSlots * 8, st));
+      hipLaunchKernelGGL(k_route_tiles, grid1(ntiles), dim3(256), 0, st, (const uint32_t*)tr_l0.as<uint32_t>(),
+                         (uint32_t)ntiles, kG1SmallMax, (const uint32_t*)g1_base.as<uint32_t>(),
+                         tr_s1.as<uint32_t>(), tr_l1.as<uint32_t>(), rl0.as<uint32_t>(), rl1.as<uint32_t>(),
+                         &cd->nlist[0]);
+      ctx->check_launch();
+      G1Counters hc;
+      auto read_counters = [&]() {
+        HIPCHK(hipMemcpyAsync(ctx->pinned, cd, sizeof hc, hipMemcpyDeviceToHost, st));
+        sync();
+        std::memcpy(&hc, ctx->pinned, sizeof hc);
+      };
+      read_counters();
       Gate1Args<CT> a{};
       a.in = cur.view();
       a.out = alt.view();
@@ -1261,87 +1375,78 @@ struct Engine final : EngineBase {
       a.hout = hp_b.as<uint32_t>();
       a.t_start = tr_s0.as<uint32_t>();
       a.t_len = tr_l0.as<uint32_t>();
-      a.t_list = nullptr;
       a.o_base = g1_base.as<uint32_t>();
       a.o_start = tr_s1.as<uint32_t>();
       a.o_len = tr_l1.as<uint32_t>();
       a.zero_on_ovf = 0;
       a.g = G;
       a.eps = G.clifford ? 0.0 : eps;
-      a.has_cut = has_cut ? 1 : 0;
-      a.cut_key = cut_key;
-      a.cut_mask = cut_mask;
-      a.ovf_tiles = g1_ovf.as<uint32_t>();
-      a.ovf_count = &cd->ovf_count;
+      a.cut = cut;
       a.dropped = dropd;
       a.big_count = &cd->big_count;
       a.big_hint = kG1Big;
-      g1_launch<SmallCfg<W>::CAP, SmallCfg<W>::BLOCK>(a, (unsigned)ntiles, true);
-      G1Counters hc;
-      HIPCHK(hipMemcpyAsync(ctx->pinned, cd, sizeof hc, hipMemcpyDeviceToHost, st));
-      sync();
-      std::memcpy(&hc, ctx->pinned, sizeof hc);
-      uint64_t giant_terms = 0;
-      if (hc.ovf_count > 0) {
-        // tiles too large for one wavefront: the 1024-thread shape, on the same ranges
-        const uint32_t nov = hc.ovf_count;
+      auto with_list = [&](const Buf& list, Buf& ovl, int k, int zero) {
         Gate1Args<CT> b = a;
-        u32c.ensure(4 * (size_t)nov + 64);
-        u32b.ensure(4 * (size_t)nov + 64);
-        HIPCHK(hipMemcpyAsync(u32c.p, g1_ovf.p, 4 * (size_t)nov, hipMemcpyDeviceToDevice, st));
-        b.t_list = u32c.as<uint32_t>();
-        b.ovf_tiles = u32b.as<uint32_t>();
-        b.zero_on_ovf = 1;
-        HIPCHK(hipMemsetAsync(cd, 0, sizeof(G1Counters), st));
-        g1_launch<LayerCfg<W>::CAP, LayerCfg<W>::BLOCK>(b, nov, false);
-        G1Counters hb;
-        HIPCHK(hipMemcpyAsync(ctx->pinned, cd, sizeof hb, hipMemcpyDeviceToHost, st));
+        b.t_list = list.as<uint32_t>();
+        b.ovf_tiles = ovl.as<uint32_t>();
+        b.ovf_count = &cd->ovf[k];
+        b.zero_on_ovf = zero;
+        return b;
+      };
+      // one wavefront for small tiles; 256 threads for the others and for small tiles that grew
+      if (hc.nlist[0]) g1_launch<SmallCfg<W>::CAP, SmallCfg<W>::BLOCK>(with_list(rl0, g1_ovf, 0, 0), hc.nlist[0], 0);
+      if (hc.nlist[1]) g1_launch<1024, 256>(with_list(rl1, ovl1, 1, 0), hc.nlist[1], 1);
+      read_counters();
+      if (hc.ovf[0]) {
+        g1_launch<1024, 256>(with_list(g1_ovf, ovl1, 1, 0), hc.ovf[0], 1);
+        read_counters();
+      }
+      uint64_t giant_terms = 0;
+      if (hc.ovf[1]) {
+        g1_launch<LayerCfg<W>::CAP, LayerCfg<W>::BLOCK>(with_list(ovl1, ovl2, 2, 1), hc.ovf[1], 2);
+        read_counters();
+      }
+      if (hc.ovf[2] > 0) {
+        // groups too large for LDS that the gate touches: gathered and tiled by pairs
+        const uint32_t n2 = hc.ovf[2];
+        std::vector<uint32_t> o2(n2), ts(ntiles), tl(ntiles);
+        HIPCHK(hipMemcpyAsync(o2.data(), ovl2.p, 4 * (size_t)n2, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(ts.data(), tr_s0.p, 4 * ntiles, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(tl.data(), tr_l0.p, 4 * ntiles, hipMemcpyDeviceToHost, st));
         sync();
-        std::memcpy(&hb, ctx->pinned, sizeof hb);
-        hc.big_count += hb.big_count;
-        if (hb.ovf_count > 0) {
-          // groups too large for LDS that the gate touches: the sort-based path, on their terms
-          const uint32_t n2 = hb.ovf_count;
-          std::vector<uint32_t> o2(n2), ts(ntiles), tl(ntiles);
-          HIPCHK(hipMemcpyAsync(o2.data(), u32b.p, 4 * (size_t)n2, hipMemcpyDeviceToHost, st));
-          HIPCHK(hipMemcpyAsync(ts.data(), tr_s0.p, 4 * ntiles, hipMemcpyDeviceToHost, st));
-          HIPCHK(hipMemcpyAsync(tl.data(), tr_l0.p, 4 * ntiles, hipMemcpyDeviceToHost, st));
-          sync();
-          std::vector<uint32_t> src_r, len_r;
-          std::vector<uint64_t> dst_r;
-          uint64_t mo = 0;
-          for (uint32_t v : o2) {
-            src_r.push_back(ts[v]);
-            len_r.push_back(tl[v]);
-            dst_r.push_back(mo);
-            mo += tl[v];
-          }
-          sa.ensure(std::max<uint64_t>(mo, 1));
-          u32c.ensure(8 * (size_t)n2 + 64);
-          partial_d.ensure(8 * (size_t)n2 + 64);
-          u32b.ensure(8 * (size_t)n2 + 64);
-          HIPCHK(hipMemcpyAsync(u32b.p, src_r.data(), 4 * (size_t)n2, hipMemcpyHostToDevice, st));
-          HIPCHK(hipMemcpyAsync(u32c.p, len_r.data(), 4 * (size_t)n2, hipMemcpyHostToDevice, st));
-          HIPCHK(hipMemcpyAsync(partial_d.p, dst_r.data(), 8 * (size_t)n2, hipMemcpyHostToDevice, st));
-          const Terms<CT> in = cur.view(), sub = sa.view();
-          const uint32_t *srcd = u32b.as<uint32_t>(), *lend = u32c.as<uint32_t>();
-          const uint64_t* dstd = partial_d.as<uint64_t>();
-          ctx->run("copy_ranges", 0, (double)mo, [&] {
-            hipLaunchKernelGGL((k_copy_ranges<W, CT, ORD>), dim3(n2), dim3(256), 0, st, in, sub, srcd, lend, dstd,
-                               (int)n2);
-          });
-          ctx->check_launch();
-          sync();
-          uint64_t mm = mo;
-          if (has_cut) mm = cut_subset(mm, cut_key, cut_mask);   // the pending cut, on this subset
-          ls.n_fallback += (int64_t)mm;
-          mm = per_gate(mm, {G}, G.clifford ? 0.0 : eps, nullptr, 0.0, &dropd[0]);
-          uint64_t oc = out_extent;
-          append(alt, oc, sa, mm);
-          giant_terms = mm;
-          out_extent = oc;
-          need_tiles = true;   // these terms are no longer laid out by tile
+        std::vector<uint32_t> src_r, len_r;
+        std::vector<uint64_t> dst_r;
+        uint64_t mo = 0;
+        for (uint32_t v : o2) {
+          src_r.push_back(ts[v]);
+          len_r.push_back(tl[v]);
+          dst_r.push_back(mo);
+          mo += tl[v];
         }
+        sa.ensure(std::max<uint64_t>(mo, 1));
+        u32c.ensure(8 * (size_t)n2 + 64);
+        partial_d.ensure(8 * (size_t)n2 + 64);
+        u32b.ensure(8 * (size_t)n2 + 64);
+        HIPCHK(hipMemcpyAsync(u32b.p, src_r.data(), 4 * (size_t)n2, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(u32c.p, len_r.data(), 4 * (size_t)n2, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(partial_d.p, dst_r.data(), 8 * (size_t)n2, hipMemcpyHostToDevice, st));
+        const Terms<CT> in = cur.view(), sub = sa.view();
+        const uint32_t *srcd = u32b.as<uint32_t>(), *lend = u32c.as<uint32_t>();
+        const uint64_t* dstd = partial_d.as<uint64_t>();
+        ctx->run("copy_ranges", 0, (double)mo, [&] {
+          hipLaunchKernelGGL((k_copy_ranges<W, CT, ORD>), dim3(n2), dim3(256), 0, st, in, sub, srcd, lend, dstd,
+                             (int)n2);
+        });
+        ctx->check_launch();
+        sync();
+        uint64_t mm = mo;
+        if (cut.has) mm = cut_subset(mm, cut);   // the pending cut, on this subset
+        ls.n_fallback += (int64_t)mm;
+        uint64_t oc = out_extent;
+        run_groups(sa, mm, {G}, kind, G.clifford ? 0.0 : eps, nullptr, 0.0, alt, oc, 0, ls);
+        giant_terms = oc - out_extent;
+        out_extent = oc;
+        need_tiles = true;   // these terms are no longer laid out by tile
       }
       std::vector<double> dsl(kDropSlots);
       HIPCHK(hipMemcpyAsync(dsl.data(), dropd, kDropSlots * 8, hipMemcpyDeviceToHost, st));
@@ -1356,25 +1461,16 @@ struct Engine final : EngineBase {
       N = next_extent / 2 + giant_terms;
       out_extent = next_extent;
       ls.n_peak = std::max<int64_t>(ls.n_peak, (int64_t)N);
-      has_cut = false;
+      cut.has = 0;
       if (!G.clifford && cap > 0 && N > cap) {
-        uint64_t key = 0, mask = 0;
-        if (cap_cut(cap, extent, key, mask)) {
-          has_cut = true;
-          cut_key = key;
-          cut_mask = mask;
-          ls.n_capped += (int64_t)(N - cap);
-        } else {
-          densify();   // exact ties at the cut: rank them by key on the dense array
-          cap_select(cap, ls);
-          extent = N;
-          need_tiles = true;
-        }
+        cut = cap_cut(cap, extent);
+        ls.n_capped += (int64_t)(N - cap);
+        N = cap;
       }
       // regroup when the cut has left the tiles small on average
       if (N < ntiles * kG1Target / 4) need_tiles = true;
     }
-    if (has_cut || extent != N) densify();
+    if (cut.has || extent != N) densify();
   }
 
   // ---- create ----------------------------------------------------------------------------------
@@ -1529,92 +1625,12 @@ struct Engine final : EngineBase {
     return (double)f;
   }
 
+  // Keep the K largest |c| (ties to the smaller canonical key).
   void cap_select(uint64_t K, pp_layer_stats& ls) {
     if (N <= K) return;
-    const int KB = sizeof(CT) == 8 ? 63 : 31;
-    uint64_t prefix = 0, pmask = 0, need = K, count_eq = 0;
-    u32a.ensure(2048 * 4 + 64);
-    uint32_t* hist = u32a.as<uint32_t>();
-    const CT* c = cur.view().c;
-    const uint64_t n = N;
-    int hi = KB;
-    std::vector<uint32_t> h(2048);
-    while (hi > 0) {
-      const int bits = std::min(11, hi);
-      const int shift = hi - bits;
-      const int bins = 1 << bits;
-      HIPCHK(hipMemsetAsync(hist, 0, bins * 4, st));
-      const unsigned nb = (unsigned)std::min<uint64_t>(2048, cdiv(n, 256));
-      ctx->run("cap_hist", sizeof(CT) * (double)n, (double)n, [&] {
-        hipLaunchKernelGGL((k_abs_hist<CT>), dim3(nb), dim3(256), 0, st, c, n, shift, bits, pmask, prefix, hist);
-      });
-      ctx->check_launch();
-      HIPCHK(hipMemcpyAsync(ctx->pinned, hist, bins * 4, hipMemcpyDeviceToHost, st));
-      sync();
-      std::memcpy(h.data(), ctx->pinned, bins * 4);
-      uint64_t cum = 0;
-      int d = bins - 1;
-      for (; d >= 0; --d) {
-        if (cum + h[d] >= need) break;
-        cum += h[d];
-      }
-      if (d < 0) d = 0;   // cannot happen while N > K
-      need -= cum;
-      prefix |= (uint64_t)d << shift;
-      pmask |= (uint64_t)(bins - 1) << shift;
-      count_eq = h[d];
-      hi = shift;
-      if (need == count_eq) break;   // the whole bucket is kept: the cut is its lower edge
-    }
-    const uint64_t tau_key = prefix;
     const uint64_t before = N;
-    u32b.ensure(n * 4 + 64);
-    u32c.ensure(n * 4 + 64);
-    uint32_t* keep = u32b.as<uint32_t>();
-    uint32_t* tie = u32c.as<uint32_t>();
-    double* dd = &cnt_d.as<Counters>()->dropped;
-    HIPCHK(hipMemsetAsync(dd, 0, 8, st));
-    ctx->run("cap_flags", 0, (double)n, [&] {
-      hipLaunchKernelGGL((k_cap_flags<CT>), gridb(n), dim3(256), 0, st, c, n, tau_key, pmask, keep, tie, dd);
-    });
-    ctx->check_launch();
-    if (need >= count_eq) {
-      // every tied term is kept: keep = keep | tie
-      ctx->run("cap_flags", 0, (double)n, [&] {
-        hipLaunchKernelGGL(k_or_flags, grid1(n), dim3(256), 0, st, keep, (const uint32_t*)tie, n);
-      });
-      ctx->check_launch();
-    } else {
-      // rank the tied terms by canonical key; keep the first `need`
-      Buf posb;
-      posb.ctx = ctx;
-      posb.ensure(n * 4 + 64);
-      uint32_t* pos = posb.as<uint32_t>();
-      HIPCHK(hipMemcpyAsync(pos, tie, n * 4, hipMemcpyDeviceToDevice, st));
-      scan_u32(pos, n);
-      ta.ensure(count_eq + 1);
-      const Terms<CT> in = cur.view();
-      const Terms<double> tt = ta.view();
-      ctx->run("cap_ties", 0, (double)n, [&] {
-        hipLaunchKernelGGL((k_gather_ties<W, CT, ORD>), grid1(n), dim3(256), 0, st, in, n, (const uint32_t*)tie,
-                           (const uint32_t*)pos, tt);
-      });
-      ctx->check_launch();
-      canonical_sort(ta, tb, count_eq);
-      const double* idx = ta.view().c;
-      ctx->run("cap_ties", 0, (double)need, [&] {
-        hipLaunchKernelGGL((k_mark_ties<CT>), grid1(need), dim3(256), 0, st, idx, need, keep, n);
-      });
-      ctx->check_launch();
-      sync();
-      posb.release();
-    }
-    compact_cur(keep);
-    double dropped = 0.0;
-    HIPCHK(hipMemcpyAsync(ctx->pinned, dd, 8, hipMemcpyDeviceToHost, st));
-    sync();
-    std::memcpy(&dropped, ctx->pinned, 8);
-    ls.dropped_l1 += dropped;
+    const CutDev cut = cap_cut(K, N);
+    apply_cut(cut, ls);
     ls.n_capped += (int64_t)(before - N);
   }
 

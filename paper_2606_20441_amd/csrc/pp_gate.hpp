@@ -21,6 +21,38 @@ namespace pp {
 
 constexpr int kDropSlots = 64;   // spread accumulators: one address per workgroup is a serial queue
 
+// The cut of a cap: the boundary term (the K-th in the order |c| descending, then canonical
+// key ascending) and the rule "kept iff it does not come after the boundary".  Canonical
+// key order: x words from the most significant word down, then z words, then the order tag.
+struct CutDev {
+  int has;
+  uint32_t o;
+  uint64_t val;               // |c| bits of the boundary term
+  uint64_t x[PP_MAXW], z[PP_MAXW];
+};
+
+template <int W>
+__device__ __forceinline__ bool canon_le(const uint64_t* kx, const uint64_t* kz, uint32_t ko, const CutDev& b) {
+#pragma unroll
+  for (int w = W - 1; w >= 0; --w)
+    if (kx[w] != b.x[w]) return kx[w] < b.x[w];
+#pragma unroll
+  for (int w = W - 1; w >= 0; --w)
+    if (kz[w] != b.z[w]) return kz[w] < b.z[w];
+  return ko <= b.o;
+}
+
+// Survives the cut (exact zeros never do).
+template <int W, class CT>
+__device__ __forceinline__ bool cut_keeps(CT v, const uint64_t* kx, const uint64_t* kz, uint32_t ko,
+                                          const CutDev& cut) {
+  if (v == (CT)0) return false;
+  if (!cut.has) return true;
+  const uint64_t k = abs_key<CT>(v);
+  if (k != cut.val) return k > cut.val;
+  return canon_le<W>(kx, kz, ko, cut);
+}
+
 template <class CT>
 struct Gate1Args {
   Terms<CT> in;
@@ -36,14 +68,13 @@ struct Gate1Args {
   int zero_on_ovf;              // a tile that does not fit zeroes its region (nobody retries it here)
   GateDev g;
   double eps;                   // threshold after the gate (0: none)
-  int has_cut;                  // drop terms whose (|c| key & cut_mask) < cut_key on load
-  uint64_t cut_key;
-  uint64_t cut_mask;
+  CutDev cut;                   // the previous gate's cap, applied on load
   uint32_t* ovf_tiles;          // tiles that did not fit in LDS
   uint32_t* ovf_count;
   double* dropped;              // [kDropSlots]: sum of |c| removed (cut and threshold)
   uint32_t* big_count;          // tiles whose output exceeds big_hint terms
   uint32_t big_hint;
+  unsigned long long* io;       // [2][kDropSlots]: terms loaded / written by completed tiles
 };
 
 // A tile handed to another path: its output region is left empty (c = 0, length 0).
@@ -66,7 +97,12 @@ __device__ void pass_through(const Gate1Args<CT>& a, uint32_t tile, uint32_t t0,
   const int tid = threadIdx.x, lane = tid & 63;
   auto keep = [&](uint64_t src) {
     const CT v = a.in.c[src];
-    return v != (CT)0 && !(a.has_cut && (abs_key<CT>(v) & a.cut_mask) < a.cut_key);
+    if (v == (CT)0) return false;
+    if (!a.cut.has) return true;
+    uint64_t kx[W], kz[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) { kx[w] = a.in.x[w * a.in.stride + src]; kz[w] = a.in.z[w * a.in.stride + src]; }
+    return cut_keeps<W, CT>(v, kx, kz, ORD ? a.in.o[src] : 0u, a.cut);
   };
   // count survivors per contiguous chunk of the tile
   const uint32_t chunk = (n0 + BLOCK - 1) / BLOCK;
@@ -100,6 +136,8 @@ __device__ void pass_through(const Gate1Args<CT>& a, uint32_t tile, uint32_t t0,
     for (int w = 0; w < NW; ++w) v += p_drop[w];
     if (v != 0.0) atomicAdd(&a.dropped[blockIdx.x % kDropSlots], v);
     if (total > a.big_hint) atomicAdd(a.big_count, 1u);
+    atomicAdd(&a.io[blockIdx.x % kDropSlots], (unsigned long long)n0);
+    atomicAdd(&a.io[kDropSlots + blockIdx.x % kDropSlots], (unsigned long long)total);
   }
   for (uint64_t i = base + total + tid; i < base + 2ULL * n0; i += BLOCK) a.out.c[i] = (CT)0;
   uint64_t dst = base + before + incl - cnt;
@@ -203,14 +241,14 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
     }
     const CT cv = a.in.c[src];
     double c = (double)cv;
-    if (c != 0.0 && a.has_cut && (abs_key<CT>(cv) & a.cut_mask) < a.cut_key) {
+    if (ORD) { ro[r] = a.in.o[src]; so[i] = (uint8_t)ro[r]; }
+    if (c != 0.0 && !cut_keeps<W, CT>(cv, rkx[r], rkz[r], ro[r], a.cut)) {
       lost += fabs(c);
       c = 0.0;
     }
     rc[r] = c;
     rh[r] = a.hin[src];
     sh[i] = rh[r];
-    if (ORD) { ro[r] = a.in.o[src]; so[i] = (uint8_t)ro[r]; }
     sc[i] = (CT)c;
     if (c != 0.0) {
       uint32_t slot = (rh[r] ^ (ro[r] * 0x9e3779b9u)) & (H - 1);
@@ -334,6 +372,8 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
     double v = 0.0;
     for (int w = 0; w < NW; ++w) v += s_drop[w];
     if (v != 0.0) atomicAdd(&a.dropped[blockIdx.x % kDropSlots], v);
+    atomicAdd(&a.io[blockIdx.x % kDropSlots], (unsigned long long)n0);
+    atomicAdd(&a.io[kDropSlots + blockIdx.x % kDropSlots], (unsigned long long)total);
   }
   for (uint64_t i = base + total + tid; i < base + 2ULL * n0; i += BLOCK) a.out.c[i] = (CT)0;
   uint32_t rank = before + incl - cnt;
@@ -364,6 +404,32 @@ __global__ void k_hash_plane(Terms<CT> t, uint64_t n, const uint32_t* htab, uint
   h[i] = lin_hash<W>(kx, kz, htab);
 }
 
+// Sort tiles by size: empty tiles get their (empty) output record here, tiles of at most
+// small_max terms go to list 0, the others to list 1.
+__global__ void k_route_tiles(const uint32_t* len, uint32_t ntiles, uint32_t small_max, const uint32_t* o_base,
+                              uint32_t* o_start, uint32_t* o_len, uint32_t* list0, uint32_t* list1,
+                              uint32_t* counts) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t l = t < ntiles ? len[t] : 0u;
+  if (t < ntiles && l == 0) {
+    o_start[t] = o_base[t];
+    o_len[t] = 0;
+  }
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = (1ULL << lane) - 1ULL;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const bool mine = t < ntiles && l > 0 && ((l <= small_max) == (k == 0));
+    const uint64_t bal = __ballot(mine);
+    if (!bal) continue;
+    const int leader = __ffsll((unsigned long long)bal) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(&counts[k], (uint32_t)__popcll(bal));
+    base = __shfl(base, leader, 64);
+    if (mine) (k == 0 ? list0 : list1)[base + (uint32_t)__popcll(bal & lt)] = t;
+  }
+}
+
 // v[t] = 2 * len[t] (output region sizes; an exclusive scan turns them into bases).
 __global__ void k_double_len(const uint32_t* len, uint32_t ntiles, uint32_t* v) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -379,17 +445,45 @@ __global__ void k_tile_ranges(const uint32_t* starts, uint32_t ntiles, uint32_t*
 }
 
 // keep[i] = the term survives the pending cut (and is not an exact zero).
-template <class CT>
-__global__ void k_cut_keep(const CT* c, uint64_t n, uint64_t cut_key, uint64_t cut_mask, uint32_t* keep,
-                           double* dropped) {
+template <int W, class CT, bool ORD>
+__global__ void k_cut_keep(Terms<CT> t, uint64_t n, CutDev cut, uint32_t* keep, double* dropped) {
   double lost = 0.0;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-    const CT v = c[i];
-    const bool k = v != (CT)0 && (abs_key<CT>(v) & cut_mask) >= cut_key;
+    const CT v = t.c[i];
+    bool k = v != (CT)0;
+    if (k && cut.has) {
+      uint64_t kx[W], kz[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) { kx[w] = t.x[w * t.stride + i]; kz[w] = t.z[w * t.stride + i]; }
+      k = cut_keeps<W, CT>(v, kx, kz, ORD ? t.o[i] : 0u, cut);
+    }
     keep[i] = k ? 1u : 0u;
     if (!k) lost += fabs((double)v);
   }
   add_dropped(lost, dropped);
+}
+
+// Gather the terms whose |c| bits match `prefix` on `pmask` (the candidates for the
+// boundary of a cap) into `g` (capacity gcap); *cnt counts all matches.
+template <int W, class CT, bool ORD>
+__global__ void k_gather_bucket(Terms<CT> t, uint64_t n, uint64_t pmask, uint64_t prefix, Terms<CT> g, uint64_t gcap,
+                                uint32_t* cnt) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool hit = i < n && t.c[i] != (CT)0 && (abs_key<CT>(t.c[i]) & pmask) == prefix;
+  const uint64_t bal = __ballot(hit);
+  if (!bal) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((unsigned long long)bal) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(cnt, (uint32_t)__popcll(bal));
+  base = __shfl(base, leader, 64);
+  if (!hit) return;
+  const uint64_t j = base + (uint64_t)__popcll(bal & ((1ULL << lane) - 1ULL));
+  if (j >= gcap) return;
+#pragma unroll
+  for (int w = 0; w < W; ++w) { g.x[w * g.stride + j] = t.x[w * t.stride + i]; g.z[w * g.stride + j] = t.z[w * t.stride + i]; }
+  g.c[j] = t.c[i];
+  if (ORD) g.o[j] = t.o[i];
 }
 
 }  // namespace pp

@@ -761,27 +761,40 @@ __global__ void __launch_bounds__(BLOCK) k_layer(LayerArgs<CT> a) {
   }
 }
 
-// ------------------------------------------------------------------------------------------
-// Tile boundaries after the group-hash sort: tile t starts at the first class boundary at or
-// after t * T (class = equal low k bits of the group hash).
-// ------------------------------------------------------------------------------------------
+// Tile boundaries without walking long classes: flag the first term of every class, list
+// the flagged positions (a scan), and give tile t the first class start at or after t * T.
 template <int W, class CT>
-__global__ void k_tiles(Terms<CT> t, uint64_t n, GroupMask gm, uint64_t kmask, uint64_t T, uint32_t ntiles,
-                        uint32_t* start) {
-  const uint32_t tile = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tile > ntiles) return;
-  if (tile == 0) { start[0] = 0; return; }
-  uint64_t i = (uint64_t)tile * T;
-  if (i >= n) { start[tile] = (uint32_t)n; return; }
+__global__ void k_class_flags(Terms<CT> t, uint64_t n, GroupMask gm, uint64_t kmask, uint32_t* flag) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
   auto hk = [&](uint64_t j) {
     uint64_t xs[W], zs[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) { xs[w] = t.x[w * t.stride + j]; zs[w] = t.z[w * t.stride + j]; }
     return group_hash<W>(xs, zs, gm.mx, gm.mz) & kmask;
   };
-  const uint64_t prev = hk(i - 1);
-  while (i < n && hk(i) == prev) ++i;
-  start[tile] = (uint32_t)i;
+  flag[i] = (i == 0 || hk(i) != hk(i - 1)) ? 1u : 0u;
+}
+
+__global__ void k_scatter_flagged(const uint32_t* flag, const uint32_t* pos, uint64_t n, uint32_t* list) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && flag[i]) list[pos[i]] = (uint32_t)i;
+}
+
+__global__ void k_tile_starts(const uint32_t* bnd, uint32_t nb, uint64_t n, uint64_t T, uint32_t ntiles,
+                              uint32_t* start) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > ntiles) return;
+  const uint64_t target = (uint64_t)t * T;
+  if (t == 0) { start[0] = 0; return; }
+  if (target >= n) { start[t] = (uint32_t)n; return; }
+  uint32_t lo = 0, hi = nb;   // first boundary >= target
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (bnd[mid] < target) lo = mid + 1;
+    else hi = mid;
+  }
+  start[t] = lo < nb ? bnd[lo] : (uint32_t)n;
 }
 
 // ------------------------------------------------------------------------------------------
