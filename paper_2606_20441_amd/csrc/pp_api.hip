@@ -1012,7 +1012,7 @@ struct Engine final : EngineBase {
       const uint64_t mo = fused_level(*in, mi, T, gm, (int)gates.size(), kind, any_nc, thr, nd, thr_noise, dst,
                                       dst_count, ovf, out_full, ls, small);
       if (level > 0 || depth > 0) ls.n_fallback += (int64_t)mi;
-      if (mo && out_full) grow_keep(dst, std::max<uint64_t>(2 * dst.cap, dst_count + mo * 16), dst_count);
+      if (mo && out_full) grow_keep(dst, std::max<uint64_t>(dst.cap + dst.cap / 2, dst_count + mo * 4), dst_count);
       if (level == 0 && depth == 0) {
         const double frac = (double)last_ovf_tiles / (double)std::max<uint64_t>(1, last_ntiles);
         if (frac > 0.10) tile_target[kind] = std::max(16.0, tile_target[kind] * 0.75);
@@ -1067,7 +1067,9 @@ struct Engine final : EngineBase {
     if (!capped || (int64_t)N * 2 <= cap) {
       const uint64_t n_in = N;
       const double g = growth[kind];
-      alt.ensure((uint64_t)((double)N * std::max(2.0, g) * 2.0) + 4 * CAP);
+      // first guess from the growth of the last run of this kind (refused tiles are retried
+      // after the buffer grows, so the guess only has to be good, not safe)
+      alt.ensure((uint64_t)((double)N * std::min(8.0, std::max(2.0, 1.25 * g))) + 4 * CAP);
       uint64_t out_count = 0;
       run_bound = 0;
       run_groups(cur, N, gates, kind, thr, nd, thr_noise, alt, out_count, 0, ls);
