@@ -26,11 +26,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM traffic of the fused layer kernel, taken from FETCH_SIZE / WRITE_SIZE counter runs and
+# HBM traffic of the dominant kernels, taken from FETCH_SIZE / WRITE_SIZE counter runs and
 # scaled by the same counters read on a plain device copy of known size.  The figure is
 # reported only while the kernel sources still hash to the value recorded with it.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_layer_fused_wave_tfim7x8_pna.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gate_tile_tfim7x8_pna.md")
 KERNEL_SOURCES = ["paper_2606_20441_amd/csrc/pp_layer.hpp", "paper_2606_20441_amd/csrc/pp_common.hpp",
+                  "paper_2606_20441_amd/csrc/pp_gate.hpp", "paper_2606_20441_amd/csrc/pp_misc.hpp",
+                  "paper_2606_20441_amd/csrc/pp_sort.hpp",
                   "paper_2606_20441_amd/csrc/pp_api.hip"]
 
 
@@ -208,8 +210,8 @@ def main():
     ap.add_argument("--layers", action="store_true", help="print per-layer counts of the first warmup step")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--serve-requests", type=int, default=0,
-                    help="also run the serving stream with this many measured requests")
+    ap.add_argument("--serve-requests", type=int, default=100,
+                    help="measured requests of the serving stream (0: skip it)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-warmup", type=int, default=10)
