@@ -210,9 +210,10 @@ def main():
     ap.add_argument("--layers", action="store_true", help="print per-layer counts of the first warmup step")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--serve-requests", type=int, default=100,
-                    help="measured requests of the serving stream (0: skip it)")
-    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-requests", type=int, default=30,
+                    help="measured requests of the serving stream per arrival rate (0: skip it)")
+    ap.add_argument("--serve-rates", default="200,0.5",
+                    help="arrival rates (req/s): the configured one and one the device sustains")
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-warmup", type=int, default=10)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -284,9 +285,12 @@ def main():
                          "abs_err_vs_f64_gpu": abs(f["expectation"] - r["expectation"]),
                          "roofline": f["roofline"]}
     if args.serve_requests > 0:
-        log(f"== serving: {args.serve_requests} requests at {args.serve_rate:g}/s, {args.serve_slots} slots")
-        line["serving"] = run_serving(args.serve_requests, args.serve_rate, args.serve_slots, args.serve_warmup)
-        log(f"   {line['serving']}")
+        line["serving"] = []
+        for rate in [float(r) for r in args.serve_rates.split(",") if r]:
+            log(f"== serving: {args.serve_requests} requests at {rate:g}/s, {args.serve_slots} slots")
+            res = run_serving(args.serve_requests, rate, args.serve_slots, args.serve_warmup)
+            line["serving"].append(res)
+            log(f"   {res}")
     if not args.no_cpu:
         log("== CPU reference sample")
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)

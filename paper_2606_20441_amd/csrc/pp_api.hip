@@ -284,6 +284,8 @@ struct Engine final : EngineBase {
   uint64_t N = 0;
   TBuf<CT, ORD> cur, alt, sa, sb, tmp;
   uint64_t run_bound = 0;   // upper bound of the live count after any gate of the current run
+  bool abort_on_full = false;   // a fused attempt that fills its output buffer stops (cap binds)
+  bool aborted = false;
   TBuf<double, true> ta, tb;     // tie lists for the cap
   TBuf<CT, ORD> gb;              // boundary candidates of a cap
   Buf u32a, u32b, u32c, scan_scr, tiles, gates_d, sup_d, tab_d, fidx_d, dm_d, dval_d, cnt_d, ovf_d, partial_d, f64_d, span_d, htab_d;
@@ -985,7 +987,7 @@ struct Engine final : EngineBase {
   void run_groups(TBuf<CT, ORD>& src, uint64_t m, const std::vector<GateDev>& gates, int kind, double thr,
                   const NoiseDev* nd, double thr_noise, TBuf<CT, ORD>& dst, uint64_t& dst_count, int depth,
                   pp_layer_stats& ls) {
-    if (m == 0) return;
+    if (m == 0 || aborted) return;
     bool any_nc = false;
     for (const GateDev& g : gates) any_nc |= g.clifford == 0;
     gates_d.ensure(std::max<size_t>(1, gates.size()) * sizeof(GateDev) + 64);
@@ -1012,7 +1014,13 @@ struct Engine final : EngineBase {
       const uint64_t mo = fused_level(*in, mi, T, gm, (int)gates.size(), kind, any_nc, thr, nd, thr_noise, dst,
                                       dst_count, ovf, out_full, ls, small);
       if (level > 0 || depth > 0) ls.n_fallback += (int64_t)mi;
-      if (mo && out_full) grow_keep(dst, std::max<uint64_t>(dst.cap + dst.cap / 2, dst_count + mo * 4), dst_count);
+      if (mo && out_full) {
+        if (abort_on_full) {   // more terms than the output buffer holds: the caller gives up
+          aborted = true;
+          break;
+        }
+        grow_keep(dst, std::max<uint64_t>(dst.cap + dst.cap / 2, dst_count + mo * 4), dst_count);
+      }
       if (level == 0 && depth == 0) {
         const double frac = (double)last_ovf_tiles / (double)std::max<uint64_t>(1, last_ntiles);
         if (frac > 0.10) tile_target[kind] = std::max(16.0, tile_target[kind] * 0.75);
@@ -1021,7 +1029,7 @@ struct Engine final : EngineBase {
       in = &ovf;
       mi = mo;
     }
-    if (mi > 0) {
+    if (mi > 0 && !aborted) {
       if (gates.size() >= 2 && depth < 8) {
         // groups too large for LDS under all these gates: split the gate list in two
         const size_t h = gates.size() / 2;
@@ -1041,7 +1049,11 @@ struct Engine final : EngineBase {
         uint64_t gp = 0;
         const uint64_t mm = per_gate(mi, gates, thr, nd, thr_noise, &cnt_d.as<Counters>()->dropped, &gp);
         run_bound += gp;
-        append(dst, dst_count, sa, mm);
+        if (abort_on_full && dst_count + mm > dst.cap) {
+          aborted = true;
+        } else {
+          append(dst, dst_count, sa, mm);
+        }
       }
     }
     ov_a.mem.release();
@@ -1069,11 +1081,18 @@ struct Engine final : EngineBase {
       const double g = growth[kind];
       // first guess from the growth of the last run of this kind (refused tiles are retried
       // after the buffer grows, so the guess only has to be good, not safe)
-      alt.ensure((uint64_t)((double)N * std::min(8.0, std::max(2.0, 1.25 * g))) + 4 * CAP);
+      uint64_t guess = (uint64_t)((double)N * std::min(8.0, std::max(2.0, 1.25 * g))) + 4 * CAP;
+      if (capped) guess = std::min<uint64_t>(guess, 2 * (uint64_t)cap + 4 * CAP);   // more than 2x the cap: it binds
+      alt.ensure(guess);
       uint64_t out_count = 0;
       run_bound = 0;
+      abort_on_full = capped;
+      aborted = false;
       run_groups(cur, N, gates, kind, thr, nd, thr_noise, alt, out_count, 0, ls);
-      if (!capped || run_bound <= (uint64_t)cap) {
+      abort_on_full = false;
+      const bool gave_up = aborted;
+      aborted = false;
+      if (!gave_up && (!capped || run_bound <= (uint64_t)cap)) {
         cur.swap(alt);
         N = out_count;
         const double obs_g = (double)N / (double)std::max<uint64_t>(1, n_in);

@@ -43,14 +43,13 @@ def term_bytes(n_qubits: int, precision: str, mode: str) -> int:
     return 16 * w + (8 if precision == "f64" else 4) + (1 if mode == "error_order" else 0)
 
 
-def reservation_bytes(wl, factor: float = 16.0, floor: int = 1 << 30) -> int:
+def reservation_bytes(wl, factor: float = 32.0, floor: int = 1 << 30) -> int:
     """Device bytes reserved for a request.
 
-    The observable holds a current and an output array, sort buffers and per-layer
-    overflow staging.  Terms can outgrow the cap inside a layer, because the cap applies
-    at the layer's end.  The reservation is `factor` arrays of the capped size, and at
-    least `floor`: output arrays are sized from the growth seen in earlier layers, which
-    can be large while the sum is still small.
+    The observable holds a current and an output array (each up to twice the capped size
+    between the gates of a run), per-term hashes and tile tables, sort buffers and the
+    first guess of a fused pass's output.  The reservation is `factor` arrays of the
+    capped size, and at least `floor`.
     """
     cap = wl.max_terms if wl.max_terms > 0 else DEFAULT_CAP
     b = term_bytes(wl.circuit.n_qubits, wl.precision, wl.mode)

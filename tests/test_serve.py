@@ -31,7 +31,7 @@ def test_reservation_rule():
     assert serve.term_bytes(56, "f64", "greedy") == 24
     assert serve.term_bytes(128, "f32k", "greedy") == 36
     assert serve.term_bytes(56, "f64", "error_order") == 25
-    assert serve.reservation_bytes(wl) == int(16.0 * (1 << 22) * 24)
+    assert serve.reservation_bytes(wl) == int(32.0 * (1 << 22) * 24)
     assert serve.reservation_bytes(_WL(cap=1)) == 1 << 30   # floor
 
 
