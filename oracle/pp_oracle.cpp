@@ -121,8 +121,7 @@ int angle_cos_sin(double theta, double* c, double* s) {
     *s = cs[m][1];
     return 1;
   }
-  *c = std::cos(theta);
-  *s = std::sin(theta);
+  ::sincos(theta, s, c);   // the C library's sincos (what an optimising compiler makes of cos + sin)
   return 0;
 }
 

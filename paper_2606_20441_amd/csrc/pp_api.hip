@@ -209,8 +209,8 @@ bool angle_cos_sin(double theta, double* c, double* s) {
     *s = ss[k];
     return true;
   }
-  *c = std::cos(theta);
-  *s = std::sin(theta);
+  // one call for both: the C library's sincos (a separate cos call can differ in the last bit)
+  ::sincos(theta, s, c);
   return false;
 }
 
@@ -290,7 +290,7 @@ struct Engine final : EngineBase {
   TBuf<CT, ORD> gb;              // boundary candidates of a cap
   Buf u32a, u32b, u32c, scan_scr, tiles, gates_d, sup_d, tab_d, fidx_d, dm_d, dval_d, cnt_d, ovf_d, partial_d, f64_d, span_d, htab_d;
   Buf hp_a, hp_b, tr_s0, tr_l0, tr_s1, tr_l1, g1_d, g1_ovf, g1_base, g1_drop;   // per-gate tile path
-  Buf rl0, rl1, ovl1, ovl2, tf_flag, tf_pos, tf_list, g1_io;
+  Buf rl0, rl1, ovl1, ovl2, tf_flag, tf_pos, tf_list, g1_io, g1_tab, g1_tabmeta;
   double growth[4] = {4.0, 4.0, 2.0, 3.0};
   double tile_target[4] = {80.0, 80.0, 80.0, 64.0};   // level-0 (one-wavefront) tile targets
   uint64_t last_ntiles = 1, last_ovf_tiles = 0;
@@ -300,7 +300,7 @@ struct Engine final : EngineBase {
     for (auto* t : {&ta, &tb}) { t->mem.ctx = ctx; t->W = W; }
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &fidx_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
                    &partial_d, &f64_d, &span_d, &htab_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_drop, &rl0, &rl1, &ovl1, &ovl2,
-                   &tf_flag, &tf_pos, &tf_list, &g1_io})
+                   &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta})
       b->ctx = ctx;
     cnt_d.ensure(256);
     span_d.ensure(256);
@@ -313,7 +313,7 @@ struct Engine final : EngineBase {
     for (auto* t : {&ta, &tb}) t->mem.release();
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &fidx_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
                    &partial_d, &f64_d, &span_d, &htab_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_drop, &rl0, &rl1, &ovl1, &ovl2,
-                   &tf_flag, &tf_pos, &tf_list, &g1_io})
+                   &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta})
       b->release();
   }
 
@@ -1428,46 +1428,51 @@ struct Engine final : EngineBase {
         read_counters();
       }
       if (hc.ovf[2] > 0) {
-        // groups too large for LDS that the gate touches: gathered and tiled by pairs
+        // classes too large for LDS that the gate touches: one workgroup per tile in its own
+        // output region, with a hash table in global memory
         const uint32_t n2 = hc.ovf[2];
-        std::vector<uint32_t> o2(n2), ts(ntiles), tl(ntiles);
+        std::vector<uint32_t> o2(n2), tl(ntiles);
         HIPCHK(hipMemcpyAsync(o2.data(), ovl2.p, 4 * (size_t)n2, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(ts.data(), tr_s0.p, 4 * ntiles, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(tl.data(), tr_l0.p, 4 * ntiles, hipMemcpyDeviceToHost, st));
         sync();
-        std::vector<uint32_t> src_r, len_r;
-        std::vector<uint64_t> dst_r;
-        uint64_t mo = 0;
-        for (uint32_t v : o2) {
-          src_r.push_back(ts[v]);
-          len_r.push_back(tl[v]);
-          dst_r.push_back(mo);
-          mo += tl[v];
+        std::vector<uint64_t> off(n2);
+        std::vector<uint32_t> hs(n2);
+        uint64_t tot = 0;
+        for (uint32_t b = 0; b < n2; ++b) {
+          const uint32_t n0 = tl[o2[b]];
+          uint32_t h = 64;
+          while (h < 2 * n0) h <<= 1;
+          off[b] = tot;
+          hs[b] = h;
+          tot += h;
+          ls.n_fallback += n0;
         }
-        sa.ensure(std::max<uint64_t>(mo, 1));
-        u32c.ensure(8 * (size_t)n2 + 64);
-        partial_d.ensure(8 * (size_t)n2 + 64);
-        u32b.ensure(8 * (size_t)n2 + 64);
-        HIPCHK(hipMemcpyAsync(u32b.p, src_r.data(), 4 * (size_t)n2, hipMemcpyHostToDevice, st));
-        HIPCHK(hipMemcpyAsync(u32c.p, len_r.data(), 4 * (size_t)n2, hipMemcpyHostToDevice, st));
-        HIPCHK(hipMemcpyAsync(partial_d.p, dst_r.data(), 8 * (size_t)n2, hipMemcpyHostToDevice, st));
-        const Terms<CT> in = cur.view(), sub = sa.view();
-        const uint32_t *srcd = u32b.as<uint32_t>(), *lend = u32c.as<uint32_t>();
-        const uint64_t* dstd = partial_d.as<uint64_t>();
-        ctx->run("copy_ranges", 0, (double)mo, [&] {
-          hipLaunchKernelGGL((k_copy_ranges<W, CT, ORD>), dim3(n2), dim3(256), 0, st, in, sub, srcd, lend, dstd,
-                             (int)n2);
+        g1_tab.ensure(tot * 4 + 64);
+        g1_tabmeta.ensure(12 * (size_t)n2 + 64);
+        HIPCHK(hipMemsetAsync(g1_tab.p, 0xff, tot * 4, st));
+        uint64_t* offd = g1_tabmeta.as<uint64_t>();
+        uint32_t* hsd = (uint32_t*)(offd + n2);
+        HIPCHK(hipMemcpyAsync(offd, off.data(), 8 * (size_t)n2, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(hsd, hs.data(), 4 * (size_t)n2, hipMemcpyHostToDevice, st));
+        Gate1Args<CT> b = with_list(ovl2, ovl2, 2, 0);
+        g1_io.ensure(2 * kDropSlots * 8 + 64);
+        b.io = g1_io.as<unsigned long long>();
+        if (ctx->timing) HIPCHK(hipMemsetAsync(b.io, 0, 2 * kDropSlots * 8, st));
+        uint32_t* tabd = g1_tab.as<uint32_t>();
+        const int pi = ctx->run("gate_tile_global", 0, (double)n2, [&] {
+          hipLaunchKernelGGL((k_gate1_big<W, CT, ORD>), dim3(n2), dim3(1024), 0, st, b, tabd, (const uint64_t*)offd,
+                             (const uint32_t*)hsd);
         });
         ctx->check_launch();
-        sync();
-        uint64_t mm = mo;
-        if (cut.has) mm = cut_subset(mm, cut);   // the pending cut, on this subset
-        ls.n_fallback += (int64_t)mm;
-        uint64_t oc = out_extent;
-        run_groups(sa, mm, {G}, kind, G.clifford ? 0.0 : eps, nullptr, 0.0, alt, oc, 0, ls);
-        giant_terms = oc - out_extent;
-        out_extent = oc;
-        need_tiles = true;   // these terms are no longer laid out by tile
+        if (pi >= 0) {
+          std::vector<unsigned long long> h(2 * kDropSlots);
+          HIPCHK(hipMemcpyAsync(h.data(), b.io, h.size() * 8, hipMemcpyDeviceToHost, st));
+          sync();
+          double terms = 0.0;
+          for (unsigned long long v : h) terms += (double)v;
+          ctx->pending[pi].bytes = kTermBytes * terms;
+        }
+        sync();   // host vectors above are copy sources
       }
       std::vector<double> dsl(kDropSlots);
       HIPCHK(hipMemcpyAsync(dsl.data(), dropd, kDropSlots * 8, hipMemcpyDeviceToHost, st));

@@ -98,6 +98,7 @@ __device__ void pass_through(const Gate1Args<CT>& a, uint32_t tile, uint32_t t0,
   auto keep = [&](uint64_t src) {
     const CT v = a.in.c[src];
     if (v == (CT)0) return false;
+    if (fabs((double)v) < a.eps) return false;   // the threshold after a non-Clifford gate
     if (!a.cut.has) return true;
     uint64_t kx[W], kz[W];
 #pragma unroll
@@ -264,7 +265,11 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
   for (int r = 0; r < R; ++r) {
     const uint32_t i = (uint32_t)r * BLOCK + tid;
     if (i >= n0 || rc[r] == 0.0) continue;
-    if (!anticommutes<W>(rkx[r], rkz[r], m)) continue;
+    if (!anticommutes<W>(rkx[r], rkz[r], m)) {
+      // untouched, but the threshold after a non-Clifford gate covers every term
+      if (fabs(rc[r]) < thr) { lost += fabs(rc[r]); sc[i] = (CT)0; }
+      continue;
+    }
     const double ci = rc[r];
     if (snd == 0.0) {            // cos = +-1, sin = 0: a sign, no branching
       sc[i] = (CT)(ci * cs);
@@ -391,6 +396,190 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
     if (ORD) a.out.o[dst] = so[i];
     a.hout[dst] = sh[i];
   }
+}
+
+// A tile too large for LDS that the gate touches: one 1024-thread workgroup per tile works
+// in the tile's own output region (2 * n0 slots) with an open-addressing table in global
+// memory (table[off[b] .. off[b] + hsize[b]), hsize a power of two >= 2 * n0, preset to
+// ~0), then compacts the region in place.  Same arithmetic as k_gate1.
+template <int W, class CT, bool ORD>
+__global__ void __launch_bounds__(1024) k_gate1_big(Gate1Args<CT> a, uint32_t* table, const uint64_t* off,
+                                                    const uint32_t* hsize) {
+  constexpr int BLOCK = 1024;
+  constexpr int NW = BLOCK / 64;
+  constexpr uint32_t EMPTY = 0xffffffffu;
+  __shared__ uint32_t s_new;
+  __shared__ uint32_t s_wsum[NW];
+  __shared__ uint32_t s_done;
+  __shared__ double s_drop[NW];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const uint32_t tile = a.t_list[blockIdx.x];
+  const uint64_t t0 = a.t_start[tile];
+  const uint32_t n0 = a.t_len[tile];
+  const uint64_t base = a.o_base[tile];
+  uint32_t* tab = table + off[blockIdx.x];
+  const uint32_t hm = hsize[blockIdx.x] - 1;
+  uint64_t m[2 * W];
+#pragma unroll
+  for (int w = 0; w < 2 * W; ++w) m[w] = a.g.m[w];
+  const double cs = a.g.cs, snd = a.g.sn_dir, thr = a.eps;
+  const uint32_t gh = a.g.hash;
+  const int pw = a.g.pivot_word, pb = a.g.pivot_bit;
+  Terms<CT> o = a.out;
+  if (tid == 0) { s_new = 0; s_done = 0; }
+  double lost = 0.0;
+  auto okey = [&](uint64_t j, uint64_t* kx, uint64_t* kz) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) { kx[w] = o.x[w * o.stride + j]; kz[w] = o.z[w * o.stride + j]; }
+  };
+  // copy into the region, apply the pending cut, insert the live terms
+  for (uint32_t i = tid; i < n0; i += BLOCK) {
+    uint64_t kx[W], kz[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      kx[w] = a.in.x[w * a.in.stride + t0 + i];
+      kz[w] = a.in.z[w * a.in.stride + t0 + i];
+      o.x[w * o.stride + base + i] = kx[w];
+      o.z[w * o.stride + base + i] = kz[w];
+    }
+    const uint32_t oi = ORD ? a.in.o[t0 + i] : 0u;
+    if (ORD) o.o[base + i] = (uint8_t)oi;
+    const uint32_t h = a.hin[t0 + i];
+    a.hout[base + i] = h;
+    const CT cv = a.in.c[t0 + i];
+    CT keep = cv;
+    if (cv != (CT)0 && !cut_keeps<W, CT>(cv, kx, kz, oi, a.cut)) {
+      lost += fabs((double)cv);
+      keep = (CT)0;
+    }
+    o.c[base + i] = keep;
+    if (keep != (CT)0) {
+      uint32_t slot = (h ^ (oi * 0x9e3779b9u)) & hm;
+      while (atomicCAS(&tab[slot], EMPTY, i) != EMPTY) slot = (slot + 1) & hm;
+    }
+  }
+  __syncthreads();
+  // the gate
+  for (uint32_t i = tid; i < n0; i += BLOCK) {
+    const double ci = (double)o.c[base + i];
+    if (ci == 0.0) continue;
+    uint64_t kx[W], kz[W];
+    okey(base + i, kx, kz);
+    if (!anticommutes<W>(kx, kz, m)) {
+      if (fabs(ci) < thr) { lost += fabs(ci); o.c[base + i] = (CT)0; }   // threshold on every term
+      continue;
+    }
+    if (snd == 0.0) {
+      o.c[base + i] = (CT)(ci * cs);
+      continue;
+    }
+    const uint32_t oi = ORD ? o.o[base + i] : 0u;
+    const uint32_t h = a.hout[base + i];
+    const bool neg_i = irp_negative<W>(kx, kz, m, a.g.rr_phase);
+    uint64_t qx[W], qz[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) { qx[w] = kx[w] ^ m[w]; qz[w] = kz[w] ^ m[W + w]; }
+    if (cs == 0.0) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) { o.x[w * o.stride + base + i] = qx[w]; o.z[w * o.stride + base + i] = qz[w]; }
+      a.hout[base + i] = h ^ gh;
+      o.c[base + i] = (CT)((neg_i ? -ci : ci) * snd);
+      continue;
+    }
+    const uint32_t hq = h ^ gh;
+    uint32_t slot = (hq ^ (oi * 0x9e3779b9u)) & hm;
+    uint32_t j = EMPTY;
+    for (;;) {
+      const uint32_t k = tab[slot];
+      if (k == EMPTY) break;
+      if (a.hout[base + k] == hq && (!ORD || o.o[base + k] == oi)) {
+        uint64_t px[W], pz[W];
+        okey(base + k, px, pz);
+        bool eq = true;
+#pragma unroll
+        for (int w = 0; w < W; ++w) eq = eq && px[w] == qx[w] && pz[w] == qz[w];
+        if (eq) { j = k; break; }
+      }
+      slot = (slot + 1) & hm;
+    }
+    if (j != EMPTY) {
+      const uint64_t pv = pw < W ? pick<W>(kx, pw) : pick<W>(kz, pw - W);
+      if ((pv >> pb) & 1ULL) continue;
+      const double cj = (double)o.c[base + j];
+      const bool neg_j = irp_negative<W>(qx, qz, m, a.g.rr_phase);
+      double ni = ci * cs + (neg_j ? -cj : cj) * snd;
+      double nj = cj * cs + (neg_i ? -ci : ci) * snd;
+      if (fabs(ni) < thr || ni == 0.0) { lost += fabs(ni); ni = 0.0; }
+      if (fabs(nj) < thr || nj == 0.0) { lost += fabs(nj); nj = 0.0; }
+      o.c[base + i] = (CT)ni;
+      o.c[base + j] = (CT)nj;
+    } else {
+      double ni = ci * cs;
+      const double nq = (neg_i ? -ci : ci) * snd;
+      if (fabs(ni) < thr || ni == 0.0) { lost += fabs(ni); ni = 0.0; }
+      o.c[base + i] = (CT)ni;
+      if (fabs(nq) < thr || nq == 0.0) {
+        lost += fabs(nq);
+      } else {
+        const uint64_t k = base + n0 + atomicAdd(&s_new, 1u);   // at most one child per term: fits 2 * n0
+#pragma unroll
+        for (int w = 0; w < W; ++w) { o.x[w * o.stride + k] = qx[w]; o.z[w * o.stride + k] = qz[w]; }
+        if (ORD) o.o[k] = (uint8_t)oi;
+        o.c[k] = (CT)nq;
+        a.hout[k] = hq;
+      }
+    }
+  }
+  __syncthreads();
+  // compact the region in place, chunk by chunk (destinations never pass their sources)
+  const uint32_t n = n0 + s_new;
+  uint32_t written = 0;
+  for (uint32_t c0 = 0; c0 < n; c0 += BLOCK) {
+    const uint32_t i = c0 + tid;
+    const bool live = i < n && o.c[base + i] != (CT)0;
+    uint64_t kx[W], kz[W];
+    CT cv = (CT)0;
+    uint32_t h = 0, oi = 0;
+    if (live) {
+      okey(base + i, kx, kz);
+      cv = o.c[base + i];
+      h = a.hout[base + i];
+      if (ORD) oi = o.o[base + i];
+    }
+    const uint64_t bal = __ballot(live);
+    const uint32_t below = (uint32_t)__popcll(bal & ((1ULL << lane) - 1ULL));
+    if (lane == 0) s_wsum[tid >> 6] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (int w = 0; w < NW; ++w) {
+      before += (w < (tid >> 6)) ? s_wsum[w] : 0u;
+      total += s_wsum[w];
+    }
+    if (live) {
+      const uint64_t d = base + written + before + below;
+#pragma unroll
+      for (int w = 0; w < W; ++w) { o.x[w * o.stride + d] = kx[w]; o.z[w * o.stride + d] = kz[w]; }
+      o.c[d] = cv;
+      if (ORD) o.o[d] = (uint8_t)oi;
+      a.hout[d] = h;
+    }
+    written += total;
+    __syncthreads();
+  }
+  for (uint64_t i = base + written + tid; i < base + 2ULL * n0; i += BLOCK) o.c[i] = (CT)0;
+  for (int d = 32; d >= 1; d >>= 1) lost += __shfl_xor(lost, d, 64);
+  if (lane == 0) s_drop[tid >> 6] = lost;
+  __syncthreads();
+  if (tid == 0) {
+    a.o_start[tile] = (uint32_t)base;
+    a.o_len[tile] = written;
+    double v = 0.0;
+    for (int w = 0; w < NW; ++w) v += s_drop[w];
+    if (v != 0.0) atomicAdd(&a.dropped[blockIdx.x % kDropSlots], v);
+    atomicAdd(&a.io[blockIdx.x % kDropSlots], (unsigned long long)n0);
+    atomicAdd(&a.io[kDropSlots + blockIdx.x % kDropSlots], (unsigned long long)written);
+  }
+  (void)s_done;
 }
 
 // Per-term linear hash of the string (order tag not included).

@@ -212,6 +212,38 @@ def test_group_overflow_falls_back(pp, ctx, orc):
     compare_sums(g.as_dict(), o.as_dict(), thresholds=[1e-12], rtol=0.0, atol=0.0, context="overflow")
 
 
+@pytest.mark.parametrize("cap", [40000, 15000])
+@pytest.mark.parametrize("W_qubits", [20, 100])
+def test_capped_gates_with_oversize_classes(pp, ctx, orc, cap, W_qubits):
+    """Gate by gate under a binding cap, with z-classes far larger than an LDS tile: 2^14
+    strings share one z (all x patterns on its 14 qubits), plus smaller classes; every X
+    rotation on those qubits pairs the whole class."""
+    n = W_qubits
+    rng = np.random.default_rng(5 + n)
+    zq = list(range(14))
+    terms = []
+    for xm in range(1 << 14):
+        ops = {q: ("Y" if (xm >> i) & 1 else "Z") for i, q in enumerate(zq)}
+        terms.append((ops, float(rng.uniform(-1, 1))))
+    for k in range(3000):   # smaller classes elsewhere
+        qs = rng.choice(np.arange(14, n), 4, replace=False)
+        terms.append(({int(q): "XYZ"[int(rng.integers(0, 3))] for q in qs}, float(rng.uniform(-1, 1))))
+    ps = W.pauli_sum(n, terms)
+    layer = W.make_layer(n, [({q: "X"}, 0.4 + 0.01 * q) for q in range(n)], [])
+    log(f"oversize classes: n={n} cap={cap} terms={len(ps.c)}")
+    for direction in (1, -1):
+        g = pp.Observable.from_sum(ctx, ps, eps=1e-4, max_terms=cap)
+        o = orc.OracleSum.from_sum(ps)
+        g.apply_layer(layer, direction, with_noise=False)
+        st = g.last_layer_stats()
+        o.apply_layer(layer, direction, with_noise=False, eps=1e-4, max_terms=cap)
+        assert st["n_fallback"] > 0
+        gd, od = g.as_dict(), o.as_dict()
+        assert set(gd) == set(od)
+        assert all(gd[k] == od[k] for k in od)   # no noise: the arithmetic is identical
+        assert len(gd) <= cap
+
+
 def test_invalid_arguments_leave_state(pp, ctx):
     ps = W.random_pauli_sum(56, 50, seed=1)
     g = pp.Observable.from_sum(ctx, ps)
