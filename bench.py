@@ -40,7 +40,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_gpu(ctx, wl, precision, steps, warmup, layers_verbose=False):
+def run_gpu(ctx, wl, precision, steps, warmup, layers_verbose=False, progress=False):
     import torch
     from paper_2606_20441_amd import pp
 
@@ -71,7 +71,7 @@ def run_gpu(ctx, wl, precision, steps, warmup, layers_verbose=False):
     total_upd = 0
     res = None
     for _ in range(steps):
-        u, e, n = one()
+        u, e, n = one(verbose=progress)
         total_upd += u
         res = (e, n)
     torch.cuda.synchronize()
@@ -208,6 +208,8 @@ def main():
     ap.add_argument("--workload", default="tfim7x8_pna")
     ap.add_argument("--precision", default="both", choices=["both", "f64", "f32k"])
     ap.add_argument("--layers", action="store_true", help="print per-layer counts of the first warmup step")
+    ap.add_argument("--progress", action="store_true", help="print per-layer counts of the timed steps too")
+    ap.add_argument("--max-terms", type=int, default=None, help="override the workload's cap")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--serve-requests", type=int, default=30,
@@ -234,14 +236,14 @@ def main():
         copy_probe(args.copy_probe)
         return
     pp.lib()
-    wl = W.named_workload(args.workload)
+    wl = W.named_workload(args.workload, **({} if args.max_terms is None else {"max_terms": args.max_terms}))
     ctx = pp.Context(0)
     Wd = wl.circuit.W
     results = {}
     precs = ["f64", "f32k"] if args.precision == "both" else [args.precision]
     for prec in precs:
         log(f"== {args.workload} {prec}: warmup {args.warmup}, steps {args.steps}")
-        r = run_gpu(ctx, wl, prec, args.steps, args.warmup, layers_verbose=args.layers)
+        r = run_gpu(ctx, wl, prec, args.steps, args.warmup, layers_verbose=args.layers, progress=args.progress)
         tb = 16 * Wd + (8 if prec == "f64" else 4) + (1 if wl.mode == "error_order" else 0)
         r["term_bytes"] = tb
         r["roofline"] = roofline(r["kernels"], tb, prec)

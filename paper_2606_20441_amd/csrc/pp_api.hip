@@ -1115,6 +1115,8 @@ struct Engine final : EngineBase {
   static constexpr uint64_t kG1Target = 96;     // terms per one-wavefront tile when tiling
   static constexpr uint32_t kG1Big = 160;       // a tile above this may outgrow 256 at the next gate
   uint64_t g1_ntiles = 0;
+  bool routed = false;      // tile lists by size are current for this tiling
+  uint32_t route_n[2] = {0, 0};
 
   // Group the terms by the run's invariant bits, cut them into tiles of whole groups and
   // compute the per-term hash plane (cur must be dense).
@@ -1144,6 +1146,7 @@ struct Engine final : EngineBase {
     });
     ctx->check_launch();
     g1_ntiles = ntiles;
+    routed = false;
   }
 
   // Output bases of the tiles for the next gate: exclusive prefix of 2 * len.  Returns the
@@ -1227,40 +1230,8 @@ struct Engine final : EngineBase {
                          cntd);
     });
     ctx->check_launch();
-    const uint64_t m = count_eq;
-    std::vector<uint64_t> gx(m * W), gz(m * W);
-    std::vector<CT> gc(m);
-    std::vector<uint8_t> go(m, 0);
-    for (int w = 0; w < W; ++w) {
-      HIPCHK(hipMemcpyAsync(gx.data() + (size_t)w * m, g.x + (size_t)w * g.stride, m * 8, hipMemcpyDeviceToHost, st));
-      HIPCHK(hipMemcpyAsync(gz.data() + (size_t)w * m, g.z + (size_t)w * g.stride, m * 8, hipMemcpyDeviceToHost, st));
-    }
-    HIPCHK(hipMemcpyAsync(gc.data(), g.c, m * sizeof(CT), hipMemcpyDeviceToHost, st));
-    if (ORD) HIPCHK(hipMemcpyAsync(go.data(), g.o, m, hipMemcpyDeviceToHost, st));
     sync();
-    std::vector<uint32_t> idx(m);
-    for (uint32_t i = 0; i < m; ++i) idx[i] = i;
-    auto before = [&](uint32_t a, uint32_t b) {   // a precedes b in the cap order
-      const uint64_t ka = abs_key_host(gc[a]), kb = abs_key_host(gc[b]);
-      if (ka != kb) return ka > kb;
-      for (int w = W - 1; w >= 0; --w)
-        if (gx[(size_t)w * m + a] != gx[(size_t)w * m + b]) return gx[(size_t)w * m + a] < gx[(size_t)w * m + b];
-      for (int w = W - 1; w >= 0; --w)
-        if (gz[(size_t)w * m + a] != gz[(size_t)w * m + b]) return gz[(size_t)w * m + a] < gz[(size_t)w * m + b];
-      return go[a] < go[b];
-    };
-    if (need < 1 || need > m) throw_fail(PP_ERR_DEVICE, "cap selection lost its boundary");
-    std::nth_element(idx.begin(), idx.begin() + (need - 1), idx.end(), before);
-    const uint32_t bi = idx[need - 1];
-    CutDev cut{};
-    cut.has = 1;
-    cut.val = abs_key_host(gc[bi]);
-    for (int w = 0; w < W; ++w) {
-      cut.x[w] = gx[(size_t)w * m + bi];
-      cut.z[w] = gz[(size_t)w * m + bi];
-    }
-    cut.o = go[bi];
-    return cut;
+    return rank_bucket(g, count_eq, need);
   }
 
   // Drop the terms a cut removes (and exact zeros) from cur (N slots).
@@ -1339,6 +1310,43 @@ struct Engine final : EngineBase {
     }
   }
 
+  // The need-th term (1-based) of m gathered candidates in the cap order.
+  CutDev rank_bucket(const Terms<CT>& g, uint64_t m, uint64_t need) {
+    std::vector<uint64_t> gx(m * W), gz(m * W);
+    std::vector<CT> gc(m);
+    std::vector<uint8_t> go(m, 0);
+    for (int w = 0; w < W; ++w) {
+      HIPCHK(hipMemcpyAsync(gx.data() + (size_t)w * m, g.x + (size_t)w * g.stride, m * 8, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(gz.data() + (size_t)w * m, g.z + (size_t)w * g.stride, m * 8, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipMemcpyAsync(gc.data(), g.c, m * sizeof(CT), hipMemcpyDeviceToHost, st));
+    if (ORD) HIPCHK(hipMemcpyAsync(go.data(), g.o, m, hipMemcpyDeviceToHost, st));
+    sync();
+    std::vector<uint32_t> idx(m);
+    for (uint32_t i = 0; i < m; ++i) idx[i] = i;
+    auto before = [&](uint32_t a, uint32_t b) {   // a precedes b in the cap order
+      const uint64_t ka = abs_key_host(gc[a]), kb = abs_key_host(gc[b]);
+      if (ka != kb) return ka > kb;
+      for (int w = W - 1; w >= 0; --w)
+        if (gx[(size_t)w * m + a] != gx[(size_t)w * m + b]) return gx[(size_t)w * m + a] < gx[(size_t)w * m + b];
+      for (int w = W - 1; w >= 0; --w)
+        if (gz[(size_t)w * m + a] != gz[(size_t)w * m + b]) return gz[(size_t)w * m + a] < gz[(size_t)w * m + b];
+      return go[a] < go[b];
+    };
+    if (need < 1 || need > m) throw_fail(PP_ERR_DEVICE, "cap selection lost its boundary");
+    std::nth_element(idx.begin(), idx.begin() + (need - 1), idx.end(), before);
+    const uint32_t bi = idx[need - 1];
+    CutDev cut{};
+    cut.has = 1;
+    cut.val = abs_key_host(gc[bi]);
+    for (int w = 0; w < W; ++w) {
+      cut.x[w] = gx[(size_t)w * m + bi];
+      cut.z[w] = gz[(size_t)w * m + bi];
+    }
+    cut.o = go[bi];
+    return cut;
+  }
+
   // Apply `gates` one at a time with the cap after each non-Clifford gate (Section I.A's
   // truncation of intermediate results, taken after every such gate).  The terms are tiled
   // once by the run's invariant bits; each gate is one pass over the tiles.  Between gates
@@ -1377,18 +1385,28 @@ struct Engine final : EngineBase {
       for (Buf* b : {&rl0, &rl1, &g1_ovf, &ovl1, &ovl2}) b->ensure(ntiles * 4 + 64);
       HIPCHK(hipMemsetAsync(cd, 0, sizeof(G1Counters), st));
       HIPCHK(hipMemsetAsync(dropd, 0, kDropSlots * 8, st));
-      hipLaunchKernelGGL(k_route_tiles, grid1(ntiles), dim3(256), 0, st, (const uint32_t*)tr_l0.as<uint32_t>(),
-                         (uint32_t)ntiles, kG1SmallMax, (const uint32_t*)g1_base.as<uint32_t>(),
-                         tr_s1.as<uint32_t>(), tr_l1.as<uint32_t>(), rl0.as<uint32_t>(), rl1.as<uint32_t>(),
-                         &cd->nlist[0]);
-      ctx->check_launch();
       G1Counters hc;
       auto read_counters = [&]() {
         HIPCHK(hipMemcpyAsync(ctx->pinned, cd, sizeof hc, hipMemcpyDeviceToHost, st));
         sync();
         std::memcpy(&hc, ctx->pinned, sizeof hc);
       };
-      read_counters();
+      if (!routed) {
+        // sort the tiles by size once per tiling (a tile changes size slowly; one that
+        // outgrows the wavefront shape is retried in the next shape)
+        hipLaunchKernelGGL(k_route_tiles, grid1(ntiles), dim3(256), 0, st, (const uint32_t*)tr_l0.as<uint32_t>(),
+                           (uint32_t)ntiles, kG1SmallMax, (const uint32_t*)g1_base.as<uint32_t>(),
+                           tr_s1.as<uint32_t>(), tr_l1.as<uint32_t>(), rl0.as<uint32_t>(), rl1.as<uint32_t>(),
+                           &cd->nlist[0]);
+        ctx->check_launch();
+        read_counters();
+        route_n[0] = hc.nlist[0];
+        route_n[1] = hc.nlist[1];
+        routed = true;
+        HIPCHK(hipMemsetAsync(cd, 0, sizeof(G1Counters), st));
+      }
+      hc.nlist[0] = route_n[0];
+      hc.nlist[1] = route_n[1];
       Gate1Args<CT> a{};
       a.in = cur.view();
       a.out = alt.view();
@@ -1417,8 +1435,14 @@ struct Engine final : EngineBase {
       // one wavefront for small tiles; 256 threads for the others and for small tiles that grew
       if (hc.nlist[0]) g1_launch<SmallCfg<W>::CAP, SmallCfg<W>::BLOCK>(with_list(rl0, g1_ovf, 0, 0), hc.nlist[0], 0);
       if (hc.nlist[1]) g1_launch<1024, 256>(with_list(rl1, ovl1, 1, 0), hc.nlist[1], 1);
-      read_counters();
+      {
+        const uint32_t n0l = hc.nlist[0], n1l = hc.nlist[1];
+        read_counters();
+        hc.nlist[0] = n0l;
+        hc.nlist[1] = n1l;
+      }
       if (hc.ovf[0]) {
+        if (hc.ovf[0] * 16 > hc.nlist[0]) routed = false;   // many tiles outgrew the wavefront shape
         g1_launch<1024, 256>(with_list(g1_ovf, ovl1, 1, 0), hc.ovf[0], 1);
         read_counters();
       }
