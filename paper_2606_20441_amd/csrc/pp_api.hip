@@ -630,6 +630,7 @@ struct Engine final : EngineBase {
           for (int k : groups[si]) cnt += anti_pat(k, q0, q1, pat);
           slots = std::max(slots, cnt);
         }
+        slots = (slots + 3) & ~3;   // rows of whole 4-index groups (padding: the 1.0)
         SupportDev sd = make_sup(q0, q1);
         sd.table = (int32_t)hn.fidx.size();
         sd.nslot = (int16_t)slots;
@@ -1182,23 +1183,63 @@ struct Engine final : EngineBase {
   // select on the |c| bits narrows the K-th largest to a bucket of few candidates, which
   // are gathered and ranked exactly on the host by (|c| descending, canonical key
   // ascending); the K-th of that order is the boundary term.
+  // Last cut of this engine: the next cut's first histogram spans a window around it.
+  bool hint_valid = false;
+  uint64_t hint_key = 0;
+  int hint_shift = sizeof(CT) == 8 ? 43 : 14;   // 2048 bins of 2^shift keys: about 4 octaves
+
   CutDev cap_cut(uint64_t K, uint64_t n) {
     constexpr uint32_t kGather = 4096;
     const int KB = sizeof(CT) == 8 ? 63 : 31;
     uint64_t prefix = 0, pmask = 0, need = K, count_eq = 0;
-    u32a.ensure(2048 * 4 + 64);
+    u32a.ensure(2049 * 4 + 64);
     uint32_t* hist = u32a.as<uint32_t>();
     const CT* c = cur.view().c;
     int hi = KB;
-    std::vector<uint32_t> h(2048);
-    while (hi > 0) {
+    std::vector<uint32_t> h(2049);
+    const unsigned nbh = (unsigned)std::min<uint64_t>(2048, cdiv(n, 256));
+    bool done = false;
+    if (hint_valid) {
+      // The window's bins are the key prefixes above bit `shift`, so a hit continues the
+      // radix passes below it; a miss falls back to the passes from the top.
+      const int sh = hint_shift;
+      const uint64_t half = 1024ULL << sh;
+      const uint64_t lo = hint_key > half ? ((hint_key - half) >> sh) << sh : 0ULL;
+      HIPCHK(hipMemsetAsync(hist, 0, 2049 * 4, st));
+      ctx->run("cap_hist", sizeof(CT) * (double)n, (double)n, [&] {
+        hipLaunchKernelGGL((k_abs_hist_win<CT>), dim3(nbh), dim3(256), 0, st, c, n, lo, sh, hist);
+      });
+      ctx->check_launch();
+      HIPCHK(hipMemcpyAsync(ctx->pinned, hist, 2049 * 4, hipMemcpyDeviceToHost, st));
+      sync();
+      std::memcpy(h.data(), ctx->pinned, 2049 * 4);
+      uint64_t cum = h[2048];
+      int d = -1;
+      if (cum < need) {
+        for (d = 2047; d >= 0; --d) {
+          if (cum + h[d] >= need) break;
+          cum += h[d];
+        }
+      }
+      if (d >= 0) {
+        need -= cum;
+        prefix = lo + ((uint64_t)d << sh);
+        pmask = ~0ULL << sh;
+        count_eq = h[d];
+        hi = sh;
+        done = count_eq <= kGather;
+        if (!done && hint_shift > 4) --hint_shift;   // finer bins next time
+      } else {
+        hint_shift = std::min(hint_shift + 2, KB - 11);   // wider window next time
+      }
+    }
+    while (hi > 0 && !done) {
       const int bits = std::min(11, hi);
       const int shift = hi - bits;
       const int bins = 1 << bits;
       HIPCHK(hipMemsetAsync(hist, 0, bins * 4, st));
-      const unsigned nb = (unsigned)std::min<uint64_t>(2048, cdiv(n, 256));
       ctx->run("cap_hist", sizeof(CT) * (double)n, (double)n, [&] {
-        hipLaunchKernelGGL((k_abs_hist<CT>), dim3(nb), dim3(256), 0, st, c, n, shift, bits, pmask, prefix, hist);
+        hipLaunchKernelGGL((k_abs_hist<CT>), dim3(nbh), dim3(256), 0, st, c, n, shift, bits, pmask, prefix, hist);
       });
       ctx->check_launch();
       HIPCHK(hipMemcpyAsync(ctx->pinned, hist, bins * 4, hipMemcpyDeviceToHost, st));
@@ -1231,7 +1272,10 @@ struct Engine final : EngineBase {
     });
     ctx->check_launch();
     sync();
-    return rank_bucket(g, count_eq, need);
+    const CutDev cut = rank_bucket(g, count_eq, need);
+    hint_valid = true;
+    hint_key = cut.val;
+    return cut;
   }
 
   // Drop the terms a cut removes (and exact zeros) from cur (N slots).

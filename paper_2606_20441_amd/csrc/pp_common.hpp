@@ -35,7 +35,7 @@ struct Terms {
 struct SupportDev {
   int16_t w0, b0, w1, b1;   // word/bit of the two qubits (w1 < 0: single qubit)
   int32_t table;            // offset into the value table
-  int16_t nslot;            // greedy mode: factor slots per pattern
+  int16_t nslot;            // greedy mode: factor slots per pattern (a multiple of 4)
   int16_t pad;
 };
 

@@ -250,6 +250,26 @@ __global__ void __launch_bounds__(256) k_abs_hist(const CT* c, uint64_t n, int s
     if (h[b]) atomicAdd(&hist[b], h[b]);
 }
 
+// Histogram of |c| keys over the window [lo, lo + 2048 * 2^shift): bins of 2^shift keys,
+// hist[2048] counts the keys above the window (lo is a multiple of 2^shift).
+template <class CT>
+__global__ void __launch_bounds__(256) k_abs_hist_win(const CT* c, uint64_t n, uint64_t lo, int shift,
+                                                      uint32_t* hist) {
+  __shared__ uint32_t h[2049];
+  for (int b = threadIdx.x; b < 2049; b += 256) h[b] = 0;
+  __syncthreads();
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+    const uint64_t k = abs_key<CT>(c[i]);
+    if (k >= lo) {
+      const uint64_t d = (k - lo) >> shift;
+      atomicAdd(&h[d < 2048 ? d : 2048], 1u);
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < 2049; b += 256)
+    if (h[b]) atomicAdd(&hist[b], h[b]);
+}
+
 // keep: |c| > tau, or |c| == tau and marked; ties flagged for the tie-break list.  Only the
 // key bits in pmask take part (the selection may stop at a bucket that is kept whole).
 template <class CT>
