@@ -323,6 +323,10 @@ struct Engine final : EngineBase {
   // bounded grid for grid-stride kernels that reduce per block
   static dim3 gridb(uint64_t n) { return dim3((unsigned)std::min<uint64_t>(2048, std::max<uint64_t>(1, cdiv(n, 256)))); }
 
+  // Grid of the elementwise kernels that stage tables in LDS: 1024-thread blocks (a block's
+  // tables serve 16 wavefronts), two per compute unit, grid-stride over the terms.
+  static unsigned table_grid(uint64_t n) { return (unsigned)std::min<uint64_t>(cdiv(n, 1024), 512); }
+
   void sync() { HIPCHK(hipStreamSynchronize(st)); }
 
   // ---- scans ---------------------------------------------------------------------------------
@@ -723,9 +727,8 @@ struct Engine final : EngineBase {
     if (lds > kNoiseLdsMax)
       HIPCHK(hipFuncSetAttribute((const void*)k_noise_greedy<W, CT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)lds));
-    const unsigned nb = (unsigned)std::min<uint64_t>(cdiv(n, 256), 4096);
     ctx->run(name, 2.0 * kTermBytes * n, (double)n, [&] {
-      hipLaunchKernelGGL((k_noise_greedy<W, CT>), dim3(nb), dim3(256), lds, st, t, n, nd);
+      hipLaunchKernelGGL((k_noise_greedy<W, CT>), dim3(table_grid(n)), dim3(1024), lds, st, t, n, nd);
     });
     ctx->check_launch();
   }
@@ -1656,9 +1659,9 @@ struct Engine final : EngineBase {
         if (lds > kNoiseLdsMax)
           HIPCHK(hipFuncSetAttribute((const void*)k_clifford<W, CT, ORD>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        const unsigned nb = (unsigned)std::min<uint64_t>(cdiv(n, 256), 4096);
         ctx->run("clifford_layer", 2.0 * kTermBytes * n, (double)n, [&] {
-          hipLaunchKernelGGL((k_clifford<W, CT, ORD>), dim3(nb), dim3(256), lds, st, t, n, gd, ng, with_noise, nd);
+          hipLaunchKernelGGL((k_clifford<W, CT, ORD>), dim3(table_grid(n)), dim3(1024), lds, st, t, n, gd, ng,
+                             with_noise, nd);
         });
         ctx->check_launch();
         sync();   // gv is a host vector

@@ -829,7 +829,7 @@ __device__ __forceinline__ void stage_noise(const NoiseDev& nd, double* stab, Su
 // apply the gates (staged in LDS) in order in registers, optionally followed by the
 // greedy-mode rescale (tables staged in dynamic LDS after the gates).
 template <int W, class CT, bool ORD>
-__global__ void __launch_bounds__(256) k_clifford(Terms<CT> t, uint64_t n, const GateDev* gates, int ngates,
+__global__ void __launch_bounds__(1024) k_clifford(Terms<CT> t, uint64_t n, const GateDev* gates, int ngates,
                                                   int has_noise, NoiseDev nd) {
   extern __shared__ double dsm[];
   GateDev* sg = (GateDev*)dsm;
@@ -867,7 +867,7 @@ __global__ void __launch_bounds__(256) k_clifford(Terms<CT> t, uint64_t n, const
 }
 
 template <int W, class CT>
-__global__ void __launch_bounds__(256) k_noise_greedy(Terms<CT> t, uint64_t n, NoiseDev nd) {
+__global__ void __launch_bounds__(1024) k_noise_greedy(Terms<CT> t, uint64_t n, NoiseDev nd) {
   extern __shared__ double dsm[];
   double* stab = dsm;
   SupportDev* ssup = (SupportDev*)(stab + nd.ntab);
