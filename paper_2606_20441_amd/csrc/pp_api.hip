@@ -1116,8 +1116,11 @@ struct Engine final : EngineBase {
     uint32_t big_count;
   };
   static constexpr uint32_t kG1SmallMax = 128;   // tiles up to this size start in one wavefront
+  // LDS capacity of the one-wavefront shape: less LDS per wavefront, more of them per compute
+  // unit; a tile that outgrows it is redone in the 256-thread shape
+  static constexpr int kG1WaveCap = 256;
   static constexpr uint64_t kG1Target = 96;     // terms per one-wavefront tile when tiling
-  static constexpr uint32_t kG1Big = 160;       // a tile above this may outgrow 256 at the next gate
+  static constexpr uint32_t kG1Big = 160;       // a tile above this may outgrow the one-wavefront shape at the next gate
   uint64_t g1_ntiles = 0;
   bool routed = false;      // tile lists by size are current for this tiling
   uint32_t route_n[2] = {0, 0};
@@ -1336,14 +1339,30 @@ struct Engine final : EngineBase {
 
   // One launch of the gate pass; its algorithmic bytes (terms loaded and written by the
   // tiles it completed, times the term size) are read back when timing is on.
+  // The workgroups of k_gate1<CAPK, BLOCKK> that the device holds at once: its persistent grid.
   template <int CAPK, int BLOCKK>
-  void g1_launch(Gate1Args<CT> a, unsigned nblocks, int shape) {
+  unsigned g1_resident() {
+    static const unsigned resident = [] {
+      int dev = 0, cus = 0, per_cu = 0;
+      HIPCHK(hipGetDevice(&dev));
+      HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_gate1<W, CT, ORD, CAPK, BLOCKK>,
+                                                          BLOCKK, 0));
+      return (unsigned)std::max(1, cus * std::max(1, per_cu));
+    }();
+    return resident;
+  }
+
+  template <int CAPK, int BLOCKK>
+  void g1_launch(Gate1Args<CT> a, unsigned ntiles, int shape) {
     static const char* names[3] = {"gate_tile_wave", "gate_tile_256", "gate_tile_1024"};
     g1_io.ensure(2 * kDropSlots * 8 + 64);
     unsigned long long* io = g1_io.as<unsigned long long>();
     a.io = io;
+    a.t_count = ntiles;
+    const unsigned nblocks = std::min(ntiles, g1_resident<CAPK, BLOCKK>());
     if (ctx->timing) HIPCHK(hipMemsetAsync(io, 0, 2 * kDropSlots * 8, st));
-    const int pi = ctx->run(names[shape], 0, (double)nblocks, [&] {
+    const int pi = ctx->run(names[shape], 0, (double)ntiles, [&] {
       hipLaunchKernelGGL((k_gate1<W, CT, ORD, CAPK, BLOCKK>), dim3(nblocks), dim3(BLOCKK), 0, st, a);
     });
     ctx->check_launch();
@@ -1480,7 +1499,7 @@ struct Engine final : EngineBase {
         return b;
       };
       // one wavefront for small tiles; 256 threads for the others and for small tiles that grew
-      if (hc.nlist[0]) g1_launch<SmallCfg<W>::CAP, SmallCfg<W>::BLOCK>(with_list(rl0, g1_ovf, 0, 0), hc.nlist[0], 0);
+      if (hc.nlist[0]) g1_launch<kG1WaveCap, 64>(with_list(rl0, g1_ovf, 0, 0), hc.nlist[0], 0);
       if (hc.nlist[1]) g1_launch<1024, 256>(with_list(rl1, ovl1, 1, 0), hc.nlist[1], 1);
       {
         const uint32_t n0l = hc.nlist[0], n1l = hc.nlist[1];

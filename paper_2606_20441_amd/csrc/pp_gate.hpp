@@ -61,7 +61,8 @@ struct Gate1Args {
   uint32_t* hout;               // per-term hash of `out`
   const uint32_t* t_start;      // tile ranges in `in`
   const uint32_t* t_len;
-  const uint32_t* t_list;       // optional: blockIdx.x -> tile
+  const uint32_t* t_list;       // optional: list entry -> tile
+  uint32_t t_count;             // list entries (tiles) to process
   const uint32_t* o_base;       // start of each tile's output region (2 * t_len slots)
   uint32_t* o_start;            // tile ranges in `out` (same tile index)
   uint32_t* o_len;
@@ -157,10 +158,49 @@ __device__ void pass_through(const Gate1Args<CT>& a, uint32_t tile, uint32_t t0,
   }
 }
 
+// Smallest power of two above n: an open-addressing table of that size holding at most n
+// keys always has an empty slot, so every probe sequence ends.
+constexpr int pow2_above(int n) { return n < 1 ? 1 : 2 * pow2_above(n / 2); }
+
+// One tile's terms in registers: entry r of thread tid is term r * BLOCK + tid of the tile.
+template <int W, class CT, int R>
+struct G1Regs {
+  uint64_t x[R][W], z[R][W];
+  CT c[R];
+  uint32_t h[R];
+  uint32_t o[R];
+};
+
+// Issue the loads of a tile's terms (nothing for a tile above CAP, which takes another path).
+template <int W, class CT, bool ORD, int CAP, int BLOCK>
+__device__ __forceinline__ void g1_fetch(const Gate1Args<CT>& a, G1Regs<W, CT, CAP / BLOCK>& g, uint32_t t0,
+                                         uint32_t n0) {
+  constexpr int R = CAP / BLOCK;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t i = (uint32_t)r * BLOCK + threadIdx.x;
+    const bool in = n0 <= (uint32_t)CAP && i < n0;
+    const uint64_t src = (uint64_t)t0 + (in ? i : 0u);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      g.x[r][w] = in ? a.in.x[w * a.in.stride + src] : 0ULL;
+      g.z[r][w] = in ? a.in.z[w * a.in.stride + src] : 0ULL;
+    }
+    g.c[r] = in ? a.in.c[src] : (CT)0;
+    g.h[r] = in ? a.hin[src] : 0u;
+    g.o[r] = (ORD && in) ? (uint32_t)a.in.o[src] : 0u;
+  }
+}
+
+// The gate on whole tiles, one workgroup per tile at a time.  The grid is persistent: a
+// workgroup takes the tiles blockIdx.x, blockIdx.x + gridDim.x, ... of the list (t_count
+// entries) and loads the next tile's terms while it compacts and writes the current one;
+// tile ranges are read two tiles ahead.
 template <int W, class CT, bool ORD, int CAP, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
   constexpr int R = CAP / BLOCK;
-  constexpr int H = 2 * CAP;
+  constexpr int H = pow2_above(CAP);
+  static_assert(H > CAP && (H & (H - 1)) == 0 && R * BLOCK == CAP, "tile shape");
   constexpr int NW = BLOCK / 64;
   constexpr uint32_t EMPTY = 0xffffffffu;
   __shared__ uint64_t sx[W][CAP];
@@ -169,46 +209,17 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
   __shared__ uint32_t sh[CAP];
   __shared__ uint8_t so[ORD ? CAP : 1];
   __shared__ uint32_t hidx[H];
-  __shared__ uint32_t s_new, s_ovf;
+  __shared__ uint32_t s_new, s_ovf, s_any;
   __shared__ uint32_t s_wsum[NW];
   __shared__ double s_drop[NW];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const uint32_t tile = a.t_list ? a.t_list[blockIdx.x] : blockIdx.x;
-  const uint32_t t0 = a.t_start[tile];
-  const uint32_t n0 = a.t_len[tile];
-  if (n0 > (uint32_t)CAP) {
-    // Too large for LDS.  If no term of the tile anticommutes with the gate, the tile
-    // passes through unchanged apart from the pending cut; otherwise it is reported.
-    __shared__ uint32_t s_any;
-    if (tid == 0) s_any = 0;
-    __syncthreads();
-    bool any = false;
-    for (uint32_t i = tid; i < n0 && !any; i += BLOCK) {
-      uint64_t kx[W], kz[W], mm[2 * W];
-#pragma unroll
-      for (int w = 0; w < W; ++w) {
-        kx[w] = a.in.x[w * a.in.stride + t0 + i];
-        kz[w] = a.in.z[w * a.in.stride + t0 + i];
-      }
-#pragma unroll
-      for (int w = 0; w < 2 * W; ++w) mm[w] = a.g.m[w];
-      any = anticommutes<W>(kx, kz, mm) != 0;
-    }
-    if (any) s_any = 1;
-    __syncthreads();
-    if (s_any || BLOCK < 256) {
-      if (tid == 0) a.ovf_tiles[atomicAdd(a.ovf_count, 1u)] = tile;
-      if (a.zero_on_ovf) zero_region(a, tile, n0);
-      return;
-    }
-    pass_through<W, CT, ORD, BLOCK>(a, tile, t0, n0);
-    return;
-  }
-  for (int j = tid; j < H; j += BLOCK) hidx[j] = EMPTY;
-  if (tid == 0) { s_new = 0; s_ovf = 0; }
-  __syncthreads();
+  const uint32_t count = a.t_count;
+  const uint32_t G = gridDim.x;
+  uint32_t li = blockIdx.x;
+  if (li >= count) return;
+  auto tile_at = [&](uint32_t l) { return a.t_list ? a.t_list[l] : l; };
 
   uint64_t m[2 * W];
 #pragma unroll
@@ -216,185 +227,234 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
   const double cs = a.g.cs, snd = a.g.sn_dir;
   const uint32_t gh = a.g.hash;
   const int pw = a.g.pivot_word, pb = a.g.pivot_bit;
-
-  // ---- load, cut, insert -----------------------------------------------------------------------
-  double lost = 0.0;
-  uint64_t rkx[R][W], rkz[R][W];
-  uint32_t rh[R];
-  double rc[R];
-  uint32_t ro[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint32_t i = (uint32_t)r * BLOCK + tid;
-    rc[r] = 0.0;
-    rh[r] = 0;
-    ro[r] = 0;
-#pragma unroll
-    for (int w = 0; w < W; ++w) { rkx[r][w] = 0; rkz[r][w] = 0; }
-    if (i >= n0) continue;
-    const uint64_t src = (uint64_t)t0 + i;
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-      rkx[r][w] = a.in.x[w * a.in.stride + src];
-      rkz[r][w] = a.in.z[w * a.in.stride + src];
-      sx[w][i] = rkx[r][w];
-      sz[w][i] = rkz[r][w];
-    }
-    const CT cv = a.in.c[src];
-    double c = (double)cv;
-    if (ORD) { ro[r] = a.in.o[src]; so[i] = (uint8_t)ro[r]; }
-    if (c != 0.0 && !cut_keeps<W, CT>(cv, rkx[r], rkz[r], ro[r], a.cut)) {
-      lost += fabs(c);
-      c = 0.0;
-    }
-    rc[r] = c;
-    rh[r] = a.hin[src];
-    sh[i] = rh[r];
-    sc[i] = (CT)c;
-    if (c != 0.0) {
-      uint32_t slot = (rh[r] ^ (ro[r] * 0x9e3779b9u)) & (H - 1);
-      while (atomicCAS(&hidx[slot], EMPTY, i) != EMPTY) slot = (slot + 1) & (H - 1);
-    }
-  }
-  __syncthreads();
-
-  // ---- the gate ----------------------------------------------------------------------------------
-  const bool nonclifford = cs != 0.0 && snd != 0.0;
   const double thr = a.eps;
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint32_t i = (uint32_t)r * BLOCK + tid;
-    if (i >= n0 || rc[r] == 0.0) continue;
-    if (!anticommutes<W>(rkx[r], rkz[r], m)) {
-      // untouched, but the threshold after a non-Clifford gate covers every term
-      if (fabs(rc[r]) < thr) { lost += fabs(rc[r]); sc[i] = (CT)0; }
-      continue;
+
+  // current tile and the next one (ranges), the current tile's terms in flight
+  uint32_t tile = tile_at(li), t0 = a.t_start[tile], n0 = a.t_len[tile];
+  uint32_t tile_n = 0, t0_n = 0, n0_n = 0;
+  if (li + G < count) {
+    tile_n = tile_at(li + G);
+    t0_n = a.t_start[tile_n];
+    n0_n = a.t_len[tile_n];
+  }
+  G1Regs<W, CT, R> cur;
+  g1_fetch<W, CT, ORD, CAP, BLOCK>(a, cur, t0, n0);
+  // the workgroup's statistics (thread 0), added to the global counters once at the end
+  double acc_drop = 0.0;
+  unsigned long long acc_in = 0, acc_out = 0;
+  uint32_t acc_big = 0;
+
+  // One tile with its terms in `cur`.  Once the gate has read them, `cur` receives the next
+  // tile's terms, which arrive while this tile is compacted and written.
+  for (;;) {
+    const bool more = li + G < count;
+    uint32_t tile_nn = 0, t0_nn = 0, n0_nn = 0;
+    if (li + 2 * G < count) {
+      tile_nn = tile_at(li + 2 * G);
+      t0_nn = a.t_start[tile_nn];
+      n0_nn = a.t_len[tile_nn];
     }
-    const double ci = rc[r];
-    if (snd == 0.0) {            // cos = +-1, sin = 0: a sign, no branching
-      sc[i] = (CT)(ci * cs);
-      continue;
-    }
-    const bool neg_i = irp_negative<W>(rkx[r], rkz[r], m, a.g.rr_phase);
-    uint64_t qx[W], qz[W];
+    const uint64_t base = a.o_base[tile];
+    double lost = 0.0;
+    if (n0 > (uint32_t)CAP) {
+      if (more) g1_fetch<W, CT, ORD, CAP, BLOCK>(a, cur, t0_n, n0_n);
+      // Too large for LDS.  If no term of the tile anticommutes with the gate, the tile
+      // passes through unchanged apart from the pending cut; otherwise it is reported.
+      if (tid == 0) s_any = 0;
+      __syncthreads();
+      bool any = false;
+      for (uint32_t i = tid; i < n0 && !any; i += BLOCK) {
+        uint64_t kx[W], kz[W];
 #pragma unroll
-    for (int w = 0; w < W; ++w) { qx[w] = rkx[r][w] ^ m[w]; qz[w] = rkz[r][w] ^ m[W + w]; }
-    if (cs == 0.0) {             // sin = +-1: P -> +-iRP in place (a permutation of strings)
-#pragma unroll
-      for (int w = 0; w < W; ++w) { sx[w][i] = qx[w]; sz[w][i] = qz[w]; }
-      sh[i] = rh[r] ^ gh;
-      sc[i] = (CT)((neg_i ? -ci : ci) * snd);
-      continue;
-    }
-    // non-Clifford: find the partner string (same order tag) in the tile
-    const uint32_t hq = rh[r] ^ gh;
-    uint32_t slot = (hq ^ (ro[r] * 0x9e3779b9u)) & (H - 1);
-    uint32_t j = EMPTY;
-    for (;;) {
-      const uint32_t k = hidx[slot];
-      if (k == EMPTY) break;
-      if (sh[k] == hq) {
-        bool eq = !ORD || so[k] == ro[r];
-#pragma unroll
-        for (int w = 0; w < W; ++w) eq = eq && sx[w][k] == qx[w] && sz[w][k] == qz[w];
-        if (eq) { j = k; break; }
+        for (int w = 0; w < W; ++w) {
+          kx[w] = a.in.x[w * a.in.stride + t0 + i];
+          kz[w] = a.in.z[w * a.in.stride + t0 + i];
+        }
+        any = anticommutes<W>(kx, kz, m) != 0;
       }
-      slot = (slot + 1) & (H - 1);
-    }
-    if (j != EMPTY) {
-      // both present: the member with the pivot bit clear updates the pair
-      const uint64_t pv = pw < W ? pick<W>(rkx[r], pw) : pick<W>(rkz[r], pw - W);
-      if ((pv >> pb) & 1ULL) continue;
-      const double cj = (double)sc[j];
-      const bool neg_j = irp_negative<W>(qx, qz, m, a.g.rr_phase);
-      double ni = ci * cs + (neg_j ? -cj : cj) * snd;
-      double nj = cj * cs + (neg_i ? -ci : ci) * snd;
-      if (fabs(ni) < thr || ni == 0.0) { lost += fabs(ni); ni = 0.0; }
-      if (fabs(nj) < thr || nj == 0.0) { lost += fabs(nj); nj = 0.0; }
-      sc[i] = (CT)ni;
-      sc[j] = (CT)nj;
-    } else {
-      double ni = ci * cs;
-      const double nq = (neg_i ? -ci : ci) * snd;
-      if (fabs(ni) < thr || ni == 0.0) { lost += fabs(ni); ni = 0.0; }
-      sc[i] = (CT)ni;
-      if (fabs(nq) < thr || nq == 0.0) {
-        lost += fabs(nq);
+      if (any) s_any = 1;
+      __syncthreads();
+      if (s_any || BLOCK < 256) {
+        if (tid == 0) a.ovf_tiles[atomicAdd(a.ovf_count, 1u)] = tile;
+        if (a.zero_on_ovf) zero_region(a, tile, n0);
       } else {
-        const uint32_t k = n0 + atomicAdd(&s_new, 1u);
-        if (k < (uint32_t)CAP) {
+        pass_through<W, CT, ORD, BLOCK>(a, tile, t0, n0);
+      }
+    } else {
+      for (int j = tid; j < H; j += BLOCK) hidx[j] = EMPTY;
+      if (tid == 0) { s_new = 0; s_ovf = 0; }
+      __syncthreads();
+
+      // ---- stage, cut, insert ----------------------------------------------------------------
 #pragma unroll
-          for (int w = 0; w < W; ++w) { sx[w][k] = qx[w]; sz[w][k] = qz[w]; }
-          sh[k] = hq;
-          if (ORD) so[k] = (uint8_t)ro[r];
-          sc[k] = (CT)nq;
+      for (int r = 0; r < R; ++r) {
+        const uint32_t i = (uint32_t)r * BLOCK + tid;
+        if (i >= n0) continue;
+#pragma unroll
+        for (int w = 0; w < W; ++w) { sx[w][i] = cur.x[r][w]; sz[w][i] = cur.z[r][w]; }
+        if (ORD) so[i] = (uint8_t)cur.o[r];
+        const CT cv = cur.c[r];
+        if (cv != (CT)0 && !cut_keeps<W, CT>(cv, cur.x[r], cur.z[r], cur.o[r], a.cut)) {
+          lost += fabs((double)cv);
+          cur.c[r] = (CT)0;
+        }
+        sh[i] = cur.h[r];
+        sc[i] = cur.c[r];
+        if (cur.c[r] != (CT)0) {
+          uint32_t slot = (cur.h[r] ^ (cur.o[r] * 0x9e3779b9u)) & (H - 1);
+          while (atomicCAS(&hidx[slot], EMPTY, i) != EMPTY) slot = (slot + 1) & (H - 1);
+        }
+      }
+      __syncthreads();
+
+      // ---- the gate ----------------------------------------------------------------------------
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const uint32_t i = (uint32_t)r * BLOCK + tid;
+        const double ci = (double)cur.c[r];
+        if (i >= n0 || ci == 0.0) continue;
+        if (!anticommutes<W>(cur.x[r], cur.z[r], m)) {
+          // untouched, but the threshold after a non-Clifford gate covers every term
+          if (fabs(ci) < thr) { lost += fabs(ci); sc[i] = (CT)0; }
+          continue;
+        }
+        if (snd == 0.0) {            // cos = +-1, sin = 0: a sign, no branching
+          sc[i] = (CT)(ci * cs);
+          continue;
+        }
+        const bool neg_i = irp_negative<W>(cur.x[r], cur.z[r], m, a.g.rr_phase);
+        uint64_t qx[W], qz[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) { qx[w] = cur.x[r][w] ^ m[w]; qz[w] = cur.z[r][w] ^ m[W + w]; }
+        if (cs == 0.0) {             // sin = +-1: P -> +-iRP in place (a permutation of strings)
+#pragma unroll
+          for (int w = 0; w < W; ++w) { sx[w][i] = qx[w]; sz[w][i] = qz[w]; }
+          sh[i] = cur.h[r] ^ gh;
+          sc[i] = (CT)((neg_i ? -ci : ci) * snd);
+          continue;
+        }
+        // non-Clifford: find the partner string (same order tag) in the tile
+        const uint32_t hq = cur.h[r] ^ gh;
+        uint32_t slot = (hq ^ (cur.o[r] * 0x9e3779b9u)) & (H - 1);
+        uint32_t j = EMPTY;
+        for (;;) {
+          const uint32_t k = hidx[slot];
+          if (k == EMPTY) break;
+          if (sh[k] == hq) {
+            bool eq = !ORD || so[k] == cur.o[r];
+#pragma unroll
+            for (int w = 0; w < W; ++w) eq = eq && sx[w][k] == qx[w] && sz[w][k] == qz[w];
+            if (eq) { j = k; break; }
+          }
+          slot = (slot + 1) & (H - 1);
+        }
+        if (j != EMPTY) {
+          // both present: the member with the pivot bit clear updates the pair
+          const uint64_t pv = pw < W ? pick<W>(cur.x[r], pw) : pick<W>(cur.z[r], pw - W);
+          if ((pv >> pb) & 1ULL) continue;
+          const double cj = (double)sc[j];
+          const bool neg_j = irp_negative<W>(qx, qz, m, a.g.rr_phase);
+          double ni = ci * cs + (neg_j ? -cj : cj) * snd;
+          double nj = cj * cs + (neg_i ? -ci : ci) * snd;
+          if (fabs(ni) < thr || ni == 0.0) { lost += fabs(ni); ni = 0.0; }
+          if (fabs(nj) < thr || nj == 0.0) { lost += fabs(nj); nj = 0.0; }
+          sc[i] = (CT)ni;
+          sc[j] = (CT)nj;
         } else {
-          s_ovf = 1;
+          double ni = ci * cs;
+          const double nq = (neg_i ? -ci : ci) * snd;
+          if (fabs(ni) < thr || ni == 0.0) { lost += fabs(ni); ni = 0.0; }
+          sc[i] = (CT)ni;
+          if (fabs(nq) < thr || nq == 0.0) {
+            lost += fabs(nq);
+          } else {
+            const uint32_t k = n0 + atomicAdd(&s_new, 1u);
+            if (k < (uint32_t)CAP) {
+#pragma unroll
+              for (int w = 0; w < W; ++w) { sx[w][k] = qx[w]; sz[w][k] = qz[w]; }
+              sh[k] = hq;
+              if (ORD) so[k] = (uint8_t)cur.o[r];
+              sc[k] = (CT)nq;
+            } else {
+              s_ovf = 1;
+            }
+          }
+        }
+      }
+      if (more) g1_fetch<W, CT, ORD, CAP, BLOCK>(a, cur, t0_n, n0_n);
+      __syncthreads();
+      if (s_ovf) {
+        if (tid == 0) a.ovf_tiles[atomicAdd(a.ovf_count, 1u)] = tile;
+        if (a.zero_on_ovf) zero_region(a, tile, n0);
+      } else {
+        const uint32_t n = n0 + s_new;
+        // ---- compact and write -------------------------------------------------------------------
+        // thread tid owns entries [tid * R, tid * R + R): contiguous ranks keep the tile's order
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const uint32_t i = (uint32_t)tid * R + r;
+          cnt += (i < n && sc[i] != (CT)0) ? 1u : 0u;
+        }
+        uint32_t incl = cnt;
+        for (int d = 1; d < 64; d <<= 1) {
+          const uint32_t v = __shfl_up(incl, d, 64);
+          if (lane >= d) incl += v;
+        }
+        double lsum = lost;
+        for (int d = 32; d >= 1; d >>= 1) lsum += __shfl_xor(lsum, d, 64);
+        if (lane == 63) s_wsum[tid >> 6] = incl;
+        if (lane == 0) s_drop[tid >> 6] = lsum;
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          before += (w < (tid >> 6)) ? s_wsum[w] : 0u;
+          total += s_wsum[w];
+        }
+        // the tile's output region holds 2 * n0 slots (a gate at most doubles a tile); unused
+        // slots get a zero coefficient so that sweeps over the whole buffer skip them
+        if (tid == 0) {
+          a.o_start[tile] = (uint32_t)base;
+          a.o_len[tile] = total;
+          acc_big += total > a.big_hint ? 1u : 0u;
+          for (int w = 0; w < NW; ++w) acc_drop += s_drop[w];
+          acc_in += n0;
+          acc_out += total;
+        }
+        for (uint64_t i = base + total + tid; i < base + 2ULL * n0; i += BLOCK) a.out.c[i] = (CT)0;
+        uint32_t rank = before + incl - cnt;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const uint32_t i = (uint32_t)tid * R + r;
+          if (i >= n || sc[i] == (CT)0) continue;
+          const uint64_t dst = base + rank++;
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            a.out.x[w * a.out.stride + dst] = sx[w][i];
+            a.out.z[w * a.out.stride + dst] = sz[w][i];
+          }
+          a.out.c[dst] = sc[i];
+          if (ORD) a.out.o[dst] = so[i];
+          a.hout[dst] = sh[i];
         }
       }
     }
+    __syncthreads();   // the tile's LDS is free
+    li += G;
+    tile = tile_n;
+    t0 = t0_n;
+    n0 = n0_n;
+    tile_n = tile_nn;
+    t0_n = t0_nn;
+    n0_n = n0_nn;
+    if (!more) break;
   }
-  (void)nonclifford;
-  __syncthreads();
-  if (s_ovf) {
-    if (tid == 0) a.ovf_tiles[atomicAdd(a.ovf_count, 1u)] = tile;
-    if (a.zero_on_ovf) zero_region(a, tile, n0);
-    return;
-  }
-  const uint32_t n = n0 + s_new;
-
-  // ---- compact and write -----------------------------------------------------------------------
-  // thread tid owns entries [tid * R, tid * R + R): contiguous ranks keep the tile's order
-  uint32_t cnt = 0;
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint32_t i = (uint32_t)tid * R + r;
-    cnt += (i < n && sc[i] != (CT)0) ? 1u : 0u;
-  }
-  uint32_t incl = cnt;
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t v = __shfl_up(incl, d, 64);
-    if (lane >= d) incl += v;
-  }
-  double lsum = lost;
-  for (int d = 32; d >= 1; d >>= 1) lsum += __shfl_xor(lsum, d, 64);
-  if (lane == 63) s_wsum[tid >> 6] = incl;
-  if (lane == 0) s_drop[tid >> 6] = lsum;
-  __syncthreads();
-  uint32_t before = 0, total = 0;
-#pragma unroll
-  for (int w = 0; w < NW; ++w) {
-    before += (w < (tid >> 6)) ? s_wsum[w] : 0u;
-    total += s_wsum[w];
-  }
-  // the tile's output region holds 2 * n0 slots (a gate at most doubles a tile); unused
-  // slots get a zero coefficient so that sweeps over the whole buffer skip them
-  const uint64_t base = a.o_base[tile];
   if (tid == 0) {
-    a.o_start[tile] = (uint32_t)base;
-    a.o_len[tile] = total;
-    if (total > a.big_hint) atomicAdd(a.big_count, 1u);
-    double v = 0.0;
-    for (int w = 0; w < NW; ++w) v += s_drop[w];
-    if (v != 0.0) atomicAdd(&a.dropped[blockIdx.x % kDropSlots], v);
-    atomicAdd(&a.io[blockIdx.x % kDropSlots], (unsigned long long)n0);
-    atomicAdd(&a.io[kDropSlots + blockIdx.x % kDropSlots], (unsigned long long)total);
-  }
-  for (uint64_t i = base + total + tid; i < base + 2ULL * n0; i += BLOCK) a.out.c[i] = (CT)0;
-  uint32_t rank = before + incl - cnt;
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint32_t i = (uint32_t)tid * R + r;
-    if (i >= n || sc[i] == (CT)0) continue;
-    const uint64_t dst = base + rank++;
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-      a.out.x[w * a.out.stride + dst] = sx[w][i];
-      a.out.z[w * a.out.stride + dst] = sz[w][i];
-    }
-    a.out.c[dst] = sc[i];
-    if (ORD) a.out.o[dst] = so[i];
-    a.hout[dst] = sh[i];
+    if (acc_drop != 0.0) atomicAdd(&a.dropped[blockIdx.x % kDropSlots], acc_drop);
+    if (acc_big) atomicAdd(a.big_count, acc_big);
+    if (acc_in) atomicAdd(&a.io[blockIdx.x % kDropSlots], acc_in);
+    if (acc_out) atomicAdd(&a.io[kDropSlots + blockIdx.x % kDropSlots], acc_out);
   }
 }
 
