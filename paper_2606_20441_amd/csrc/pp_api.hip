@@ -288,7 +288,7 @@ struct Engine final : EngineBase {
   bool aborted = false;
   TBuf<double, true> ta, tb;     // tie lists for the cap
   TBuf<CT, ORD> gb;              // boundary candidates of a cap
-  Buf u32a, u32b, u32c, scan_scr, tiles, gates_d, sup_d, tab_d, fidx_d, dm_d, dval_d, cnt_d, ovf_d, partial_d, f64_d, span_d, htab_d;
+  Buf u32a, u32b, u32c, scan_scr, tiles, gates_d, sup_d, tab_d, fidx_d, dm_d, dval_d, cnt_d, ovf_d, partial_d, f64_d, span_d, htab_d, lstat_d;
   Buf hp_a, hp_b, tr_s0, tr_l0, tr_s1, tr_l1, g1_d, g1_ovf, g1_base, g1_drop;   // per-gate tile path
   Buf rl0, rl1, ovl1, ovl2, tf_flag, tf_pos, tf_list, g1_io, g1_tab, g1_tabmeta;
   double growth[4] = {4.0, 4.0, 2.0, 3.0};
@@ -299,7 +299,7 @@ struct Engine final : EngineBase {
     for (auto* t : {&cur, &alt, &sa, &sb, &tmp, &gb}) { t->mem.ctx = ctx; t->W = W; }
     for (auto* t : {&ta, &tb}) { t->mem.ctx = ctx; t->W = W; }
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &fidx_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
-                   &partial_d, &f64_d, &span_d, &htab_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_drop, &rl0, &rl1, &ovl1, &ovl2,
+                   &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_drop, &rl0, &rl1, &ovl1, &ovl2,
                    &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta})
       b->ctx = ctx;
     cnt_d.ensure(256);
@@ -312,7 +312,7 @@ struct Engine final : EngineBase {
     for (auto* t : {&cur, &alt, &sa, &sb, &tmp, &gb}) t->mem.release();
     for (auto* t : {&ta, &tb}) t->mem.release();
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &fidx_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
-                   &partial_d, &f64_d, &span_d, &htab_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_drop, &rl0, &rl1, &ovl1, &ovl2,
+                   &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_drop, &rl0, &rl1, &ovl1, &ovl2,
                    &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta})
       b->release();
   }
@@ -865,9 +865,13 @@ struct Engine final : EngineBase {
     a.out_fail = &cd->out_fail;
     a.ovf_tiles = ovf_d.as<uint32_t>();
     a.ovf_count = &cd->ovf_count;
-    a.dropped = &cd->dropped;
-    a.peak = &cd->peak;
-    a.peak_sum = &cd->peak_sum;
+    // per-slot statistics: dropped (double), peak_sum (u64), peak (u32)
+    constexpr size_t kStatBytes = kStatSlots * (8 + 8 + 4);
+    lstat_d.ensure(kStatBytes + 64);
+    HIPCHK(hipMemsetAsync(lstat_d.p, 0, kStatBytes, st));
+    a.dropped = (double*)lstat_d.p;
+    a.peak_sum = (unsigned long long*)((char*)lstat_d.p + kStatSlots * 8);
+    a.peak = (unsigned int*)((char*)lstat_d.p + kStatSlots * 16);
     const int pi = ctx->run(small ? "layer_fused_wave" : "layer_fused_block", 0, (double)m, [&] {
       if (small)
         hipLaunchKernelGGL((k_layer<W, CT, ORD, SmallCfg<W>::CAP, SmallCfg<W>::BLOCK, SmallCfg<W>::GATES>),
@@ -879,8 +883,26 @@ struct Engine final : EngineBase {
     ctx->check_launch();
     Counters hc;
     HIPCHK(hipMemcpyAsync(ctx->pinned, cd, sizeof(Counters), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync((char*)ctx->pinned + 1024, lstat_d.p, kStatBytes, hipMemcpyDeviceToHost, st));
     sync();
     std::memcpy(&hc, ctx->pinned, sizeof hc);
+    {
+      const char* ps = (const char*)ctx->pinned + 1024;
+      hc.dropped = 0.0;
+      hc.peak = 0;
+      hc.peak_sum = 0;
+      for (int k = 0; k < kStatSlots; ++k) {
+        double d;
+        unsigned long long q;
+        uint32_t pk;
+        std::memcpy(&d, ps + 8 * k, 8);
+        std::memcpy(&q, ps + kStatSlots * 8 + 8 * k, 8);
+        std::memcpy(&pk, ps + kStatSlots * 16 + 4 * k, 4);
+        hc.dropped += d;
+        hc.peak_sum += q;
+        hc.peak = std::max(hc.peak, pk);
+      }
+    }
     last_ntiles = ntiles;
     last_ovf_tiles = hc.ovf_count;
     const uint64_t end = std::min<uint64_t>(hc.out_count, hc.out_fail);   // valid prefix

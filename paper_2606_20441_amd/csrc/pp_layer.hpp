@@ -53,10 +53,13 @@ struct LayerArgs {
   unsigned long long* out_fail;  // smallest start refused for lack of output space
   uint32_t* ovf_tiles;
   uint32_t* ovf_count;
+  // statistics, each spread over kStatSlots addresses (one workgroup adds to slot
+  // blockIdx.x % kStatSlots; a single address would serialise the workgroups)
   double* dropped;              // sum of |c| removed by thresholds
   unsigned int* peak;           // largest live count seen in a tile
   unsigned long long* peak_sum; // sum over tiles of each tile's largest live count during the gates
 };
+constexpr int kStatSlots = 64;
 
 // Compact per-W gate record staged in LDS by the fused kernel.
 template <int W>
@@ -756,9 +759,10 @@ __global__ void __launch_bounds__(BLOCK) k_layer(LayerArgs<CT> a) {
   if (tid == 0) {
     double v = 0.0;
     for (int w = 0; w < BLOCK / 64; ++w) v += s_drop[w];
-    if (v != 0.0) atomicAdd(a.dropped, v);
-    atomicMax(a.peak, peak);
-    if (a.peak_sum) atomicAdd(a.peak_sum, (unsigned long long)live_peak);
+    const uint32_t slot = blockIdx.x % kStatSlots;
+    if (v != 0.0) atomicAdd(&a.dropped[slot], v);
+    atomicMax(&a.peak[slot], peak);
+    if (a.peak_sum) atomicAdd(&a.peak_sum[slot], (unsigned long long)live_peak);
   }
   for (uint32_t i = tid; i < n; i += BLOCK) {
     const uint64_t j = base + i;
