@@ -289,8 +289,8 @@ struct Engine final : EngineBase {
   TBuf<double, true> ta, tb;     // tie lists for the cap
   TBuf<CT, ORD> gb;              // boundary candidates of a cap
   Buf u32a, u32b, u32c, scan_scr, tiles, gates_d, sup_d, tab_d, fidx_d, dm_d, dval_d, cnt_d, ovf_d, partial_d, f64_d, span_d, htab_d, lstat_d;
-  Buf hp_a, hp_b, tr_s0, tr_l0, tr_s1, tr_l1, g1_d, g1_ovf, g1_base, g1_drop;   // per-gate tile path
-  Buf rl0, rl1, ovl1, ovl2, tf_flag, tf_pos, tf_list, g1_io, g1_tab, g1_tabmeta;
+  Buf hp_a, hp_b, tr_s0, tr_l0, tr_s1, tr_l1, g1_d, g1_ovf, g1_base, g1_base2, g1_drop;   // per-gate tile path
+  Buf rl0, rl1, ovl1, ovl2, tf_flag, tf_pos, tf_list, g1_io, g1_tab, g1_tabmeta, win_hist_d;
   double growth[4] = {4.0, 4.0, 2.0, 3.0};
   double tile_target[4] = {80.0, 80.0, 80.0, 64.0};   // level-0 (one-wavefront) tile targets
   uint64_t last_ntiles = 1, last_ovf_tiles = 0;
@@ -299,8 +299,8 @@ struct Engine final : EngineBase {
     for (auto* t : {&cur, &alt, &sa, &sb, &tmp, &gb}) { t->mem.ctx = ctx; t->W = W; }
     for (auto* t : {&ta, &tb}) { t->mem.ctx = ctx; t->W = W; }
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &fidx_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
-                   &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_drop, &rl0, &rl1, &ovl1, &ovl2,
-                   &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta})
+                   &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &g1_drop, &rl0, &rl1, &ovl1, &ovl2,
+                   &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d})
       b->ctx = ctx;
     cnt_d.ensure(256);
     span_d.ensure(256);
@@ -312,8 +312,8 @@ struct Engine final : EngineBase {
     for (auto* t : {&cur, &alt, &sa, &sb, &tmp, &gb}) t->mem.release();
     for (auto* t : {&ta, &tb}) t->mem.release();
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &fidx_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
-                   &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_drop, &rl0, &rl1, &ovl1, &ovl2,
-                   &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta})
+                   &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &g1_drop, &rl0, &rl1, &ovl1, &ovl2,
+                   &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d})
       b->release();
   }
 
@@ -1132,6 +1132,10 @@ struct Engine final : EngineBase {
   }
 
   // ---- gate by gate over persistent tiles --------------------------------------------------------
+  // host-pinned scratch layout: counters at 0, the bases' total at kPinBases, the dropped
+  // weight at kPinDrop, the window histogram at kPinWin
+  static constexpr size_t kPinBases = 512, kPinDrop = 2048, kPinWin = 4096;
+
   struct G1Counters {
     uint32_t nlist[2];   // routed tiles: small, larger
     uint32_t ovf[3];     // tiles reported by the one-wavefront, 256-thread and 1024-thread shapes
@@ -1180,20 +1184,27 @@ struct Engine final : EngineBase {
 
   // Output bases of the tiles for the next gate: exclusive prefix of 2 * len.  Returns the
   // total (the extent of the output buffer).
-  uint64_t g1_bases(const uint32_t* len, uint64_t ntiles) {
-    g1_base.ensure(ntiles * 4 + 64);
-    uint32_t* b = g1_base.as<uint32_t>();
+  // Enqueue the bases into `out` and the copy of their total to the host (read after a sync
+  // with g1_bases_read).
+  void g1_bases_launch(const uint32_t* len, uint64_t ntiles, Buf& out) {
+    out.ensure(ntiles * 4 + 64);
+    uint32_t* b = out.as<uint32_t>();
     hipLaunchKernelGGL(k_double_len, grid1(ntiles), dim3(256), 0, st, len, (uint32_t)ntiles, b);
     ctx->check_launch();
-    uint32_t last = 0;
-    HIPCHK(hipMemcpyAsync(ctx->pinned, b + ntiles - 1, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync((char*)ctx->pinned + kPinBases, b + ntiles - 1, 4, hipMemcpyDeviceToHost, st));
     scan_u32(b, ntiles);
-    uint32_t lastb = 0;
-    HIPCHK(hipMemcpyAsync((char*)ctx->pinned + 4, b + ntiles - 1, 4, hipMemcpyDeviceToHost, st));
-    sync();
-    std::memcpy(&last, ctx->pinned, 4);
-    std::memcpy(&lastb, (char*)ctx->pinned + 4, 4);
+    HIPCHK(hipMemcpyAsync((char*)ctx->pinned + kPinBases + 4, b + ntiles - 1, 4, hipMemcpyDeviceToHost, st));
+  }
+  uint64_t g1_bases_read() const {
+    uint32_t last = 0, lastb = 0;
+    std::memcpy(&last, (const char*)ctx->pinned + kPinBases, 4);
+    std::memcpy(&lastb, (const char*)ctx->pinned + kPinBases + 4, 4);
     return (uint64_t)lastb + last;
+  }
+  uint64_t g1_bases(const uint32_t* len, uint64_t ntiles) {
+    g1_bases_launch(len, ntiles, g1_base);
+    sync();
+    return g1_bases_read();
   }
 
   static uint64_t abs_key_host(CT v) {
@@ -1216,6 +1227,27 @@ struct Engine final : EngineBase {
   uint64_t hint_key = 0;
   int hint_shift = sizeof(CT) == 8 ? 43 : 14;   // 2048 bins of 2^shift keys: about 4 octaves
 
+  // The window histogram (first pass of the cut) for the n coefficients at c, enqueued with
+  // the copy of its bins to the host.
+  uint64_t win_lo = 0;
+  int win_sh = 0;
+  void win_hist_launch(const CT* c, uint64_t n) {
+    win_sh = hint_shift;
+    const uint64_t half = 1024ULL << win_sh;
+    win_lo = hint_key > half ? ((hint_key - half) >> win_sh) << win_sh : 0ULL;
+    win_hist_d.ensure(2049 * 4 + 64);
+    uint32_t* hist = win_hist_d.as<uint32_t>();
+    HIPCHK(hipMemsetAsync(hist, 0, 2049 * 4, st));
+    const unsigned nbh = (unsigned)std::min<uint64_t>(2048, cdiv(n, 256));
+    const uint64_t lo = win_lo;
+    const int sh = win_sh;
+    ctx->run("cap_hist", sizeof(CT) * (double)n, (double)n, [&] {
+      hipLaunchKernelGGL((k_abs_hist_win<CT>), dim3(nbh), dim3(256), 0, st, c, n, lo, sh, hist);
+    });
+    ctx->check_launch();
+    HIPCHK(hipMemcpyAsync((char*)ctx->pinned + kPinWin, hist, 2049 * 4, hipMemcpyDeviceToHost, st));
+  }
+
   CutDev cap_cut(uint64_t K, uint64_t n) {
     constexpr uint32_t kGather = 4096;
     const int KB = sizeof(CT) == 8 ? 63 : 31;
@@ -1230,17 +1262,11 @@ struct Engine final : EngineBase {
     if (hint_valid) {
       // The window's bins are the key prefixes above bit `shift`, so a hit continues the
       // radix passes below it; a miss falls back to the passes from the top.
-      const int sh = hint_shift;
-      const uint64_t half = 1024ULL << sh;
-      const uint64_t lo = hint_key > half ? ((hint_key - half) >> sh) << sh : 0ULL;
-      HIPCHK(hipMemsetAsync(hist, 0, 2049 * 4, st));
-      ctx->run("cap_hist", sizeof(CT) * (double)n, (double)n, [&] {
-        hipLaunchKernelGGL((k_abs_hist_win<CT>), dim3(nbh), dim3(256), 0, st, c, n, lo, sh, hist);
-      });
-      ctx->check_launch();
-      HIPCHK(hipMemcpyAsync(ctx->pinned, hist, 2049 * 4, hipMemcpyDeviceToHost, st));
+      win_hist_launch(c, n);
       sync();
-      std::memcpy(h.data(), ctx->pinned, 2049 * 4);
+      const int sh = win_sh;
+      const uint64_t lo = win_lo;
+      std::memcpy(h.data(), (const char*)ctx->pinned + kPinWin, 2049 * 4);
       uint64_t cum = h[2048];
       int d = -1;
       if (cum < need) {
@@ -1299,8 +1325,7 @@ struct Engine final : EngineBase {
                          cntd);
     });
     ctx->check_launch();
-    sync();
-    const CutDev cut = rank_bucket(g, count_eq, need);
+    const CutDev cut = rank_bucket(g, count_eq, need);   // its copies wait for the gather
     hint_valid = true;
     hint_key = cut.val;
     return cut;
@@ -1375,13 +1400,15 @@ struct Engine final : EngineBase {
     return resident;
   }
 
+  // `ntiles` list entries, or, with dev_count, the count the device holds there (at most ntiles).
   template <int CAPK, int BLOCKK>
-  void g1_launch(Gate1Args<CT> a, unsigned ntiles, int shape) {
+  void g1_launch(Gate1Args<CT> a, unsigned ntiles, int shape, const uint32_t* dev_count = nullptr) {
     static const char* names[3] = {"gate_tile_wave", "gate_tile_256", "gate_tile_1024"};
     g1_io.ensure(2 * kDropSlots * 8 + 64);
     unsigned long long* io = g1_io.as<unsigned long long>();
     a.io = io;
     a.t_count = ntiles;
+    a.t_count_dev = dev_count;
     const unsigned nblocks = std::min(ntiles, g1_resident<CAPK, BLOCKK>());
     if (ctx->timing) HIPCHK(hipMemsetAsync(io, 0, 2 * kDropSlots * 8, st));
     const int pi = ctx->run(names[shape], 0, (double)ntiles, [&] {
@@ -1520,25 +1547,29 @@ struct Engine final : EngineBase {
         b.zero_on_ovf = zero;
         return b;
       };
-      // one wavefront for small tiles; 256 threads for the others and for small tiles that grew
-      if (hc.nlist[0]) g1_launch<kG1WaveCap, 64>(with_list(rl0, g1_ovf, 0, 0), hc.nlist[0], 0);
-      if (hc.nlist[1]) g1_launch<1024, 256>(with_list(rl1, ovl1, 1, 0), hc.nlist[1], 1);
-      {
-        const uint32_t n0l = hc.nlist[0], n1l = hc.nlist[1];
-        read_counters();
-        hc.nlist[0] = n0l;
-        hc.nlist[1] = n1l;
-      }
-      if (hc.ovf[0]) {
-        if (hc.ovf[0] * 16 > hc.nlist[0]) routed = false;   // many tiles outgrew the wavefront shape
-        g1_launch<1024, 256>(with_list(g1_ovf, ovl1, 1, 0), hc.ovf[0], 1);
-        read_counters();
-      }
+      // One wavefront for small tiles, 256 threads for the others.  Tiles that outgrow a shape
+      // are retried in the next; the retries read their counts on the device, so the whole
+      // cascade is enqueued without waiting.
+      const uint32_t nl0 = hc.nlist[0], nl1 = hc.nlist[1];
+      if (nl0) g1_launch<kG1WaveCap, 64>(with_list(rl0, g1_ovf, 0, 0), nl0, 0);
+      if (nl1) g1_launch<1024, 256>(with_list(rl1, ovl1, 1, 0), nl1, 1);
+      if (nl0) g1_launch<1024, 256>(with_list(g1_ovf, ovl1, 1, 0), nl0, 1, &cd->ovf[0]);
+      if (nl0 + nl1)
+        g1_launch<LayerCfg<W>::CAP, LayerCfg<W>::BLOCK>(with_list(ovl1, ovl2, 2, 1), nl0 + nl1, 2, &cd->ovf[1]);
+      // counters, the next gate's output bases (other buffer: the oversize pass below still
+      // reads these) and the dropped weight, read back together
+      HIPCHK(hipMemcpyAsync(ctx->pinned, cd, sizeof hc, hipMemcpyDeviceToHost, st));
+      g1_bases_launch(tr_l1.as<uint32_t>(), ntiles, g1_base2);
+      HIPCHK(hipMemcpyAsync((char*)ctx->pinned + kPinDrop, dropd, kDropSlots * 8, hipMemcpyDeviceToHost, st));
+      sync();
+      std::memcpy(&hc, ctx->pinned, sizeof hc);
+      hc.nlist[0] = nl0;
+      hc.nlist[1] = nl1;
+      if (hc.ovf[0] * 16 > nl0) routed = false;   // many tiles outgrew the wavefront shape
       uint64_t giant_terms = 0;
-      if (hc.ovf[1]) {
-        g1_launch<LayerCfg<W>::CAP, LayerCfg<W>::BLOCK>(with_list(ovl1, ovl2, 2, 1), hc.ovf[1], 2);
-        read_counters();
-      }
+      uint64_t next_extent = g1_bases_read();
+      std::vector<double> dsl(kDropSlots);
+      std::memcpy(dsl.data(), (const char*)ctx->pinned + kPinDrop, kDropSlots * 8);
       if (hc.ovf[2] > 0) {
         // classes too large for LDS that the gate touches: one workgroup per tile in its own
         // output region, with a hash table in global memory
@@ -1585,16 +1616,19 @@ struct Engine final : EngineBase {
           ctx->pending[pi].bytes = kTermBytes * terms;
         }
         sync();   // host vectors above are copy sources
+        // the tiles it wrote change the bases and the dropped weight read above
+        g1_bases_launch(tr_l1.as<uint32_t>(), ntiles, g1_base2);
+        HIPCHK(hipMemcpyAsync((char*)ctx->pinned + kPinDrop, dropd, kDropSlots * 8, hipMemcpyDeviceToHost, st));
+        sync();
+        next_extent = g1_bases_read();
+        std::memcpy(dsl.data(), (const char*)ctx->pinned + kPinDrop, kDropSlots * 8);
       }
-      std::vector<double> dsl(kDropSlots);
-      HIPCHK(hipMemcpyAsync(dsl.data(), dropd, kDropSlots * 8, hipMemcpyDeviceToHost, st));
       cur.swap(alt);
       std::swap(hp_a, hp_b);
       std::swap(tr_s0, tr_s1);
       std::swap(tr_l0, tr_l1);
+      std::swap(g1_base, g1_base2);
       extent = out_extent;
-      // live terms, and the output bases of the next gate
-      const uint64_t next_extent = g1_bases(tr_l0.as<uint32_t>(), ntiles);
       for (double v : dsl) ls.dropped_l1 += v;
       N = next_extent / 2 + giant_terms;
       out_extent = next_extent;

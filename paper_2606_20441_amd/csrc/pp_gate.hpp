@@ -63,6 +63,7 @@ struct Gate1Args {
   const uint32_t* t_len;
   const uint32_t* t_list;       // optional: list entry -> tile
   uint32_t t_count;             // list entries (tiles) to process
+  const uint32_t* t_count_dev;  // if set: the count, read on the device (t_count bounds it)
   const uint32_t* o_base;       // start of each tile's output region (2 * t_len slots)
   uint32_t* o_start;            // tile ranges in `out` (same tile index)
   uint32_t* o_len;
@@ -215,7 +216,7 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const uint32_t count = a.t_count;
+  const uint32_t count = a.t_count_dev ? min(*a.t_count_dev, a.t_count) : a.t_count;
   const uint32_t G = gridDim.x;
   uint32_t li = blockIdx.x;
   if (li >= count) return;

@@ -234,6 +234,22 @@ __device__ __forceinline__ uint64_t abs_key(CT v) {
   return coef_bits<CT>(v) & (sizeof(CT) == 8 ? 0x7fffffffffffffffULL : 0x7fffffffULL);
 }
 
+// Visit the |c| keys of c[0..n) over a grid-stride loop of 256-thread blocks, eight loads
+// in flight per thread.
+template <class CT, class F>
+__device__ __forceinline__ void grid_keys(const CT* c, uint64_t n, F&& f) {
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  for (; i + 7 * stride < n; i += 8 * stride) {
+    uint64_t k[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) k[u] = abs_key<CT>(c[i + u * stride]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) f(k[u]);
+  }
+  for (; i < n; i += stride) f(abs_key<CT>(c[i]));
+}
+
 template <class CT>
 __global__ void __launch_bounds__(256) k_abs_hist(const CT* c, uint64_t n, int shift, int bits,
                                                   uint64_t pmask, uint64_t prefix, uint32_t* hist) {
@@ -241,10 +257,16 @@ __global__ void __launch_bounds__(256) k_abs_hist(const CT* c, uint64_t n, int s
   const int bins = 1 << bits;
   for (int b = threadIdx.x; b < bins; b += 256) h[b] = 0;
   __syncthreads();
-  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
-    const uint64_t k = abs_key<CT>(c[i]);
-    if ((k & pmask) == prefix) atomicAdd(&h[(k >> shift) & (uint64_t)(bins - 1)], 1u);
-  }
+  uint32_t zeros = 0;   // unused slots (c = 0) are many: counted in a register, not in LDS
+  auto add = [&](uint64_t k) {
+    if ((k & pmask) == prefix) {
+      if (k == 0) ++zeros;
+      else atomicAdd(&h[(k >> shift) & (uint64_t)(bins - 1)], 1u);
+    }
+  };
+  grid_keys<CT>(c, n, add);
+  for (int d = 32; d >= 1; d >>= 1) zeros += __shfl_xor(zeros, d, 64);
+  if ((threadIdx.x & 63) == 0 && zeros) atomicAdd(&h[0], zeros);
   __syncthreads();
   for (int b = threadIdx.x; b < bins; b += 256)
     if (h[b]) atomicAdd(&hist[b], h[b]);
@@ -258,13 +280,24 @@ __global__ void __launch_bounds__(256) k_abs_hist_win(const CT* c, uint64_t n, u
   __shared__ uint32_t h[2049];
   for (int b = threadIdx.x; b < 2049; b += 256) h[b] = 0;
   __syncthreads();
-  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
-    const uint64_t k = abs_key<CT>(c[i]);
+  // counted in registers: most keys lie above a window near the cut, and unused slots (c = 0)
+  // are many
+  uint32_t above = 0, zeros = 0;
+  auto add = [&](uint64_t k) {
     if (k >= lo) {
       const uint64_t d = (k - lo) >> shift;
-      atomicAdd(&h[d < 2048 ? d : 2048], 1u);
+      if (d >= 2048) ++above;
+      else if (k == 0) ++zeros;
+      else atomicAdd(&h[d], 1u);
     }
+  };
+  grid_keys<CT>(c, n, add);
+  for (int d = 32; d >= 1; d >>= 1) {
+    above += __shfl_xor(above, d, 64);
+    zeros += __shfl_xor(zeros, d, 64);
   }
+  if ((threadIdx.x & 63) == 0 && above) atomicAdd(&h[2048], above);
+  if ((threadIdx.x & 63) == 0 && zeros) atomicAdd(&h[0], zeros);
   __syncthreads();
   for (int b = threadIdx.x; b < 2049; b += 256)
     if (h[b]) atomicAdd(&hist[b], h[b]);
