@@ -198,10 +198,37 @@ void noise(or_sum* s, int n_gen, const uint64_t* ex, const uint64_t* ez, const d
   const int W = s->W;
   if (mode == 0) {
     // Eq. evolve_noise for every generator of the layer: P -> prod_{k: <P,E_k>=1} f_k P.
+    // The layer's channel is a composition of local channels (Section I, the noise
+    // model): the generators acting on one qubit or one pair, consecutive in the list.
+    // The product is taken channel by channel -- inside a run of consecutive generators
+    // with the same support, then over the runs in list order.  Identity generators
+    // commute with every string and are left out.
+    std::vector<int> gens, run_start;
+    std::vector<uint64_t> prev(2 * (size_t)W, 0);
+    for (int k = 0; k < n_gen; ++k) {
+      std::vector<uint64_t> sup(2 * (size_t)W, 0);
+      bool any = false;
+      for (int w = 0; w < W; ++w) {
+        const uint64_t m = ex[(size_t)k * W + w] | ez[(size_t)k * W + w];
+        sup[w] = m;
+        any = any || m != 0;
+      }
+      if (!any) continue;
+      run_start.push_back(gens.empty() || sup != prev ? 1 : 0);
+      gens.push_back(k);
+      prev = sup;
+    }
     for (auto& kv : s->m) {
-      double prod = 1.0;
-      for (int k = 0; k < n_gen; ++k)
-        if (anticommutes(kv.first, ex + (size_t)k * W, ez + (size_t)k * W, W)) prod *= f[k];
+      double prod = 1.0, run = 1.0;
+      for (size_t j = 0; j < gens.size(); ++j) {
+        if (run_start[j] && j > 0) {
+          prod *= run;
+          run = 1.0;
+        }
+        const int k = gens[j];
+        if (anticommutes(kv.first, ex + (size_t)k * W, ez + (size_t)k * W, W)) run *= f[k];
+      }
+      prod *= run;
       kv.second *= prod;
     }
     return;

@@ -288,7 +288,7 @@ struct Engine final : EngineBase {
   bool aborted = false;
   TBuf<double, true> ta, tb;     // tie lists for the cap
   TBuf<CT, ORD> gb;              // boundary candidates of a cap
-  Buf u32a, u32b, u32c, scan_scr, tiles, gates_d, sup_d, tab_d, fidx_d, dm_d, dval_d, cnt_d, ovf_d, partial_d, f64_d, span_d, htab_d, lstat_d;
+  Buf u32a, u32b, u32c, scan_scr, tiles, gates_d, sup_d, tab_d, drun_d, dm_d, dval_d, cnt_d, ovf_d, partial_d, f64_d, span_d, htab_d, lstat_d;
   Buf hp_a, hp_b, tr_s0, tr_l0, tr_s1, tr_l1, g1_d, g1_ovf, g1_base, g1_base2, g1_drop;   // per-gate tile path
   Buf rl0, rl1, ovl1, ovl2, tf_flag, tf_pos, tf_list, g1_io, g1_tab, g1_tabmeta, win_hist_d;
   double growth[4] = {4.0, 4.0, 2.0, 3.0};
@@ -298,7 +298,7 @@ struct Engine final : EngineBase {
   explicit Engine(pp_obs* o) : obs(o), ctx(o->ctx), st(o->ctx->stream) {
     for (auto* t : {&cur, &alt, &sa, &sb, &tmp, &gb}) { t->mem.ctx = ctx; t->W = W; }
     for (auto* t : {&ta, &tb}) { t->mem.ctx = ctx; t->W = W; }
-    for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &fidx_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
+    for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &drun_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
                    &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &g1_drop, &rl0, &rl1, &ovl1, &ovl2,
                    &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d})
       b->ctx = ctx;
@@ -311,7 +311,7 @@ struct Engine final : EngineBase {
   ~Engine() override {
     for (auto* t : {&cur, &alt, &sa, &sb, &tmp, &gb}) t->mem.release();
     for (auto* t : {&ta, &tb}) t->mem.release();
-    for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &fidx_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
+    for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &drun_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
                    &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &g1_drop, &rl0, &rl1, &ovl1, &ovl2,
                    &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d})
       b->release();
@@ -532,7 +532,7 @@ struct Engine final : EngineBase {
   struct HostNoise {
     std::vector<SupportDev> sup;
     std::vector<double> tab;
-    std::vector<uint16_t> fidx;
+    std::vector<uint8_t> drun;
     std::vector<uint64_t> dm;
     std::vector<double> dval;
     int np = 1;
@@ -594,59 +594,47 @@ struct Engine final : EngineBase {
       return sd;
     };
     if (mode == PP_MODE_GREEDY) {
+      // The layer's channel is a composition of local channels: runs of consecutive
+      // generators on the same one or two qubits (identity generators left out).  A
+      // string's factor is the product over runs, in list order, of the run's product of
+      // f_k over the generators it anticommutes with, in list order.
       std::vector<std::pair<int, int>> order;
       std::vector<std::vector<int>> groups;
-      std::map<std::pair<int, int>, int> seen;
       bool tabled = true;
       for (int k = 0; k < L->n_gen && tabled; ++k) {
         const auto sup = gen_support(L, k);
         if (sup.first == -1) continue;             // the identity commutes with everything
         if (sup.first == -2) { tabled = false; break; }
         if (order.empty() || order.back() != sup) {
-          if (seen.count(sup)) { tabled = false; break; }
-          seen[sup] = (int)order.size();
           order.push_back(sup);
           groups.emplace_back();
         }
         groups.back().push_back(k);
       }
       if (!tabled) {
-        for (int k = 0; k < L->n_gen; ++k)
-          if (gen_support(L, k).first != -1) add_direct(k, {fidelity_factor(L->lambda[k], L->noise_sign)});
+        // generators tested one by one; drun marks where a run with a new support starts
+        std::vector<uint64_t> prev;
+        for (int k = 0; k < L->n_gen; ++k) {
+          if (gen_support(L, k).first == -1) continue;
+          std::vector<uint64_t> m(W);
+          for (int w = 0; w < W; ++w) m[w] = L->ex[(size_t)k * W + w] | L->ez[(size_t)k * W + w];
+          hn.drun.push_back(hn.drun.empty() || m != prev ? 1 : 0);
+          prev = m;
+          add_direct(k, {fidelity_factor(L->lambda[k], L->noise_sign)});
+        }
         return hn;
       }
-      // tab: one factor per tabled generator, then 1.0 (the padding target)
-      std::vector<int> slot_of(L->n_gen, -1);
-      for (auto& gk : groups)
-        for (int k : gk) {
-          slot_of[k] = (int)hn.tab.size();
-          hn.tab.push_back(fidelity_factor(L->lambda[k], L->noise_sign));
-        }
-      const int one = (int)hn.tab.size();
-      hn.tab.push_back(1.0);
-      if (one > 65535) throw_fail(PP_ERR_UNSUPPORTED, "more than 65535 noise generators in one layer");
+      // tab: per run and local pattern, the run's product for that pattern (1.0 for none)
       for (size_t si = 0; si < order.size(); ++si) {
         const int q0 = order[si].first, q1 = order[si].second;
         const int npat = q1 < 0 ? 4 : 16;
-        int slots = 1;
-        for (int pat = 1; pat < npat; ++pat) {
-          int cnt = 0;
-          for (int k : groups[si]) cnt += anti_pat(k, q0, q1, pat);
-          slots = std::max(slots, cnt);
-        }
-        slots = (slots + 3) & ~3;   // rows of whole 4-index groups (padding: the 1.0)
         SupportDev sd = make_sup(q0, q1);
-        sd.table = (int32_t)hn.fidx.size();
-        sd.nslot = (int16_t)slots;
         for (int pat = 0; pat < npat; ++pat) {
-          int used = 0;
+          double run = 1.0;
           if (pat)
             for (int k : groups[si])
-              if (anti_pat(k, q0, q1, pat)) {
-                hn.fidx.push_back((uint16_t)slot_of[k]);
-                ++used;
-              }
-          for (; used < slots; ++used) hn.fidx.push_back((uint16_t)one);
+              if (anti_pat(k, q0, q1, pat)) run *= fidelity_factor(L->lambda[k], L->noise_sign);
+          hn.tab.push_back(run);
         }
         hn.sup.push_back(sd);
       }
@@ -669,7 +657,6 @@ struct Engine final : EngineBase {
     for (auto& kv : by_sup) {
       const int q0 = kv.first.first, q1 = kv.first.second;
       SupportDev sd = make_sup(q0, q1);
-      sd.nslot = 0;
       const int npat = q1 < 0 ? 4 : 16;
       for (int pat = 0; pat < npat; ++pat) {
         std::vector<double> acc(np, 0.0);
@@ -691,26 +678,24 @@ struct Engine final : EngineBase {
     nd.nsup = (int)hn.sup.size();
     nd.ndirect = (int)(hn.dm.size() / (2 * W));
     nd.ntab = (int)hn.tab.size();
-    nd.nidx = (int)hn.fidx.size();
     nd.sign = sign;
     nd.mode = mode == PP_MODE_GREEDY ? 0 : 1;
     nd.max_order = max_order;
     sup_d.ensure(hn.sup.size() * sizeof(SupportDev) + 64);
     tab_d.ensure(hn.tab.size() * 8 + 64);
-    fidx_d.ensure(hn.fidx.size() * 2 + 64);
+    drun_d.ensure(hn.drun.size() + 64);
     dm_d.ensure(hn.dm.size() * 8 + 64);
     dval_d.ensure(hn.dval.size() * 8 + 64);
     if (!hn.sup.empty())
       HIPCHK(hipMemcpyAsync(sup_d.p, hn.sup.data(), hn.sup.size() * sizeof(SupportDev), hipMemcpyHostToDevice, st));
     if (!hn.tab.empty()) HIPCHK(hipMemcpyAsync(tab_d.p, hn.tab.data(), hn.tab.size() * 8, hipMemcpyHostToDevice, st));
-    if (!hn.fidx.empty())
-      HIPCHK(hipMemcpyAsync(fidx_d.p, hn.fidx.data(), hn.fidx.size() * 2, hipMemcpyHostToDevice, st));
+    if (!hn.drun.empty()) HIPCHK(hipMemcpyAsync(drun_d.p, hn.drun.data(), hn.drun.size(), hipMemcpyHostToDevice, st));
     if (!hn.dm.empty()) HIPCHK(hipMemcpyAsync(dm_d.p, hn.dm.data(), hn.dm.size() * 8, hipMemcpyHostToDevice, st));
     if (!hn.dval.empty())
       HIPCHK(hipMemcpyAsync(dval_d.p, hn.dval.data(), hn.dval.size() * 8, hipMemcpyHostToDevice, st));
     nd.sup = sup_d.as<SupportDev>();
     nd.tab = tab_d.as<double>();
-    nd.fidx = fidx_d.as<uint16_t>();
+    nd.drun = hn.drun.empty() ? nullptr : drun_d.as<uint8_t>();
     nd.dm = dm_d.as<uint64_t>();
     nd.dval = dval_d.as<double>();
     // The uploads above are ordered on the stream before the kernels that read them; the

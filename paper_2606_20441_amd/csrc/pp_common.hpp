@@ -29,29 +29,28 @@ struct Terms {
 // Noise of one layer, decomposed by generator support on the host:
 //  * `nsup` supports of one or two qubits, each with a table over the 4 or 16 local
 //    Pauli patterns giving, for the generators on that support that anticommute with
-//    the pattern, sum(lambda) (greedy mode) or sum(x_k) and sum(x_k^2) (error-order
-//    mode, x_k = f_k - 1);
-//  * `ndirect` generators with larger support, tested one by one.
+//    the pattern, the product of their factors f_k in list order (greedy mode: one run
+//    of consecutive generators on the same qubits) or the power sums of x_k = f_k - 1
+//    (error-order mode);
+//  * `ndirect` generators tested one by one (larger supports).
 struct SupportDev {
   int16_t w0, b0, w1, b1;   // word/bit of the two qubits (w1 < 0: single qubit)
   int32_t table;            // offset into the value table
-  int16_t nslot;            // greedy mode: factor slots per pattern (a multiple of 4)
-  int16_t pad;
+  int32_t pad;
 };
 
 struct NoiseDev {
   int nsup;
   int ndirect;
   int ntab;                 // doubles in `tab`
-  int nidx;                 // greedy mode: entries of `fidx`
   int sign;                 // +1 inverse map, -1 channel
   int mode;                 // 0 greedy, 1 error order
   int max_order;
   const SupportDev* sup;
-  const double* tab;        // greedy: one fidelity factor per generator, then 1.0; error order: max_order power sums per pattern
-  const uint16_t* fidx;     // greedy: per support and pattern, nslot indices into tab (padding: the 1.0)
+  const double* tab;        // per support and pattern: greedy, the run's product; error order, max_order power sums
   const uint64_t* dm;       // direct generators: [ndirect][2W]
   const double* dval;       // greedy: fidelity factor; error order: max_order powers of x_k
+  const uint8_t* drun;      // greedy, direct generators: 1 where a run on new qubits starts
 };
 
 __device__ __forceinline__ int popc64(uint64_t v) { return __popcll(v); }

@@ -158,32 +158,28 @@ __device__ __forceinline__ void noise_sums(const uint64_t* px, const uint64_t* p
 // generators handled directly come after them.
 template <int W>
 __device__ __forceinline__ double noise_factor(const uint64_t* px, const uint64_t* pz, const double* tab,
-                                               const uint16_t* fidx, const SupportDev* sup, const NoiseDev& nd) {
+                                               const SupportDev* sup, const NoiseDev& nd) {
+  // Greedy mode: the product over runs of generators on the same qubits, in list order, of
+  // each run's product for the string's local pattern (pattern 0: exactly 1.0, skipped).
   double prod = 1.0;
   for (int s = 0; s < nd.nsup; ++s) {
     const SupportDev sp = sup[s];
     uint32_t pat = (uint32_t)((pick<W>(px, sp.w0) >> sp.b0) & 1u) | (uint32_t)(((pick<W>(pz, sp.w0) >> sp.b0) & 1u) << 1);
     if (sp.w1 >= 0)
       pat |= (uint32_t)(((pick<W>(px, sp.w1) >> sp.b1) & 1u) << 2) | (uint32_t)(((pick<W>(pz, sp.w1) >> sp.b1) & 1u) << 3);
-    if (pat) {
-      // rows hold a multiple of 4 indices (8-byte aligned): read 4 at a time so that the
-      // factor loads of a support are in flight together; the product keeps list order
-      const uint64_t* f4 = (const uint64_t*)(fidx + sp.table + (size_t)pat * sp.nslot);
-#pragma unroll 2
-      for (int j = 0; j < (sp.nslot >> 2); ++j) {
-        const uint64_t q = f4[j];
-        const double a0 = tab[q & 0xffffu], a1 = tab[(q >> 16) & 0xffffu];
-        const double a2 = tab[(q >> 32) & 0xffffu], a3 = tab[q >> 48];
-        prod *= a0;
-        prod *= a1;
-        prod *= a2;
-        prod *= a3;
-      }
-    }
+    if (pat) prod *= tab[sp.table + (int)pat];
   }
-  for (int d = 0; d < nd.ndirect; ++d) {
-    const uint64_t* m = nd.dm + (size_t)d * 2 * W;
-    if (anticommutes<W>(px, pz, m)) prod *= nd.dval[d];
+  if (nd.ndirect > 0) {
+    double run = 1.0;
+    for (int d = 0; d < nd.ndirect; ++d) {
+      if (d > 0 && nd.drun[d]) {
+        prod *= run;
+        run = 1.0;
+      }
+      const uint64_t* m = nd.dm + (size_t)d * 2 * W;
+      if (anticommutes<W>(px, pz, m)) run *= nd.dval[d];
+    }
+    prod *= run;
   }
   return prod;
 }
@@ -661,7 +657,7 @@ __global__ void __launch_bounds__(BLOCK) k_layer(LayerArgs<CT> a) {
         if (c == 0.0) continue;
         uint64_t kx[W], kz[W];
         load_key(i, kx, kz);
-        sc[i] = (CT)(c * noise_factor<W>(kx, kz, nd.tab, nd.fidx, nd.sup, nd));
+        sc[i] = (CT)(c * noise_factor<W>(kx, kz, nd.tab, nd.sup, nd));
       }
       __syncthreads();
     } else if (ORD) {
@@ -817,14 +813,12 @@ __global__ void k_tile_starts(const uint32_t* bnd, uint32_t nb, uint64_t n, uint
 // ------------------------------------------------------------------------------------------
 // Bytes of LDS a noise descriptor needs when staged (table, then supports).
 inline size_t noise_lds_bytes(const NoiseDev& nd) {
-  return (size_t)nd.ntab * sizeof(double) + (size_t)nd.nsup * sizeof(SupportDev) +
-         (((size_t)nd.nidx * sizeof(uint16_t) + 15) & ~(size_t)15);
+  return (size_t)nd.ntab * sizeof(double) + (size_t)nd.nsup * sizeof(SupportDev);
 }
 constexpr size_t kNoiseLdsMax = 64 * 1024;
 
-// LDS layout of a staged noise descriptor: tab (doubles), supports, factor indices.
-__device__ __forceinline__ void stage_noise(const NoiseDev& nd, double* stab, SupportDev* ssup, uint16_t* sidx) {
-  for (int j = threadIdx.x; j < nd.nidx; j += blockDim.x) sidx[j] = nd.fidx[j];
+// LDS layout of a staged noise descriptor: tab (doubles), then supports.
+__device__ __forceinline__ void stage_noise(const NoiseDev& nd, double* stab, SupportDev* ssup) {
   for (int j = threadIdx.x; j < nd.ntab; j += blockDim.x) stab[j] = nd.tab[j];
   for (int j = threadIdx.x; j < nd.nsup; j += blockDim.x) ssup[j] = nd.sup[j];
 }
@@ -839,9 +833,8 @@ __global__ void __launch_bounds__(1024) k_clifford(Terms<CT> t, uint64_t n, cons
   GateDev* sg = (GateDev*)dsm;
   double* stab = (double*)(sg + ngates);
   SupportDev* ssup = (SupportDev*)(stab + (has_noise ? nd.ntab : 0));
-  uint16_t* sidx = (uint16_t*)(ssup + (has_noise ? nd.nsup : 0));
   for (int j = threadIdx.x; j < ngates; j += blockDim.x) sg[j] = gates[j];
-  if (has_noise) stage_noise(nd, stab, ssup, sidx);
+  if (has_noise) stage_noise(nd, stab, ssup);
   __syncthreads();
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
     uint64_t kx[W], kz[W];
@@ -863,7 +856,7 @@ __global__ void __launch_bounds__(1024) k_clifford(Terms<CT> t, uint64_t n, cons
         for (int w = 0; w < W; ++w) { kx[w] ^= m[w]; kz[w] ^= m[W + w]; }
       }
     }
-    if (has_noise) c = c * noise_factor<W>(kx, kz, stab, sidx, ssup, nd);
+    if (has_noise) c = c * noise_factor<W>(kx, kz, stab, ssup, nd);
 #pragma unroll
     for (int w = 0; w < W; ++w) { t.x[w * t.stride + i] = kx[w]; t.z[w * t.stride + i] = kz[w]; }
     t.c[i] = (CT)c;
@@ -875,15 +868,14 @@ __global__ void __launch_bounds__(1024) k_noise_greedy(Terms<CT> t, uint64_t n, 
   extern __shared__ double dsm[];
   double* stab = dsm;
   SupportDev* ssup = (SupportDev*)(stab + nd.ntab);
-  uint16_t* sidx = (uint16_t*)(ssup + nd.nsup);
-  stage_noise(nd, stab, ssup, sidx);
+  stage_noise(nd, stab, ssup);
   __syncthreads();
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
     uint64_t kx[W], kz[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) { kx[w] = t.x[w * t.stride + i]; kz[w] = t.z[w * t.stride + i]; }
     const double c = (double)t.c[i];
-    t.c[i] = (CT)(c * noise_factor<W>(kx, kz, stab, sidx, ssup, nd));
+    t.c[i] = (CT)(c * noise_factor<W>(kx, kz, stab, ssup, nd));
   }
 }
 

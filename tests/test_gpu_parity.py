@@ -138,6 +138,38 @@ def test_noise_general_generators(pp, ctx, orc):
     compare_sums(g.as_dict(), o.as_dict(), rtol=1e-13, context="noise general")
 
 
+@pytest.mark.parametrize("variant", ["interleaved", "with_weight3"])
+def test_noise_runs_bit_exact(pp, ctx, orc, variant):
+    """Greedy factors are products over runs of consecutive generators on the same qubits,
+    in list order, on both sides: supports that come back later in the list (a new run) and
+    lists with a weight-3 generator (all generators tested one by one) match bit for bit."""
+    log(f"noise runs {variant}")
+    n = 12
+    rng = np.random.default_rng(21)
+    gens = []
+    for _ in range(60):
+        if variant == "with_weight3" and rng.random() < 0.1:
+            qs = rng.choice(n, 3, replace=False)
+        elif rng.random() < 0.5:
+            qs = [int(rng.integers(0, n))]
+        else:
+            q = int(rng.integers(0, n - 1))
+            qs = [q, q + 1]
+        ops = {int(q): "XYZ"[int(rng.integers(0, 3))] for q in qs}
+        # runs of 1-3 generators on the same qubits
+        for _ in range(int(rng.integers(1, 4))):
+            ops2 = {q: "XYZ"[int(rng.integers(0, 3))] for q in ops}
+            gens.append((ops2, float(rng.uniform(1e-3, 5e-2))))
+    layer = W.make_layer(n, [], gens)
+    ps = W.random_pauli_arrays(n, 3000, seed=9, density=0.5)
+    for sign in (1, -1):
+        g = pp.Observable.from_sum(ctx, ps)
+        o = orc.OracleSum.from_sum(ps)
+        g.apply_layer(layer, with_gates=False, noise_sign=sign)
+        o.noise(layer.ex, layer.ez, layer.lam, sign=sign)
+        compare_sums(g.as_dict(), o.as_dict(), rtol=0.0, atol=0.0, context=f"noise runs {variant} {sign}")
+
+
 @pytest.mark.parametrize("max_order", [0, 1, 2, 3])
 def test_noise_error_order(pp, ctx, orc, max_order):
     log(f"error-order noise M={max_order}")
