@@ -211,7 +211,8 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
   __shared__ uint8_t so[ORD ? CAP : 1];
   __shared__ uint32_t hidx[H];
   __shared__ uint32_t s_new, s_ovf, s_any;
-  __shared__ uint32_t s_wsum[NW];
+  __shared__ uint32_t s_slice[R * NW];
+  __shared__ uint32_t s_total;
   __shared__ double s_drop[NW];
 
   const int tid = threadIdx.x;
@@ -390,28 +391,51 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
       } else {
         const uint32_t n = n0 + s_new;
         // ---- compact and write -------------------------------------------------------------------
-        // thread tid owns entries [tid * R, tid * R + R): contiguous ranks keep the tile's order
-        uint32_t cnt = 0;
+        // Entry i = r * BLOCK + tid: the survivors of one (r, wavefront) slice are ranked by a
+        // ballot, the slices in entry order by their counts, so the tile's order is kept,
+        // LDS reads are consecutive and the global writes of a wavefront are contiguous.
+        const int wv = tid >> 6;
+        const uint64_t below = (1ULL << lane) - 1ULL;
+        uint64_t bal[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const uint32_t i = (uint32_t)tid * R + r;
-          cnt += (i < n && sc[i] != (CT)0) ? 1u : 0u;
-        }
-        uint32_t incl = cnt;
-        for (int d = 1; d < 64; d <<= 1) {
-          const uint32_t v = __shfl_up(incl, d, 64);
-          if (lane >= d) incl += v;
+          const uint32_t i = (uint32_t)r * BLOCK + tid;
+          bal[r] = __ballot(i < n && sc[i] != (CT)0);
+          if (lane == 0) s_slice[r * NW + wv] = (uint32_t)__popcll(bal[r]);
         }
         double lsum = lost;
         for (int d = 32; d >= 1; d >>= 1) lsum += __shfl_xor(lsum, d, 64);
-        if (lane == 63) s_wsum[tid >> 6] = incl;
-        if (lane == 0) s_drop[tid >> 6] = lsum;
+        if (lane == 0) s_drop[wv] = lsum;
         __syncthreads();
-        uint32_t before = 0, total = 0;
+        uint32_t pre[R];
+        uint32_t total = 0;
+        if constexpr (NW <= 4) {
 #pragma unroll
-        for (int w = 0; w < NW; ++w) {
-          before += (w < (tid >> 6)) ? s_wsum[w] : 0u;
-          total += s_wsum[w];
+          for (int r = 0; r < R; ++r) {
+            uint32_t before = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) before += w < wv ? s_slice[r * NW + w] : 0u;
+            pre[r] = total + before;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) total += s_slice[r * NW + w];
+          }
+        } else {
+          // one wavefront scans the R * NW (<= 64) slice counts in place
+          static_assert(R * NW <= 64, "slice scan");
+          if (wv == 0) {
+            const uint32_t v = lane < R * NW ? s_slice[lane] : 0u;
+            uint32_t incl = v;
+            for (int d = 1; d < 64; d <<= 1) {
+              const uint32_t u = __shfl_up(incl, d, 64);
+              if (lane >= d) incl += u;
+            }
+            if (lane < R * NW) s_slice[lane] = incl - v;
+            if (lane == R * NW - 1) s_total = incl;
+          }
+          __syncthreads();
+#pragma unroll
+          for (int r = 0; r < R; ++r) pre[r] = s_slice[r * NW + wv];
+          total = s_total;
         }
         // the tile's output region holds 2 * n0 slots (a gate at most doubles a tile); unused
         // slots get a zero coefficient so that sweeps over the whole buffer skip them
@@ -424,12 +448,11 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
           acc_out += total;
         }
         for (uint64_t i = base + total + tid; i < base + 2ULL * n0; i += BLOCK) a.out.c[i] = (CT)0;
-        uint32_t rank = before + incl - cnt;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const uint32_t i = (uint32_t)tid * R + r;
-          if (i >= n || sc[i] == (CT)0) continue;
-          const uint64_t dst = base + rank++;
+          if (!((bal[r] >> lane) & 1ULL)) continue;
+          const uint32_t i = (uint32_t)r * BLOCK + tid;
+          const uint64_t dst = base + pre[r] + (uint32_t)__popcll(bal[r] & below);
 #pragma unroll
           for (int w = 0; w < W; ++w) {
             a.out.x[w * a.out.stride + dst] = sx[w][i];
