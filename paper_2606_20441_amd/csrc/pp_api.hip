@@ -290,7 +290,7 @@ struct Engine final : EngineBase {
   TBuf<CT, ORD> gb;              // boundary candidates of a cap
   Buf u32a, u32b, u32c, scan_scr, tiles, gates_d, sup_d, tab_d, drun_d, dm_d, dval_d, cnt_d, ovf_d, partial_d, f64_d, span_d, htab_d, lstat_d;
   Buf hp_a, hp_b, tr_s0, tr_l0, tr_s1, tr_l1, g1_d, g1_ovf, g1_base, g1_base2, g1_drop;   // per-gate tile path
-  Buf rl0, rl1, ovl1, ovl2, tf_flag, tf_pos, tf_list, g1_io, g1_tab, g1_tabmeta, win_hist_d;
+  Buf rl0, rl1, rl2, ovl1, ovl2, tf_flag, tf_pos, tf_list, g1_io, g1_tab, g1_tabmeta, win_hist_d;
   double growth[4] = {4.0, 4.0, 2.0, 3.0};
   double tile_target[4] = {80.0, 80.0, 80.0, 64.0};   // level-0 (one-wavefront) tile targets
   uint64_t last_ntiles = 1, last_ovf_tiles = 0;
@@ -299,7 +299,7 @@ struct Engine final : EngineBase {
     for (auto* t : {&cur, &alt, &sa, &sb, &tmp, &gb}) { t->mem.ctx = ctx; t->W = W; }
     for (auto* t : {&ta, &tb}) { t->mem.ctx = ctx; t->W = W; }
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &drun_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
-                   &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &g1_drop, &rl0, &rl1, &ovl1, &ovl2,
+                   &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &g1_drop, &rl0, &rl1, &rl2, &ovl1, &ovl2,
                    &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d})
       b->ctx = ctx;
     cnt_d.ensure(256);
@@ -312,7 +312,7 @@ struct Engine final : EngineBase {
     for (auto* t : {&cur, &alt, &sa, &sb, &tmp, &gb}) t->mem.release();
     for (auto* t : {&ta, &tb}) t->mem.release();
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &drun_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
-                   &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &g1_drop, &rl0, &rl1, &ovl1, &ovl2,
+                   &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &g1_drop, &rl0, &rl1, &rl2, &ovl1, &ovl2,
                    &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d})
       b->release();
   }
@@ -1122,11 +1122,12 @@ struct Engine final : EngineBase {
   static constexpr size_t kPinBases = 512, kPinDrop = 2048, kPinWin = 4096;
 
   struct G1Counters {
-    uint32_t nlist[2];   // routed tiles: small, larger
+    uint32_t nlist[3];   // routed tiles: small, middle, large
     uint32_t ovf[3];     // tiles reported by the one-wavefront, 256-thread and 1024-thread shapes
     uint32_t big_count;
   };
   static constexpr uint32_t kG1SmallMax = 128;   // tiles up to this size start in one wavefront
+  static constexpr uint32_t kG1MidMax = 256;     // up to this size in 128 threads (room for 512)
   // LDS capacity of the one-wavefront shape: less LDS per wavefront, more of them per compute
   // unit; a tile that outgrows it is redone in the 256-thread shape
   static constexpr int kG1WaveCap = 256;
@@ -1134,7 +1135,7 @@ struct Engine final : EngineBase {
   static constexpr uint32_t kG1Big = 160;       // a tile above this may outgrow the one-wavefront shape at the next gate
   uint64_t g1_ntiles = 0;
   bool routed = false;      // tile lists by size are current for this tiling
-  uint32_t route_n[2] = {0, 0};
+  uint32_t route_n[3] = {0, 0, 0};
 
   // Group the terms by the run's invariant bits, cut them into tiles of whole groups and
   // compute the per-term hash plane (cur must be dense).
@@ -1388,7 +1389,7 @@ struct Engine final : EngineBase {
   // `ntiles` list entries, or, with dev_count, the count the device holds there (at most ntiles).
   template <int CAPK, int BLOCKK>
   void g1_launch(Gate1Args<CT> a, unsigned ntiles, int shape, const uint32_t* dev_count = nullptr) {
-    static const char* names[3] = {"gate_tile_wave", "gate_tile_256", "gate_tile_1024"};
+    static const char* names[4] = {"gate_tile_wave", "gate_tile_256", "gate_tile_1024", "gate_tile_128"};
     g1_io.ensure(2 * kDropSlots * 8 + 64);
     unsigned long long* io = g1_io.as<unsigned long long>();
     a.io = io;
@@ -1482,7 +1483,7 @@ struct Engine final : EngineBase {
       hp_b.ensure(alt.cap * 4 + 64);
       tr_s1.ensure(ntiles * 4 + 64);
       tr_l1.ensure(ntiles * 4 + 64);
-      for (Buf* b : {&rl0, &rl1, &g1_ovf, &ovl1, &ovl2}) b->ensure(ntiles * 4 + 64);
+      for (Buf* b : {&rl0, &rl1, &rl2, &g1_ovf, &ovl1, &ovl2}) b->ensure(ntiles * 4 + 64);
       HIPCHK(hipMemsetAsync(cd, 0, sizeof(G1Counters), st));
       HIPCHK(hipMemsetAsync(dropd, 0, kDropSlots * 8, st));
       G1Counters hc;
@@ -1495,18 +1496,16 @@ struct Engine final : EngineBase {
         // sort the tiles by size once per tiling (a tile changes size slowly; one that
         // outgrows the wavefront shape is retried in the next shape)
         hipLaunchKernelGGL(k_route_tiles, grid1(ntiles), dim3(256), 0, st, (const uint32_t*)tr_l0.as<uint32_t>(),
-                           (uint32_t)ntiles, kG1SmallMax, (const uint32_t*)g1_base.as<uint32_t>(),
+                           (uint32_t)ntiles, kG1SmallMax, kG1MidMax, (const uint32_t*)g1_base.as<uint32_t>(),
                            tr_s1.as<uint32_t>(), tr_l1.as<uint32_t>(), rl0.as<uint32_t>(), rl1.as<uint32_t>(),
-                           &cd->nlist[0]);
+                           rl2.as<uint32_t>(), &cd->nlist[0]);
         ctx->check_launch();
         read_counters();
-        route_n[0] = hc.nlist[0];
-        route_n[1] = hc.nlist[1];
+        for (int k = 0; k < 3; ++k) route_n[k] = hc.nlist[k];
         routed = true;
         HIPCHK(hipMemsetAsync(cd, 0, sizeof(G1Counters), st));
       }
-      hc.nlist[0] = route_n[0];
-      hc.nlist[1] = route_n[1];
+      for (int k = 0; k < 3; ++k) hc.nlist[k] = route_n[k];
       Gate1Args<CT> a{};
       a.in = cur.view();
       a.out = alt.view();
@@ -1535,12 +1534,14 @@ struct Engine final : EngineBase {
       // One wavefront for small tiles, 256 threads for the others.  Tiles that outgrow a shape
       // are retried in the next; the retries read their counts on the device, so the whole
       // cascade is enqueued without waiting.
-      const uint32_t nl0 = hc.nlist[0], nl1 = hc.nlist[1];
+      const uint32_t nl0 = hc.nlist[0], nl1 = hc.nlist[1], nl2 = hc.nlist[2];
       if (nl0) g1_launch<kG1WaveCap, 64>(with_list(rl0, g1_ovf, 0, 0), nl0, 0);
-      if (nl1) g1_launch<1024, 256>(with_list(rl1, ovl1, 1, 0), nl1, 1);
-      if (nl0) g1_launch<1024, 256>(with_list(g1_ovf, ovl1, 1, 0), nl0, 1, &cd->ovf[0]);
-      if (nl0 + nl1)
-        g1_launch<LayerCfg<W>::CAP, LayerCfg<W>::BLOCK>(with_list(ovl1, ovl2, 2, 1), nl0 + nl1, 2, &cd->ovf[1]);
+      if (nl1) g1_launch<512, 128>(with_list(rl1, g1_ovf, 0, 0), nl1, 3);
+      if (nl2) g1_launch<1024, 256>(with_list(rl2, ovl1, 1, 0), nl2, 1);
+      if (nl0 + nl1) g1_launch<1024, 256>(with_list(g1_ovf, ovl1, 1, 0), nl0 + nl1, 1, &cd->ovf[0]);
+      if (nl0 + nl1 + nl2)
+        g1_launch<LayerCfg<W>::CAP, LayerCfg<W>::BLOCK>(with_list(ovl1, ovl2, 2, 1), nl0 + nl1 + nl2, 2,
+                                                         &cd->ovf[1]);
       // counters, the next gate's output bases (other buffer: the oversize pass below still
       // reads these) and the dropped weight, read back together
       HIPCHK(hipMemcpyAsync(ctx->pinned, cd, sizeof hc, hipMemcpyDeviceToHost, st));
@@ -1550,7 +1551,8 @@ struct Engine final : EngineBase {
       std::memcpy(&hc, ctx->pinned, sizeof hc);
       hc.nlist[0] = nl0;
       hc.nlist[1] = nl1;
-      if (hc.ovf[0] * 16 > nl0) routed = false;   // many tiles outgrew the wavefront shape
+      hc.nlist[2] = nl2;
+      if (hc.ovf[0] * 16 > nl0 + nl1) routed = false;   // many tiles outgrew their shape
       uint64_t giant_terms = 0;
       uint64_t next_extent = g1_bases_read();
       std::vector<double> dsl(kDropSlots);

@@ -678,10 +678,10 @@ __global__ void k_hash_plane(Terms<CT> t, uint64_t n, const uint32_t* htab, uint
 }
 
 // Sort tiles by size: empty tiles get their (empty) output record here, tiles of at most
-// small_max terms go to list 0, the others to list 1.
-__global__ void k_route_tiles(const uint32_t* len, uint32_t ntiles, uint32_t small_max, const uint32_t* o_base,
-                              uint32_t* o_start, uint32_t* o_len, uint32_t* list0, uint32_t* list1,
-                              uint32_t* counts) {
+// small_max terms go to list 0, of at most mid_max to list 1, the others to list 2.
+__global__ void k_route_tiles(const uint32_t* len, uint32_t ntiles, uint32_t small_max, uint32_t mid_max,
+                              const uint32_t* o_base, uint32_t* o_start, uint32_t* o_len, uint32_t* list0,
+                              uint32_t* list1, uint32_t* list2, uint32_t* counts) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t l = t < ntiles ? len[t] : 0u;
   if (t < ntiles && l == 0) {
@@ -690,16 +690,17 @@ __global__ void k_route_tiles(const uint32_t* len, uint32_t ntiles, uint32_t sma
   }
   const int lane = threadIdx.x & 63;
   const uint64_t lt = (1ULL << lane) - 1ULL;
+  const int cls = l <= small_max ? 0 : (l <= mid_max ? 1 : 2);
 #pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const bool mine = t < ntiles && l > 0 && ((l <= small_max) == (k == 0));
+  for (int k = 0; k < 3; ++k) {
+    const bool mine = t < ntiles && l > 0 && cls == k;
     const uint64_t bal = __ballot(mine);
     if (!bal) continue;
     const int leader = __ffsll((unsigned long long)bal) - 1;
     uint32_t base = 0;
     if (lane == leader) base = atomicAdd(&counts[k], (uint32_t)__popcll(bal));
     base = __shfl(base, leader, 64);
-    if (mine) (k == 0 ? list0 : list1)[base + (uint32_t)__popcll(bal & lt)] = t;
+    if (mine) (k == 0 ? list0 : (k == 1 ? list1 : list2))[base + (uint32_t)__popcll(bal & lt)] = t;
   }
 }
 
