@@ -163,6 +163,13 @@ __device__ void pass_through(const Gate1Args<CT>& a, uint32_t tile, uint32_t t0,
 // keys always has an empty slot, so every probe sequence ends.
 constexpr int pow2_above(int n) { return n < 1 ? 1 : 2 * pow2_above(n / 2); }
 
+// A uniform read of a table that no kernel writes while this one runs, through the
+// constant address space: a scalar load, counted apart from the vector loads and stores,
+// so waiting for it does not drain them.
+__device__ __forceinline__ uint32_t ld_uniform(const uint32_t* p, uint32_t i) {
+  return ((const __attribute__((address_space(4))) uint32_t*)p)[i];
+}
+
 // One tile's terms in registers: entry r of thread tid is term r * BLOCK + tid of the tile.
 template <int W, class CT, int R>
 struct G1Regs {
@@ -221,7 +228,7 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
   const uint32_t G = gridDim.x;
   uint32_t li = blockIdx.x;
   if (li >= count) return;
-  auto tile_at = [&](uint32_t l) { return a.t_list ? a.t_list[l] : l; };
+  auto tile_at = [&](uint32_t l) { return a.t_list ? ld_uniform(a.t_list, l) : l; };
 
   uint64_t m[2 * W];
 #pragma unroll
@@ -232,12 +239,12 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
   const double thr = a.eps;
 
   // current tile and the next one (ranges), the current tile's terms in flight
-  uint32_t tile = tile_at(li), t0 = a.t_start[tile], n0 = a.t_len[tile];
+  uint32_t tile = tile_at(li), t0 = ld_uniform(a.t_start, tile), n0 = ld_uniform(a.t_len, tile);
   uint32_t tile_n = 0, t0_n = 0, n0_n = 0;
   if (li + G < count) {
     tile_n = tile_at(li + G);
-    t0_n = a.t_start[tile_n];
-    n0_n = a.t_len[tile_n];
+    t0_n = ld_uniform(a.t_start, tile_n);
+    n0_n = ld_uniform(a.t_len, tile_n);
   }
   G1Regs<W, CT, R> cur;
   g1_fetch<W, CT, ORD, CAP, BLOCK>(a, cur, t0, n0);
@@ -253,10 +260,10 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
     uint32_t tile_nn = 0, t0_nn = 0, n0_nn = 0;
     if (li + 2 * G < count) {
       tile_nn = tile_at(li + 2 * G);
-      t0_nn = a.t_start[tile_nn];
-      n0_nn = a.t_len[tile_nn];
+      t0_nn = ld_uniform(a.t_start, tile_nn);
+      n0_nn = ld_uniform(a.t_len, tile_nn);
     }
-    const uint64_t base = a.o_base[tile];
+    const uint64_t base = ld_uniform(a.o_base, tile);
     double lost = 0.0;
     if (n0 > (uint32_t)CAP) {
       if (more) g1_fetch<W, CT, ORD, CAP, BLOCK>(a, cur, t0_n, n0_n);
