@@ -289,7 +289,7 @@ struct Engine final : EngineBase {
   TBuf<double, true> ta, tb;     // tie lists for the cap
   TBuf<CT, ORD> gb;              // boundary candidates of a cap
   Buf u32a, u32b, u32c, scan_scr, tiles, gates_d, sup_d, tab_d, drun_d, dm_d, dval_d, cnt_d, ovf_d, partial_d, f64_d, span_d, htab_d, lstat_d;
-  Buf hp_a, hp_b, tr_s0, tr_l0, tr_s1, tr_l1, g1_d, g1_ovf, g1_base, g1_base2, g1_drop;   // per-gate tile path
+  Buf hp_a, hp_b, tr_s0, tr_l0, tr_s1, tr_l1, g1_d, g1_ovf, g1_base, g1_base2;   // per-gate tile path
   Buf rl0, rl1, rl2, ovl1, ovl2, tf_flag, tf_pos, tf_list, g1_io, g1_tab, g1_tabmeta, win_hist_d;
   double growth[4] = {4.0, 4.0, 2.0, 3.0};
   double tile_target[4] = {80.0, 80.0, 80.0, 64.0};   // level-0 (one-wavefront) tile targets
@@ -299,7 +299,7 @@ struct Engine final : EngineBase {
     for (auto* t : {&cur, &alt, &sa, &sb, &tmp, &gb}) { t->mem.ctx = ctx; t->W = W; }
     for (auto* t : {&ta, &tb}) { t->mem.ctx = ctx; t->W = W; }
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &drun_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
-                   &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &g1_drop, &rl0, &rl1, &rl2, &ovl1, &ovl2,
+                   &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &rl0, &rl1, &rl2, &ovl1, &ovl2,
                    &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d})
       b->ctx = ctx;
     cnt_d.ensure(256);
@@ -312,7 +312,7 @@ struct Engine final : EngineBase {
     for (auto* t : {&cur, &alt, &sa, &sb, &tmp, &gb}) t->mem.release();
     for (auto* t : {&ta, &tb}) t->mem.release();
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &drun_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
-                   &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &g1_drop, &rl0, &rl1, &rl2, &ovl1, &ovl2,
+                   &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &rl0, &rl1, &rl2, &ovl1, &ovl2,
                    &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d})
       b->release();
   }
@@ -1117,14 +1117,17 @@ struct Engine final : EngineBase {
   }
 
   // ---- gate by gate over persistent tiles --------------------------------------------------------
-  // host-pinned scratch layout: counters at 0, the bases' total at kPinBases, the dropped
-  // weight at kPinDrop, the window histogram at kPinWin
-  static constexpr size_t kPinBases = 512, kPinDrop = 2048, kPinWin = 4096;
+  // host-pinned scratch layout: the gate pass's counter block at 0, a bases total at
+  // kPinBases, the window histogram at kPinWin
+  static constexpr size_t kPinBases = 3072, kPinWin = 4096;
 
   struct G1Counters {
     uint32_t nlist[3];   // routed tiles: small, middle, large
     uint32_t ovf[3];     // tiles reported by the one-wavefront, 256-thread and 1024-thread shapes
     uint32_t big_count;
+    uint32_t pad;
+    unsigned long long bases_total;   // the next gate's output extent
+    double drop[kDropSlots];          // sum of |c| removed, per slot
   };
   static constexpr uint32_t kG1SmallMax = 128;   // tiles up to this size start in one wavefront
   static constexpr uint32_t kG1MidMax = 256;     // up to this size in 128 threads (room for 512)
@@ -1170,27 +1173,34 @@ struct Engine final : EngineBase {
 
   // Output bases of the tiles for the next gate: exclusive prefix of 2 * len.  Returns the
   // total (the extent of the output buffer).
-  // Enqueue the bases into `out` and the copy of their total to the host (read after a sync
-  // with g1_bases_read).
-  void g1_bases_launch(const uint32_t* len, uint64_t ntiles, Buf& out) {
+  // Enqueue the bases into `out` (exclusive prefix of 2 * len) and their total into *total.
+  void g1_bases_launch(const uint32_t* len, uint64_t ntiles, Buf& out, unsigned long long* total) {
     out.ensure(ntiles * 4 + 64);
     uint32_t* b = out.as<uint32_t>();
-    hipLaunchKernelGGL(k_double_len, grid1(ntiles), dim3(256), 0, st, len, (uint32_t)ntiles, b);
+    const uint64_t nb = cdiv(ntiles, kSortTile);
+    ctx->run("scan", 0, (double)ntiles, [&] {
+      if (nb == 1) {
+        hipLaunchKernelGGL(k_bases_apply, dim3(1), dim3(kSortBlock), 0, st, len, ntiles, (const uint32_t*)nullptr, b,
+                           total);
+      } else {
+        scan_scr.ensure(scan_scratch_words(nb) * 4 + nb * 4 + 256);
+        uint32_t* sums = scan_scr.as<uint32_t>();
+        hipLaunchKernelGGL(k_bases_sums, dim3((unsigned)nb), dim3(kSortBlock), 0, st, len, ntiles, sums);
+        exclusive_scan_u32(sums, nb, sums + nb + 64, st);
+        hipLaunchKernelGGL(k_bases_apply, dim3((unsigned)nb), dim3(kSortBlock), 0, st, len, ntiles,
+                           (const uint32_t*)sums, b, total);
+      }
+    });
     ctx->check_launch();
-    HIPCHK(hipMemcpyAsync((char*)ctx->pinned + kPinBases, b + ntiles - 1, 4, hipMemcpyDeviceToHost, st));
-    scan_u32(b, ntiles);
-    HIPCHK(hipMemcpyAsync((char*)ctx->pinned + kPinBases + 4, b + ntiles - 1, 4, hipMemcpyDeviceToHost, st));
-  }
-  uint64_t g1_bases_read() const {
-    uint32_t last = 0, lastb = 0;
-    std::memcpy(&last, (const char*)ctx->pinned + kPinBases, 4);
-    std::memcpy(&lastb, (const char*)ctx->pinned + kPinBases + 4, 4);
-    return (uint64_t)lastb + last;
   }
   uint64_t g1_bases(const uint32_t* len, uint64_t ntiles) {
-    g1_bases_launch(len, ntiles, g1_base);
+    unsigned long long* tot = &g1_d.as<G1Counters>()->bases_total;
+    g1_bases_launch(len, ntiles, g1_base, tot);
+    HIPCHK(hipMemcpyAsync((char*)ctx->pinned + kPinBases, tot, 8, hipMemcpyDeviceToHost, st));
     sync();
-    return g1_bases_read();
+    unsigned long long v = 0;
+    std::memcpy(&v, (const char*)ctx->pinned + kPinBases, 8);
+    return v;
   }
 
   static uint64_t abs_key_host(CT v) {
@@ -1460,9 +1470,8 @@ struct Engine final : EngineBase {
     uint64_t extent = N;      // slots of cur that hold terms or zeros
     uint64_t out_extent = 0;  // slots the next pass writes
     g1_d.ensure(sizeof(G1Counters) + 64);
-    g1_drop.ensure(kDropSlots * 8 + 64);
     G1Counters* cd = g1_d.as<G1Counters>();
-    double* dropd = g1_drop.as<double>();
+    double* dropd = &cd->drop[0];
     auto densify = [&]() {   // apply a pending cut and squeeze out the unused slots
       N = extent;
       apply_cut(cut, ls);
@@ -1485,7 +1494,6 @@ struct Engine final : EngineBase {
       tr_l1.ensure(ntiles * 4 + 64);
       for (Buf* b : {&rl0, &rl1, &rl2, &g1_ovf, &ovl1, &ovl2}) b->ensure(ntiles * 4 + 64);
       HIPCHK(hipMemsetAsync(cd, 0, sizeof(G1Counters), st));
-      HIPCHK(hipMemsetAsync(dropd, 0, kDropSlots * 8, st));
       G1Counters hc;
       auto read_counters = [&]() {
         HIPCHK(hipMemcpyAsync(ctx->pinned, cd, sizeof hc, hipMemcpyDeviceToHost, st));
@@ -1542,11 +1550,11 @@ struct Engine final : EngineBase {
       if (nl0 + nl1 + nl2)
         g1_launch<LayerCfg<W>::CAP, LayerCfg<W>::BLOCK>(with_list(ovl1, ovl2, 2, 1), nl0 + nl1 + nl2, 2,
                                                          &cd->ovf[1]);
-      // counters, the next gate's output bases (other buffer: the oversize pass below still
-      // reads these) and the dropped weight, read back together
+      // the next gate's output bases (other buffer: the oversize pass below still reads the
+      // current ones) and their total, then the counter block (counts, total, dropped
+      // weight) read back in one copy
+      g1_bases_launch(tr_l1.as<uint32_t>(), ntiles, g1_base2, &cd->bases_total);
       HIPCHK(hipMemcpyAsync(ctx->pinned, cd, sizeof hc, hipMemcpyDeviceToHost, st));
-      g1_bases_launch(tr_l1.as<uint32_t>(), ntiles, g1_base2);
-      HIPCHK(hipMemcpyAsync((char*)ctx->pinned + kPinDrop, dropd, kDropSlots * 8, hipMemcpyDeviceToHost, st));
       sync();
       std::memcpy(&hc, ctx->pinned, sizeof hc);
       hc.nlist[0] = nl0;
@@ -1554,9 +1562,8 @@ struct Engine final : EngineBase {
       hc.nlist[2] = nl2;
       if (hc.ovf[0] * 16 > nl0 + nl1) routed = false;   // many tiles outgrew their shape
       uint64_t giant_terms = 0;
-      uint64_t next_extent = g1_bases_read();
-      std::vector<double> dsl(kDropSlots);
-      std::memcpy(dsl.data(), (const char*)ctx->pinned + kPinDrop, kDropSlots * 8);
+      uint64_t next_extent = hc.bases_total;
+      std::vector<double> dsl(hc.drop, hc.drop + kDropSlots);
       if (hc.ovf[2] > 0) {
         // classes too large for LDS that the gate touches: one workgroup per tile in its own
         // output region, with a hash table in global memory
@@ -1604,11 +1611,12 @@ struct Engine final : EngineBase {
         }
         sync();   // host vectors above are copy sources
         // the tiles it wrote change the bases and the dropped weight read above
-        g1_bases_launch(tr_l1.as<uint32_t>(), ntiles, g1_base2);
-        HIPCHK(hipMemcpyAsync((char*)ctx->pinned + kPinDrop, dropd, kDropSlots * 8, hipMemcpyDeviceToHost, st));
+        g1_bases_launch(tr_l1.as<uint32_t>(), ntiles, g1_base2, &cd->bases_total);
+        HIPCHK(hipMemcpyAsync(ctx->pinned, cd, sizeof hc, hipMemcpyDeviceToHost, st));
         sync();
-        next_extent = g1_bases_read();
-        std::memcpy(dsl.data(), (const char*)ctx->pinned + kPinDrop, kDropSlots * 8);
+        std::memcpy(&hc, ctx->pinned, sizeof hc);
+        next_extent = hc.bases_total;
+        dsl.assign(hc.drop, hc.drop + kDropSlots);
       }
       cur.swap(alt);
       std::swap(hp_a, hp_b);

@@ -711,12 +711,6 @@ __global__ void k_route_tiles(const uint32_t* len, uint32_t ntiles, uint32_t sma
   }
 }
 
-// v[t] = 2 * len[t] (output region sizes; an exclusive scan turns them into bases).
-__global__ void k_double_len(const uint32_t* len, uint32_t ntiles, uint32_t* v) {
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < ntiles) v[t] = 2u * len[t];
-}
-
 // Tile ranges from tile starts ([ntiles + 1] prefix form).
 __global__ void k_tile_ranges(const uint32_t* starts, uint32_t ntiles, uint32_t* start, uint32_t* len) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;

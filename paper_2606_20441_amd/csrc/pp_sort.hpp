@@ -87,6 +87,44 @@ __global__ void __launch_bounds__(kSortBlock) k_scan_apply(uint32_t* data, uint6
   }
 }
 
+// Output-region bases of tiles: out[t] = exclusive prefix of 2 * len[t], and *total = the
+// sum of 2 * len (tiles of kSortTile; sums scanned in between like exclusive_scan_u32).
+__global__ void __launch_bounds__(kSortBlock) k_bases_sums(const uint32_t* len, uint64_t n, uint32_t* sums) {
+  __shared__ uint32_t tmp[kSortBlock / 64];
+  const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+  uint32_t s = 0;
+  for (int k = 0; k < kSortItems; ++k) {
+    const uint64_t i = base + (uint64_t)k * kSortBlock + threadIdx.x;
+    if (i < n) s += 2u * len[i];
+  }
+  uint32_t tot;
+  block_exclusive_scan<kSortBlock>(s, tmp, &tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(kSortBlock) k_bases_apply(const uint32_t* len, uint64_t n, const uint32_t* sums,
+                                                            uint32_t* out, unsigned long long* total) {
+  __shared__ uint32_t tmp[kSortBlock / 64];
+  const uint64_t base = (uint64_t)blockIdx.x * kSortTile + (uint64_t)threadIdx.x * kSortItems;
+  uint32_t v[kSortItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kSortItems; ++k) {
+    const uint64_t i = base + k;
+    v[k] = i < n ? 2u * len[i] : 0u;
+    s += v[k];
+  }
+  uint32_t ex = block_exclusive_scan<kSortBlock>(s, tmp, (uint32_t*)nullptr);
+  if (sums) ex += sums[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kSortItems; ++k) {
+    const uint64_t i = base + k;
+    if (i < n) out[i] = ex;
+    if (i == n - 1) *total = (unsigned long long)ex + v[k];
+    ex += v[k];
+  }
+}
+
 // scratch must hold scan_scratch_words(n) uint32 values.
 inline uint64_t scan_scratch_words(uint64_t n) {
   uint64_t tot = 0;
