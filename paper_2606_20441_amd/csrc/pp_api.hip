@@ -289,7 +289,7 @@ struct Engine final : EngineBase {
   TBuf<double, true> ta, tb;     // tie lists for the cap
   TBuf<CT, ORD> gb;              // boundary candidates of a cap
   Buf u32a, u32b, u32c, scan_scr, tiles, gates_d, sup_d, tab_d, drun_d, dm_d, dval_d, cnt_d, ovf_d, partial_d, f64_d, span_d, htab_d, lstat_d;
-  Buf hp_a, hp_b, tr_s0, tr_l0, tr_s1, tr_l1, g1_d, g1_ovf, g1_base, g1_base2;   // per-gate tile path
+  Buf hp_b, tr_s0, tr_l0, tr_s1, tr_l1, g1_d, g1_ovf, g1_base, g1_base2;   // per-gate tile path
   Buf rl0, rl1, rl2, ovl1, ovl2, tf_flag, tf_pos, tf_list, g1_io, g1_tab, g1_tabmeta, win_hist_d;
   double growth[4] = {4.0, 4.0, 2.0, 3.0};
   double tile_target[4] = {80.0, 80.0, 80.0, 64.0};   // level-0 (one-wavefront) tile targets
@@ -299,7 +299,7 @@ struct Engine final : EngineBase {
     for (auto* t : {&cur, &alt, &sa, &sb, &tmp, &gb}) { t->mem.ctx = ctx; t->W = W; }
     for (auto* t : {&ta, &tb}) { t->mem.ctx = ctx; t->W = W; }
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &drun_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
-                   &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &rl0, &rl1, &rl2, &ovl1, &ovl2,
+                   &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &rl0, &rl1, &rl2, &ovl1, &ovl2,
                    &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d})
       b->ctx = ctx;
     cnt_d.ensure(256);
@@ -312,7 +312,7 @@ struct Engine final : EngineBase {
     for (auto* t : {&cur, &alt, &sa, &sb, &tmp, &gb}) t->mem.release();
     for (auto* t : {&ta, &tb}) t->mem.release();
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &drun_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
-                   &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hp_a, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &rl0, &rl1, &rl2, &ovl1, &ovl2,
+                   &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &rl0, &rl1, &rl2, &ovl1, &ovl2,
                    &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d})
       b->release();
   }
@@ -524,6 +524,7 @@ struct Engine final : EngineBase {
         }
       }
       h.g.hash = lin_hash<W>(h.g.m, h.g.m + W, hash_tables().data());
+      h.g.khash = key_hash<W>(h.g.m, h.g.m + W);
       out.push_back(h);
     }
     return out;
@@ -1151,7 +1152,6 @@ struct Engine final : EngineBase {
     hash_sort(cur, tmp, m, gm, kk);
     const uint64_t ntiles = std::max<uint64_t>(1, cdiv(m, T));
     tiles.ensure((ntiles + 2) * 4);
-    const Terms<CT> t = cur.view();
     const uint64_t kmask = kk >= 64 ? ~0ULL : ((1ULL << kk) - 1);
     uint32_t* ts = tiles.as<uint32_t>();
     make_tiles(cur, m, gm, kmask, T, ntiles, ts);
@@ -1159,13 +1159,6 @@ struct Engine final : EngineBase {
     tr_l0.ensure(ntiles * 4 + 64);
     uint32_t *s0 = tr_s0.as<uint32_t>(), *l0 = tr_l0.as<uint32_t>();
     hipLaunchKernelGGL(k_tile_ranges, grid1(ntiles), dim3(256), 0, st, (const uint32_t*)ts, (uint32_t)ntiles, s0, l0);
-    ctx->check_launch();
-    hp_a.ensure(cur.cap * 4 + 64);
-    uint32_t* hp = hp_a.as<uint32_t>();
-    const uint32_t* ht = htab_d.as<uint32_t>();
-    ctx->run("hash_plane", 0, (double)m, [&] {
-      hipLaunchKernelGGL((k_hash_plane<W, CT>), grid1(m), dim3(256), 0, st, t, m, ht, hp);
-    });
     ctx->check_launch();
     g1_ntiles = ntiles;
     routed = false;
@@ -1517,8 +1510,7 @@ struct Engine final : EngineBase {
       Gate1Args<CT> a{};
       a.in = cur.view();
       a.out = alt.view();
-      a.hin = hp_a.as<uint32_t>();
-      a.hout = hp_b.as<uint32_t>();
+      a.hscr = hp_b.as<uint32_t>();
       a.t_start = tr_s0.as<uint32_t>();
       a.t_len = tr_l0.as<uint32_t>();
       a.o_base = g1_base.as<uint32_t>();
@@ -1619,7 +1611,6 @@ struct Engine final : EngineBase {
         dsl.assign(hc.drop, hc.drop + kDropSlots);
       }
       cur.swap(alt);
-      std::swap(hp_a, hp_b);
       std::swap(tr_s0, tr_s1);
       std::swap(tr_l0, tr_l1);
       std::swap(g1_base, g1_base2);

@@ -77,6 +77,7 @@ struct GateDev {
   int type;           // GATE_X1: R = X on qubit (w0,b0); GATE_ZZ: R = Z Z on (w0,b0), (w1,b1)
   int w0, b0, w1, b1; // for GATE_ZZ (w0,b0) is the lower qubit (the pivot)
   uint32_t hash;      // linear key hash of the flip mask (x = m[0..W), z = m[W..2W))
+  uint32_t khash;     // key_hash of the flip mask
 };
 
 // GF(2)-linear 32-bit hash of a Pauli key: XOR of one table word per key byte.  Linear, so
@@ -92,6 +93,26 @@ __device__ __host__ __forceinline__ uint32_t lin_hash(const uint64_t* kx, const 
     }
   return h;
 }
+
+// A GF(2)-linear 32-bit hash computed in registers (rotations, xor-shifts and a fold are
+// all linear): key_hash(P xor R) = key_hash(P) xor key_hash(R).  Used where the table hash
+// would need a per-term plane in memory; a match is always confirmed on the full key.
+__device__ __host__ __forceinline__ uint64_t kh_rotl(uint64_t v, int r) { return (v << r) | (v >> (64 - r)); }
+template <int W>
+__device__ __host__ __forceinline__ uint32_t key_hash(const uint64_t* kx, const uint64_t* kz) {
+  uint64_t y = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    uint64_t v = kx[w] ^ kh_rotl(kz[w], 32);
+    v ^= v << 13;
+    v ^= v >> 7;
+    v ^= v << 17;
+    y ^= w == 0 ? v : kh_rotl(v, 11 * w);
+  }
+  y ^= y >> 29;
+  return (uint32_t)(y ^ (y >> 32));
+}
+
 __device__ __host__ __forceinline__ uint32_t ord_hash(uint32_t o) {
   return o ? (uint32_t)(mix64(0x5851f42d4c957f2dULL + o) >> 32) : 0u;
 }

@@ -57,8 +57,7 @@ template <class CT>
 struct Gate1Args {
   Terms<CT> in;
   Terms<CT> out;
-  const uint32_t* hin;          // per-term hash of `in`
-  uint32_t* hout;               // per-term hash of `out`
+  uint32_t* hscr;               // per-slot hash scratch of `out` (the oversize kernel only)
   const uint32_t* t_start;      // tile ranges in `in`
   const uint32_t* t_len;
   const uint32_t* t_list;       // optional: list entry -> tile
@@ -154,7 +153,6 @@ __device__ void pass_through(const Gate1Args<CT>& a, uint32_t tile, uint32_t t0,
     }
     a.out.c[dst] = a.in.c[src];
     if (ORD) a.out.o[dst] = a.in.o[src];
-    a.hout[dst] = a.hin[src];
     ++dst;
   }
 }
@@ -175,7 +173,6 @@ template <int W, class CT, int R>
 struct G1Regs {
   uint64_t x[R][W], z[R][W];
   CT c[R];
-  uint32_t h[R];
   uint32_t o[R];
 };
 
@@ -195,7 +192,6 @@ __device__ __forceinline__ void g1_fetch(const Gate1Args<CT>& a, G1Regs<W, CT, C
       g.z[r][w] = in ? a.in.z[w * a.in.stride + src] : 0ULL;
     }
     g.c[r] = in ? a.in.c[src] : (CT)0;
-    g.h[r] = in ? a.hin[src] : 0u;
     g.o[r] = (ORD && in) ? (uint32_t)a.in.o[src] : 0u;
   }
 }
@@ -234,7 +230,7 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
 #pragma unroll
   for (int w = 0; w < 2 * W; ++w) m[w] = a.g.m[w];
   const double cs = a.g.cs, snd = a.g.sn_dir;
-  const uint32_t gh = a.g.hash;
+  const uint32_t gh = a.g.khash;
   const int pw = a.g.pivot_word, pb = a.g.pivot_bit;
   const double thr = a.eps;
 
@@ -295,9 +291,11 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
       __syncthreads();
 
       // ---- stage, cut, insert ----------------------------------------------------------------
+      uint32_t hh[R];   // key hashes of this thread's terms
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const uint32_t i = (uint32_t)r * BLOCK + tid;
+        hh[r] = key_hash<W>(cur.x[r], cur.z[r]);
         if (i >= n0) continue;
 #pragma unroll
         for (int w = 0; w < W; ++w) { sx[w][i] = cur.x[r][w]; sz[w][i] = cur.z[r][w]; }
@@ -307,10 +305,10 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
           lost += fabs((double)cv);
           cur.c[r] = (CT)0;
         }
-        sh[i] = cur.h[r];
+        sh[i] = hh[r];
         sc[i] = cur.c[r];
         if (cur.c[r] != (CT)0) {
-          uint32_t slot = (cur.h[r] ^ (cur.o[r] * 0x9e3779b9u)) & (H - 1);
+          uint32_t slot = (hh[r] ^ (cur.o[r] * 0x9e3779b9u)) & (H - 1);
           while (atomicCAS(&hidx[slot], EMPTY, i) != EMPTY) slot = (slot + 1) & (H - 1);
         }
       }
@@ -338,12 +336,12 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
         if (cs == 0.0) {             // sin = +-1: P -> +-iRP in place (a permutation of strings)
 #pragma unroll
           for (int w = 0; w < W; ++w) { sx[w][i] = qx[w]; sz[w][i] = qz[w]; }
-          sh[i] = cur.h[r] ^ gh;
+          sh[i] = hh[r] ^ gh;
           sc[i] = (CT)((neg_i ? -ci : ci) * snd);
           continue;
         }
         // non-Clifford: find the partner string (same order tag) in the tile
-        const uint32_t hq = cur.h[r] ^ gh;
+        const uint32_t hq = hh[r] ^ gh;
         uint32_t slot = (hq ^ (cur.o[r] * 0x9e3779b9u)) & (H - 1);
         uint32_t j = EMPTY;
         for (;;) {
@@ -467,7 +465,6 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
           }
           a.out.c[dst] = sc[i];
           if (ORD) a.out.o[dst] = so[i];
-          a.hout[dst] = sh[i];
         }
       }
     }
@@ -514,7 +511,7 @@ __global__ void __launch_bounds__(1024) k_gate1_big(Gate1Args<CT> a, uint32_t* t
 #pragma unroll
   for (int w = 0; w < 2 * W; ++w) m[w] = a.g.m[w];
   const double cs = a.g.cs, snd = a.g.sn_dir, thr = a.eps;
-  const uint32_t gh = a.g.hash;
+  const uint32_t gh = a.g.khash;
   const int pw = a.g.pivot_word, pb = a.g.pivot_bit;
   Terms<CT> o = a.out;
   if (tid == 0) { s_new = 0; s_done = 0; }
@@ -535,8 +532,8 @@ __global__ void __launch_bounds__(1024) k_gate1_big(Gate1Args<CT> a, uint32_t* t
     }
     const uint32_t oi = ORD ? a.in.o[t0 + i] : 0u;
     if (ORD) o.o[base + i] = (uint8_t)oi;
-    const uint32_t h = a.hin[t0 + i];
-    a.hout[base + i] = h;
+    const uint32_t h = key_hash<W>(kx, kz);
+    a.hscr[base + i] = h;
     const CT cv = a.in.c[t0 + i];
     CT keep = cv;
     if (cv != (CT)0 && !cut_keeps<W, CT>(cv, kx, kz, oi, a.cut)) {
@@ -565,7 +562,7 @@ __global__ void __launch_bounds__(1024) k_gate1_big(Gate1Args<CT> a, uint32_t* t
       continue;
     }
     const uint32_t oi = ORD ? o.o[base + i] : 0u;
-    const uint32_t h = a.hout[base + i];
+    const uint32_t h = a.hscr[base + i];
     const bool neg_i = irp_negative<W>(kx, kz, m, a.g.rr_phase);
     uint64_t qx[W], qz[W];
 #pragma unroll
@@ -573,7 +570,7 @@ __global__ void __launch_bounds__(1024) k_gate1_big(Gate1Args<CT> a, uint32_t* t
     if (cs == 0.0) {
 #pragma unroll
       for (int w = 0; w < W; ++w) { o.x[w * o.stride + base + i] = qx[w]; o.z[w * o.stride + base + i] = qz[w]; }
-      a.hout[base + i] = h ^ gh;
+      a.hscr[base + i] = h ^ gh;
       o.c[base + i] = (CT)((neg_i ? -ci : ci) * snd);
       continue;
     }
@@ -583,7 +580,7 @@ __global__ void __launch_bounds__(1024) k_gate1_big(Gate1Args<CT> a, uint32_t* t
     for (;;) {
       const uint32_t k = tab[slot];
       if (k == EMPTY) break;
-      if (a.hout[base + k] == hq && (!ORD || o.o[base + k] == oi)) {
+      if (a.hscr[base + k] == hq && (!ORD || o.o[base + k] == oi)) {
         uint64_t px[W], pz[W];
         okey(base + k, px, pz);
         bool eq = true;
@@ -617,7 +614,7 @@ __global__ void __launch_bounds__(1024) k_gate1_big(Gate1Args<CT> a, uint32_t* t
         for (int w = 0; w < W; ++w) { o.x[w * o.stride + k] = qx[w]; o.z[w * o.stride + k] = qz[w]; }
         if (ORD) o.o[k] = (uint8_t)oi;
         o.c[k] = (CT)nq;
-        a.hout[k] = hq;
+        a.hscr[k] = hq;
       }
     }
   }
@@ -634,7 +631,7 @@ __global__ void __launch_bounds__(1024) k_gate1_big(Gate1Args<CT> a, uint32_t* t
     if (live) {
       okey(base + i, kx, kz);
       cv = o.c[base + i];
-      h = a.hout[base + i];
+      h = a.hscr[base + i];
       if (ORD) oi = o.o[base + i];
     }
     const uint64_t bal = __ballot(live);
@@ -652,7 +649,7 @@ __global__ void __launch_bounds__(1024) k_gate1_big(Gate1Args<CT> a, uint32_t* t
       for (int w = 0; w < W; ++w) { o.x[w * o.stride + d] = kx[w]; o.z[w * o.stride + d] = kz[w]; }
       o.c[d] = cv;
       if (ORD) o.o[d] = (uint8_t)oi;
-      a.hout[d] = h;
+      a.hscr[d] = h;
     }
     written += total;
     __syncthreads();
@@ -671,17 +668,6 @@ __global__ void __launch_bounds__(1024) k_gate1_big(Gate1Args<CT> a, uint32_t* t
     atomicAdd(&a.io[kDropSlots + blockIdx.x % kDropSlots], (unsigned long long)written);
   }
   (void)s_done;
-}
-
-// Per-term linear hash of the string (order tag not included).
-template <int W, class CT>
-__global__ void k_hash_plane(Terms<CT> t, uint64_t n, const uint32_t* htab, uint32_t* h) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  uint64_t kx[W], kz[W];
-#pragma unroll
-  for (int w = 0; w < W; ++w) { kx[w] = t.x[w * t.stride + i]; kz[w] = t.z[w * t.stride + i]; }
-  h[i] = lin_hash<W>(kx, kz, htab);
 }
 
 // Sort tiles by size: empty tiles get their (empty) output record here, tiles of at most
