@@ -126,7 +126,27 @@ def copy_probe(nbytes: int, reps: int = 5):
     log(f"copy probe: {reps} copies of {n * 4} bytes")
 
 
-def roofline(kstats, term_bytes, precision="f64"):
+def copy_ceiling(nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """Measured device copy bandwidth (bytes read + written per second, GB/s): the practical
+    HBM ceiling of this machine, reported beside the vendor peak."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def roofline(kstats, term_bytes, precision="f64", copy_gbs=None):
     timed = [k for k in kstats if k["total_ms"] > 0]
     total = sum(k["total_ms"] for k in timed)
     dom = max(timed, key=lambda k: k["total_ms"])
@@ -142,6 +162,13 @@ def roofline(kstats, term_bytes, precision="f64"):
            "algo_bytes_per_launch": round(per_launch_bytes),
            "share_of_device_time": round(pick["total_ms"] / total, 3),
            "avg_launch_ms": round(avg_ms, 4), "launches": pick["launches"]}
+    if traffic is not None and avg_ms > 0:
+        tg = traffic / (avg_ms * 1e-3) / 1e9   # counted DRAM bytes per second
+        out["traffic_gbs"] = round(tg, 1)
+        out["traffic_frac"] = round(tg / HBM_PEAK_GBS, 4)
+    if copy_gbs:
+        out["copy_ceiling_gbs"] = round(copy_gbs, 1)
+        out["frac_of_copy"] = round(achieved / copy_gbs, 4)
     if fused is not None and fused is not pick:
         f_ms = fused["total_ms"] / fused["launches"]
         f_ach = fused["algo_bytes"] / fused["launches"] / (f_ms * 1e-3) / 1e9
@@ -240,13 +267,15 @@ def main():
     ctx = pp.Context(0)
     Wd = wl.circuit.W
     results = {}
+    copy_gbs = copy_ceiling()
+    log(f"device copy ceiling: {copy_gbs:.0f} GB/s (read + write)")
     precs = ["f64", "f32k"] if args.precision == "both" else [args.precision]
     for prec in precs:
         log(f"== {args.workload} {prec}: warmup {args.warmup}, steps {args.steps}")
         r = run_gpu(ctx, wl, prec, args.steps, args.warmup, layers_verbose=args.layers, progress=args.progress)
         tb = 16 * Wd + (8 if prec == "f64" else 4) + (1 if wl.mode == "error_order" else 0)
         r["term_bytes"] = tb
-        r["roofline"] = roofline(r["kernels"], tb, prec)
+        r["roofline"] = roofline(r["kernels"], tb, prec, copy_gbs)
         results[prec] = r
         log(f"   {r['updates'] / r['seconds']:.4g} term-updates/s, {1e3 * r['seconds'] / args.steps:.1f} ms/step, "
             f"<O> = {r['expectation']!r}, {r['terms']} terms")
