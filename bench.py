@@ -177,6 +177,28 @@ def roofline(kstats, term_bytes, precision="f64", copy_gbs=None):
     return out
 
 
+def noisy_check(ctx, wl, precision):
+    """Propagate O~ back through the noisy circuit (the check that the mitigated observable
+    recovers the ideal value): Tr[O~ rho_noisy], its time and term-updates/s, once."""
+    import torch
+    from paper_2606_20441_amd import pp
+    obs = pp.run_workload(ctx, wl, precision=precision)
+    torch.cuda.synchronize()
+    upd = [0]
+
+    def on_layer(m, o):
+        upd[0] += o.last_layer_stats()["n_in"]
+
+    t0 = time.perf_counter()
+    v = pp.noisy_evaluation(wl.circuit, obs, on_layer=on_layer)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n = len(obs)
+    obs.destroy()
+    log(f"   noisy evaluation: Tr[O~ rho_noisy] = {v!r} in {1e3 * dt:.1f} ms ({upd[0] / dt:.4g} term-updates/s)")
+    return {"value": v, "ms": round(1e3 * dt, 3), "term_updates_per_s": round(upd[0] / dt, 1), "terms_out": n}
+
+
 def cpu_baseline(wl, budget_s=15.0):
     """The FP64 CPU reference (single thread) on a bounded prefix of the same propagation:
     layer calls in the same order until the time budget is spent."""
@@ -238,6 +260,8 @@ def main():
     ap.add_argument("--progress", action="store_true", help="print per-layer counts of the timed steps too")
     ap.add_argument("--max-terms", type=int, default=None, help="override the workload's cap")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-noisy-check", action="store_true",
+                    help="skip propagating O~ back through the noisy circuit")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--serve-requests", type=int, default=30,
                     help="measured requests of the serving stream per arrival rate (0: skip it)")
@@ -285,6 +309,7 @@ def main():
             log(f"   {k['name']:24s} {k['launches']:6d} launches {k['total_ms']:9.2f} ms  avg {avg:8.4f} ms  "
                 f"algo {bw:8.1f} GB/s")
     main_prec = precs[0]
+    noisy = noisy_check(ctx, wl, main_prec) if not args.no_noisy_check else None
     r = results[main_prec]
     value = r["updates"] / r["seconds"]
     line = {
@@ -307,6 +332,8 @@ def main():
                    "term_updates_per_step": r["updates"] // args.steps, "parallelism": "1 GPU"},
         "roofline": r["roofline"],
     }
+    if noisy is not None:
+        line["noisy_evaluation"] = noisy
     if "f32k" in results and main_prec != "f32k":
         f = results["f32k"]
         line["fp32k"] = {"value": round(f["updates"] / f["seconds"], 1),

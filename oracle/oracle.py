@@ -188,5 +188,16 @@ def noise_canceling(circuit, observable, eps: float = 0.0, max_terms: int = 0,
     return OracleSum(circuit.n_qubits, None, None, None, _handle=h)
 
 
+def noisy_evaluation(circuit, obs: OracleSum, eps: float = 0.0, max_terms: int = 0) -> float:
+    """Tr[O~ rho_noisy] by noisy Pauli propagation (Section II's check that the mitigated
+    observable recovers the ideal value): C_noisy = N_M G_M .. N_1 G_1 (noise after every
+    layer's gates), so its adjoint applies, from m = M down to 1, the channel N_m itself
+    (a Pauli channel is self-adjoint) and then G_m^dag.  Changes `obs` in place."""
+    for layer in reversed(circuit.layers):
+        obs.apply_layer(layer, +1, with_gates=True, with_noise=True, noise_sign=-1, noise_after_gates=False,
+                        eps=eps, max_terms=max_terms)
+    return obs.expectation()
+
+
 def run_workload(wl) -> OracleSum:
     return noise_canceling(wl.circuit, wl.observable, wl.eps, wl.max_terms, wl.mode, wl.max_order)

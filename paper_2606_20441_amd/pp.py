@@ -342,6 +342,23 @@ def noise_canceling(ctx: Context, circuit, observable, eps: float = 0.0, max_ter
     return obs
 
 
+def noisy_evaluation(circuit, obs_tilde: "Observable", on_layer=None) -> float:
+    """Tr[O~ rho_noisy] by noisy Pauli propagation, with rho_noisy = C_noisy(|0><0|).
+
+    This is the paper's check that propagating the mitigated observable back through the
+    noisy circuit recovers the ideal value (Section II).  C_noisy = N_M G_M .. N_1 G_1, so
+    its adjoint on O~ walks back from m = M to 1 applying the channel N_m itself (noise
+    sign -1; a Pauli channel is its own adjoint) and then G_m^dag (U^dag P U).  The
+    observable keeps its own threshold and cap, and is changed in place.
+    """
+    layers = circuit.layers
+    for m in range(len(layers) - 1, -1, -1):
+        obs_tilde.apply_layer(layers[m], PP_HEISENBERG, noise_sign=-1, noise_after_gates=False)
+        if on_layer:
+            on_layer(m, obs_tilde)
+    return obs_tilde.expectation()
+
+
 def run_workload(ctx: Context, wl, precision: Optional[str] = None, on_layer=None) -> Observable:
     return noise_canceling(ctx, wl.circuit, wl.observable, wl.eps, wl.max_terms, wl.mode, wl.max_order,
                            precision or wl.precision, on_layer=on_layer)

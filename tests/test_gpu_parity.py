@@ -331,6 +331,29 @@ def test_workload_parity(pp, ctx, orc, wname, kw):
 
 
 @pytest.mark.parametrize("wname,kw", [
+    ("tfim3x3", dict(eps=0.0)),
+    ("tfim3x3", {}),
+    ("tfim7x8_pna", dict(steps=2)),
+    ("tfim7x8_pna", dict(steps=3, max_terms=20000)),
+])
+def test_noisy_evaluation(pp, ctx, orc, wname, kw):
+    """O~ propagated back through the noisy circuit on the GPU: Tr[O~ rho_noisy] against the
+    reference's same walk, and against the ideal value (statevector) at zero threshold."""
+    wl = W.named_workload(wname, **kw)
+    log(f"noisy evaluation {wname} {kw}")
+    g, o = run_both(pp, ctx, orc, wl)
+    vg = pp.noisy_evaluation(wl.circuit, g)
+    vo = orc.noisy_evaluation(wl.circuit, o, eps=wl.eps, max_terms=wl.max_terms)
+    log(f"  Tr[O~ rho_noisy]: {vg!r} vs {vo!r}")
+    assert abs(vg - vo) < 1e-10
+    if wl.eps == 0.0 and wl.circuit.n_qubits <= 10:
+        from oracle import brute as B
+        psi = B.statevector(wl.circuit)
+        om = B.pauli_sum_matrix(wl.circuit.n_qubits, wl.observable.x, wl.observable.z, wl.observable.c)
+        assert abs(vg - np.vdot(psi, om @ psi).real) < 1e-10
+
+
+@pytest.mark.parametrize("wname,kw", [
     ("tfim3x3", {}),
     ("tfim7x8_pna", dict(steps=2)),
     ("tfim8x16", dict(steps=1, eps=1e-4)),

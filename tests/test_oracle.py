@@ -144,6 +144,27 @@ def test_trace_identity_and_superoperator(oracle_lib, rows, cols, steps):
         _assert_same_sum(_oracle_dict(res), want, 1e-12)
 
 
+@pytest.mark.parametrize("rows,cols,steps", [(2, 3, 3), (3, 3, 2)])
+def test_noisy_evaluation_recovers_ideal(oracle_lib, rows, cols, steps):
+    """Propagating O~ back through the noisy circuit (channel, then adjoint gates, layer by
+    layer from the last) gives Tr[O~ rho_noisy] = the ideal value at zero threshold; the
+    same walk on the unmitigated O gives the noisy value (density-matrix brute force)."""
+    B = _brute()
+    wl = W.named_workload("tfim3x3", rows=rows, cols=cols, steps=steps)
+    n = wl.circuit.n_qubits
+    psi = B.statevector(wl.circuit)
+    rho = B.density_matrix(wl.circuit)
+    om = B.pauli_sum_matrix(n, wl.observable.x, wl.observable.z, wl.observable.c)
+    ideal = np.vdot(psi, om @ psi).real
+    noisy = B.expectation(om, rho).real
+    res = oracle_lib.noise_canceling(wl.circuit, wl.observable, eps=0.0)
+    assert abs(oracle_lib.noisy_evaluation(wl.circuit, res) - ideal) < 1e-12
+    raw = oracle_lib.OracleSum.from_sum(wl.observable)
+    v = oracle_lib.noisy_evaluation(wl.circuit, raw)
+    assert abs(v - noisy) < 1e-12
+    assert abs(v - ideal) > 1e-5
+
+
 def test_trace_identity_noise_after_entangling_only(oracle_lib):
     B = _brute()
     wl = W.named_workload("tfim3x3", rows=2, cols=3, steps=3, noise="entangling")
