@@ -150,7 +150,7 @@ def roofline(kstats, term_bytes, precision="f64", copy_gbs=None):
     timed = [k for k in kstats if k["total_ms"] > 0]
     total = sum(k["total_ms"] for k in timed)
     dom = max(timed, key=lambda k: k["total_ms"])
-    fused = next((k for k in timed if k["name"] == "layer_fused"), None)
+    fused = next((k for k in timed if k["name"] == "layer_fused_wave"), None)
     pick = dom
     avg_ms = pick["total_ms"] / pick["launches"]
     per_launch_bytes = pick["algo_bytes"] / pick["launches"]
@@ -172,7 +172,7 @@ def roofline(kstats, term_bytes, precision="f64", copy_gbs=None):
     if fused is not None and fused is not pick:
         f_ms = fused["total_ms"] / fused["launches"]
         f_ach = fused["algo_bytes"] / fused["launches"] / (f_ms * 1e-3) / 1e9
-        out["layer_fused"] = {"achieved": round(f_ach, 1), "frac": round(f_ach / HBM_PEAK_GBS, 4),
+        out["layer_fused_wave"] = {"achieved": round(f_ach, 1), "frac": round(f_ach / HBM_PEAK_GBS, 4),
                               "avg_launch_ms": round(f_ms, 4), "share_of_device_time": round(fused["total_ms"] / total, 3)}
     return out
 
