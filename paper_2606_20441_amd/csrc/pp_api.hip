@@ -1552,7 +1552,7 @@ struct Engine final : EngineBase {
       hc.nlist[0] = nl0;
       hc.nlist[1] = nl1;
       hc.nlist[2] = nl2;
-      if (hc.ovf[0] * 16 > nl0 + nl1) routed = false;   // many tiles outgrew their shape
+      if (hc.ovf[0] * 64 > nl0 + nl1) routed = false;   // tiles outgrew their shape: sort again
       uint64_t giant_terms = 0;
       uint64_t next_extent = hc.bases_total;
       std::vector<double> dsl(hc.drop, hc.drop + kDropSlots);
