@@ -289,7 +289,7 @@ struct Engine final : EngineBase {
   TBuf<double, true> ta, tb;     // tie lists for the cap
   TBuf<CT, ORD> gb;              // boundary candidates of a cap
   Buf u32a, u32b, u32c, scan_scr, tiles, gates_d, sup_d, tab_d, drun_d, dm_d, dval_d, cnt_d, ovf_d, partial_d, f64_d, span_d, htab_d, lstat_d;
-  Buf hp_b, tr_s0, tr_l0, tr_s1, tr_l1, g1_d, g1_ovf, g1_base, g1_base2;   // per-gate tile path
+  Buf hscr_d, tr_s0, tr_l0, tr_s1, tr_l1, g1_d, g1_ovf, g1_base, g1_base2;   // per-gate tile path
   Buf rl0, rl1, rl2, ovl1, ovl2, tf_flag, tf_pos, tf_list, g1_io, g1_tab, g1_tabmeta, win_hist_d;
   double growth[4] = {4.0, 4.0, 2.0, 3.0};
   double tile_target[4] = {80.0, 80.0, 80.0, 64.0};   // level-0 (one-wavefront) tile targets
@@ -299,7 +299,7 @@ struct Engine final : EngineBase {
     for (auto* t : {&cur, &alt, &sa, &sb, &tmp, &gb}) { t->mem.ctx = ctx; t->W = W; }
     for (auto* t : {&ta, &tb}) { t->mem.ctx = ctx; t->W = W; }
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &drun_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
-                   &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &rl0, &rl1, &rl2, &ovl1, &ovl2,
+                   &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hscr_d, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &rl0, &rl1, &rl2, &ovl1, &ovl2,
                    &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d})
       b->ctx = ctx;
     cnt_d.ensure(256);
@@ -312,7 +312,7 @@ struct Engine final : EngineBase {
     for (auto* t : {&cur, &alt, &sa, &sb, &tmp, &gb}) t->mem.release();
     for (auto* t : {&ta, &tb}) t->mem.release();
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &drun_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
-                   &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hp_b, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &rl0, &rl1, &rl2, &ovl1, &ovl2,
+                   &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hscr_d, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &rl0, &rl1, &rl2, &ovl1, &ovl2,
                    &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d})
       b->release();
   }
@@ -1124,9 +1124,7 @@ struct Engine final : EngineBase {
 
   struct G1Counters {
     uint32_t nlist[3];   // routed tiles: small, middle, large
-    uint32_t ovf[3];     // tiles reported by the one-wavefront, 256-thread and 1024-thread shapes
-    uint32_t big_count;
-    uint32_t pad;
+    uint32_t ovf[3];     // tiles reported by the small shapes, the 256-thread and the 1024-thread shape
     unsigned long long bases_total;   // the next gate's output extent
     double drop[kDropSlots];          // sum of |c| removed, per slot
   };
@@ -1136,13 +1134,12 @@ struct Engine final : EngineBase {
   // unit; a tile that outgrows it is redone in the 256-thread shape
   static constexpr int kG1WaveCap = 256;
   static constexpr uint64_t kG1Target = 96;     // terms per one-wavefront tile when tiling
-  static constexpr uint32_t kG1Big = 160;       // a tile above this may outgrow the one-wavefront shape at the next gate
   uint64_t g1_ntiles = 0;
   bool routed = false;      // tile lists by size are current for this tiling
   uint32_t route_n[3] = {0, 0, 0};
 
-  // Group the terms by the run's invariant bits, cut them into tiles of whole groups and
-  // compute the per-term hash plane (cur must be dense).
+  // Group the terms by the run's invariant bits and cut them into tiles of whole groups
+  // (cur must be dense).
   void g1_tile(const GroupMask& gm) {
     const uint64_t m = N;
     const uint64_t T = kG1Target;
@@ -1482,7 +1479,6 @@ struct Engine final : EngineBase {
       }
       const uint64_t ntiles = g1_ntiles;
       alt.ensure(out_extent + 64);
-      hp_b.ensure(alt.cap * 4 + 64);
       tr_s1.ensure(ntiles * 4 + 64);
       tr_l1.ensure(ntiles * 4 + 64);
       for (Buf* b : {&rl0, &rl1, &rl2, &g1_ovf, &ovl1, &ovl2}) b->ensure(ntiles * 4 + 64);
@@ -1510,7 +1506,6 @@ struct Engine final : EngineBase {
       Gate1Args<CT> a{};
       a.in = cur.view();
       a.out = alt.view();
-      a.hscr = hp_b.as<uint32_t>();
       a.t_start = tr_s0.as<uint32_t>();
       a.t_len = tr_l0.as<uint32_t>();
       a.o_base = g1_base.as<uint32_t>();
@@ -1521,8 +1516,6 @@ struct Engine final : EngineBase {
       a.eps = G.clifford ? 0.0 : eps;
       a.cut = cut;
       a.dropped = dropd;
-      a.big_count = &cd->big_count;
-      a.big_hint = kG1Big;
       auto with_list = [&](const Buf& list, Buf& ovl, int k, int zero) {
         Gate1Args<CT> b = a;
         b.t_list = list.as<uint32_t>();
@@ -1583,7 +1576,9 @@ struct Engine final : EngineBase {
         uint32_t* hsd = (uint32_t*)(offd + n2);
         HIPCHK(hipMemcpyAsync(offd, off.data(), 8 * (size_t)n2, hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(hsd, hs.data(), 4 * (size_t)n2, hipMemcpyHostToDevice, st));
+        hscr_d.ensure(alt.cap * 4 + 64);   // hash scratch, one slot per output slot
         Gate1Args<CT> b = with_list(ovl2, ovl2, 2, 0);
+        b.hscr = hscr_d.as<uint32_t>();
         g1_io.ensure(2 * kDropSlots * 8 + 64);
         b.io = g1_io.as<unsigned long long>();
         if (ctx->timing) HIPCHK(hipMemsetAsync(b.io, 0, 2 * kDropSlots * 8, st));

@@ -73,8 +73,6 @@ struct Gate1Args {
   uint32_t* ovf_tiles;          // tiles that did not fit in LDS
   uint32_t* ovf_count;
   double* dropped;              // [kDropSlots]: sum of |c| removed (cut and threshold)
-  uint32_t* big_count;          // tiles whose output exceeds big_hint terms
-  uint32_t big_hint;
   unsigned long long* io;       // [2][kDropSlots]: terms loaded / written by completed tiles
 };
 
@@ -137,7 +135,6 @@ __device__ void pass_through(const Gate1Args<CT>& a, uint32_t tile, uint32_t t0,
     double v = 0.0;
     for (int w = 0; w < NW; ++w) v += p_drop[w];
     if (v != 0.0) atomicAdd(&a.dropped[blockIdx.x % kDropSlots], v);
-    if (total > a.big_hint) atomicAdd(a.big_count, 1u);
     atomicAdd(&a.io[blockIdx.x % kDropSlots], (unsigned long long)n0);
     atomicAdd(&a.io[kDropSlots + blockIdx.x % kDropSlots], (unsigned long long)total);
   }
@@ -247,7 +244,6 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
   // the workgroup's statistics (thread 0), added to the global counters once at the end
   double acc_drop = 0.0;
   unsigned long long acc_in = 0, acc_out = 0;
-  uint32_t acc_big = 0;
 
   // One tile with its terms in `cur`.  Once the gate has read them, `cur` receives the next
   // tile's terms, which arrive while this tile is compacted and written.
@@ -447,7 +443,6 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
         if (tid == 0) {
           a.o_start[tile] = (uint32_t)base;
           a.o_len[tile] = total;
-          acc_big += total > a.big_hint ? 1u : 0u;
           for (int w = 0; w < NW; ++w) acc_drop += s_drop[w];
           acc_in += n0;
           acc_out += total;
@@ -480,7 +475,6 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
   }
   if (tid == 0) {
     if (acc_drop != 0.0) atomicAdd(&a.dropped[blockIdx.x % kDropSlots], acc_drop);
-    if (acc_big) atomicAdd(a.big_count, acc_big);
     if (acc_in) atomicAdd(&a.io[blockIdx.x % kDropSlots], acc_in);
     if (acc_out) atomicAdd(&a.io[kDropSlots + blockIdx.x % kDropSlots], acc_out);
   }
