@@ -48,6 +48,7 @@ def _lib():
         lib.or_noise_canceling.restype = C.c_void_p
         lib.or_noise_canceling.argtypes = [C.c_void_p, C.c_int, _i32p, _u64p, _u64p, _f64p, _i32p,
                                            _u64p, _u64p, _f64p, C.c_double, C.c_int64, C.c_int, C.c_int]
+        lib.or_antinoise.argtypes = [C.c_void_p, C.c_void_p, C.c_double]
         lib.or_expectation.restype = C.c_double
         lib.or_expectation.argtypes = [C.c_void_p, _u64p]
         lib.or_norm2.restype = C.c_double
@@ -121,6 +122,10 @@ class OracleSum:
 
     def truncate(self, eps: float, max_terms: int = 0) -> None:
         _lib().or_truncate(self._h, float(eps), int(max_terms))
+
+    def antinoise(self, eprime: "OracleSum", q: float) -> None:
+        """O -> (1 - q) O + q E' O E' (Section II, Eq. applyantinoise); no truncation."""
+        _lib().or_antinoise(self._h, eprime._h, float(q))
 
     def apply_layer(self, layer, direction: int, with_gates: bool = True, with_noise: bool = True,
                     noise_sign: int = 1, noise_after_gates: bool = True, eps: float = 0.0,
@@ -197,6 +202,45 @@ def noisy_evaluation(circuit, obs: OracleSum, eps: float = 0.0, max_terms: int =
         obs.apply_layer(layer, +1, with_gates=True, with_noise=True, noise_sign=-1, noise_after_gates=False,
                         eps=eps, max_terms=max_terms)
     return obs.expectation()
+
+
+def antinoise_q(lam: float) -> float:
+    """Quasi-probability of one generator's inverse map (Section I: the channel applies
+    E with probability p = (1 - e^{-2 lambda})/2; the inverse negates lambda)."""
+    return (1.0 - np.exp(2.0 * lam)) / 2.0
+
+
+def propagated_error(circuit, t: int, k: int, eps_fwd: float = 0.0, max_terms_fwd: int = 0) -> OracleSum:
+    """E'_{t,k} = U E U^dag: generator k of layer t's noise carried through the gates of
+    layers t+1..M, forward in time (Section II; truncation per non-Clifford gate)."""
+    layer = circuit.layers[t]
+    W = (circuit.n_qubits + 63) // 64
+    ex = np.asarray(layer.ex, np.uint64).reshape(-1, W)[k:k + 1]
+    ez = np.asarray(layer.ez, np.uint64).reshape(-1, W)[k:k + 1]
+    e = OracleSum(circuit.n_qubits, ex, ez, np.ones(1))
+    for later in circuit.layers[t + 1:]:
+        e.apply_layer(later, -1, with_gates=True, with_noise=False, eps=eps_fwd, max_terms=max_terms_fwd)
+    return e
+
+
+def pna(circuit, observable, eps: float = 0.0, max_terms: int = 0, eps_fwd: float = 0.0,
+        max_terms_fwd: int = 0) -> OracleSum:
+    """Propagated noise absorption (Section II).  The hardware circuit is
+    C_noisy = N_M G_M .. N_1 G_1.  Writing each ideal layer as N_t^{-1} N_t G_t and carrying
+    the inverse maps to the end one at a time, from t = 1 up, through the later gates only,
+    gives C_ideal = N'_1^{-1} .. N'_M^{-1} C_noisy, where N'_t^{-1} applies, for every
+    generator E of N_t, the evolved error E' = U E U^dag with quasi-probability q.  The
+    adjoint of that product acts on O with N'_1^{-1} first, so
+    O~ = N'_M^{-1}( .. N'_1^{-1}(O)), each generator's map being
+    O -> (1 - q) O + q E' O E' (Eq. applyantinoise; a generator's maps within one layer
+    commute).  After every update |c| < eps is dropped and the cap applied."""
+    o = observable.clone() if isinstance(observable, OracleSum) else OracleSum.from_sum(observable)
+    for t, layer in enumerate(circuit.layers):
+        for k in range(layer.n_gen):
+            e = propagated_error(circuit, t, k, eps_fwd, max_terms_fwd)
+            o.antinoise(e, antinoise_q(float(np.asarray(layer.lam)[k])))
+            o.truncate(eps, max_terms)
+    return o
 
 
 def run_workload(wl) -> OracleSum:

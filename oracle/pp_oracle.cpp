@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -284,6 +285,61 @@ void truncate(or_sum* s, double eps, int64_t max_terms) {
   }
 }
 
+// Product of two Hermitian Paulis, A B = i^e C with C = (xA ^ xB, zA ^ zB) in Hermitian
+// form: A = i^{|xA&zA|} X^xA Z^zA, and moving Z^zA past X^xB gives (-1)^{|zA&xB|}, so
+// e = |xA&zA| + |xB&zB| + 2|zA&xB| - |xC&zC| (mod 4).  C keeps A's order tag.
+int pauli_mul(const Key& a, const Key& b, int W, Key* c) {
+  *c = a;
+  int e = 0;
+  for (int w = 0; w < W; ++w) {
+    c->x[w] = a.x[w] ^ b.x[w];
+    c->z[w] = a.z[w] ^ b.z[w];
+    e += popc(a.x[w] & a.z[w]) + popc(b.x[w] & b.z[w]) + 2 * popc(a.z[w] & b.x[w]) -
+         popc(c->x[w] & c->z[w]);
+  }
+  return ((e % 4) + 4) % 4;
+}
+
+// Propagated antinoise absorbed into the observable (Section II, Eq. applyantinoise): the
+// inverse map of one generator, carried to the end of the circuit, applies the evolved
+// error E' = sum_a e_a P_a with quasi-probability q, so O -> (1 - q) O + q E' O E'.
+// E' O E' is written out as the plain sum over ordered pairs (a, b) of e_a e_b P_a P P_b
+// for every term P of O, in complex arithmetic; the result is Hermitian, so every
+// imaginary part must cancel.  Exact zeros are dropped; nothing else is truncated here.
+void antinoise(or_sum* s, const or_sum* e, double q) {
+  if (e->W != s->W || e->n != s->n) fail("E' and O must have the same qubit count");
+  if (!std::isfinite(q)) fail("q must be finite");
+  const int W = s->W;
+  std::vector<std::pair<Key, double>> ev(e->m.begin(), e->m.end());
+  std::unordered_map<Key, std::complex<double>, KeyHash> acc;
+  acc.reserve(s->m.size() * (ev.size() * ev.size() + 1) + 16);
+  static const std::complex<double> ipow[4] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}};
+  double scale = 0.0;
+  for (const auto& kv : s->m) {
+    const Key& p = kv.first;
+    const double c = kv.second;
+    acc[p] += (1.0 - q) * c;
+    for (const auto& ea : ev) {
+      for (const auto& eb : ev) {
+        Key t, r;
+        const int k1 = pauli_mul(ea.first, p, W, &t);
+        const int k2 = pauli_mul(t, eb.first, W, &r);
+        r.o = p.o;
+        const double w = q * ea.second * eb.second * c;
+        acc[r] += w * ipow[(k1 + k2) & 3];
+        scale = std::max(scale, std::fabs(w));
+      }
+    }
+  }
+  Map out;
+  out.reserve(acc.size() * 2 + 16);
+  for (const auto& kv : acc) {
+    if (std::fabs(kv.second.imag()) > 1e-12 * std::max(1.0, scale)) fail("E' O E' is not Hermitian");
+    if (kv.second.real() != 0.0) out.emplace(kv.first, kv.second.real());
+  }
+  s->m.swap(out);
+}
+
 void apply_layer(or_sum* s, int n_gates, const uint64_t* gx, const uint64_t* gz, const double* theta,
                  int dir, int n_gen, const uint64_t* ex, const uint64_t* ez, const double* lambda,
                  int noise_sign, int noise_after_gates, double eps, int64_t max_terms, int mode,
@@ -370,6 +426,8 @@ void or_noise(or_sum* s, int n_gen, const uint64_t* ex, const uint64_t* ez, cons
 }
 
 void or_truncate(or_sum* s, double eps, int64_t max_terms) { truncate(s, eps, max_terms); }
+
+void or_antinoise(or_sum* s, const or_sum* eprime, double q) { antinoise(s, eprime, q); }
 
 void or_apply_layer(or_sum* s, int n_gates, const uint64_t* gx, const uint64_t* gz,
                     const double* theta, int dir, int n_gen, const uint64_t* ex, const uint64_t* ez,

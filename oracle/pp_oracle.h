@@ -59,6 +59,9 @@ void    or_noise(or_sum* s, int n_gen, const uint64_t* ex, const uint64_t* ez,
 /* Drop |c| < eps; then, if more than max_terms remain (max_terms > 0), keep the
  * max_terms largest |c| (ties: smaller canonical key first). */
 void    or_truncate(or_sum* s, double eps, int64_t max_terms);
+/* O -> (1 - q) O + q E' O E' for E' = eprime (Section II, Eq. applyantinoise); exact zeros
+ * dropped, no other truncation.  eprime must have the same qubit count. */
+void    or_antinoise(or_sum* s, const or_sum* eprime, double q);
 
 /* One circuit layer with the truncation schedule of the propagation:
  *   [noise if !noise_after_gates] ; gates (dir = +1: reverse list order, U^dag P U;

@@ -433,3 +433,134 @@ def test_layer_truncation_schedule_against_brute_force(oracle_lib):
             assert set(got) == set(cur), (direction, eps, cap)
             for k in cur:
                 assert abs(got[k] - cur[k]) < 1e-12
+
+
+# --------------------------------------------------------------------------------------
+# Propagated noise absorption (Section II, Eq. applyantinoise; Appendix D panel b).
+# --------------------------------------------------------------------------------------
+def _small_random_circuit(n, n_layers, n_gates, n_gen, seed, clifford=False):
+    rng = np.random.default_rng(seed)
+    layers = []
+    for _ in range(n_layers):
+        gates = []
+        for _g in range(n_gates):
+            w = int(rng.integers(1, 3))
+            ops = {int(q): "XYZ"[int(rng.integers(0, 3))] for q in rng.choice(n, w, replace=False)}
+            th = float(rng.integers(-3, 4)) * math.pi / 2 if clifford else float(rng.uniform(-1.2, 1.2))
+            gates.append((ops, th))
+        gens = []
+        for _k in range(n_gen):
+            w = int(rng.integers(1, 3))
+            ops = {int(q): "XYZ"[int(rng.integers(0, 3))] for q in rng.choice(n, w, replace=False)}
+            gens.append((ops, float(rng.uniform(1e-3, 3e-2))))
+        layers.append(W.make_layer(n, gates, gens))
+    return W.Circuit(n, layers)
+
+
+def test_pna_lightcone_worked_example(oracle_lib):
+    """Standard PNA on the one-qubit circuit of Appendix D (panel b) gives the printed
+    closed form (1 - q1) Z - q1 (1 - 2 q2) X."""
+    fx = json.load(open(os.path.join(HERE, "golden", "pna_lightcone_1q.json")))
+    for case in fx["cases"]:
+        l1, l2 = case["lambda1"], case["lambda2"]
+        env = dict(q1=(1 - math.exp(2 * l1)) / 2, q2=(1 - math.exp(2 * l2)) / 2)
+        circ = W.Circuit(1, [W.make_layer(1, [], [({0: "X"}, l1)]),
+                             W.make_layer(1, [({0: "Y"}, math.pi / 4)], [({0: "Z"}, l2)])])
+        e = oracle_lib.propagated_error(circ, 0, 0).as_dict()
+        # the evolved error of the first map is (X - Z)/sqrt 2
+        assert abs(e[((1,), (0,), 0)] - 2 ** -0.5) < 1e-15 and abs(e[((0,), (1,), 0)] + 2 ** -0.5) < 1e-15
+        got = oracle_lib.pna(circ, W.obs_single_z(1, 0)).as_dict()
+        assert len(got) == 2
+        assert abs(got[((0,), (1,), 0)] - eval(fx["exact"]["Z"], {}, env)) < 1e-15
+        assert abs(got[((1,), (0,), 0)] - eval(fx["exact"]["X"], {}, env)) < 1e-15
+
+
+@pytest.mark.parametrize("n,k,m,seed", [(2, 3, 5, 0), (3, 6, 12, 1), (4, 9, 20, 2), (3, 1, 7, 3)])
+def test_antinoise_against_matrices(oracle_lib, n, k, m, seed):
+    """(1 - q) O + q E' O E' on explicit 2^n x 2^n matrices, for a random real E' (not
+    normalised) and a random O."""
+    B = _brute()
+    e = W.random_pauli_sum(n, k, seed=100 + seed)
+    o = W.random_pauli_sum(n, m, seed=200 + seed)
+    q = -0.0137 * (seed + 1)
+    s = oracle_lib.OracleSum.from_sum(o)
+    s.antinoise(oracle_lib.OracleSum.from_sum(e), q)
+    em = B.pauli_sum_matrix(n, e.x, e.z, e.c)
+    om = B.pauli_sum_matrix(n, o.x, o.z, o.c)
+    want = _dict_from_decomp(B.pauli_decompose((1 - q) * om + q * em @ om @ em, n, tol=1e-14), n)
+    _assert_same_sum(_oracle_dict(s), want, 1e-13)
+
+
+@pytest.mark.parametrize("case", ["lattice2x2", "random3", "random4"])
+def test_pna_recovers_ideal_and_equals_deconvolution(oracle_lib, case):
+    """At zero threshold PNA's observable satisfies the trace identity Tr[O~ rho_noisy] =
+    <psi|O|psi> (density-matrix brute force), and so equals D O term by term (the
+    identity fixes O~ when the noise is invertible; D O from explicit superoperators)."""
+    B = _brute()
+    if case == "lattice2x2":
+        wl = W.named_workload("tfim3x3", rows=2, cols=2, steps=1)
+        circ, obs = wl.circuit, wl.observable
+    else:
+        n = int(case[-1])
+        circ = _small_random_circuit(n, 3, 3, 3, seed=n)
+        obs = W.pauli_sum(n, [({0: "Z"}, 0.7), ({1: "X", n - 1: "Z"}, -0.4)])
+    n = circ.n_qubits
+    res = oracle_lib.pna(circ, obs)
+    x, z, c, _ = res.export()
+    ot = B.pauli_sum_matrix(n, x, z, c)
+    rho = B.density_matrix(circ)
+    psi = B.statevector(circ)
+    om = B.pauli_sum_matrix(n, obs.x, obs.z, obs.c)
+    ideal = np.vdot(psi, om @ psi).real
+    assert abs(B.expectation(ot, rho).real - ideal) < 1e-12
+    assert abs(B.expectation(om, rho).real - ideal) > 1e-5
+    d = B.deconvolved_observable(circ, om)
+    want = _dict_from_decomp(B.pauli_decompose(d, n, tol=1e-13), n)
+    _assert_same_sum(_oracle_dict(res), want, 1e-12)
+
+
+def test_pna_clifford_closed_form(oracle_lib):
+    """Clifford circuit: every E' is one Pauli and O~ = O prod (1 - 2 q) over the errors
+    whose E' anticommutes with O (Section III's sampling-cost argument); E' from explicit
+    matrices."""
+    B = _brute()
+    n = 4
+    circ = _small_random_circuit(n, 3, 3, 4, seed=11, clifford=True)
+    o = W.pauli_sum(n, [({0: "Z", 2: "X"}, 1.0)])
+    d = oracle_lib.pna(circ, o).as_dict()
+    assert len(d) == 1
+    (key, coef), = d.items()
+    assert key[0] == tuple(int(v) for v in o.x[0]) and key[1] == tuple(int(v) for v in o.z[0])
+    om = B.pauli_sum_matrix(n, o.x, o.z, o.c)
+    want, n_anti = 1.0, 0
+    for t, layer in enumerate(circ.layers):
+        for k in range(layer.n_gen):
+            e = B.PauliOp(n, layer.ex[k], layer.ez[k]).matrix()
+            for later in circ.layers[t + 1:]:
+                for g in range(later.n_gates):
+                    e = B.conj_forward(e, B.PauliOp(n, later.gx[g], later.gz[g]), later.theta[g])
+            if np.abs(e @ om + om @ e).max() < 1e-9:
+                want *= 1 - 2 * (1 - math.exp(2 * layer.lam[k])) / 2
+                n_anti += 1
+    assert n_anti > 0
+    assert abs(coef - want) < 1e-14
+
+
+def test_pna_threshold_and_cap_after_every_update(oracle_lib):
+    """Truncation reading: after every absorbed map, |c| < eps is dropped and the cap
+    applied (brute force: the same walk with explicit truncation steps)."""
+    circ = _small_random_circuit(4, 3, 3, 3, seed=5)
+    obs = W.random_pauli_sum(4, 12, seed=9)
+    eps, cap = 3e-3, 10
+    got = oracle_lib.pna(circ, obs, eps=eps, max_terms=cap).as_dict()
+    o = oracle_lib.OracleSum.from_sum(obs)
+    for t, layer in enumerate(circ.layers):
+        for k in range(layer.n_gen):
+            o.antinoise(oracle_lib.propagated_error(circ, t, k), (1 - math.exp(2 * layer.lam[k])) / 2)
+            d = {kk: v for kk, v in o.as_dict().items() if abs(v) >= eps}
+            top = sorted(d.items(), key=lambda kv: (-abs(kv[1]), kv[0][0][::-1], kv[0][1][::-1], kv[0][2]))[:cap]
+            x = np.array([kk[0] for kk, _ in top], np.uint64).reshape(-1, 1)
+            z = np.array([kk[1] for kk, _ in top], np.uint64).reshape(-1, 1)
+            o = oracle_lib.OracleSum(4, x, z, np.array([v for _, v in top]))
+    assert got == o.as_dict()
+    assert len(got) <= cap
