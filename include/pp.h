@@ -134,6 +134,19 @@ pp_status pp_create_observable(pp_ctx* ctx, int n_qubits, int64_t n_terms, const
  * (string, order) and the max_terms cap. */
 pp_status pp_apply_layer(pp_obs* obs, const pp_layer* layer);
 
+/* Absorb one propagated antinoise map into the observable (Section II, Eq.
+ * applyantinoise): O -> (1 - q) O + q E' O E'.  E' = sum_a e_a P_a is the observable
+ * `eprime`, normally one noise generator E evolved to the end of the circuit, U E U^dag
+ * (pp_apply_layer with PP_FORWARD over the later layers, noise off); q is the inverse
+ * map's quasi-probability (1 - e^{2 lambda})/2 <= 0, though any finite q is accepted.
+ * Each term of O expands into 1 + K(K-1)/2 strings for K = |E'| (P itself, and one string
+ * per unordered pair of E' terms), duplicates are merged, then |c| < eps and the max_terms
+ * cap of obs's pp_trunc are applied; eprime is not changed.  Both observables must share
+ * the context, qubit count and precision (PP_ERR_INVALID otherwise) and be in
+ * PP_MODE_GREEDY (PP_ERR_UNSUPPORTED otherwise).  PP_ERR_UNSUPPORTED as well when
+ * K > 4096 or the expansion exceeds 2^31 - 1 strings; obs is then unchanged. */
+pp_status pp_apply_antinoise(pp_obs* obs, const pp_obs* eprime, double q);
+
 /* Explicit greedy truncation: drop |c| < eps, then keep the max_terms largest |c|
  * (0 = no cap; ties to the smaller canonical key).  E.g. the K_M leading terms of
  * Section I.C's estimation step. */

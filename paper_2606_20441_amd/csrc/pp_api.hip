@@ -238,6 +238,8 @@ const std::vector<uint32_t>& hash_tables() {
   return t;
 }
 
+constexpr uint64_t kMaxAntinoiseTerms = 4096;   // E' terms per antinoise update (16-bit pair indices)
+
 struct HostGate {
   GateDev g;
   int kind;
@@ -253,6 +255,7 @@ struct EngineBase {
   virtual void create(int64_t n, const uint64_t* x, const uint64_t* z, const double* c) = 0;
   virtual void apply_layer(const pp_layer* L) = 0;
   virtual void truncate(double eps, int64_t cap) = 0;
+  virtual void antinoise(const EngineBase* eprime, double q) = 0;
   virtual double expectation(const uint64_t* basis) = 0;
   virtual void export_terms(uint64_t* x, uint64_t* z, double* c, uint8_t* o) = 0;
   virtual uint64_t size() const = 0;
@@ -290,7 +293,7 @@ struct Engine final : EngineBase {
   TBuf<CT, ORD> gb;              // boundary candidates of a cap
   Buf u32a, u32b, u32c, scan_scr, tiles, gates_d, sup_d, tab_d, drun_d, dm_d, dval_d, cnt_d, ovf_d, partial_d, f64_d, span_d, htab_d, lstat_d;
   Buf hscr_d, tr_s0, tr_l0, tr_s1, tr_l1, g1_d, g1_ovf, g1_base, g1_base2;   // per-gate tile path
-  Buf rl0, rl1, rl2, ovl1, ovl2, tf_flag, tf_pos, tf_list, g1_io, g1_tab, g1_tabmeta, win_hist_d;
+  Buf rl0, rl1, rl2, ovl1, ovl2, tf_flag, tf_pos, tf_list, g1_io, g1_tab, g1_tabmeta, win_hist_d, pair_d;
   double growth[4] = {4.0, 4.0, 2.0, 3.0};
   double tile_target[4] = {80.0, 80.0, 80.0, 64.0};   // level-0 (one-wavefront) tile targets
   uint64_t last_ntiles = 1, last_ovf_tiles = 0;
@@ -300,7 +303,7 @@ struct Engine final : EngineBase {
     for (auto* t : {&ta, &tb}) { t->mem.ctx = ctx; t->W = W; }
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &drun_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
                    &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hscr_d, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &rl0, &rl1, &rl2, &ovl1, &ovl2,
-                   &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d})
+                   &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d, &pair_d})
       b->ctx = ctx;
     cnt_d.ensure(256);
     span_d.ensure(256);
@@ -313,7 +316,7 @@ struct Engine final : EngineBase {
     for (auto* t : {&ta, &tb}) t->mem.release();
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &drun_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
                    &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hscr_d, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &rl0, &rl1, &rl2, &ovl1, &ovl2,
-                   &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d})
+                   &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d, &pair_d})
       b->release();
   }
 
@@ -1803,6 +1806,47 @@ struct Engine final : EngineBase {
     if (cap > 0 && (int64_t)N > cap) cap_select((uint64_t)cap, ls);
   }
 
+  // Propagated antinoise (Section II, Eq. applyantinoise): O -> (1 - q) O + q E' O E'.
+  // Every term expands into 1 + K(K-1)/2 slots (k_expand_antinoise), the slots are put in
+  // canonical order and merged with the observable's eps threshold, then the cap applies.
+  void antinoise(const EngineBase* eb, double q) override {
+    const auto* e = dynamic_cast<const Engine*>(eb);
+    if (!e) throw_fail(PP_ERR_UNSUPPORTED, "E' must have the same word count, precision and mode as O");
+    if (N == 0) return;
+    const uint64_t K = e->N;
+    if (K > kMaxAntinoiseTerms)
+      throw_fail(PP_ERR_UNSUPPORTED, "E' has " + std::to_string(K) + " terms; at most " +
+                                         std::to_string(kMaxAntinoiseTerms) + " are supported");
+    const uint64_t S = 1 + K * (K - (K > 0)) / 2;
+    const uint64_t total = N * S;
+    if (total >= (1ULL << 31))
+      throw_fail(PP_ERR_UNSUPPORTED, "antinoise expansion of " + std::to_string(total) + " terms exceeds 2^31 - 1");
+    std::vector<uint32_t> pr;
+    pr.reserve(S);
+    for (uint32_t a = 0; a < K; ++a)
+      for (uint32_t b = a + 1; b < K; ++b) pr.push_back(a | (b << 16));
+    pr.push_back(0);   // never read; keeps the upload non-empty
+    pair_d.ensure(pr.size() * 4);
+    HIPCHK(hipMemcpyAsync(pair_d.p, pr.data(), pr.size() * 4, hipMemcpyHostToDevice, st));
+    sa.ensure(total);
+    const Terms<CT> in = cur.view(), ev = e->cur.view(), out = sa.view();
+    const uint32_t* pairs = pair_d.as<uint32_t>();
+    const uint64_t n = N;
+    const unsigned grid = (unsigned)std::min<uint64_t>(cdiv(total, 256), 1u << 20);
+    ctx->run("antinoise_expand", kTermBytes * (double)(n + total), (double)total, [&] {
+      hipLaunchKernelGGL((k_expand_antinoise<W, CT, ORD>), dim3(grid), dim3(256), 0, st, in, n, ev, (uint32_t)K,
+                         pairs, S, q, out);
+    });
+    ctx->check_launch();
+    sync();   // the pair table's host source goes out of scope
+    canonical_sort(sa, sb, total);
+    const uint64_t m = merge_sorted(sa, sb, total, obs->trunc.eps, nullptr);
+    cur.swap(sa);
+    N = m;
+    pp_layer_stats ls{};
+    if (obs->trunc.max_terms > 0 && (int64_t)N > obs->trunc.max_terms) cap_select((uint64_t)obs->trunc.max_terms, ls);
+  }
+
   double expectation(const uint64_t* basis) override {
     GroupMask b;
     for (int w = 0; w < PP_MAXW; ++w) { b.mx[w] = 0; b.mz[w] = 0; }
@@ -2067,6 +2111,22 @@ pp_status pp_truncate(pp_obs* obs, double eps, int64_t max_terms) {
   const pp_status s = guarded([&] {
     HIPCHK(hipSetDevice(obs->ctx->device));
     obs->eng->truncate(eps, max_terms);
+  });
+  if (s == PP_ERR_DEVICE || s == PP_ERR_OOM) obs->broken = true;
+  return s;
+}
+
+pp_status pp_apply_antinoise(pp_obs* obs, const pp_obs* eprime, double q) {
+  if (!obs || !eprime) { g_last_error = "NULL argument"; return PP_ERR_INVALID; }
+  if (obs->broken || eprime->broken) { g_last_error = "observable is unusable after an earlier device error"; return PP_ERR_INVALID; }
+  if (obs->ctx != eprime->ctx) { g_last_error = "O and E' belong to different contexts"; return PP_ERR_INVALID; }
+  if (obs->n_qubits != eprime->n_qubits) { g_last_error = "O and E' have different qubit counts"; return PP_ERR_INVALID; }
+  if (obs->prec != eprime->prec) { g_last_error = "O and E' have different precisions"; return PP_ERR_INVALID; }
+  if (obs->mode != PP_MODE_GREEDY || eprime->mode != PP_MODE_GREEDY) { g_last_error = "antinoise needs PP_MODE_GREEDY observables"; return PP_ERR_UNSUPPORTED; }
+  if (!std::isfinite(q)) { g_last_error = "q must be finite"; return PP_ERR_INVALID; }
+  const pp_status s = guarded([&] {
+    HIPCHK(hipSetDevice(obs->ctx->device));
+    obs->eng->antinoise(eprime->eng.get(), q);
   });
   if (s == PP_ERR_DEVICE || s == PP_ERR_OOM) obs->broken = true;
   return s;

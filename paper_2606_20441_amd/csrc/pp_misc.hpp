@@ -97,6 +97,92 @@ __device__ __forceinline__ bool same_term(const Terms<CT>& t, uint64_t a, uint64
   return eq;
 }
 
+// Phase of a product of Hermitian Paulis, A B = i^k (A xor B), k mod 4.  Per qubit,
+// XY = iZ, YZ = iX and ZX = iY contribute +i, the reverse orders -i, all other pairs 1.
+template <int W>
+__device__ __forceinline__ int herm_mul_phase(const uint64_t* ax, const uint64_t* az, const uint64_t* bx,
+                                              const uint64_t* bz) {
+  int k = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const uint64_t aX = ax[w] & ~az[w], aY = ax[w] & az[w], aZ = ~ax[w] & az[w];
+    const uint64_t bX = bx[w] & ~bz[w], bY = bx[w] & bz[w], bZ = ~bx[w] & bz[w];
+    k += popc64((aX & bY) | (aY & bZ) | (aZ & bX)) - popc64((aX & bZ) | (aY & bX) | (aZ & bY));
+  }
+  return k & 3;
+}
+
+// Expansion of one propagated antinoise map (Section II, Eq. applyantinoise):
+// O -> (1 - q) O + q E' O E' with E' = sum_a e_a P_a (K terms, in `e`).  Term i of O owns
+// S = 1 + K(K-1)/2 consecutive output slots:
+//  * slot 0: P_i with c_i [(1 - q) + q sum_a e_a^2 (-1)^{<P_a, P_i>}]  (P_a P P_a = +-P);
+//  * slot 1 + j, pair (a, b) = pairs[j] with a < b: the two orders are adjoints of each
+//    other, so P_a P P_b + P_b P P_a = 2 Re(i^k) R for P_a P P_b = i^k R: 2 q e_a e_b c_i
+//    times +1 (k = 0) or -1 (k = 2), and 0 for odd k.
+// Zero slots keep P_i's key; the merge that follows drops them.  Grid-stride over n * S
+// slots, so consecutive threads write consecutive slots of every plane.
+template <int W, class CT, bool ORD>
+__global__ void k_expand_antinoise(Terms<CT> in, uint64_t n, Terms<CT> e, uint32_t K, const uint32_t* pairs,
+                                   uint64_t S, double q, Terms<CT> out) {
+  const uint64_t total = n * S;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t i = t / S;
+    const uint64_t j = t - i * S;
+    uint64_t px[W], pz[W], rx[W], rz[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      px[w] = in.x[(size_t)w * in.stride + i];
+      pz[w] = in.z[(size_t)w * in.stride + i];
+      rx[w] = px[w];
+      rz[w] = pz[w];
+    }
+    const double c = (double)in.c[i];
+    double v = 0.0;
+    if (j == 0) {
+      double s = 0.0;
+      for (uint32_t a = 0; a < K; ++a) {
+        int par = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+          par += popc64(e.x[(size_t)w * e.stride + a] & pz[w]) + popc64(e.z[(size_t)w * e.stride + a] & px[w]);
+        const double ea = (double)e.c[a];
+        s += (par & 1) ? -ea * ea : ea * ea;
+      }
+      v = c * ((1.0 - q) + q * s);
+    } else {
+      const uint32_t pr = pairs[j - 1];
+      const uint32_t a = pr & 0xffffu, b = pr >> 16;
+      uint64_t ax[W], az[W], bx[W], bz[W], tx[W], tz[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        ax[w] = e.x[(size_t)w * e.stride + a];
+        az[w] = e.z[(size_t)w * e.stride + a];
+        bx[w] = e.x[(size_t)w * e.stride + b];
+        bz[w] = e.z[(size_t)w * e.stride + b];
+        tx[w] = ax[w] ^ px[w];
+        tz[w] = az[w] ^ pz[w];
+      }
+      const int k = (herm_mul_phase<W>(ax, az, px, pz) + herm_mul_phase<W>(tx, tz, bx, bz)) & 3;
+      if (!(k & 1)) {
+        v = (k == 0 ? 2.0 : -2.0) * q * (double)e.c[a] * (double)e.c[b] * c;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          rx[w] = tx[w] ^ bx[w];
+          rz[w] = tz[w] ^ bz[w];
+        }
+      }
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      out.x[(size_t)w * out.stride + t] = rx[w];
+      out.z[(size_t)w * out.stride + t] = rz[w];
+    }
+    out.c[t] = (CT)v;
+    if (ORD) out.o[t] = in.o[i];
+  }
+}
+
 template <int W, class CT, bool ORD>
 __device__ __forceinline__ double reduce_run(Terms<CT>& t, uint64_t n, uint64_t i, double thr, uint32_t* keep) {
   if (i > 0 && same_term<W, CT, ORD>(t, i, i - 1)) { keep[i] = 0; return 0.0; }

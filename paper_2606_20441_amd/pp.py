@@ -7,6 +7,7 @@ caching allocator.  Loading fails loudly if the library was not built.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import threading
 from dataclasses import dataclass
@@ -109,6 +110,8 @@ def lib():
         L.pp_apply_layer.argtypes = [C.c_void_p, C.POINTER(pp_layer)]
         L.pp_apply_layer.restype = C.c_int
         L.pp_truncate.argtypes = [C.c_void_p, C.c_double, C.c_int64]
+        L.pp_apply_antinoise.argtypes = [C.c_void_p, C.c_void_p, C.c_double]
+        L.pp_apply_antinoise.restype = C.c_int
         L.pp_truncate.restype = C.c_int
         L.pp_expectation.argtypes = [C.c_void_p, _u64p, _f64p]
         L.pp_expectation.restype = C.c_int
@@ -274,6 +277,10 @@ class Observable:
         _check(lib().pp_apply_layer(self._h, C.byref(L)))
         del keep
 
+    def apply_antinoise(self, eprime: "Observable", q: float):
+        """O -> (1 - q) O + q E' O E' (``pp_apply_antinoise``)."""
+        _check(lib().pp_apply_antinoise(self._h, eprime._h, float(q)))
+
     def truncate(self, eps: float, max_terms: int = 0):
         _check(lib().pp_truncate(self._h, float(eps), int(max_terms)))
 
@@ -357,6 +364,52 @@ def noisy_evaluation(circuit, obs_tilde: "Observable", on_layer=None) -> float:
         if on_layer:
             on_layer(m, obs_tilde)
     return obs_tilde.expectation()
+
+
+def antinoise_q(lam: float) -> float:
+    """Quasi-probability q = (1 - e^{2 lambda})/2 <= 0 of a generator's inverse map
+    (Section I: the channel applies E with probability (1 - e^{-2 lambda})/2)."""
+    return (1.0 - math.exp(2.0 * float(lam))) / 2.0
+
+
+def propagated_error(ctx: Context, circuit, t: int, k: int, eps_fwd: float = 0.0, max_terms_fwd: int = 0,
+                     precision: str = "f64") -> Observable:
+    """E' = U E U^dag for generator k of layer t's noise: E carried forward in time
+    through the gates of layers t+1..M (Section II), on the device."""
+    W = (circuit.n_qubits + 63) // 64
+    layer = circuit.layers[t]
+    ex = _words(layer.ex, W)[k:k + 1]
+    ez = _words(layer.ez, W)[k:k + 1]
+    e = Observable(ctx, circuit.n_qubits, ex, ez, np.ones(1), precision=precision, eps=eps_fwd,
+                   max_terms=max_terms_fwd)
+    for later in circuit.layers[t + 1:]:
+        e.apply_layer(later, PP_FORWARD, with_noise=False)
+    return e
+
+
+def pna(ctx: Context, circuit, observable, eps: float = 0.0, max_terms: int = 0, eps_fwd: float = 0.0,
+        max_terms_fwd: int = 0, precision: str = "f64", on_map=None) -> Observable:
+    """Propagated noise absorption (Section II).
+
+    With C_noisy = N_M G_M .. N_1 G_1, inserting N_t^{-1} N_t after every G_t and carrying
+    each inverse map to the end of the circuit, from t = 1 up and through the later gates
+    only, gives C_ideal = N'_1^{-1} .. N'_M^{-1} C_noisy.  The adjoint of that product acts
+    on O with N'_1^{-1} first: for t = 1..M and every generator E of N_t (whose maps
+    commute), O -> (1 - q) O + q E' O E' with E' = U E U^dag (Eq. applyantinoise), then the
+    observable's eps threshold and cap.
+    """
+    obs = Observable.from_sum(ctx, observable, precision=precision, eps=eps, max_terms=max_terms)
+    for t, layer in enumerate(circuit.layers):
+        lam = np.asarray(layer.lam, np.float64)
+        for k in range(layer.n_gen):
+            e = propagated_error(ctx, circuit, t, k, eps_fwd, max_terms_fwd, precision)
+            try:
+                obs.apply_antinoise(e, antinoise_q(lam[k]))
+            finally:
+                e.destroy()
+            if on_map:
+                on_map(t, k, obs)
+    return obs
 
 
 def run_workload(ctx: Context, wl, precision: Optional[str] = None, on_layer=None) -> Observable:

@@ -1,0 +1,185 @@
+"""GPU parity of propagated noise absorption (Section II, Eq. applyantinoise).
+
+``pp_apply_antinoise`` through the C ABI against the FP64 reference's plain double sum over
+ordered pairs, on random sums at one, two and four words per string; then whole PNA runs
+(forward-propagated errors on the device, one update per generator) against the
+reference's same walk, and at zero threshold against the statevector through the noisy
+evaluation.  Strings compared exactly (terms within 1e-12 of a threshold exempt),
+coefficients to 1e-11 relative, <O> to 1e-10.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2606_20441_amd import workloads as W
+from tests.parity import cap_cut, compare_sums
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2606_20441_amd import pp as _pp
+    _pp.lib()
+    return _pp
+
+
+@pytest.fixture(scope="module")
+def ctx(pp):
+    c = pp.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def orc():
+    from oracle import build
+    build.build(force=False)
+    from oracle import oracle
+    return oracle
+
+
+def _pair(pp, ctx, orc, ps, **kw):
+    return pp.Observable.from_sum(ctx, ps, **kw), orc.OracleSum.from_sum(ps)
+
+
+@pytest.mark.parametrize("n,m,k,q,eps,cap", [
+    (56, 3000, 7, -0.0123, 0.0, 0),
+    (56, 1500, 40, -0.004, 1e-6, 0),
+    (56, 2000, 1, -0.3, 0.0, 0),
+    (128, 1200, 25, -0.02, 1e-7, 700),
+    (200, 800, 12, 0.05, 0.0, 0),
+    (9, 100, 300, -0.001, 1e-9, 0),
+])
+def test_antinoise_random(pp, ctx, orc, n, m, k, q, eps, cap):
+    log(f"antinoise n={n} |O|={m} |E'|={k} q={q} eps={eps} cap={cap}")
+    o = W.random_pauli_sum(n, m, seed=n + m)
+    e = W.random_pauli_sum(n, k, seed=7 * n + k)
+    g, r = _pair(pp, ctx, orc, o, eps=eps, max_terms=cap)
+    ge = pp.Observable.from_sum(ctx, e)
+    g.apply_antinoise(ge, q)
+    r.antinoise(orc.OracleSum.from_sum(e), q)
+    r.truncate(eps, cap)
+    ref = r.as_dict()
+    got = g.as_dict()
+    th = [eps] + ([cap_cut(ref)] if cap else [])
+    rep = compare_sums(got, ref, thresholds=th, context="antinoise")
+    log(f"  {rep}")
+    assert abs(g.expectation() - r.expectation()) < 1e-10
+    # E' is left as it was
+    assert ge.as_dict() == {kk: v for kk, v in orc.OracleSum.from_sum(e).as_dict().items()}
+    g.destroy()
+    ge.destroy()
+
+
+def test_antinoise_edge_cases(pp, ctx, orc):
+    n = 56
+    o = W.random_pauli_sum(n, 300, seed=1)
+    # empty E': O -> (1 - q) O
+    g = pp.Observable.from_sum(ctx, o)
+    empty = pp.Observable(ctx, n, np.zeros((0, 1), np.uint64), np.zeros((0, 1), np.uint64), np.zeros(0))
+    g.apply_antinoise(empty, -0.25)
+    want = {kk: 1.25 * v for kk, v in orc.OracleSum.from_sum(o).as_dict().items()}
+    compare_sums(g.as_dict(), want, context="empty E'")
+    # empty O stays empty
+    e = pp.Observable.from_sum(ctx, W.random_pauli_sum(n, 5, seed=2))
+    empty.apply_antinoise(e, -0.1)
+    assert len(empty) == 0
+    # argument errors leave O unchanged
+    before = g.as_dict()
+    other = pp.Observable.from_sum(ctx, W.random_pauli_sum(57, 3, seed=3))
+    with pytest.raises(pp.PPError):
+        g.apply_antinoise(other, -0.1)
+    eo = pp.Observable.from_sum(ctx, W.random_pauli_sum(n, 3, seed=4), mode="error_order")
+    with pytest.raises(pp.PPError):
+        g.apply_antinoise(eo, -0.1)
+    with pytest.raises(pp.PPError):
+        eo.apply_antinoise(e, -0.1)
+    f32 = pp.Observable.from_sum(ctx, W.random_pauli_sum(n, 3, seed=5), precision="f32k")
+    with pytest.raises(pp.PPError):
+        g.apply_antinoise(f32, -0.1)
+    with pytest.raises(pp.PPError):
+        g.apply_antinoise(e, float("nan"))
+    assert g.as_dict() == before
+    for h in (g, empty, e, other, eo, f32):
+        h.destroy()
+
+
+def test_antinoise_f32k(pp, ctx, orc):
+    """FP32 coefficients: the same strings, coefficients to FP32 rounding."""
+    n = 56
+    o = W.random_pauli_sum(n, 1000, seed=11)
+    e = W.random_pauli_sum(n, 9, seed=12)
+    g = pp.Observable.from_sum(ctx, o, precision="f32k")
+    ge = pp.Observable.from_sum(ctx, e, precision="f32k")
+    g.apply_antinoise(ge, -0.03)
+    r = orc.OracleSum.from_sum(o)
+    r.antinoise(orc.OracleSum.from_sum(e), -0.03)
+    got, ref = g.as_dict(), r.as_dict()
+    big = {kk for kk, v in ref.items() if abs(v) > 1e-5}
+    assert big <= set(got)
+    for kk in big:
+        assert abs(got[kk] - ref[kk]) <= 1e-6 * max(1.0, abs(ref[kk])), kk
+    g.destroy()
+    ge.destroy()
+
+
+def _lightcone_circuit(l1, l2):
+    return W.Circuit(1, [W.make_layer(1, [], [({0: "X"}, l1)]),
+                         W.make_layer(1, [({0: "Y"}, math.pi / 4)], [({0: "Z"}, l2)])])
+
+
+@pytest.mark.parametrize("case", [
+    ("lightcone", None, 0.0, 0, 0.0),
+    ("tfim3x3", dict(rows=2, cols=2, steps=1), 0.0, 0, 0.0),
+    ("tfim3x3", dict(rows=2, cols=3, steps=1), 0.0, 0, 0.0),
+    ("tfim3x3", dict(steps=2), 1e-4, 0, 1e-4),
+    ("tfim3x3", dict(steps=2), 1e-4, 8, 1e-3),
+    ("tfim7x8_pna", dict(steps=1), 1e-5, 0, 1e-5),
+    ("tfim7x8_pna", dict(steps=1), 0.0, 60, 0.0),
+    ("tfim8x16", dict(steps=1), 1e-4, 0, 1e-4),
+], ids=lambda c: f"{c[0]}-{c[1]}-eps{c[2]}-cap{c[3]}")
+def test_pna_parity(pp, ctx, orc, case):
+    name, kw, eps, cap, eps_fwd = case
+    if name == "lightcone":
+        circ, obs = _lightcone_circuit(0.05, 0.01), W.obs_single_z(1, 0)
+    else:
+        wl = W.named_workload(name, **kw)
+        circ, obs = wl.circuit, wl.observable
+    log(f"pna {name} {kw} eps={eps} cap={cap} eps_fwd={eps_fwd}")
+    g = pp.pna(ctx, circ, obs, eps=eps, max_terms=cap, eps_fwd=eps_fwd)
+    r = orc.pna(circ, obs, eps=eps, max_terms=cap, eps_fwd=eps_fwd)
+    ref = r.as_dict()
+    th = [eps] + ([cap_cut(ref)] if cap else [])
+    rep = compare_sums(g.as_dict(), ref, thresholds=th, context=f"pna {name}")
+    eg, eo = g.expectation(), r.expectation()
+    log(f"  {rep}; <O~> {eg!r} vs {eo!r}")
+    assert abs(eg - eo) < 1e-10
+    if eps == 0.0 and cap == 0 and circ.n_qubits <= 10:
+        # trace identity: the noisy evaluation of O~ gives the ideal value
+        from oracle import brute as B
+        psi = B.statevector(circ)
+        om = B.pauli_sum_matrix(circ.n_qubits, obs.x, obs.z, obs.c)
+        v = pp.noisy_evaluation(circ, g)
+        assert abs(v - np.vdot(psi, om @ psi).real) < 1e-10
+    g.destroy()
+
+
+def test_pna_equals_deconvolution_at_zero_threshold(pp, ctx):
+    """Both constructions of O~ satisfy Tr[O~ C_noisy(rho)] = Tr[O C_ideal(rho)] for every
+    rho, which fixes O~; on the device they agree term by term."""
+    wl = W.named_workload("tfim3x3", rows=2, cols=3, steps=1)
+    a = pp.pna(ctx, wl.circuit, wl.observable)
+    b = pp.noise_canceling(ctx, wl.circuit, wl.observable)
+    compare_sums(a.as_dict(), b.as_dict(), rtol=1e-12, context="PNA vs D O")
+    a.destroy()
+    b.destroy()
