@@ -199,6 +199,66 @@ def noisy_check(ctx, wl, precision):
     return {"value": v, "ms": round(1e3 * dt, 3), "term_updates_per_s": round(upd[0] / dt, 1), "terms_out": n}
 
 
+def pna_check(ctx, cpu: bool, prefix_maps: int = 300):
+    """Propagated noise absorption (Section II) on the same 7x8 lattice, angles and noise
+    as the headline workload at 2 Trotter steps (4 layers, 4164 generators): every
+    generator's error propagated forward through the later gates on the device (threshold
+    1e-4), then absorbed into O (threshold 1e-5), one update per generator.  Timed whole,
+    once; the oracle and the device are also timed on the same prefix of the walk."""
+    import torch
+    from paper_2606_20441_amd import pp, workloads as W
+    wl = W.named_workload("tfim7x8_pna", steps=2)
+    eps, eps_fwd = wl.eps, 1e-4
+    circ = wl.circuit
+    n_maps = sum(l.n_gen for l in circ.layers)
+    ctx.timing(True)
+    ctx.timing_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = pp.pna(ctx, circ, wl.observable, eps=eps, eps_fwd=eps_fwd)
+    v = g.expectation()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ks = ctx.timing_read(reset=True)
+    ctx.timing(False)
+    n_out = len(g)
+    g.destroy()
+    top = sorted(ks, key=lambda k: -k["total_ms"])[:6]
+    out = {"workload": "tfim7x8_pna at 2 Trotter steps: 56q, 4 layers, eps 1e-5, forward eps 1e-4, no cap",
+           "maps": n_maps, "ms": round(1e3 * dt, 1), "maps_per_s": round(n_maps / dt, 1), "expectation": v,
+           "terms_out": n_out,
+           "kernels": [{"name": k["name"], "launches": k["launches"], "total_ms": round(k["total_ms"], 2)} for k in top]}
+    log(f"   PNA: {n_maps} maps in {1e3 * dt:.0f} ms ({n_maps / dt:.0f} maps/s), <O~> = {v!r}, {n_out} terms")
+    for k in top:
+        log(f"      {k['name']:24s} {k['launches']:6d} launches {k['total_ms']:9.2f} ms")
+    if cpu:
+        from oracle import oracle
+        maps = [(t, k) for t, l in enumerate(circ.layers) for k in range(l.n_gen)][:prefix_maps]
+        t0 = time.perf_counter()
+        o = oracle.OracleSum.from_sum(wl.observable)
+        for t, k in maps:
+            o.antinoise(oracle.propagated_error(circ, t, k, eps_fwd), oracle.antinoise_q(circ.layers[t].lam[k]))
+            o.truncate(eps, 0)
+        t_cpu = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gg = pp.Observable.from_sum(ctx, wl.observable, eps=eps)
+        for t, k in maps:
+            e = pp.propagated_error(ctx, circ, t, k, eps_fwd)
+            gg.apply_antinoise(e, pp.antinoise_q(circ.layers[t].lam[k]))
+            e.destroy()
+        torch.cuda.synchronize()
+        t_gpu = time.perf_counter() - t0
+        same = abs(gg.expectation() - o.expectation())
+        gg.destroy()
+        out["cpu_baseline"] = {"kind": "oracle", "cores": 1, "maps": len(maps),
+                               "sample": f"the first {len(maps)} maps of the walk (errors of the first layer, carried through 3 layers)",
+                               "oracle_s": round(t_cpu, 3), "gpu_s": round(t_gpu, 3),
+                               "maps_per_s": round(len(maps) / t_cpu, 2), "abs_diff_expectation": same}
+        log(f"   PNA prefix of {len(maps)} maps: oracle {t_cpu:.2f} s, device {t_gpu:.3f} s, |d<O~>| = {same:.2e}")
+    return out
+
+
 def cpu_baseline(wl, budget_s=15.0):
     """The FP64 CPU reference (single thread) on a bounded prefix of the same propagation:
     layer calls in the same order until the time budget is spent."""
@@ -262,6 +322,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-noisy-check", action="store_true",
                     help="skip propagating O~ back through the noisy circuit")
+    ap.add_argument("--no-pna", action="store_true", help="skip the propagated-noise-absorption leg")
+    ap.add_argument("--pna-only", action="store_true", help="run only the propagated-noise-absorption leg")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--serve-requests", type=int, default=30,
                     help="measured requests of the serving stream per arrival rate (0: skip it)")
@@ -289,6 +351,10 @@ def main():
     pp.lib()
     wl = W.named_workload(args.workload, **({} if args.max_terms is None else {"max_terms": args.max_terms}))
     ctx = pp.Context(0)
+    if args.pna_only:
+        print(json.dumps({"pna": pna_check(ctx, not args.no_cpu)}), flush=True)
+        ctx.close()
+        return
     Wd = wl.circuit.W
     results = {}
     copy_gbs = copy_ceiling()
@@ -310,6 +376,7 @@ def main():
                 f"algo {bw:8.1f} GB/s")
     main_prec = precs[0]
     noisy = noisy_check(ctx, wl, main_prec) if not args.no_noisy_check else None
+    pna = pna_check(ctx, not args.no_cpu) if not args.no_pna else None
     r = results[main_prec]
     value = r["updates"] / r["seconds"]
     line = {
@@ -334,6 +401,8 @@ def main():
     }
     if noisy is not None:
         line["noisy_evaluation"] = noisy
+    if pna is not None:
+        line["pna"] = pna
     if "f32k" in results and main_prec != "f32k":
         f = results["f32k"]
         line["fp32k"] = {"value": round(f["updates"] / f["seconds"], 1),
