@@ -1829,18 +1829,39 @@ struct Engine final : EngineBase {
     pair_d.ensure(pr.size() * 4);
     HIPCHK(hipMemcpyAsync(pair_d.p, pr.data(), pr.size() * 4, hipMemcpyHostToDevice, st));
     sa.ensure(total);
+    u32b.ensure(total * 4 + 64);
+    u32c.ensure(total * 4 + 64);
+    uint32_t* keep = u32b.as<uint32_t>();
+    uint32_t* pos = u32c.as<uint32_t>();
     const Terms<CT> in = cur.view(), ev = e->cur.view(), out = sa.view();
     const uint32_t* pairs = pair_d.as<uint32_t>();
     const uint64_t n = N;
     const unsigned grid = (unsigned)std::min<uint64_t>(cdiv(total, 256), 1u << 20);
-    ctx->run("antinoise_expand", kTermBytes * (double)(n + total), (double)total, [&] {
+    ctx->run("antinoise_expand", kTermBytes * (double)(n + total) + 4.0 * total, (double)total, [&] {
       hipLaunchKernelGGL((k_expand_antinoise<W, CT, ORD>), dim3(grid), dim3(256), 0, st, in, n, ev, (uint32_t)K,
-                         pairs, S, q, out);
+                         pairs, S, q, out, keep);
     });
     ctx->check_launch();
-    sync();   // the pair table's host source goes out of scope
-    canonical_sort(sa, sb, total);
-    const uint64_t m = merge_sorted(sa, sb, total, obs->trunc.eps, nullptr);
+    // exact zeros (pairs whose two orders cancel) are dropped before the sort
+    HIPCHK(hipMemcpyAsync(pos, keep, total * 4, hipMemcpyDeviceToDevice, st));
+    scan_u32(pos, total);
+    HIPCHK(hipMemcpyAsync(ctx->pinned, pos + total - 1, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync((char*)ctx->pinned + 4, keep + total - 1, 4, hipMemcpyDeviceToHost, st));
+    sync();   // also: the pair table's host source goes out of scope
+    uint32_t lp = 0, lk = 0;
+    std::memcpy(&lp, ctx->pinned, 4);
+    std::memcpy(&lk, (char*)ctx->pinned + 4, 4);
+    const uint64_t nz = (uint64_t)lp + lk;
+    sb.ensure(std::max<uint64_t>(nz, 1));
+    const Terms<CT> dense = sb.view();
+    ctx->run("compact", 0, (double)total, [&] {
+      hipLaunchKernelGGL((k_compact<W, CT, ORD>), grid1(total), dim3(256), 0, st, out, dense, total,
+                         (const uint32_t*)keep, (const uint32_t*)pos);
+    });
+    ctx->check_launch();
+    sa.swap(sb);
+    canonical_sort(sa, sb, nz);
+    const uint64_t m = merge_sorted(sa, sb, nz, obs->trunc.eps, nullptr);
     cur.swap(sa);
     N = m;
     pp_layer_stats ls{};

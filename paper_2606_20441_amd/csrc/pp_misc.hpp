@@ -119,11 +119,12 @@ __device__ __forceinline__ int herm_mul_phase(const uint64_t* ax, const uint64_t
 //  * slot 1 + j, pair (a, b) = pairs[j] with a < b: the two orders are adjoints of each
 //    other, so P_a P P_b + P_b P P_a = 2 Re(i^k) R for P_a P P_b = i^k R: 2 q e_a e_b c_i
 //    times +1 (k = 0) or -1 (k = 2), and 0 for odd k.
-// Zero slots keep P_i's key; the merge that follows drops them.  Grid-stride over n * S
-// slots, so consecutive threads write consecutive slots of every plane.
+// keep[t] flags the nonzero slots, which are compacted before the canonical sort.
+// Grid-stride over n * S slots, so consecutive threads write consecutive slots of every
+// plane.
 template <int W, class CT, bool ORD>
 __global__ void k_expand_antinoise(Terms<CT> in, uint64_t n, Terms<CT> e, uint32_t K, const uint32_t* pairs,
-                                   uint64_t S, double q, Terms<CT> out) {
+                                   uint64_t S, double q, Terms<CT> out, uint32_t* keep) {
   const uint64_t total = n * S;
   for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (uint64_t)gridDim.x * blockDim.x) {
@@ -164,13 +165,11 @@ __global__ void k_expand_antinoise(Terms<CT> in, uint64_t n, Terms<CT> e, uint32
         tz[w] = az[w] ^ pz[w];
       }
       const int k = (herm_mul_phase<W>(ax, az, px, pz) + herm_mul_phase<W>(tx, tz, bx, bz)) & 3;
-      if (!(k & 1)) {
-        v = (k == 0 ? 2.0 : -2.0) * q * (double)e.c[a] * (double)e.c[b] * c;
+      if (!(k & 1)) v = (k == 0 ? 2.0 : -2.0) * q * (double)e.c[a] * (double)e.c[b] * c;
 #pragma unroll
-        for (int w = 0; w < W; ++w) {
-          rx[w] = tx[w] ^ bx[w];
-          rz[w] = tz[w] ^ bz[w];
-        }
+      for (int w = 0; w < W; ++w) {
+        rx[w] = tx[w] ^ bx[w];
+        rz[w] = tz[w] ^ bz[w];
       }
     }
 #pragma unroll
@@ -180,6 +179,7 @@ __global__ void k_expand_antinoise(Terms<CT> in, uint64_t n, Terms<CT> e, uint32
     }
     out.c[t] = (CT)v;
     if (ORD) out.o[t] = in.o[i];
+    keep[t] = (CT)v != (CT)0 ? 1u : 0u;
   }
 }
 
