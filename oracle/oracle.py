@@ -49,6 +49,7 @@ def _lib():
         lib.or_noise_canceling.argtypes = [C.c_void_p, C.c_int, _i32p, _u64p, _u64p, _f64p, _i32p,
                                            _u64p, _u64p, _f64p, C.c_double, C.c_int64, C.c_int, C.c_int]
         lib.or_antinoise.argtypes = [C.c_void_p, C.c_void_p, C.c_double]
+        lib.or_antinoise_topk.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_int64]
         lib.or_expectation.restype = C.c_double
         lib.or_expectation.argtypes = [C.c_void_p, _u64p]
         lib.or_norm2.restype = C.c_double
@@ -126,6 +127,11 @@ class OracleSum:
     def antinoise(self, eprime: "OracleSum", q: float) -> None:
         """O -> (1 - q) O + q E' O E' (Section II, Eq. applyantinoise); no truncation."""
         _lib().or_antinoise(self._h, eprime._h, float(q))
+
+    def antinoise_topk(self, eprime: "OracleSum", q: float, k: int) -> None:
+        """As ``antinoise`` with E' O E' limited to the k most significant products
+        (Appendix B; ties with the k-th kept)."""
+        _lib().or_antinoise_topk(self._h, eprime._h, float(q), int(k))
 
     def apply_layer(self, layer, direction: int, with_gates: bool = True, with_noise: bool = True,
                     noise_sign: int = 1, noise_after_gates: bool = True, eps: float = 0.0,
@@ -224,7 +230,7 @@ def propagated_error(circuit, t: int, k: int, eps_fwd: float = 0.0, max_terms_fw
 
 
 def pna(circuit, observable, eps: float = 0.0, max_terms: int = 0, eps_fwd: float = 0.0,
-        max_terms_fwd: int = 0) -> OracleSum:
+        max_terms_fwd: int = 0, max_products: int = 0) -> OracleSum:
     """Propagated noise absorption (Section II).  The hardware circuit is
     C_noisy = N_M G_M .. N_1 G_1.  Writing each ideal layer as N_t^{-1} N_t G_t and carrying
     the inverse maps to the end one at a time, from t = 1 up, through the later gates only,
@@ -233,12 +239,17 @@ def pna(circuit, observable, eps: float = 0.0, max_terms: int = 0, eps_fwd: floa
     adjoint of that product acts on O with N'_1^{-1} first, so
     O~ = N'_M^{-1}( .. N'_1^{-1}(O)), each generator's map being
     O -> (1 - q) O + q E' O E' (Eq. applyantinoise; a generator's maps within one layer
-    commute).  After every update |c| < eps is dropped and the cap applied."""
+    commute).  After every update |c| < eps is dropped and the cap applied.  With
+    max_products > 0, E' O E' keeps only that many most significant products (Appendix B)."""
     o = observable.clone() if isinstance(observable, OracleSum) else OracleSum.from_sum(observable)
     for t, layer in enumerate(circuit.layers):
         for k in range(layer.n_gen):
             e = propagated_error(circuit, t, k, eps_fwd, max_terms_fwd)
-            o.antinoise(e, antinoise_q(float(np.asarray(layer.lam)[k])))
+            qk = antinoise_q(float(np.asarray(layer.lam)[k]))
+            if max_products > 0:
+                o.antinoise_topk(e, qk, max_products)
+            else:
+                o.antinoise(e, qk)
             o.truncate(eps, max_terms)
     return o
 

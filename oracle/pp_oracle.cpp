@@ -340,6 +340,60 @@ void antinoise(or_sum* s, const or_sum* e, double q) {
   s->m.swap(out);
 }
 
+// Approximate conjugation by the most significant products (Appendix B, Algorithm
+// heuristic-conjugation): of the products P_i P P_j over ordered index triplets
+// (i, term of O, j), only those with the k largest magnitudes mu = |alpha| (|beta_i|
+// |beta_j|) enter E' O E'.  Reading for ties: every product whose mu equals the k-th
+// largest is kept as well, so two orders of one pair (equal mu) are never split and the
+// result stays Hermitian; without a tie at the cut this is the set the paper's
+// priority-queue search pops.  k <= 0, or k at least the number of triplets, keeps all.
+// Written as the definition: every triplet's mu, sorted, the k-th taken as the cut.
+void antinoise_topk(or_sum* s, const or_sum* e, double q, int64_t k) {
+  if (e->W != s->W || e->n != s->n) fail("E' and O must have the same qubit count");
+  if (!std::isfinite(q)) fail("q must be finite");
+  const int W = s->W;
+  std::vector<std::pair<Key, double>> ev(e->m.begin(), e->m.end());
+  std::vector<std::pair<Key, double>> ov(s->m.begin(), s->m.end());
+  double cut = 0.0;
+  const uint64_t n_trip = (uint64_t)ov.size() * ev.size() * ev.size();
+  if (k > 0 && (uint64_t)k < n_trip) {
+    std::vector<double> mu;
+    mu.reserve(n_trip);
+    for (const auto& p : ov)
+      for (const auto& a : ev)
+        for (const auto& b : ev) mu.push_back(std::fabs(p.second) * (std::fabs(a.second) * std::fabs(b.second)));
+    std::sort(mu.begin(), mu.end(), [](double x, double y) { return x > y; });
+    cut = mu[(size_t)k - 1];
+  }
+  std::unordered_map<Key, std::complex<double>, KeyHash> acc;
+  static const std::complex<double> ipow[4] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}};
+  double scale = 0.0;
+  for (const auto& kv : ov) {
+    const Key& p = kv.first;
+    const double c = kv.second;
+    acc[p] += (1.0 - q) * c;
+    for (const auto& ea : ev) {
+      for (const auto& eb : ev) {
+        if (!(std::fabs(c) * (std::fabs(ea.second) * std::fabs(eb.second)) >= cut)) continue;
+        Key t, r;
+        const int k1 = pauli_mul(ea.first, p, W, &t);
+        const int k2 = pauli_mul(t, eb.first, W, &r);
+        r.o = p.o;
+        const double w = q * ea.second * eb.second * c;
+        acc[r] += w * ipow[(k1 + k2) & 3];
+        scale = std::max(scale, std::fabs(w));
+      }
+    }
+  }
+  Map out;
+  out.reserve(acc.size() * 2 + 16);
+  for (const auto& kv : acc) {
+    if (std::fabs(kv.second.imag()) > 1e-12 * std::max(1.0, scale)) fail("kept products are not Hermitian");
+    if (kv.second.real() != 0.0) out.emplace(kv.first, kv.second.real());
+  }
+  s->m.swap(out);
+}
+
 void apply_layer(or_sum* s, int n_gates, const uint64_t* gx, const uint64_t* gz, const double* theta,
                  int dir, int n_gen, const uint64_t* ex, const uint64_t* ez, const double* lambda,
                  int noise_sign, int noise_after_gates, double eps, int64_t max_terms, int mode,
@@ -428,6 +482,10 @@ void or_noise(or_sum* s, int n_gen, const uint64_t* ex, const uint64_t* ez, cons
 void or_truncate(or_sum* s, double eps, int64_t max_terms) { truncate(s, eps, max_terms); }
 
 void or_antinoise(or_sum* s, const or_sum* eprime, double q) { antinoise(s, eprime, q); }
+
+void or_antinoise_topk(or_sum* s, const or_sum* eprime, double q, int64_t k) {
+  antinoise_topk(s, eprime, q, k);
+}
 
 void or_apply_layer(or_sum* s, int n_gates, const uint64_t* gx, const uint64_t* gz,
                     const double* theta, int dir, int n_gen, const uint64_t* ex, const uint64_t* ez,

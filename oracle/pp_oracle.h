@@ -62,6 +62,9 @@ void    or_truncate(or_sum* s, double eps, int64_t max_terms);
 /* O -> (1 - q) O + q E' O E' for E' = eprime (Section II, Eq. applyantinoise); exact zeros
  * dropped, no other truncation.  eprime must have the same qubit count. */
 void    or_antinoise(or_sum* s, const or_sum* eprime, double q);
+/* As or_antinoise, with E' O E' limited to the products P_i P P_j of the k largest
+ * |alpha||beta_i||beta_j| (Appendix B's heuristic conjugation); ties with the k-th kept. */
+void    or_antinoise_topk(or_sum* s, const or_sum* eprime, double q, int64_t k);
 
 /* One circuit layer with the truncation schedule of the propagation:
  *   [noise if !noise_after_gates] ; gates (dir = +1: reverse list order, U^dag P U;

@@ -564,3 +564,82 @@ def test_pna_threshold_and_cap_after_every_update(oracle_lib):
             o = oracle_lib.OracleSum(4, x, z, np.array([v for _, v in top]))
     assert got == o.as_dict()
     assert len(got) <= cap
+
+
+# --------------------------------------------------------------------------------------
+# Heuristic conjugation (Appendix B): E' O E' limited to the most significant products.
+# --------------------------------------------------------------------------------------
+def _priority_queue_conjugation(n, a, b, k):
+    """The appendix's search, on explicit matrices: both operators sorted by |coefficient|,
+    index triplets (i, s, j) popped from a max-queue by |beta_i alpha_s beta_j|, the three
+    neighbours of each popped triplet pushed once, until k products are taken."""
+    import heapq
+    B = _brute()
+    oa = sorted(range(len(a.c)), key=lambda t: -abs(a.c[t]))
+    ob = sorted(range(len(b.c)), key=lambda t: -abs(b.c[t]))
+    pa = [(a.c[t], B.PauliOp(n, a.x[t], a.z[t]).matrix()) for t in oa]
+    pb = [(b.c[t], B.PauliOp(n, b.x[t], b.z[t]).matrix()) for t in ob]
+    M, N = len(pb), len(pa)
+    mag = lambda i, s, j: abs(pb[i][0] * pa[s][0] * pb[j][0])
+    heap, seen, out, taken = [(-mag(0, 0, 0), (0, 0, 0))], {(0, 0, 0)}, 0, 0
+    while heap and taken < k:
+        _, (i, s, j) = heapq.heappop(heap)
+        out = out + pb[i][0] * pa[s][0] * pb[j][0] * (pb[i][1] @ pa[s][1] @ pb[j][1])
+        taken += 1
+        for nb in ((i + 1, s, j), (i, s + 1, j), (i, s, j + 1)):
+            if nb[0] < M and nb[1] < N and nb[2] < M and nb not in seen:
+                seen.add(nb)
+                heapq.heappush(heap, (-mag(*nb), nb))
+    return out
+
+
+def _mus(a, b):
+    return sorted((abs(ca) * (abs(bi) * abs(bj)) for ca in a.c for bi in b.c for bj in b.c), reverse=True)
+
+
+def test_antinoise_topk_all_products_is_exact(oracle_lib):
+    e = W.random_pauli_sum(5, 6, seed=31, allow_duplicates=False)
+    o = W.random_pauli_sum(5, 20, seed=32, allow_duplicates=False)
+    want = oracle_lib.OracleSum.from_sum(o)
+    want.antinoise(oracle_lib.OracleSum.from_sum(e), -0.02)
+    for k in (0, 6 * 6 * 20, 10 ** 9):
+        got = oracle_lib.OracleSum.from_sum(o)
+        got.antinoise_topk(oracle_lib.OracleSum.from_sum(e), -0.02, k)
+        _assert_same_sum(_oracle_dict(got), _oracle_dict(want), 1e-15)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_antinoise_topk_against_priority_queue(oracle_lib, seed):
+    """Wherever no tie straddles the cut, the kept products are the ones the appendix's
+    priority-queue search pops; the update is compared on explicit 2^n matrices."""
+    B = _brute()
+    n = 3
+    e = W.random_pauli_sum(n, 5, seed=40 + seed, allow_duplicates=False)
+    o = W.random_pauli_sum(n, 9, seed=50 + seed, allow_duplicates=False)
+    q = -0.031
+    mus = _mus(o, e)
+    om = B.pauli_sum_matrix(n, o.x, o.z, o.c)
+    ks = [k for k in range(1, len(mus)) if mus[k - 1] > mus[k]]
+    assert len(ks) > 20
+    for k in ks[:: max(1, len(ks) // 12)]:
+        got = oracle_lib.OracleSum.from_sum(o)
+        got.antinoise_topk(oracle_lib.OracleSum.from_sum(e), q, k)
+        m = (1 - q) * om + q * _priority_queue_conjugation(n, o, e, k)
+        want = _dict_from_decomp(B.pauli_decompose(m, n, tol=1e-14), n)
+        _assert_same_sum(_oracle_dict(got), want, 1e-13)
+
+
+def test_antinoise_topk_keeps_ties_with_the_cut(oracle_lib):
+    """A cut between the two orders (i, s, j), (j, s, i) of one pair keeps both."""
+    e = W.random_pauli_sum(4, 4, seed=61, allow_duplicates=False)
+    o = W.random_pauli_sum(4, 7, seed=62, allow_duplicates=False)
+    mus = _mus(o, e)
+    k = next(k for k in range(2, len(mus)) if mus[k - 1] == mus[k] and mus[k - 2] > mus[k - 1])
+    a = oracle_lib.OracleSum.from_sum(o)
+    a.antinoise_topk(oracle_lib.OracleSum.from_sum(e), -0.05, k)
+    b = oracle_lib.OracleSum.from_sum(o)
+    b.antinoise_topk(oracle_lib.OracleSum.from_sum(e), -0.05, k + 1)
+    assert a.as_dict() == b.as_dict()
+    c = oracle_lib.OracleSum.from_sum(o)
+    c.antinoise_topk(oracle_lib.OracleSum.from_sum(e), -0.05, k - 1)
+    assert c.as_dict() != a.as_dict()
