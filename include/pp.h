@@ -147,6 +147,17 @@ pp_status pp_apply_layer(pp_obs* obs, const pp_layer* layer);
  * K > 4096 or the expansion exceeds 2^31 - 1 strings; obs is then unchanged. */
 pp_status pp_apply_antinoise(pp_obs* obs, const pp_obs* eprime, double q);
 
+/* As pp_apply_antinoise, with E' O E' approximated by its most significant products
+ * (Appendix B, the heuristic conjugation of large Pauli sums): of the products P_a P P_b
+ * over ordered triplets (a, term of O, b), only those whose magnitude
+ * |c_P| (|e_a| |e_b|) is among the max_products largest enter; every product tied with
+ * the max_products-th is kept as well, so both orders of a pair stay together and the
+ * result is Hermitian.  The (1 - q) O part is exact.  max_products <= 0, or at least
+ * |O| K^2, gives pp_apply_antinoise's result.  Only the kept products are expanded, so
+ * the 2^31 - 1 limit applies to |O| + (kept unordered pairs); other arguments and errors
+ * as pp_apply_antinoise. */
+pp_status pp_apply_antinoise_topk(pp_obs* obs, const pp_obs* eprime, double q, int64_t max_products);
+
 /* Explicit greedy truncation: drop |c| < eps, then keep the max_terms largest |c|
  * (0 = no cap; ties to the smaller canonical key).  E.g. the K_M leading terms of
  * Section I.C's estimation step. */

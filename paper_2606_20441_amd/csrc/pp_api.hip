@@ -256,6 +256,7 @@ struct EngineBase {
   virtual void apply_layer(const pp_layer* L) = 0;
   virtual void truncate(double eps, int64_t cap) = 0;
   virtual void antinoise(const EngineBase* eprime, double q) = 0;
+  virtual void antinoise_topk(const EngineBase* eprime, double q, int64_t k) = 0;
   virtual double expectation(const uint64_t* basis) = 0;
   virtual void export_terms(uint64_t* x, uint64_t* z, double* c, uint8_t* o) = 0;
   virtual uint64_t size() const = 0;
@@ -293,7 +294,7 @@ struct Engine final : EngineBase {
   TBuf<CT, ORD> gb;              // boundary candidates of a cap
   Buf u32a, u32b, u32c, scan_scr, tiles, gates_d, sup_d, tab_d, drun_d, dm_d, dval_d, cnt_d, ovf_d, partial_d, f64_d, span_d, htab_d, lstat_d;
   Buf hscr_d, tr_s0, tr_l0, tr_s1, tr_l1, g1_d, g1_ovf, g1_base, g1_base2;   // per-gate tile path
-  Buf rl0, rl1, rl2, ovl1, ovl2, tf_flag, tf_pos, tf_list, g1_io, g1_tab, g1_tabmeta, win_hist_d, pair_d;
+  Buf rl0, rl1, rl2, ovl1, ovl2, tf_flag, tf_pos, tf_list, g1_io, g1_tab, g1_tabmeta, win_hist_d, pair_d, topk_d, topk_off;
   double growth[4] = {4.0, 4.0, 2.0, 3.0};
   double tile_target[4] = {80.0, 80.0, 80.0, 64.0};   // level-0 (one-wavefront) tile targets
   uint64_t last_ntiles = 1, last_ovf_tiles = 0;
@@ -303,7 +304,7 @@ struct Engine final : EngineBase {
     for (auto* t : {&ta, &tb}) { t->mem.ctx = ctx; t->W = W; }
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &drun_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
                    &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hscr_d, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &rl0, &rl1, &rl2, &ovl1, &ovl2,
-                   &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d, &pair_d})
+                   &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d, &pair_d, &topk_d, &topk_off})
       b->ctx = ctx;
     cnt_d.ensure(256);
     span_d.ensure(256);
@@ -316,7 +317,7 @@ struct Engine final : EngineBase {
     for (auto* t : {&ta, &tb}) t->mem.release();
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &drun_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
                    &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hscr_d, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &rl0, &rl1, &rl2, &ovl1, &ovl2,
-                   &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d, &pair_d})
+                   &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d, &pair_d, &topk_d, &topk_off})
       b->release();
   }
 
@@ -1830,9 +1831,7 @@ struct Engine final : EngineBase {
     HIPCHK(hipMemcpyAsync(pair_d.p, pr.data(), pr.size() * 4, hipMemcpyHostToDevice, st));
     sa.ensure(total);
     u32b.ensure(total * 4 + 64);
-    u32c.ensure(total * 4 + 64);
     uint32_t* keep = u32b.as<uint32_t>();
-    uint32_t* pos = u32c.as<uint32_t>();
     const Terms<CT> in = cur.view(), ev = e->cur.view(), out = sa.view();
     const uint32_t* pairs = pair_d.as<uint32_t>();
     const uint64_t n = N;
@@ -1842,18 +1841,28 @@ struct Engine final : EngineBase {
                          pairs, S, q, out, keep);
     });
     ctx->check_launch();
-    // exact zeros (pairs whose two orders cancel) are dropped before the sort
+    sync();   // the pair table's host source goes out of scope
+    finish_expansion(total);
+  }
+
+  // After an antinoise expansion: sa holds `total` slots and u32b their nonzero flags.
+  // Exact zeros (pairs whose two orders cancel) are dropped, the rest put in canonical
+  // order and merged with the eps threshold, and the cap applied; the result becomes O.
+  void finish_expansion(uint64_t total) {
+    u32c.ensure(total * 4 + 64);
+    uint32_t* keep = u32b.as<uint32_t>();
+    uint32_t* pos = u32c.as<uint32_t>();
     HIPCHK(hipMemcpyAsync(pos, keep, total * 4, hipMemcpyDeviceToDevice, st));
     scan_u32(pos, total);
     HIPCHK(hipMemcpyAsync(ctx->pinned, pos + total - 1, 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync((char*)ctx->pinned + 4, keep + total - 1, 4, hipMemcpyDeviceToHost, st));
-    sync();   // also: the pair table's host source goes out of scope
+    sync();
     uint32_t lp = 0, lk = 0;
     std::memcpy(&lp, ctx->pinned, 4);
     std::memcpy(&lk, (char*)ctx->pinned + 4, 4);
     const uint64_t nz = (uint64_t)lp + lk;
     sb.ensure(std::max<uint64_t>(nz, 1));
-    const Terms<CT> dense = sb.view();
+    const Terms<CT> out = sa.view(), dense = sb.view();
     ctx->run("compact", 0, (double)total, [&] {
       hipLaunchKernelGGL((k_compact<W, CT, ORD>), grid1(total), dim3(256), 0, st, out, dense, total,
                          (const uint32_t*)keep, (const uint32_t*)pos);
@@ -1866,6 +1875,93 @@ struct Engine final : EngineBase {
     N = m;
     pp_layer_stats ls{};
     if (obs->trunc.max_terms > 0 && (int64_t)N > obs->trunc.max_terms) cap_select((uint64_t)obs->trunc.max_terms, ls);
+  }
+
+  // E' O E' limited to the products of the k largest magnitudes |c_s| |e_a| |e_b| over
+  // ordered triplets, ties with the k-th kept (Appendix B's heuristic conjugation).  The
+  // cut tau is found on the device by bisection; only the kept pairs are expanded.
+  void antinoise_topk(const EngineBase* eb, double q, int64_t kmax) override {
+    const auto* e = dynamic_cast<const Engine*>(eb);
+    if (!e) throw_fail(PP_ERR_UNSUPPORTED, "E' must have the same word count, precision and mode as O");
+    if (N == 0) return;
+    const uint64_t K = e->N;
+    if (K > kMaxAntinoiseTerms)
+      throw_fail(PP_ERR_UNSUPPORTED, "E' has " + std::to_string(K) + " terms; at most " +
+                                         std::to_string(kMaxAntinoiseTerms) + " are supported");
+    if (kmax <= 0 || (uint64_t)kmax >= N * K * K) {
+      antinoise(eb, q);
+      return;
+    }
+    // pairs a <= b of E' (in device order), largest |e_a| |e_b| first
+    std::vector<CT> ec(K);
+    HIPCHK(hipMemcpyAsync(ec.data(), e->cur.view().c, K * sizeof(CT), hipMemcpyDeviceToHost, st));
+    sync();
+    const uint64_t P = K * (K + 1) / 2;
+    std::vector<std::pair<double, uint32_t>> pr;
+    pr.reserve(P);
+    for (uint32_t a = 0; a < K; ++a)
+      for (uint32_t b = a; b < K; ++b)
+        pr.push_back({std::fabs((double)ec[a]) * std::fabs((double)ec[b]), a | (b << 16)});
+    std::sort(pr.begin(), pr.end(), [](const std::pair<double, uint32_t>& x, const std::pair<double, uint32_t>& y) {
+      return x.first > y.first || (x.first == y.first && x.second < y.second);
+    });
+    // one upload: pm[P] doubles, cw[P + 1] u64, tau (one double), the slot total (u64,
+    // zero), pidx[P] u32
+    const size_t o_cw = P * 8, o_tau = o_cw + (P + 1) * 8, o_sum = o_tau + 8, o_idx = o_sum + 8;
+    std::vector<char> host(o_idx + P * 4, 0);
+    double* pm = (double*)host.data();
+    uint64_t* cw = (uint64_t*)(host.data() + o_cw);
+    uint32_t* pidx = (uint32_t*)(host.data() + o_idx);
+    cw[0] = 0;
+    for (uint64_t p = 0; p < P; ++p) {
+      pm[p] = pr[p].first;
+      pidx[p] = pr[p].second;
+      const bool diag = (pr[p].second & 0xffffu) == (pr[p].second >> 16);
+      cw[p + 1] = cw[p] + (diag ? 1 : 2);
+    }
+    topk_d.ensure(host.size());
+    HIPCHK(hipMemcpyAsync(topk_d.p, host.data(), host.size(), hipMemcpyHostToDevice, st));
+    const double* pm_d = (const double*)topk_d.p;
+    const uint64_t* cw_d = (const uint64_t*)((char*)topk_d.p + o_cw);
+    double* tau_d = (double*)((char*)topk_d.p + o_tau);
+    unsigned long long* sum_d = (unsigned long long*)((char*)topk_d.p + o_sum);
+    const uint32_t* pidx_d = (const uint32_t*)((char*)topk_d.p + o_idx);
+    const CT* c = cur.view().c;
+    const uint64_t n = N;
+    ctx->run("topk_cut", 0, (double)n, [&] {
+      hipLaunchKernelGGL((k_topk_cut<CT>), dim3(1), dim3(1024), 0, st, c, n, pm_d, cw_d, (uint32_t)P,
+                         (uint64_t)kmax, 0x7FF0000000000000ULL, tau_d);
+    });
+    ctx->check_launch();
+    u32b.ensure(n * 4 + 64);
+    topk_off.ensure(n * 4 + 64);
+    uint32_t* lens = u32b.as<uint32_t>();
+    uint32_t* off = topk_off.as<uint32_t>();
+    ctx->run("topk_lens", 0, (double)n, [&] {
+      hipLaunchKernelGGL((k_topk_lens<CT>), grid1(n), dim3(256), 0, st, c, n, pm_d, (uint32_t)P,
+                         (const double*)tau_d, lens, sum_d);
+    });
+    ctx->check_launch();
+    HIPCHK(hipMemcpyAsync(ctx->pinned, sum_d, 8, hipMemcpyDeviceToHost, st));
+    sync();   // also: the upload's host source goes out of scope
+    uint64_t total = 0;
+    std::memcpy(&total, ctx->pinned, 8);
+    if (total >= (1ULL << 31))
+      throw_fail(PP_ERR_UNSUPPORTED, "antinoise expansion of " + std::to_string(total) + " terms exceeds 2^31 - 1");
+    HIPCHK(hipMemcpyAsync(off, lens, n * 4, hipMemcpyDeviceToDevice, st));
+    scan_u32(off, n);
+    sa.ensure(total);
+    u32b.ensure(total * 4 + 64);   // the flags replace lens, which is no longer read
+    uint32_t* keep = u32b.as<uint32_t>();
+    const Terms<CT> in = cur.view(), ev = e->cur.view(), out = sa.view();
+    const uint32_t* offc = topk_off.as<uint32_t>();
+    const unsigned grid = (unsigned)std::min<uint64_t>(cdiv(total, 256), 1u << 20);
+    ctx->run("antinoise_topk_expand", kTermBytes * (double)(n + total) + 4.0 * total, (double)total, [&] {
+      hipLaunchKernelGGL((k_expand_topk<W, CT, ORD>), dim3(grid), dim3(256), 0, st, in, n, offc, total, ev, pidx_d,
+                         q, out, keep);
+    });
+    ctx->check_launch();
+    finish_expansion(total);
   }
 
   double expectation(const uint64_t* basis) override {
@@ -2148,6 +2244,22 @@ pp_status pp_apply_antinoise(pp_obs* obs, const pp_obs* eprime, double q) {
   const pp_status s = guarded([&] {
     HIPCHK(hipSetDevice(obs->ctx->device));
     obs->eng->antinoise(eprime->eng.get(), q);
+  });
+  if (s == PP_ERR_DEVICE || s == PP_ERR_OOM) obs->broken = true;
+  return s;
+}
+
+pp_status pp_apply_antinoise_topk(pp_obs* obs, const pp_obs* eprime, double q, int64_t max_products) {
+  if (!obs || !eprime) { g_last_error = "NULL argument"; return PP_ERR_INVALID; }
+  if (obs->broken || eprime->broken) { g_last_error = "observable is unusable after an earlier device error"; return PP_ERR_INVALID; }
+  if (obs->ctx != eprime->ctx) { g_last_error = "O and E' belong to different contexts"; return PP_ERR_INVALID; }
+  if (obs->n_qubits != eprime->n_qubits) { g_last_error = "O and E' have different qubit counts"; return PP_ERR_INVALID; }
+  if (obs->prec != eprime->prec) { g_last_error = "O and E' have different precisions"; return PP_ERR_INVALID; }
+  if (obs->mode != PP_MODE_GREEDY || eprime->mode != PP_MODE_GREEDY) { g_last_error = "antinoise needs PP_MODE_GREEDY observables"; return PP_ERR_UNSUPPORTED; }
+  if (!std::isfinite(q)) { g_last_error = "q must be finite"; return PP_ERR_INVALID; }
+  const pp_status s = guarded([&] {
+    HIPCHK(hipSetDevice(obs->ctx->device));
+    obs->eng->antinoise_topk(eprime->eng.get(), q, max_products);
   });
   if (s == PP_ERR_DEVICE || s == PP_ERR_OOM) obs->broken = true;
   return s;

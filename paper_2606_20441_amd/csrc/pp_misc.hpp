@@ -183,6 +183,133 @@ __global__ void k_expand_antinoise(Terms<CT> in, uint64_t n, Terms<CT> e, uint32
   }
 }
 
+// ---- most significant products only (Appendix B, heuristic conjugation) --------------------
+// Unordered pairs p = (a <= b) of E' terms are sorted on the host by pm[p] = |e_a| |e_b|,
+// largest first; cw[p] = sum of the pair weights before p (1 for a = b, 2 otherwise: the
+// number of ordered triplets).  A triplet's magnitude is mu = |c_s| pm[p], non-increasing
+// in p for a fixed term s, so the pairs with mu >= tau form a prefix of the list.
+__device__ __forceinline__ uint32_t topk_prefix(double ac, const double* pm, uint32_t P, double tau) {
+  uint32_t lo = 0, hi = P;   // first p with ac * pm[p] < tau
+  while (lo < hi) {
+    const uint32_t mid = lo + (hi - lo) / 2;
+    if (ac * pm[mid] >= tau) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// One workgroup: tau = the largest value with at least k triplets of mu >= tau, by
+// bisection on the bit pattern of tau (order-preserving for non-negative doubles).  Every
+// round ends in barriers that all waves reach; at most 64 rounds.
+template <class CT>
+__global__ void __launch_bounds__(1024) k_topk_cut(const CT* c, uint64_t n, const double* pm, const uint64_t* cw,
+                                                   uint32_t P, uint64_t k, uint64_t hi_bits, double* tau_out) {
+  __shared__ unsigned long long part[16];
+  __shared__ uint64_t s_lo, s_hi;
+  if (threadIdx.x == 0) { s_lo = 0; s_hi = hi_bits; }
+  __syncthreads();
+  for (int round = 0; round < 64; ++round) {
+    const uint64_t lo = s_lo, hi = s_hi;
+    if (hi - lo <= 1) break;
+    const uint64_t mid = lo + (hi - lo) / 2;
+    const double tau = __longlong_as_double((long long)mid);
+    unsigned long long cnt = 0;
+    for (uint64_t s = threadIdx.x; s < n; s += blockDim.x) cnt += cw[topk_prefix(fabs((double)c[s]), pm, P, tau)];
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_down(cnt, off);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long tot = 0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += part[w];
+      if (tot >= k) s_lo = mid; else s_hi = mid;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *tau_out = __longlong_as_double((long long)s_lo);
+}
+
+// Slots of term s: 1 (the (1 - q) c_s P_s part) + the pairs kept for it.  `total` (zeroed
+// by the host) receives their exact 64-bit sum, one atomic per wavefront, so the host can
+// reject an expansion whose 32-bit offsets would wrap.
+template <class CT>
+__global__ void k_topk_lens(const CT* c, uint64_t n, const double* pm, uint32_t P, const double* tau,
+                            uint32_t* lens, unsigned long long* total) {
+  const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long v = 0;
+  if (s < n) {
+    v = 1u + topk_prefix(fabs((double)c[s]), pm, P, *tau);
+    lens[s] = (uint32_t)v;
+  }
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(total, v);
+}
+
+// Expansion with the kept pairs only.  off[s] = first slot of term s (exclusive scan of
+// lens).  Slot 0 of a term: (1 - q) c P.  Pair (a, a): q e_a^2 c (-1)^{<P_a, P>} on P.  Pair
+// (a, b), a < b: both orders, 2 Re(i^k) q e_a e_b c on R for P_a P P_b = i^k R.
+template <int W, class CT, bool ORD>
+__global__ void k_expand_topk(Terms<CT> in, uint64_t n, const uint32_t* off, uint64_t total, Terms<CT> e,
+                              const uint32_t* pidx, double q, Terms<CT> out, uint32_t* keep) {
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t lo = 0, hi = n;   // last s with off[s] <= t
+    while (hi - lo > 1) {
+      const uint64_t mid = lo + (hi - lo) / 2;
+      if ((uint64_t)off[mid] <= t) lo = mid; else hi = mid;
+    }
+    const uint64_t i = lo;
+    const uint64_t j = t - off[i];
+    uint64_t px[W], pz[W], rx[W], rz[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      px[w] = in.x[(size_t)w * in.stride + i];
+      pz[w] = in.z[(size_t)w * in.stride + i];
+      rx[w] = px[w];
+      rz[w] = pz[w];
+    }
+    const double c = (double)in.c[i];
+    double v;
+    if (j == 0) {
+      v = (1.0 - q) * c;
+    } else {
+      const uint32_t pr = pidx[j - 1];
+      const uint32_t a = pr & 0xffffu, b = pr >> 16;
+      uint64_t ax[W], az[W], bx[W], bz[W], tx[W], tz[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        ax[w] = e.x[(size_t)w * e.stride + a];
+        az[w] = e.z[(size_t)w * e.stride + a];
+        bx[w] = e.x[(size_t)w * e.stride + b];
+        bz[w] = e.z[(size_t)w * e.stride + b];
+        tx[w] = ax[w] ^ px[w];
+        tz[w] = az[w] ^ pz[w];
+      }
+      const double ea = (double)e.c[a], eb = (double)e.c[b];
+      if (a == b) {
+        int par = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) par += popc64(ax[w] & pz[w]) + popc64(az[w] & px[w]);
+        v = (par & 1) ? -(q * ea * ea * c) : q * ea * ea * c;
+      } else {
+        const int k = (herm_mul_phase<W>(ax, az, px, pz) + herm_mul_phase<W>(tx, tz, bx, bz)) & 3;
+        v = (k & 1) ? 0.0 : (k == 0 ? 2.0 : -2.0) * q * ea * eb * c;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          rx[w] = tx[w] ^ bx[w];
+          rz[w] = tz[w] ^ bz[w];
+        }
+      }
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      out.x[(size_t)w * out.stride + t] = rx[w];
+      out.z[(size_t)w * out.stride + t] = rz[w];
+    }
+    out.c[t] = (CT)v;
+    if (ORD) out.o[t] = in.o[i];
+    keep[t] = (CT)v != (CT)0 ? 1u : 0u;
+  }
+}
+
 template <int W, class CT, bool ORD>
 __device__ __forceinline__ double reduce_run(Terms<CT>& t, uint64_t n, uint64_t i, double thr, uint32_t* keep) {
   if (i > 0 && same_term<W, CT, ORD>(t, i, i - 1)) { keep[i] = 0; return 0.0; }

@@ -112,6 +112,8 @@ def lib():
         L.pp_truncate.argtypes = [C.c_void_p, C.c_double, C.c_int64]
         L.pp_apply_antinoise.argtypes = [C.c_void_p, C.c_void_p, C.c_double]
         L.pp_apply_antinoise.restype = C.c_int
+        L.pp_apply_antinoise_topk.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_int64]
+        L.pp_apply_antinoise_topk.restype = C.c_int
         L.pp_truncate.restype = C.c_int
         L.pp_expectation.argtypes = [C.c_void_p, _u64p, _f64p]
         L.pp_expectation.restype = C.c_int
@@ -281,6 +283,11 @@ class Observable:
         """O -> (1 - q) O + q E' O E' (``pp_apply_antinoise``)."""
         _check(lib().pp_apply_antinoise(self._h, eprime._h, float(q)))
 
+    def apply_antinoise_topk(self, eprime: "Observable", q: float, max_products: int):
+        """As ``apply_antinoise`` with E' O E' limited to its most significant products
+        (``pp_apply_antinoise_topk``)."""
+        _check(lib().pp_apply_antinoise_topk(self._h, eprime._h, float(q), int(max_products)))
+
     def truncate(self, eps: float, max_terms: int = 0):
         _check(lib().pp_truncate(self._h, float(eps), int(max_terms)))
 
@@ -388,7 +395,7 @@ def propagated_error(ctx: Context, circuit, t: int, k: int, eps_fwd: float = 0.0
 
 
 def pna(ctx: Context, circuit, observable, eps: float = 0.0, max_terms: int = 0, eps_fwd: float = 0.0,
-        max_terms_fwd: int = 0, precision: str = "f64", on_map=None) -> Observable:
+        max_terms_fwd: int = 0, precision: str = "f64", on_map=None, max_products: int = 0) -> Observable:
     """Propagated noise absorption (Section II).
 
     With C_noisy = N_M G_M .. N_1 G_1, inserting N_t^{-1} N_t after every G_t and carrying
@@ -396,7 +403,8 @@ def pna(ctx: Context, circuit, observable, eps: float = 0.0, max_terms: int = 0,
     only, gives C_ideal = N'_1^{-1} .. N'_M^{-1} C_noisy.  The adjoint of that product acts
     on O with N'_1^{-1} first: for t = 1..M and every generator E of N_t (whose maps
     commute), O -> (1 - q) O + q E' O E' with E' = U E U^dag (Eq. applyantinoise), then the
-    observable's eps threshold and cap.
+    observable's eps threshold and cap.  With max_products > 0 each E' O E' keeps only that
+    many most significant products (Appendix B's heuristic conjugation).
     """
     obs = Observable.from_sum(ctx, observable, precision=precision, eps=eps, max_terms=max_terms)
     for t, layer in enumerate(circuit.layers):
@@ -404,7 +412,10 @@ def pna(ctx: Context, circuit, observable, eps: float = 0.0, max_terms: int = 0,
         for k in range(layer.n_gen):
             e = propagated_error(ctx, circuit, t, k, eps_fwd, max_terms_fwd, precision)
             try:
-                obs.apply_antinoise(e, antinoise_q(lam[k]))
+                if max_products > 0:
+                    obs.apply_antinoise_topk(e, antinoise_q(lam[k]), max_products)
+                else:
+                    obs.apply_antinoise(e, antinoise_q(lam[k]))
             finally:
                 e.destroy()
             if on_map:

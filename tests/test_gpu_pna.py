@@ -183,3 +183,68 @@ def test_pna_equals_deconvolution_at_zero_threshold(pp, ctx):
     compare_sums(a.as_dict(), b.as_dict(), rtol=1e-12, context="PNA vs D O")
     a.destroy()
     b.destroy()
+
+
+# --------------------------------------------------------------------------------------
+# Most significant products only (Appendix B's heuristic conjugation).
+# --------------------------------------------------------------------------------------
+def _from_export(orc, n, x, z, c):
+    return orc.OracleSum(n, x, z, c)
+
+
+@pytest.mark.parametrize("n,m,k,q,kmax", [
+    (56, 2000, 12, -0.01, 1),
+    (56, 2000, 12, -0.01, 5000),
+    (56, 2000, 12, -0.01, 100000),
+    (56, 2000, 12, -0.01, 2000 * 144),
+    (128, 900, 30, -0.02, 40000),
+    (9, 300, 200, -0.003, 2_000_000),
+])
+def test_antinoise_topk_random(pp, ctx, orc, n, m, k, q, kmax):
+    log(f"antinoise top-k n={n} |O|={m} |E'|={k} kmax={kmax}")
+    o = W.random_pauli_sum(n, m, seed=3 * n + m, allow_duplicates=False)
+    e = W.random_pauli_sum(n, k, seed=5 * n + k, allow_duplicates=False)
+    g = pp.Observable.from_sum(ctx, o)
+    ge = pp.Observable.from_sum(ctx, e)
+    g.apply_antinoise_topk(ge, q, kmax)
+    r = orc.OracleSum.from_sum(o)
+    r.antinoise_topk(orc.OracleSum.from_sum(e), q, kmax)
+    rep = compare_sums(g.as_dict(), r.as_dict(), context="antinoise top-k")
+    log(f"  {rep}")
+    assert abs(g.expectation() - r.expectation()) < 1e-10
+    g.destroy()
+    ge.destroy()
+
+
+def test_antinoise_topk_along_a_walk(pp, ctx, orc):
+    """Every update of a PNA walk with a product limit, the oracle fed the device's own O
+    and E' before each update (identical inputs give the identical cut)."""
+    wl = W.named_workload("tfim3x3", steps=2)
+    circ = wl.circuit
+    n = circ.n_qubits
+    g = pp.Observable.from_sum(ctx, wl.observable, eps=1e-5)
+    checked = 0
+    for t, layer in enumerate(circ.layers):
+        for kk in range(0, layer.n_gen, 17):
+            e = pp.propagated_error(ctx, circ, t, kk, 1e-4)
+            qk = pp.antinoise_q(layer.lam[kk])
+            x, z, c, _ = g.export()
+            r = _from_export(orc, n, x, z, c)
+            ex, ez, ec, _ = e.export()
+            g.apply_antinoise_topk(e, qk, 400)
+            r.antinoise_topk(_from_export(orc, n, ex, ez, ec), qk, 400)
+            r.truncate(1e-5, 0)
+            compare_sums(g.as_dict(), r.as_dict(), thresholds=[1e-5], context=f"map ({t}, {kk})")
+            e.destroy()
+            checked += 1
+    log(f"  {checked} updates checked, final |O~| = {len(g)}")
+    g.destroy()
+
+
+def test_pna_topk_unlimited_equals_exact(pp, ctx):
+    wl = W.named_workload("tfim3x3", rows=2, cols=3, steps=1)
+    a = pp.pna(ctx, wl.circuit, wl.observable, max_products=10 ** 12)
+    b = pp.pna(ctx, wl.circuit, wl.observable)
+    compare_sums(a.as_dict(), b.as_dict(), rtol=0.0, atol=0.0, context="unlimited top-k vs exact")
+    a.destroy()
+    b.destroy()
