@@ -199,30 +199,36 @@ def noisy_check(ctx, wl, precision):
     return {"value": v, "ms": round(1e3 * dt, 3), "term_updates_per_s": round(upd[0] / dt, 1), "terms_out": n}
 
 
-def pna_check(ctx, cpu: bool, prefix_maps: int = 300):
+def pna_check(ctx, cpu: bool, prefix_maps: int = 300, topk=()):
     """Propagated noise absorption (Section II) on the same 7x8 lattice, angles and noise
     as the headline workload at 2 Trotter steps (4 layers, 4164 generators): every
     generator's error propagated forward through the later gates on the device (threshold
     1e-4), then absorbed into O (threshold 1e-5), one update per generator.  Timed whole,
-    once; the oracle and the device are also timed on the same prefix of the walk."""
+    uninstrumented, once, and again with per-launch HIP events for the kernel breakdown; the
+    oracle and the device are also timed on the same prefix of the walk.  Each
+    value in `topk` reruns the walk with E' O E' limited to that many most significant
+    products (Appendix B) and reports its time and the shift of <O~> from the exact walk."""
     import torch
     from paper_2606_20441_amd import pp, workloads as W
     wl = W.named_workload("tfim7x8_pna", steps=2)
     eps, eps_fwd = wl.eps, 1e-4
     circ = wl.circuit
     n_maps = sum(l.n_gen for l in circ.layers)
-    ctx.timing(True)
-    ctx.timing_read(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     g = pp.pna(ctx, circ, wl.observable, eps=eps, eps_fwd=eps_fwd)
     v = g.expectation()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ks = ctx.timing_read(reset=True)
-    ctx.timing(False)
     n_out = len(g)
     g.destroy()
+    # kernel breakdown from a second walk with HIP events around every launch (slower)
+    ctx.timing(True)
+    ctx.timing_read(reset=True)
+    pp.pna(ctx, circ, wl.observable, eps=eps, eps_fwd=eps_fwd).destroy()
+    torch.cuda.synchronize()
+    ks = ctx.timing_read(reset=True)
+    ctx.timing(False)
     top = sorted(ks, key=lambda k: -k["total_ms"])[:6]
     out = {"workload": "tfim7x8_pna at 2 Trotter steps: 56q, 4 layers, eps 1e-5, forward eps 1e-4, no cap",
            "maps": n_maps, "ms": round(1e3 * dt, 1), "maps_per_s": round(n_maps / dt, 1), "expectation": v,
@@ -231,6 +237,18 @@ def pna_check(ctx, cpu: bool, prefix_maps: int = 300):
     log(f"   PNA: {n_maps} maps in {1e3 * dt:.0f} ms ({n_maps / dt:.0f} maps/s), <O~> = {v!r}, {n_out} terms")
     for k in top:
         log(f"      {k['name']:24s} {k['launches']:6d} launches {k['total_ms']:9.2f} ms")
+    out["topk"] = []
+    for mp in topk:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gk = pp.pna(ctx, circ, wl.observable, eps=eps, eps_fwd=eps_fwd, max_products=int(mp))
+        vk = gk.expectation()
+        torch.cuda.synchronize()
+        dk = time.perf_counter() - t0
+        out["topk"].append({"max_products": int(mp), "ms": round(1e3 * dk, 1), "expectation": vk,
+                            "abs_shift_vs_exact": abs(vk - v), "terms_out": len(gk)})
+        gk.destroy()
+        log(f"   PNA, at most {int(mp)} products per map: {1e3 * dk:.0f} ms, <O~> = {vk!r} (shift {abs(vk - v):.3e})")
     if cpu:
         from oracle import oracle
         maps = [(t, k) for t, l in enumerate(circ.layers) for k in range(l.n_gen)][:prefix_maps]
@@ -324,6 +342,7 @@ def main():
                     help="skip propagating O~ back through the noisy circuit")
     ap.add_argument("--no-pna", action="store_true", help="skip the propagated-noise-absorption leg")
     ap.add_argument("--pna-only", action="store_true", help="run only the propagated-noise-absorption leg")
+    ap.add_argument("--pna-topk", default="", help="comma-separated product limits for extra PNA walks")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--serve-requests", type=int, default=30,
                     help="measured requests of the serving stream per arrival rate (0: skip it)")
@@ -352,7 +371,8 @@ def main():
     wl = W.named_workload(args.workload, **({} if args.max_terms is None else {"max_terms": args.max_terms}))
     ctx = pp.Context(0)
     if args.pna_only:
-        print(json.dumps({"pna": pna_check(ctx, not args.no_cpu)}), flush=True)
+        tk = [int(v) for v in args.pna_topk.split(",") if v]
+        print(json.dumps({"pna": pna_check(ctx, not args.no_cpu, topk=tk)}), flush=True)
         ctx.close()
         return
     Wd = wl.circuit.W
