@@ -185,7 +185,43 @@ def _circuit_arrays(circuit):
     return ng, nk, gx, gz, th, ex, ez, lam
 
 
-MODES = {"greedy": 0, "error_order": 1}
+MODES = {"greedy": 0, "error_order": 1, "sine_order": 2}
+
+
+def interaction_picture(circuit):
+    """The Clifford interaction picture of the Euclid appendix: every rotation angle theta
+    is split into its nearest multiple m pi/2 (an exact Clifford rotation about the same
+    Pauli, applied first; the two commute) and a residual with |theta'| <= pi/4, so every
+    sine the expansion counts is at most 1/sqrt 2.  A whole turn (m = 0 mod 4) is only a
+    phase under conjugation and is left out; Clifford angles are kept as they are."""
+    import copy
+    import math
+    out = copy.deepcopy(circuit)
+    half = math.pi / 2
+    for layer in out.layers:
+        if layer.n_gates == 0:
+            continue
+        gx = np.asarray(layer.gx, np.uint64).reshape(layer.n_gates, -1)
+        gz = np.asarray(layer.gz, np.uint64).reshape(layer.n_gates, -1)
+        xs, zs, th = [], [], []
+        for g in range(layer.n_gates):
+            t = float(layer.theta[g])
+            m = round(t / half)
+            r = t - m * half
+            if abs(r) <= 1e-12 * half:
+                parts = [t]
+            elif m % 4 == 0:
+                parts = [r]
+            else:
+                parts = [m * half, r]
+            for a in parts:
+                xs.append(gx[g])
+                zs.append(gz[g])
+                th.append(a)
+        layer.gx = np.array(xs, np.uint64).reshape(len(th), -1)
+        layer.gz = np.array(zs, np.uint64).reshape(len(th), -1)
+        layer.theta = np.array(th, np.float64)
+    return out
 
 
 def noise_canceling(circuit, observable, eps: float = 0.0, max_terms: int = 0,

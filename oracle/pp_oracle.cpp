@@ -151,7 +151,11 @@ void threshold(Map& m, double eps) {
 //   forward  U P U^dag = cos(theta) P - sin(theta) (i R P)
 //   backward U^dag P U = cos(theta) P + sin(theta) (i R P)
 // and duplicated strings are accumulated (Appendix B's A'[P'] += c').
-int rotate(or_sum* s, const uint64_t* rx, const uint64_t* rz, double theta, int dir) {
+// With sine_max >= 0 (the sine-order mode) the tag counts the sine factors along a term's
+// path, the CPT order kappa = k + 2p of the Euclid appendix (k steps, p bubbles, each step
+// one sin): the sin child of a non-Clifford rotation gets tag + 1 and is dropped above
+// sine_max.  Clifford rotations are exact frame changes and do not count.
+int rotate(or_sum* s, const uint64_t* rx, const uint64_t* rz, double theta, int dir, int sine_max = -1) {
   if (dir != 1 && dir != -1) fail("dir must be +1 or -1");
   double cs, sn;
   const int clifford = angle_cos_sin(theta, &cs, &sn);
@@ -169,6 +173,10 @@ int rotate(or_sum* s, const uint64_t* rx, const uint64_t* rz, double theta, int 
       Key q;
       const int sg = irp_sign(p, rx, rz, s->W, &q);
       const double child = (dir == 1 ? 1.0 : -1.0) * sg * c;
+      if (sine_max >= 0 && !clifford) {
+        if (p.o + 1 > sine_max) continue;
+        q.o = (uint8_t)(p.o + 1);
+      }
       out[q] += child * sn;
     }
   }
@@ -234,7 +242,7 @@ void noise(or_sum* s, int n_gen, const uint64_t* ex, const uint64_t* ez, const d
     }
     return;
   }
-  if (mode != 1) fail("mode must be 0 or 1");
+  if (mode != 1) fail("noise mode must be 0 or 1");
   if (max_order < 0 || max_order > 255) fail("max_order out of range");
   // prod_k (1 + x_k) over anticommuting k, x_k = f_k - 1, written as sum_j e_j with e_j the
   // elementary symmetric polynomial of degree j in those x_k; a term of order o receives
@@ -403,11 +411,12 @@ void apply_layer(or_sum* s, int n_gates, const uint64_t* gx, const uint64_t* gz,
   // at most max_terms of the largest |c| are kept.  Reading used here: both are applied
   // after every non-Clifford gate (merge, then threshold, then cap), and in the error-order
   // mode also after the noise layer.  Clifford gates and the greedy mode's inverse noise
-  // never lower a magnitude, so nothing is truncated after them.
+  // never lower a magnitude, so nothing is truncated after them.  Mode 2 (sine order)
+  // rescales like the greedy mode and counts sines in the tag (see rotate).
   const bool truncating = eps > 0.0 || max_terms > 0;
   auto do_noise = [&]() {
     if (n_gen <= 0) return;
-    noise(s, n_gen, ex, ez, lambda, noise_sign, mode, max_order);
+    noise(s, n_gen, ex, ez, lambda, noise_sign, mode == 2 ? 0 : mode, max_order);
     if (mode == 1 && truncating) truncate(s, eps, max_terms);
   };
   if (!noise_after_gates) do_noise();
@@ -415,7 +424,7 @@ void apply_layer(or_sum* s, int n_gates, const uint64_t* gx, const uint64_t* gz,
   // first, so the backward pass walks the list in reverse; the forward pass in order.
   for (int i = 0; i < n_gates; ++i) {
     const int g = dir == 1 ? n_gates - 1 - i : i;
-    const int clifford = rotate(s, gx + (size_t)g * W, gz + (size_t)g * W, theta[g], dir);
+    const int clifford = rotate(s, gx + (size_t)g * W, gz + (size_t)g * W, theta[g], dir, mode == 2 ? max_order : -1);
     if (!clifford && truncating) truncate(s, eps, max_terms);
   }
   if (noise_after_gates) do_noise();

@@ -70,7 +70,9 @@ void    or_antinoise_topk(or_sum* s, const or_sum* eprime, double q, int64_t k);
  *   [noise if !noise_after_gates] ; gates (dir = +1: reverse list order, U^dag P U;
  *   dir = -1: list order, U P U^dag), after every non-Clifford gate: drop |c| < eps, then
  *   keep the max_terms largest (max_terms > 0) ; [noise if noise_after_gates].  In mode 1
- *   the same truncation follows the noise.  n_gates or n_gen may be 0. */
+ *   the same truncation follows the noise.  Mode 2 (sine order): noise as in mode 0, and
+ *   the tag counts the sine factors of a term's path (the sin child of a non-Clifford
+ *   rotation gets tag + 1; tags above max_order are dropped).  n_gates or n_gen may be 0. */
 void    or_apply_layer(or_sum* s, int n_gates, const uint64_t* gx, const uint64_t* gz,
                        const double* theta, int dir, int n_gen, const uint64_t* ex,
                        const uint64_t* ez, const double* lambda, int noise_sign,

@@ -643,3 +643,104 @@ def test_antinoise_topk_keeps_ties_with_the_cut(oracle_lib):
     c = oracle_lib.OracleSum.from_sum(o)
     c.antinoise_topk(oracle_lib.OracleSum.from_sum(e), -0.05, k - 1)
     assert c.as_dict() != a.as_dict()
+
+
+# --------------------------------------------------------------------------------------
+# Sine order (Euclid appendix: CPT order kappa = k + 2p, in the Clifford interaction
+# picture): a term's tag counts the sine factors along its path.
+# --------------------------------------------------------------------------------------
+def _sine_series(circuit, obs_matrix, K):
+    """D O as a polynomial in a formal s that multiplies every non-Clifford sine, on
+    explicit matrices and in the propagation's order (backward through G_M .. G_2, the first
+    layer's inverse noise, then forward through G_m and N_m^{-1}); coefficients of s^0..s^K.
+    A rotation splits M into the parts commuting (Mc) and anticommuting (Ma) with R:
+    U M U^dag = Mc + cos Ma - sin (i R Ma), U^dag M U = Mc + cos Ma + sin (i R Ma)."""
+    B = _brute()
+    n = circuit.n_qubits
+    layers = [B._layer_ops(n, l) for l in circuit.layers]
+
+    def gate(poly, r, th, sign):
+        k = th / (math.pi / 2)
+        clifford = abs(k - round(k)) < 1e-12
+        c, s = (float(np.cos(th)), float(np.sin(th)))
+        if clifford:
+            c, s = [(1, 0), (0, 1), (-1, 0), (0, -1)][int(round(k)) % 4]
+        out = [np.zeros_like(poly[0]) for _ in poly]
+        for j, m in enumerate(poly):
+            rmr = r.conj(m)
+            mc, ma = (m + rmr) / 2, (m - rmr) / 2
+            sin_part = sign * s * 1j * r.left(ma)
+            out[j] = out[j] + mc + c * ma
+            if clifford:
+                out[j] = out[j] + sin_part
+            elif j + 1 <= K:
+                out[j + 1] = out[j + 1] + sin_part
+        return out
+
+    poly = [obs_matrix.copy()] + [np.zeros_like(obs_matrix) for _ in range(K)]
+    for gates, gens, lam in reversed(layers[1:]):
+        for r, th in reversed(gates):
+            poly = gate(poly, r, th, +1)
+    g0 = layers[0]
+    if g0[1]:
+        poly = [B.channel(m, g0[1], g0[2], -1) for m in poly]
+    for gates, gens, lam in layers[1:]:
+        for r, th in gates:
+            poly = gate(poly, r, th, -1)
+        if gens:
+            poly = [B.channel(m, gens, lam, -1) for m in poly]
+    return poly
+
+
+def test_sine_split_matches_conjugation(oracle_lib):
+    B = _brute()
+    n = 3
+    o = W.random_pauli_sum(n, 6, seed=70)
+    m = B.pauli_sum_matrix(n, o.x, o.z, o.c)
+    r = B.PauliOp(n, np.array([5], np.uint64), np.array([3], np.uint64))
+    th = 0.61
+    rmr = r.conj(m)
+    mc, ma = (m + rmr) / 2, (m - rmr) / 2
+    assert np.allclose(B.conj_forward(m, r, th), mc + np.cos(th) * ma - np.sin(th) * 1j * r.left(ma), atol=1e-13)
+    assert np.allclose(B.conj_backward(m, r, th), mc + np.cos(th) * ma + np.sin(th) * 1j * r.left(ma), atol=1e-13)
+
+
+@pytest.mark.parametrize("case", ["lattice2x2", "lattice2x3", "random4"])
+def test_sine_order_tags_against_series(oracle_lib, case):
+    """Tag j of the sine-order propagation equals the s^j coefficient of the matrix series,
+    for every j <= K; the interaction picture leaves the unitary unchanged; summing all tags
+    at a large K gives D O."""
+    B = _brute()
+    if case == "random4":
+        circ = _small_random_circuit(4, 3, 4, 3, seed=21)
+        # mixed angles: some Clifford, some beyond pi/4 (split by the interaction picture)
+        for i, layer in enumerate(circ.layers):
+            th = np.array(layer.theta, np.float64)
+            th[0] = math.pi / 2
+            th[1] = 1.3 + 0.1 * i
+            layer.theta = th
+        obs = W.pauli_sum(4, [({0: "Z", 3: "X"}, 0.8), ({2: "Y"}, -0.5)])
+    else:
+        wl = W.named_workload("tfim3x3", rows=2, cols=2 if case == "lattice2x2" else 3, steps=1)
+        circ, obs = wl.circuit, wl.observable
+    n = circ.n_qubits
+    ip = oracle_lib.interaction_picture(circ)
+    assert all(abs(t) <= math.pi / 4 + 1e-12 or abs(t / (math.pi / 2) - round(t / (math.pi / 2))) < 1e-12
+               for l in ip.layers for t in l.theta)
+    om = B.pauli_sum_matrix(n, obs.x, obs.z, obs.c)
+    assert np.allclose(B.deconvolved_observable(ip, om), B.deconvolved_observable(circ, om), atol=1e-12)
+    K = 3
+    res = oracle_lib.noise_canceling(ip, obs, mode="sine_order", max_order=K)
+    series = _sine_series(ip, om, K)
+    got = res.as_dict()
+    for j in range(K + 1):
+        want = _dict_from_decomp(B.pauli_decompose(series[j], n, tol=1e-13), n)
+        mine = {(k[0], k[1]): v for k, v in got.items() if k[2] == j}
+        _assert_same_sum(mine, want, 1e-12)
+    assert all(k[2] <= K for k in got)
+    full = oracle_lib.noise_canceling(ip, obs, mode="sine_order", max_order=200).as_dict()
+    tot = {}
+    for k, v in full.items():
+        tot[(k[0], k[1])] = tot.get((k[0], k[1]), 0.0) + v
+    want = _dict_from_decomp(B.pauli_decompose(B.deconvolved_observable(circ, om), n, tol=1e-13), n)
+    _assert_same_sum(tot, want, 1e-12)
