@@ -61,8 +61,16 @@ typedef enum { PP_F64 = 0, PP_F32_KAHAN = 1 } pp_precision;
  * expanded in powers of the x_k: a term of order o receives the degree-j elementary
  * symmetric sum of its anticommuting x_k at order o + j, orders above max_order are
  * dropped, and terms are merged by (string, order) (the expansion in the number of
- * errors of Appendix C; the Euclid appendix's first-order form 1/f ~ 1 + eps). */
-typedef enum { PP_MODE_GREEDY = 0, PP_MODE_ERROR_ORDER = 1 } pp_mode;
+ * errors of Appendix C; the Euclid appendix's first-order form 1/f ~ 1 + eps).
+ * PP_MODE_SINE_ORDER: the tag counts the sine factors along a term's path, the CPT order
+ * kappa = k + 2p of the Euclid appendix (k steps and p bubbles, one sine per step): the
+ * sin child of a non-Clifford rotation gets tag + 1 and is dropped above max_order
+ * (0..250), Clifford rotations do not count, the noise rescales as in PP_MODE_GREEDY, and
+ * terms merge by (string, tag).  Every gate takes the per-gate sort-and-merge path.  The
+ * caller writes the circuit in the Clifford interaction picture (each angle split into a
+ * multiple of pi/2 and a residual of at most pi/4) so that every counted sine is at most
+ * 1/sqrt 2; <O~> sums all tags. */
+typedef enum { PP_MODE_GREEDY = 0, PP_MODE_ERROR_ORDER = 1, PP_MODE_SINE_ORDER = 2 } pp_mode;
 
 /* Direction of a gate layer.  PP_HEISENBERG: P -> U^dag P U = cos P + sin (i R P) for
  * anticommuting P (backward rule of the Euclid appendix); gates are applied in reverse

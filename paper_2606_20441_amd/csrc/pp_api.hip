@@ -725,14 +725,14 @@ struct Engine final : EngineBase {
 
   // ---- per-gate path on a subset (sa holds m terms) ------------------------------------------
   uint64_t per_gate(uint64_t m, const std::vector<GateDev>& gates, double eps, const NoiseDev* nd,
-                    double eps_noise, double* dropped_dev, uint64_t* peak_out = nullptr) {
+                    double eps_noise, double* dropped_dev, uint64_t* peak_out = nullptr, int sine_max = -1) {
     uint64_t gate_peak = m;
     for (const GateDev& G : gates) {
       if (m == 0) break;
       sb.ensure(2 * m);
       const Terms<CT> in = sa.view(), out = sb.view();
       ctx->run("expand_gate", 0, (double)m, [&] {
-        hipLaunchKernelGGL((k_expand_gate<W, CT, ORD>), grid1(m), dim3(256), 0, st, in, m, G, out);
+        hipLaunchKernelGGL((k_expand_gate<W, CT, ORD>), grid1(m), dim3(256), 0, st, in, m, G, out, sine_max);
       });
       ctx->check_launch();
       sa.swap(sb);
@@ -1681,7 +1681,40 @@ struct Engine final : EngineBase {
     }
   }
 
+  // Sine-order mode: greedy noise, and every gate through the per-gate path, whose
+  // expansion counts the sines of non-Clifford gates in the tag; threshold and cap after
+  // every non-Clifford gate.
+  void sine_order_layer(const pp_layer* L) {
+    pp_layer_stats ls{};
+    ls.n_in = (int64_t)N;
+    auto noise = [&]() {
+      if (L->n_gen <= 0) return;
+      HostNoise hn = prepare_noise(L, PP_MODE_GREEDY, 0);
+      NoiseDev nd = upload_noise(hn, L->noise_sign, PP_MODE_GREEDY, 0);
+      if (N) noise_greedy(cur.view(), N, nd, "noise");
+    };
+    if (!L->noise_after_gates) noise();
+    for (const HostGate& h : prepare_gates(L)) {
+      if (N == 0) break;
+      cur.swap(sa);
+      const uint64_t m = per_gate(N, {h.g}, obs->trunc.eps, nullptr, 0.0, nullptr, nullptr, obs->trunc.max_order);
+      cur.swap(sa);
+      N = m;
+      ls.n_peak = std::max(ls.n_peak, (int64_t)N);
+      if (!h.g.clifford && obs->trunc.max_terms > 0 && (int64_t)N > obs->trunc.max_terms)
+        cap_select((uint64_t)obs->trunc.max_terms, ls);
+    }
+    if (L->noise_after_gates) noise();
+    ls.n_out = (int64_t)N;
+    ls.n_peak = std::max(ls.n_peak, std::max(ls.n_in, ls.n_out));
+    obs->last = ls;
+  }
+
   void apply_layer(const pp_layer* L) override {
+    if (obs->mode == PP_MODE_SINE_ORDER) {
+      sine_order_layer(L);
+      return;
+    }
     pp_layer_stats ls{};
     ls.n_in = (int64_t)N;
     // threshold (and cap) after every non-Clifford gate
@@ -2070,7 +2103,7 @@ struct Engine final : EngineBase {
 template <int W>
 EngineBase* make_engine_w(pp_obs* o) {
   const bool f32 = o->prec == PP_F32_KAHAN;
-  const bool ord = o->mode == PP_MODE_ERROR_ORDER;
+  const bool ord = o->mode != PP_MODE_GREEDY;
   if (!f32 && !ord) return new Engine<W, double, false>(o);
   if (!f32 && ord) return new Engine<W, double, true>(o);
   if (f32 && !ord) return new Engine<W, float, false>(o);
@@ -2168,7 +2201,11 @@ pp_status pp_create_observable(pp_ctx* ctx, int n_qubits, int64_t n_terms, const
   if (n_terms < 0 || n_terms >= (1LL << 31)) { g_last_error = "n_terms out of range"; return PP_ERR_INVALID; }
   if (n_terms > 0 && (!x || !z || !coeff)) { g_last_error = "NULL term array"; return PP_ERR_INVALID; }
   if (precision != PP_F64 && precision != PP_F32_KAHAN) { g_last_error = "bad precision"; return PP_ERR_INVALID; }
-  if (mode != PP_MODE_GREEDY && mode != PP_MODE_ERROR_ORDER) { g_last_error = "bad mode"; return PP_ERR_INVALID; }
+  if (mode != PP_MODE_GREEDY && mode != PP_MODE_ERROR_ORDER && mode != PP_MODE_SINE_ORDER) { g_last_error = "bad mode"; return PP_ERR_INVALID; }
+  if (mode == PP_MODE_SINE_ORDER && (trunc.max_order < 0 || trunc.max_order > 250)) {
+    g_last_error = "max_order must be in 0..250 in the sine-order mode";
+    return PP_ERR_INVALID;
+  }
   if (!(trunc.eps >= 0.0) || !std::isfinite(trunc.eps)) { g_last_error = "eps must be finite and >= 0"; return PP_ERR_INVALID; }
   if (trunc.max_terms < 0) { g_last_error = "max_terms must be >= 0"; return PP_ERR_INVALID; }
   if (mode == PP_MODE_ERROR_ORDER && (trunc.max_order < 0 || trunc.max_order > kMaxPowerSums)) {

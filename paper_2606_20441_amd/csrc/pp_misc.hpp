@@ -10,10 +10,11 @@ namespace pp {
 // ------------------------------------------------------------------------------------------
 // Per-gate path (tiles that outgrow LDS, and general gates): every term writes two slots --
 // itself (cos part, or unchanged if it commutes) and its sin child (or a zero placeholder) --
-// then a canonical sort and a segmented sum merge equal strings.
+// then a canonical sort and a segmented sum merge equal strings.  sine_max >= 0 (sine-order
+// mode): the sin child of a non-Clifford gate carries tag + 1 and is zeroed above sine_max.
 // ------------------------------------------------------------------------------------------
 template <int W, class CT, bool ORD>
-__global__ void k_expand_gate(Terms<CT> in, uint64_t n, GateDev G, Terms<CT> out) {
+__global__ void k_expand_gate(Terms<CT> in, uint64_t n, GateDev G, Terms<CT> out, int sine_max) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint64_t kx[W], kz[W], m[2 * W];
@@ -23,6 +24,7 @@ __global__ void k_expand_gate(Terms<CT> in, uint64_t n, GateDev G, Terms<CT> out
   for (int w = 0; w < 2 * W; ++w) m[w] = G.m[w];
   const double c = (double)in.c[i];
   const uint8_t o = ORD ? in.o[i] : 0;
+  uint8_t ob = o;
   const uint64_t a = 2 * i, b = 2 * i + 1;
   double ca = c, cb = 0.0;
   uint64_t bx[W], bz[W];
@@ -35,6 +37,10 @@ __global__ void k_expand_gate(Terms<CT> in, uint64_t n, GateDev G, Terms<CT> out
       cb = (neg ? -c : c) * G.sn_dir;
 #pragma unroll
       for (int w = 0; w < W; ++w) { bx[w] = kx[w] ^ m[w]; bz[w] = kz[w] ^ m[W + w]; }
+      if (ORD && sine_max >= 0 && !G.clifford) {
+        ob = (uint8_t)(o + 1);
+        if ((int)ob > sine_max) cb = 0.0;
+      }
     }
   }
 #pragma unroll
@@ -46,7 +52,7 @@ __global__ void k_expand_gate(Terms<CT> in, uint64_t n, GateDev G, Terms<CT> out
   }
   out.c[a] = (CT)ca;
   out.c[b] = (CT)cb;
-  if (ORD) { out.o[a] = o; out.o[b] = o; }
+  if (ORD) { out.o[a] = o; out.o[b] = ob; }
 }
 
 // Error-order noise for the per-gate path: term (P, o) writes M+1 slots (P, o+j, c e_j) for

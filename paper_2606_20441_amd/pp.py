@@ -20,11 +20,11 @@ LIB_PATH = os.path.join(HERE, "libpp.so")
 
 PP_OK, PP_ERR_INVALID, PP_ERR_OOM, PP_ERR_DEVICE, PP_ERR_UNSUPPORTED = 0, 1, 2, 3, 4
 PP_F64, PP_F32_KAHAN = 0, 1
-PP_MODE_GREEDY, PP_MODE_ERROR_ORDER = 0, 1
+PP_MODE_GREEDY, PP_MODE_ERROR_ORDER, PP_MODE_SINE_ORDER = 0, 1, 2
 PP_HEISENBERG, PP_FORWARD = 1, -1
 
 PRECISIONS = {"f64": PP_F64, "f32k": PP_F32_KAHAN}
-MODES = {"greedy": PP_MODE_GREEDY, "error_order": PP_MODE_ERROR_ORDER}
+MODES = {"greedy": PP_MODE_GREEDY, "error_order": PP_MODE_ERROR_ORDER, "sine_order": PP_MODE_SINE_ORDER}
 
 
 class PPError(RuntimeError):
@@ -321,6 +321,37 @@ class Observable:
         s = pp_layer_stats()
         _check(lib().pp_last_layer_stats(self._h, C.byref(s)))
         return {k: getattr(s, k) for k, _ in pp_layer_stats._fields_}
+
+
+def interaction_picture(circuit):
+    """Rewrite a circuit in the Clifford interaction picture (Euclid appendix): a rotation
+    by theta about R becomes a rotation by the nearest multiple of pi/2 (exact, Clifford)
+    followed by one by the remainder, |remainder| <= pi/4 (they commute).  Whole turns are a
+    phase under conjugation and are dropped; exact Clifford angles stay single gates.  Used
+    with mode="sine_order", where only the remainders' sines are counted."""
+    import copy
+    q = math.pi / 2
+    new = copy.deepcopy(circuit)
+    for layer in new.layers:
+        G = layer.n_gates
+        if G == 0:
+            continue
+        rows_x = np.asarray(layer.gx, np.uint64).reshape(G, -1)
+        rows_z = np.asarray(layer.gz, np.uint64).reshape(G, -1)
+        keep, angles = [], []
+        for g, th in enumerate(np.asarray(layer.theta, np.float64)):
+            k = int(np.rint(th / q))
+            rest = float(th) - k * q
+            exact = abs(rest) <= 1e-12 * q
+            if not exact and k % 4:
+                keep.append(g)
+                angles.append(k * q)
+            keep.append(g)
+            angles.append(float(th) if exact else rest)
+        layer.gx = rows_x[keep]
+        layer.gz = rows_z[keep]
+        layer.theta = np.asarray(angles, np.float64)
+    return new
 
 
 def noise_canceling(ctx: Context, circuit, observable, eps: float = 0.0, max_terms: int = 0,
