@@ -277,6 +277,27 @@ def pna_check(ctx, cpu: bool, prefix_maps: int = 300, topk=()):
     return out
 
 
+def sine_order_check(ctx, wl, orders):
+    """The headline propagation in the sine-order mode (Euclid appendix, CPT order), circuit
+    in the Clifford interaction picture, for each tag limit K: time, term count and <O~>."""
+    import torch
+    from paper_2606_20441_amd import pp
+    ip = pp.interaction_picture(wl.circuit)
+    out = []
+    for K in orders:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = pp.noise_canceling(ctx, ip, wl.observable, eps=wl.eps, max_terms=wl.max_terms, mode="sine_order",
+                               max_order=int(K))
+        v = g.expectation()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out.append({"max_sine_order": int(K), "ms": round(1e3 * dt, 1), "terms_out": len(g), "expectation": v})
+        log(f"   sine order <= {int(K)}: {1e3 * dt:.0f} ms, {len(g)} terms, <O~> = {v!r}")
+        g.destroy()
+    return out
+
+
 def cpu_baseline(wl, budget_s=15.0):
     """The FP64 CPU reference (single thread) on a bounded prefix of the same propagation:
     layer calls in the same order until the time budget is spent."""
@@ -343,6 +364,8 @@ def main():
     ap.add_argument("--no-pna", action="store_true", help="skip the propagated-noise-absorption leg")
     ap.add_argument("--pna-only", action="store_true", help="run only the propagated-noise-absorption leg")
     ap.add_argument("--pna-topk", default="", help="comma-separated product limits for extra PNA walks")
+    ap.add_argument("--sine-orders", default="", help="comma-separated CPT-order limits: run only the "
+                    "workload in the sine-order mode for each")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--serve-requests", type=int, default=30,
                     help="measured requests of the serving stream per arrival rate (0: skip it)")
@@ -370,6 +393,11 @@ def main():
     pp.lib()
     wl = W.named_workload(args.workload, **({} if args.max_terms is None else {"max_terms": args.max_terms}))
     ctx = pp.Context(0)
+    if args.sine_orders:
+        so = sine_order_check(ctx, wl, [int(v) for v in args.sine_orders.split(",") if v])
+        print(json.dumps({"sine_order": so, "workload": args.workload}), flush=True)
+        ctx.close()
+        return
     if args.pna_only:
         tk = [int(v) for v in args.pna_topk.split(",") if v]
         print(json.dumps({"pna": pna_check(ctx, not args.no_cpu, topk=tk)}), flush=True)
