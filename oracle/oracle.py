@@ -50,6 +50,7 @@ def _lib():
                                            _u64p, _u64p, _f64p, C.c_double, C.c_int64, C.c_int, C.c_int]
         lib.or_antinoise.argtypes = [C.c_void_p, C.c_void_p, C.c_double]
         lib.or_antinoise_topk.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_int64]
+        lib.or_antinoise_batch.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_void_p), _f64p, C.c_int]
         lib.or_expectation.restype = C.c_double
         lib.or_expectation.argtypes = [C.c_void_p, _u64p]
         lib.or_norm2.restype = C.c_double
@@ -127,6 +128,13 @@ class OracleSum:
     def antinoise(self, eprime: "OracleSum", q: float) -> None:
         """O -> (1 - q) O + q E' O E' (Section II, Eq. applyantinoise); no truncation."""
         _lib().or_antinoise(self._h, eprime._h, float(q))
+
+    def antinoise_batch(self, eprimes, qs, order: int = 1) -> None:
+        """A batch of commuting antinoise maps to first or second order in the number of
+        errors (Appendix C); exact for one map."""
+        hs = (C.c_void_p * len(eprimes))(*[e._h for e in eprimes])
+        qa = np.ascontiguousarray(np.asarray(qs, np.float64))
+        _lib().or_antinoise_batch(self._h, len(eprimes), hs, _p(qa, _f64p), int(order))
 
     def antinoise_topk(self, eprime: "OracleSum", q: float, k: int) -> None:
         """As ``antinoise`` with E' O E' limited to the k most significant products
@@ -266,7 +274,7 @@ def propagated_error(circuit, t: int, k: int, eps_fwd: float = 0.0, max_terms_fw
 
 
 def pna(circuit, observable, eps: float = 0.0, max_terms: int = 0, eps_fwd: float = 0.0,
-        max_terms_fwd: int = 0, max_products: int = 0) -> OracleSum:
+        max_terms_fwd: int = 0, max_products: int = 0, batch: int = 1, batch_order: int = 1) -> OracleSum:
     """Propagated noise absorption (Section II).  The hardware circuit is
     C_noisy = N_M G_M .. N_1 G_1.  Writing each ideal layer as N_t^{-1} N_t G_t and carrying
     the inverse maps to the end one at a time, from t = 1 up, through the later gates only,
@@ -276,8 +284,19 @@ def pna(circuit, observable, eps: float = 0.0, max_terms: int = 0, eps_fwd: floa
     O~ = N'_M^{-1}( .. N'_1^{-1}(O)), each generator's map being
     O -> (1 - q) O + q E' O E' (Eq. applyantinoise; a generator's maps within one layer
     commute).  After every update |c| < eps is dropped and the cap applied.  With
-    max_products > 0, E' O E' keeps only that many most significant products (Appendix B)."""
+    max_products > 0, E' O E' keeps only that many most significant products (Appendix B).
+    With batch > 1, a layer's maps are taken batch at a time, each batch expanded to
+    batch_order in the number of errors (Appendix C), then truncated once."""
     o = observable.clone() if isinstance(observable, OracleSum) else OracleSum.from_sum(observable)
+    if batch > 1:
+        for t, layer in enumerate(circuit.layers):
+            lam = np.asarray(layer.lam, np.float64)
+            for k0 in range(0, layer.n_gen, batch):
+                ks = range(k0, min(k0 + batch, layer.n_gen))
+                es = [propagated_error(circuit, t, k, eps_fwd, max_terms_fwd) for k in ks]
+                o.antinoise_batch(es, [antinoise_q(float(lam[k])) for k in ks], batch_order)
+                o.truncate(eps, max_terms)
+        return o
     for t, layer in enumerate(circuit.layers):
         for k in range(layer.n_gen):
             e = propagated_error(circuit, t, k, eps_fwd, max_terms_fwd)

@@ -402,6 +402,67 @@ void antinoise_topk(or_sum* s, const or_sum* e, double q, int64_t k) {
   s->m.swap(out);
 }
 
+// A batch of C commuting antinoise maps expanded in the number of errors (Appendix C):
+// with a_c = q_c / (1 - q_c) and C_c(X) = E'_c X E'_c, the exact product
+// prod_c (1 - q_c)(1 + a_c C_c) O is approximated by
+//   O0 = O prod_c (1 - q_c),   O1 = sum_c a_c C_c(O0),
+//   O2 = 1/2 sum_c (a_c C_c(O1) - a_c^2 O0)      (order 2 only),
+// returning O0 + O1 (+ O2).  Reading: the appendix's overbarred error carries the factor
+// whose square is q/(1 - q), negative for an inverse map, which is what the exact product
+// gives; its printed |q| drops that sign.  C = 1 is exact.  Each C_c is the plain double
+// sum over ordered pairs (as in antinoise).
+Map conj_sum(const Map& x, const or_sum* e, double scale, int W) {
+  std::unordered_map<Key, std::complex<double>, KeyHash> acc;
+  static const std::complex<double> ipow[4] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}};
+  std::vector<std::pair<Key, double>> ev(e->m.begin(), e->m.end());
+  for (const auto& kv : x)
+    for (const auto& ea : ev)
+      for (const auto& eb : ev) {
+        Key t, r;
+        const int k1 = pauli_mul(ea.first, kv.first, W, &t);
+        const int k2 = pauli_mul(t, eb.first, W, &r);
+        r.o = kv.first.o;
+        acc[r] += scale * ea.second * eb.second * kv.second * ipow[(k1 + k2) & 3];
+      }
+  Map out;
+  for (const auto& kv : acc) {
+    if (std::fabs(kv.second.imag()) > 1e-12 * std::max(1.0, std::fabs(scale))) fail("E' X E' is not Hermitian");
+    if (kv.second.real() != 0.0) out.emplace(kv.first, kv.second.real());
+  }
+  return out;
+}
+
+void antinoise_batch(or_sum* s, int C, const or_sum* const* e, const double* q, int order) {
+  if (C < 1) fail("a batch needs at least one map");
+  if (order != 1 && order != 2) fail("order must be 1 or 2");
+  const int W = s->W;
+  double p0 = 1.0;
+  for (int c = 0; c < C; ++c) {
+    if (e[c]->W != s->W || e[c]->n != s->n) fail("E' and O must have the same qubit count");
+    p0 *= 1.0 - q[c];
+  }
+  Map o0;
+  for (const auto& kv : s->m) o0[kv.first] = kv.second * p0;
+  Map o1;
+  for (int c = 0; c < C; ++c) {
+    const double a = q[c] / (1.0 - q[c]);
+    for (const auto& kv : conj_sum(o0, e[c], a, W)) o1[kv.first] += kv.second;
+  }
+  Map out = o0;
+  for (const auto& kv : o1) out[kv.first] += kv.second;
+  if (order == 2) {
+    double a2 = 0.0;
+    for (int c = 0; c < C; ++c) {
+      const double a = q[c] / (1.0 - q[c]);
+      a2 += a * a;
+      for (const auto& kv : conj_sum(o1, e[c], 0.5 * a, W)) out[kv.first] += kv.second;
+    }
+    for (const auto& kv : o0) out[kv.first] -= 0.5 * a2 * kv.second;
+  }
+  erase_zeros(out);
+  s->m.swap(out);
+}
+
 void apply_layer(or_sum* s, int n_gates, const uint64_t* gx, const uint64_t* gz, const double* theta,
                  int dir, int n_gen, const uint64_t* ex, const uint64_t* ez, const double* lambda,
                  int noise_sign, int noise_after_gates, double eps, int64_t max_terms, int mode,
@@ -491,6 +552,10 @@ void or_noise(or_sum* s, int n_gen, const uint64_t* ex, const uint64_t* ez, cons
 void or_truncate(or_sum* s, double eps, int64_t max_terms) { truncate(s, eps, max_terms); }
 
 void or_antinoise(or_sum* s, const or_sum* eprime, double q) { antinoise(s, eprime, q); }
+
+void or_antinoise_batch(or_sum* s, int C, const or_sum* const* eprimes, const double* q, int order) {
+  antinoise_batch(s, C, eprimes, q, order);
+}
 
 void or_antinoise_topk(or_sum* s, const or_sum* eprime, double q, int64_t k) {
   antinoise_topk(s, eprime, q, k);

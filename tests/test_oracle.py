@@ -744,3 +744,46 @@ def test_sine_order_tags_against_series(oracle_lib, case):
         tot[(k[0], k[1])] = tot.get((k[0], k[1]), 0.0) + v
     want = _dict_from_decomp(B.pauli_decompose(B.deconvolved_observable(circ, om), n, tol=1e-13), n)
     _assert_same_sum(tot, want, 1e-12)
+
+
+# --------------------------------------------------------------------------------------
+# Batches of antinoise maps expanded in the number of errors (Appendix C).
+# --------------------------------------------------------------------------------------
+def test_antinoise_batch_against_matrices(oracle_lib):
+    """Errors of one layer evolved through a small circuit (so E'^2 = 1 and the maps
+    commute): the batch equals O0 + O1 (+ O2) on explicit matrices; O2 from the appendix's
+    commuting-maps formula equals the plain sum over pairs c1 < c2; the second-order batch
+    is far closer to the exact serial product than the first; a single map is exact."""
+    B = _brute()
+    n = 4
+    circ = _small_random_circuit(n, 3, 4, 6, seed=17)
+    obs = W.pauli_sum(n, [({0: "Z", 1: "X"}, 0.9), ({3: "Y"}, -0.4)])
+    om = B.pauli_sum_matrix(n, obs.x, obs.z, obs.c)
+    t = 0
+    layer = circ.layers[t]
+    es = [oracle_lib.propagated_error(circ, t, k) for k in range(layer.n_gen)]
+    qs = [(1 - math.exp(2 * l)) / 2 * 40 for l in layer.lam]    # strong maps: visible orders
+    mats = []
+    for e in es:
+        x, z, c, _ = e.export()
+        mats.append(B.pauli_sum_matrix(n, x, z, c))
+    conj = lambda m, e: e @ m @ e
+    exact = om
+    for em, q in zip(mats, qs):
+        exact = (1 - q) * exact + q * conj(exact, em)
+    a = [q / (1 - q) for q in qs]
+    o0 = om * np.prod([1 - q for q in qs])
+    o1 = sum(ac * conj(o0, em) for ac, em in zip(a, mats))
+    o2 = 0.5 * sum(ac * conj(o1, em) - ac * ac * o0 for ac, em in zip(a, mats))
+    pairs = sum(a[i] * a[j] * conj(conj(o0, mats[i]), mats[j]) for i in range(len(a)) for j in range(i + 1, len(a)))
+    assert np.abs(o2 - pairs).max() < 1e-13
+    for order, want in ((1, o0 + o1), (2, o0 + o1 + o2)):
+        s = oracle_lib.OracleSum.from_sum(obs)
+        s.antinoise_batch(es, qs, order)
+        _assert_same_sum(_oracle_dict(s), _dict_from_decomp(B.pauli_decompose(want, n, tol=1e-14), n), 1e-13)
+    assert np.abs(exact - (o0 + o1 + o2)).max() < 0.05 * np.abs(exact - (o0 + o1)).max()
+    one = oracle_lib.OracleSum.from_sum(obs)
+    one.antinoise_batch(es[:1], qs[:1], 1)
+    ref = oracle_lib.OracleSum.from_sum(obs)
+    ref.antinoise(es[0], qs[0])
+    _assert_same_sum(_oracle_dict(one), _oracle_dict(ref), 1e-15)
