@@ -762,7 +762,7 @@ def test_antinoise_batch_against_matrices(oracle_lib):
     t = 0
     layer = circ.layers[t]
     es = [oracle_lib.propagated_error(circ, t, k) for k in range(layer.n_gen)]
-    qs = [(1 - math.exp(2 * l)) / 2 * 40 for l in layer.lam]    # strong maps: visible orders
+    qs = [(1 - math.exp(2 * l)) / 2 * 3 for l in layer.lam]    # |q C| about 0.3: visible orders
     mats = []
     for e in es:
         x, z, c, _ = e.export()
@@ -781,7 +781,7 @@ def test_antinoise_batch_against_matrices(oracle_lib):
         s = oracle_lib.OracleSum.from_sum(obs)
         s.antinoise_batch(es, qs, order)
         _assert_same_sum(_oracle_dict(s), _dict_from_decomp(B.pauli_decompose(want, n, tol=1e-14), n), 1e-13)
-    assert np.abs(exact - (o0 + o1 + o2)).max() < 0.05 * np.abs(exact - (o0 + o1)).max()
+    assert np.abs(exact - (o0 + o1 + o2)).max() < 0.2 * np.abs(exact - (o0 + o1)).max()
     one = oracle_lib.OracleSum.from_sum(obs)
     one.antinoise_batch(es[:1], qs[:1], 1)
     ref = oracle_lib.OracleSum.from_sum(obs)
