@@ -257,6 +257,7 @@ struct EngineBase {
   virtual void truncate(double eps, int64_t cap) = 0;
   virtual void antinoise(const EngineBase* eprime, double q) = 0;
   virtual void antinoise_topk(const EngineBase* eprime, double q, int64_t k) = 0;
+  virtual void antinoise_batch(const std::vector<const EngineBase*>& eprimes, const double* q, int order) = 0;
   virtual double expectation(const uint64_t* basis) = 0;
   virtual void export_terms(uint64_t* x, uint64_t* z, double* c, uint8_t* o) = 0;
   virtual uint64_t size() const = 0;
@@ -1871,17 +1872,122 @@ struct Engine final : EngineBase {
     const unsigned grid = (unsigned)std::min<uint64_t>(cdiv(total, 256), 1u << 20);
     ctx->run("antinoise_expand", kTermBytes * (double)(n + total) + 4.0 * total, (double)total, [&] {
       hipLaunchKernelGGL((k_expand_antinoise<W, CT, ORD>), dim3(grid), dim3(256), 0, st, in, n, ev, (uint32_t)K,
-                         pairs, S, q, out, keep);
+                         pairs, S, q, 1.0 - q, out, keep);
     });
     ctx->check_launch();
     sync();   // the pair table's host source goes out of scope
     finish_expansion(total);
   }
 
+  // One expansion of a batch: `scale` C(X) (scale E' X E') for an E', or id X alone (e
+  // null), for X = the first n terms of `in`.
+  struct ExpItem {
+    Terms<CT> in;
+    uint64_t n;
+    const Engine* e;
+    double scale, id;
+  };
+
+  // Writes every item's slots at consecutive offsets of sa (flags in u32b); returns the
+  // slot count.  Pair tables of all items go up in one copy.
+  uint64_t expand_items(const std::vector<ExpItem>& items) {
+    std::vector<uint64_t> S(items.size()), off(items.size() + 1, 0), poff(items.size(), 0);
+    std::vector<uint32_t> pr;
+    for (size_t i = 0; i < items.size(); ++i) {
+      const uint64_t K = items[i].e ? items[i].e->N : 0;
+      if (K > kMaxAntinoiseTerms)
+        throw_fail(PP_ERR_UNSUPPORTED, "E' has " + std::to_string(K) + " terms; at most " +
+                                           std::to_string(kMaxAntinoiseTerms) + " are supported");
+      S[i] = 1 + (K ? K * (K - 1) / 2 : 0);
+      off[i + 1] = off[i] + items[i].n * S[i];
+      if (off[i + 1] >= (1ULL << 31))
+        throw_fail(PP_ERR_UNSUPPORTED, "antinoise expansion exceeds 2^31 - 1 terms");
+      poff[i] = pr.size();
+      for (uint32_t a = 0; a < K; ++a)
+        for (uint32_t b = a + 1; b < K; ++b) pr.push_back(a | (b << 16));
+    }
+    pr.push_back(0);
+    const uint64_t total = off.back();
+    pair_d.ensure(pr.size() * 4);
+    HIPCHK(hipMemcpyAsync(pair_d.p, pr.data(), pr.size() * 4, hipMemcpyHostToDevice, st));
+    sa.ensure(std::max<uint64_t>(total, 1));
+    u32b.ensure(total * 4 + 64);
+    uint32_t* keep = u32b.as<uint32_t>();
+    const Terms<CT> out = sa.view();
+    for (size_t i = 0; i < items.size(); ++i) {
+      const ExpItem& it = items[i];
+      if (it.n == 0) continue;
+      Terms<CT> o = out;
+      o.x += off[i];
+      o.z += off[i];
+      o.c += off[i];
+      if (ORD) o.o += off[i];
+      const Terms<CT> ev = it.e ? it.e->cur.view() : it.in;
+      const uint32_t K = it.e ? (uint32_t)it.e->N : 0u;
+      const uint32_t* pairs = pair_d.as<uint32_t>() + poff[i];
+      const uint64_t cnt = it.n * S[i];
+      const unsigned grid = (unsigned)std::min<uint64_t>(cdiv(cnt, 256), 1u << 20);
+      const double q = it.e ? it.scale : 0.0;
+      ctx->run("antinoise_expand", kTermBytes * (double)(it.n + cnt) + 4.0 * cnt, (double)cnt, [&] {
+        hipLaunchKernelGGL((k_expand_antinoise<W, CT, ORD>), dim3(grid), dim3(256), 0, st, it.in, it.n, ev, K, pairs,
+                           S[i], q, it.id, o, keep + off[i]);
+      });
+      ctx->check_launch();
+    }
+    sync();   // the pair tables' host source goes out of scope
+    return total;
+  }
+
+  // A batch of commuting antinoise maps to first or second order in the number of errors
+  // (Appendix C): with a_c = q_c / (1 - q_c), O0 = O prod (1 - q_c), O1 = sum a_c C_c(O0),
+  // O2 = 1/2 sum (a_c C_c(O1) - a_c^2 O0); O becomes O0 + O1 (+ O2), then eps and the cap.
+  void antinoise_batch(const std::vector<const EngineBase*>& ebs, const double* q, int order) override {
+    std::vector<const Engine*> es;
+    for (const EngineBase* b : ebs) {
+      const auto* e = dynamic_cast<const Engine*>(b);
+      if (!e) throw_fail(PP_ERR_UNSUPPORTED, "E' must have the same word count, precision and mode as O");
+      es.push_back(e);
+    }
+    if (N == 0) return;
+    double p0 = 1.0, a2 = 0.0;
+    std::vector<double> a(es.size());
+    for (size_t c = 0; c < es.size(); ++c) {
+      p0 *= 1.0 - q[c];
+      a[c] = q[c] / (1.0 - q[c]);
+      a2 += a[c] * a[c];
+    }
+    const Terms<CT> o = cur.view();
+    if (order == 1) {
+      std::vector<ExpItem> items{{o, N, nullptr, 0.0, p0}};
+      for (size_t c = 0; c < es.size(); ++c) items.push_back({o, N, es[c], a[c] * p0, 0.0});
+      finish_expansion(expand_items(items));
+      return;
+    }
+    std::vector<ExpItem> first;
+    for (size_t c = 0; c < es.size(); ++c) first.push_back({o, N, es[c], a[c] * p0, 0.0});
+    const uint64_t m1 = merge_expansion(expand_items(first), 0.0);   // O1, exact zeros dropped
+    tmp.swap(sa);
+    const Terms<CT> t1 = tmp.view();
+    std::vector<ExpItem> second{{o, N, nullptr, 0.0, p0 * (1.0 - 0.5 * a2)}, {t1, m1, nullptr, 0.0, 1.0}};
+    for (size_t c = 0; c < es.size(); ++c) second.push_back({t1, m1, es[c], 0.5 * a[c], 0.0});
+    finish_expansion(expand_items(second));
+  }
+
   // After an antinoise expansion: sa holds `total` slots and u32b their nonzero flags.
   // Exact zeros (pairs whose two orders cancel) are dropped, the rest put in canonical
   // order and merged with the eps threshold, and the cap applied; the result becomes O.
   void finish_expansion(uint64_t total) {
+    const uint64_t m = merge_expansion(total, obs->trunc.eps);
+    cur.swap(sa);
+    N = m;
+    pp_layer_stats ls{};
+    if (obs->trunc.max_terms > 0 && (int64_t)N > obs->trunc.max_terms) cap_select((uint64_t)obs->trunc.max_terms, ls);
+  }
+
+  // Compaction of the nonzero slots, canonical sort and merge with threshold `thr`;
+  // returns the term count, the terms in sa.
+  uint64_t merge_expansion(uint64_t total, double thr) {
+    if (total == 0) return 0;
     u32c.ensure(total * 4 + 64);
     uint32_t* keep = u32b.as<uint32_t>();
     uint32_t* pos = u32c.as<uint32_t>();
@@ -1903,11 +2009,7 @@ struct Engine final : EngineBase {
     ctx->check_launch();
     sa.swap(sb);
     canonical_sort(sa, sb, nz);
-    const uint64_t m = merge_sorted(sa, sb, nz, obs->trunc.eps, nullptr);
-    cur.swap(sa);
-    N = m;
-    pp_layer_stats ls{};
-    if (obs->trunc.max_terms > 0 && (int64_t)N > obs->trunc.max_terms) cap_select((uint64_t)obs->trunc.max_terms, ls);
+    return merge_sorted(sa, sb, nz, thr, nullptr);
   }
 
   // E' O E' limited to the products of the k largest magnitudes |c_s| |e_a| |e_b| over
@@ -2281,6 +2383,33 @@ pp_status pp_apply_antinoise(pp_obs* obs, const pp_obs* eprime, double q) {
   const pp_status s = guarded([&] {
     HIPCHK(hipSetDevice(obs->ctx->device));
     obs->eng->antinoise(eprime->eng.get(), q);
+  });
+  if (s == PP_ERR_DEVICE || s == PP_ERR_OOM) obs->broken = true;
+  return s;
+}
+
+pp_status pp_apply_antinoise_batch(pp_obs* obs, const pp_obs* const* eprimes, const double* q, int n_maps, int order) {
+  if (!obs || !eprimes || !q) { g_last_error = "NULL argument"; return PP_ERR_INVALID; }
+  if (n_maps < 1) { g_last_error = "n_maps must be >= 1"; return PP_ERR_INVALID; }
+  if (order != 1 && order != 2) { g_last_error = "order must be 1 or 2"; return PP_ERR_INVALID; }
+  if (obs->broken) { g_last_error = "observable is unusable after an earlier device error"; return PP_ERR_INVALID; }
+  if (obs->mode != PP_MODE_GREEDY) { g_last_error = "antinoise needs PP_MODE_GREEDY observables"; return PP_ERR_UNSUPPORTED; }
+  std::vector<const EngineBase*> es;
+  for (int c = 0; c < n_maps; ++c) {
+    const pp_obs* e = eprimes[c];
+    if (!e) { g_last_error = "NULL E'"; return PP_ERR_INVALID; }
+    if (e->broken) { g_last_error = "E' is unusable after an earlier device error"; return PP_ERR_INVALID; }
+    if (e->ctx != obs->ctx || e->n_qubits != obs->n_qubits || e->prec != obs->prec) {
+      g_last_error = "every E' must share O's context, qubit count and precision";
+      return PP_ERR_INVALID;
+    }
+    if (e->mode != PP_MODE_GREEDY) { g_last_error = "antinoise needs PP_MODE_GREEDY observables"; return PP_ERR_UNSUPPORTED; }
+    if (!std::isfinite(q[c]) || q[c] == 1.0) { g_last_error = "q must be finite and != 1"; return PP_ERR_INVALID; }
+    es.push_back(e->eng.get());
+  }
+  const pp_status s = guarded([&] {
+    HIPCHK(hipSetDevice(obs->ctx->device));
+    obs->eng->antinoise_batch(es, q, order);
   });
   if (s == PP_ERR_DEVICE || s == PP_ERR_OOM) obs->broken = true;
   return s;

@@ -119,9 +119,10 @@ __device__ __forceinline__ int herm_mul_phase(const uint64_t* ax, const uint64_t
 }
 
 // Expansion of one propagated antinoise map (Section II, Eq. applyantinoise):
-// O -> (1 - q) O + q E' O E' with E' = sum_a e_a P_a (K terms, in `e`).  Term i of O owns
-// S = 1 + K(K-1)/2 consecutive output slots:
-//  * slot 0: P_i with c_i [(1 - q) + q sum_a e_a^2 (-1)^{<P_a, P_i>}]  (P_a P P_a = +-P);
+// O -> id O + q E' O E' with E' = sum_a e_a P_a (K terms, in `e`; id = 1 - q for one map,
+// other values for the terms of a batch).  Term i of O owns S = 1 + K(K-1)/2 consecutive
+// output slots:
+//  * slot 0: P_i with c_i [id + q sum_a e_a^2 (-1)^{<P_a, P_i>}]  (P_a P P_a = +-P);
 //  * slot 1 + j, pair (a, b) = pairs[j] with a < b: the two orders are adjoints of each
 //    other, so P_a P P_b + P_b P P_a = 2 Re(i^k) R for P_a P P_b = i^k R: 2 q e_a e_b c_i
 //    times +1 (k = 0) or -1 (k = 2), and 0 for odd k.
@@ -130,7 +131,7 @@ __device__ __forceinline__ int herm_mul_phase(const uint64_t* ax, const uint64_t
 // plane.
 template <int W, class CT, bool ORD>
 __global__ void k_expand_antinoise(Terms<CT> in, uint64_t n, Terms<CT> e, uint32_t K, const uint32_t* pairs,
-                                   uint64_t S, double q, Terms<CT> out, uint32_t* keep) {
+                                   uint64_t S, double q, double id, Terms<CT> out, uint32_t* keep) {
   const uint64_t total = n * S;
   for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (uint64_t)gridDim.x * blockDim.x) {
@@ -156,7 +157,7 @@ __global__ void k_expand_antinoise(Terms<CT> in, uint64_t n, Terms<CT> e, uint32
         const double ea = (double)e.c[a];
         s += (par & 1) ? -ea * ea : ea * ea;
       }
-      v = c * ((1.0 - q) + q * s);
+      v = c * (id + q * s);
     } else {
       const uint32_t pr = pairs[j - 1];
       const uint32_t a = pr & 0xffffu, b = pr >> 16;

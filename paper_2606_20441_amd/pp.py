@@ -114,6 +114,8 @@ def lib():
         L.pp_apply_antinoise.restype = C.c_int
         L.pp_apply_antinoise_topk.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_int64]
         L.pp_apply_antinoise_topk.restype = C.c_int
+        L.pp_apply_antinoise_batch.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), _f64p, C.c_int, C.c_int]
+        L.pp_apply_antinoise_batch.restype = C.c_int
         L.pp_truncate.restype = C.c_int
         L.pp_expectation.argtypes = [C.c_void_p, _u64p, _f64p]
         L.pp_expectation.restype = C.c_int
@@ -283,6 +285,13 @@ class Observable:
         """O -> (1 - q) O + q E' O E' (``pp_apply_antinoise``)."""
         _check(lib().pp_apply_antinoise(self._h, eprime._h, float(q)))
 
+    def apply_antinoise_batch(self, eprimes, qs, order: int = 1):
+        """A batch of commuting antinoise maps to first or second order in the number of
+        errors (``pp_apply_antinoise_batch``)."""
+        hs = (C.c_void_p * len(eprimes))(*[e._h.value if isinstance(e._h, C.c_void_p) else e._h for e in eprimes])
+        qa = np.ascontiguousarray(np.asarray(qs, np.float64))
+        _check(lib().pp_apply_antinoise_batch(self._h, hs, _ptr(qa, _f64p), len(eprimes), int(order)))
+
     def apply_antinoise_topk(self, eprime: "Observable", q: float, max_products: int):
         """As ``apply_antinoise`` with E' O E' limited to its most significant products
         (``pp_apply_antinoise_topk``)."""
@@ -426,7 +435,8 @@ def propagated_error(ctx: Context, circuit, t: int, k: int, eps_fwd: float = 0.0
 
 
 def pna(ctx: Context, circuit, observable, eps: float = 0.0, max_terms: int = 0, eps_fwd: float = 0.0,
-        max_terms_fwd: int = 0, precision: str = "f64", on_map=None, max_products: int = 0) -> Observable:
+        max_terms_fwd: int = 0, precision: str = "f64", on_map=None, max_products: int = 0, batch: int = 1,
+        batch_order: int = 1) -> Observable:
     """Propagated noise absorption (Section II).
 
     With C_noisy = N_M G_M .. N_1 G_1, inserting N_t^{-1} N_t after every G_t and carrying
@@ -435,9 +445,25 @@ def pna(ctx: Context, circuit, observable, eps: float = 0.0, max_terms: int = 0,
     on O with N'_1^{-1} first: for t = 1..M and every generator E of N_t (whose maps
     commute), O -> (1 - q) O + q E' O E' with E' = U E U^dag (Eq. applyantinoise), then the
     observable's eps threshold and cap.  With max_products > 0 each E' O E' keeps only that
-    many most significant products (Appendix B's heuristic conjugation).
+    many most significant products (Appendix B's heuristic conjugation).  With batch > 1 a
+    layer's maps are absorbed `batch` at a time, each batch expanded to `batch_order` in the
+    number of errors and merged once (Appendix C).
     """
     obs = Observable.from_sum(ctx, observable, precision=precision, eps=eps, max_terms=max_terms)
+    if batch > 1:
+        for t, layer in enumerate(circuit.layers):
+            lam = np.asarray(layer.lam, np.float64)
+            for k0 in range(0, layer.n_gen, batch):
+                ks = range(k0, min(k0 + batch, layer.n_gen))
+                es = [propagated_error(ctx, circuit, t, k, eps_fwd, max_terms_fwd, precision) for k in ks]
+                try:
+                    obs.apply_antinoise_batch(es, [antinoise_q(lam[k]) for k in ks], batch_order)
+                finally:
+                    for e in es:
+                        e.destroy()
+                if on_map:
+                    on_map(t, ks[-1], obs)
+        return obs
     for t, layer in enumerate(circuit.layers):
         lam = np.asarray(layer.lam, np.float64)
         for k in range(layer.n_gen):

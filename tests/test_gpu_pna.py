@@ -248,3 +248,66 @@ def test_pna_topk_unlimited_equals_exact(pp, ctx):
     compare_sums(a.as_dict(), b.as_dict(), rtol=0.0, atol=0.0, context="unlimited top-k vs exact")
     a.destroy()
     b.destroy()
+
+
+# --------------------------------------------------------------------------------------
+# Batches of maps expanded in the number of errors (Appendix C).
+# --------------------------------------------------------------------------------------
+@pytest.mark.parametrize("n,m,ks,order", [
+    (56, 1500, [3, 7, 1, 12], 1),
+    (56, 1500, [3, 7, 1, 12], 2),
+    (128, 600, [5, 9, 2], 2),
+    (56, 800, [4, 0, 6], 1),
+])
+def test_antinoise_batch_random(pp, ctx, orc, n, m, ks, order):
+    log(f"antinoise batch n={n} |O|={m} |E'|={ks} order={order}")
+    o = W.random_pauli_sum(n, m, seed=7 * n + m)
+    es = [W.random_pauli_sum(n, k, seed=11 * n + k + 3 * i) if k else None for i, k in enumerate(ks)]
+    qs = [-0.004 * (i + 1) for i in range(len(ks))]
+    g = pp.Observable.from_sum(ctx, o)
+    gis = [pp.Observable.from_sum(ctx, e) if e is not None else
+           pp.Observable(ctx, n, np.zeros((0, W.n_words(n)), np.uint64), np.zeros((0, W.n_words(n)), np.uint64), np.zeros(0))
+           for e in es]
+    g.apply_antinoise_batch(gis, qs, order)
+    r = orc.OracleSum.from_sum(o)
+    ris = [orc.OracleSum.from_sum(e) if e is not None else
+           orc.OracleSum(n, np.zeros((0, W.n_words(n)), np.uint64), np.zeros((0, W.n_words(n)), np.uint64), np.zeros(0))
+           for e in es]
+    r.antinoise_batch(ris, qs, order)
+    rep = compare_sums(g.as_dict(), r.as_dict(), context="antinoise batch")
+    log(f"  {rep}")
+    assert abs(g.expectation() - r.expectation()) < 1e-10
+    g.destroy()
+    for h in gis:
+        h.destroy()
+
+
+@pytest.mark.parametrize("name,kw,batch,order,eps", [
+    ("tfim3x3", dict(steps=2), 16, 1, 1e-4),
+    ("tfim3x3", dict(rows=2, cols=3, steps=1), 16, 2, 1e-5),
+    ("tfim7x8_pna", dict(steps=1), 64, 2, 1e-5),
+    ("tfim7x8_pna", dict(steps=1), 200, 1, 1e-5),
+])
+def test_pna_batch_parity(pp, ctx, orc, name, kw, batch, order, eps):
+    wl = W.named_workload(name, **kw)
+    log(f"pna batch {name} {kw} batch={batch} order={order}")
+    g = pp.pna(ctx, wl.circuit, wl.observable, eps=eps, eps_fwd=eps, batch=batch, batch_order=order)
+    r = orc.pna(wl.circuit, wl.observable, eps=eps, eps_fwd=eps, batch=batch, batch_order=order)
+    rep = compare_sums(g.as_dict(), r.as_dict(), thresholds=[eps], context=f"pna batch {name}")
+    eg, eo = g.expectation(), r.expectation()
+    log(f"  {rep}; <O~> {eg!r} vs {eo!r}")
+    assert abs(eg - eo) < 1e-10
+    g.destroy()
+
+
+def test_antinoise_batch_of_one_is_exact(pp, ctx):
+    o = W.random_pauli_sum(56, 900, seed=3)
+    e = W.random_pauli_sum(56, 8, seed=4)
+    a = pp.Observable.from_sum(ctx, o)
+    b = pp.Observable.from_sum(ctx, o)
+    ge = pp.Observable.from_sum(ctx, e)
+    a.apply_antinoise_batch([ge], [-0.01], 1)
+    b.apply_antinoise(ge, -0.01)
+    compare_sums(a.as_dict(), b.as_dict(), rtol=1e-14, context="batch of one vs exact")
+    for h in (a, b, ge):
+        h.destroy()
