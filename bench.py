@@ -199,7 +199,7 @@ def noisy_check(ctx, wl, precision):
     return {"value": v, "ms": round(1e3 * dt, 3), "term_updates_per_s": round(upd[0] / dt, 1), "terms_out": n}
 
 
-def pna_check(ctx, cpu: bool, prefix_maps: int = 300, topk=()):
+def pna_check(ctx, cpu: bool, prefix_maps: int = 300, topk=(), batches=()):
     """Propagated noise absorption (Section II) on the same 7x8 lattice, angles and noise
     as the headline workload at 2 Trotter steps (4 layers, 4164 generators): every
     generator's error propagated forward through the later gates on the device (threshold
@@ -207,7 +207,9 @@ def pna_check(ctx, cpu: bool, prefix_maps: int = 300, topk=()):
     uninstrumented, once, and again with per-launch HIP events for the kernel breakdown; the
     oracle and the device are also timed on the same prefix of the walk.  Each
     value in `topk` reruns the walk with E' O E' limited to that many most significant
-    products (Appendix B) and reports its time and the shift of <O~> from the exact walk."""
+    products (Appendix B), and each (C, order) in `batches` reruns it with the maps of a
+    layer absorbed C at a time to that order in the number of errors (Appendix C); both
+    report their time and the shift of <O~> from the exact walk."""
     import torch
     from paper_2606_20441_amd import pp, workloads as W
     wl = W.named_workload("tfim7x8_pna", steps=2)
@@ -249,6 +251,18 @@ def pna_check(ctx, cpu: bool, prefix_maps: int = 300, topk=()):
                             "abs_shift_vs_exact": abs(vk - v), "terms_out": len(gk)})
         gk.destroy()
         log(f"   PNA, at most {int(mp)} products per map: {1e3 * dk:.0f} ms, <O~> = {vk!r} (shift {abs(vk - v):.3e})")
+    out["batches"] = []
+    for C_, order in batches:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gb = pp.pna(ctx, circ, wl.observable, eps=eps, eps_fwd=eps_fwd, batch=int(C_), batch_order=int(order))
+        vb = gb.expectation()
+        torch.cuda.synchronize()
+        db = time.perf_counter() - t0
+        out["batches"].append({"batch": int(C_), "order": int(order), "ms": round(1e3 * db, 1), "expectation": vb,
+                               "abs_shift_vs_exact": abs(vb - v), "terms_out": len(gb)})
+        gb.destroy()
+        log(f"   PNA, batches of {int(C_)} to order {int(order)}: {1e3 * db:.0f} ms, <O~> = {vb!r} (shift {abs(vb - v):.3e})")
     if cpu:
         from oracle import oracle
         maps = [(t, k) for t, l in enumerate(circ.layers) for k in range(l.n_gen)][:prefix_maps]
@@ -364,6 +378,7 @@ def main():
     ap.add_argument("--no-pna", action="store_true", help="skip the propagated-noise-absorption leg")
     ap.add_argument("--pna-only", action="store_true", help="run only the propagated-noise-absorption leg")
     ap.add_argument("--pna-topk", default="", help="comma-separated product limits for extra PNA walks")
+    ap.add_argument("--pna-batch", default="", help="comma-separated C:order pairs for batched PNA walks")
     ap.add_argument("--sine-orders", default="", help="comma-separated CPT-order limits: run only the "
                     "workload in the sine-order mode for each")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -400,7 +415,8 @@ def main():
         return
     if args.pna_only:
         tk = [int(v) for v in args.pna_topk.split(",") if v]
-        print(json.dumps({"pna": pna_check(ctx, not args.no_cpu, topk=tk)}), flush=True)
+        bt = [tuple(int(x) for x in v.split(":")) for v in args.pna_batch.split(",") if v]
+        print(json.dumps({"pna": pna_check(ctx, not args.no_cpu, topk=tk, batches=bt)}), flush=True)
         ctx.close()
         return
     Wd = wl.circuit.W
