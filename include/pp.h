@@ -158,8 +158,9 @@ pp_status pp_apply_antinoise(pp_obs* obs, const pp_obs* eprime, double q);
 /* A batch of n_maps commuting antinoise maps (e.g. generators of one layer) absorbed at
  * once, expanded in the number of errors (Appendix C): with a_c = q_c / (1 - q_c) and
  * C_c(X) = E'_c X E'_c, O0 = O prod (1 - q_c), O1 = sum_c a_c C_c(O0), and for order 2
- * also O2 = 1/2 sum_c (a_c C_c(O1) - a_c^2 O0); O becomes O0 + O1 (+ O2), then |c| < eps
- * and the max_terms cap of obs's pp_trunc apply.  Exact for n_maps = 1; the error of a
+ * also O2 = 1/2 sum_c (a_c C_c(O1') - a_c^2 O0), where O1' is O1 without its terms below
+ * obs's eps (the second pass's input only); O becomes O0 + O1 (+ O2), then |c| < eps and
+ * the max_terms cap of obs's pp_trunc apply.  Exact for n_maps = 1; the error of a
  * batch is of order (q C)^2 (order 1) or (q C)^3 (order 2).  eprimes: n_maps observables
  * sharing O's context, qubit count and precision, in PP_MODE_GREEDY; q: n_maps finite
  * values != 1 (host array).  All maps of the batch are expanded into one buffer and merged

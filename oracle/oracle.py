@@ -50,7 +50,7 @@ def _lib():
                                            _u64p, _u64p, _f64p, C.c_double, C.c_int64, C.c_int, C.c_int]
         lib.or_antinoise.argtypes = [C.c_void_p, C.c_void_p, C.c_double]
         lib.or_antinoise_topk.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_int64]
-        lib.or_antinoise_batch.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_void_p), _f64p, C.c_int]
+        lib.or_antinoise_batch.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_void_p), _f64p, C.c_int, C.c_double]
         lib.or_expectation.restype = C.c_double
         lib.or_expectation.argtypes = [C.c_void_p, _u64p]
         lib.or_norm2.restype = C.c_double
@@ -129,12 +129,13 @@ class OracleSum:
         """O -> (1 - q) O + q E' O E' (Section II, Eq. applyantinoise); no truncation."""
         _lib().or_antinoise(self._h, eprime._h, float(q))
 
-    def antinoise_batch(self, eprimes, qs, order: int = 1) -> None:
+    def antinoise_batch(self, eprimes, qs, order: int = 1, eps1: float = 0.0) -> None:
         """A batch of commuting antinoise maps to first or second order in the number of
-        errors (Appendix C); exact for one map."""
+        errors (Appendix C); exact for one map.  The second-order pass takes the
+        first-order part without its terms below eps1."""
         hs = (C.c_void_p * len(eprimes))(*[e._h for e in eprimes])
         qa = np.ascontiguousarray(np.asarray(qs, np.float64))
-        _lib().or_antinoise_batch(self._h, len(eprimes), hs, _p(qa, _f64p), int(order))
+        _lib().or_antinoise_batch(self._h, len(eprimes), hs, _p(qa, _f64p), int(order), float(eps1))
 
     def antinoise_topk(self, eprime: "OracleSum", q: float, k: int) -> None:
         """As ``antinoise`` with E' O E' limited to the k most significant products
@@ -294,7 +295,7 @@ def pna(circuit, observable, eps: float = 0.0, max_terms: int = 0, eps_fwd: floa
             for k0 in range(0, layer.n_gen, batch):
                 ks = range(k0, min(k0 + batch, layer.n_gen))
                 es = [propagated_error(circuit, t, k, eps_fwd, max_terms_fwd) for k in ks]
-                o.antinoise_batch(es, [antinoise_q(float(lam[k])) for k in ks], batch_order)
+                o.antinoise_batch(es, [antinoise_q(float(lam[k])) for k in ks], batch_order, eps)
                 o.truncate(eps, max_terms)
         return o
     for t, layer in enumerate(circuit.layers):

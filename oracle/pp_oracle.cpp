@@ -406,8 +406,9 @@ void antinoise_topk(or_sum* s, const or_sum* e, double q, int64_t k) {
 // with a_c = q_c / (1 - q_c) and C_c(X) = E'_c X E'_c, the exact product
 // prod_c (1 - q_c)(1 + a_c C_c) O is approximated by
 //   O0 = O prod_c (1 - q_c),   O1 = sum_c a_c C_c(O0),
-//   O2 = 1/2 sum_c (a_c C_c(O1) - a_c^2 O0)      (order 2 only),
-// returning O0 + O1 (+ O2).  Reading: the appendix's overbarred error carries the factor
+//   O2 = 1/2 sum_c (a_c C_c(O1') - a_c^2 O0)     (order 2 only),
+// returning O0 + O1 (+ O2), where O1' is O1 with |c| < eps1 dropped (the input of the
+// second-order pass only; eps1 = 0 keeps it whole).  Reading: the appendix's overbarred error carries the factor
 // whose square is q/(1 - q), negative for an inverse map, which is what the exact product
 // gives; its printed |q| drops that sign.  C = 1 is exact.  Each C_c is the plain double
 // sum over ordered pairs (as in antinoise).
@@ -432,7 +433,7 @@ Map conj_sum(const Map& x, const or_sum* e, double scale, int W) {
   return out;
 }
 
-void antinoise_batch(or_sum* s, int C, const or_sum* const* e, const double* q, int order) {
+void antinoise_batch(or_sum* s, int C, const or_sum* const* e, const double* q, int order, double eps1) {
   if (C < 1) fail("a batch needs at least one map");
   if (order != 1 && order != 2) fail("order must be 1 or 2");
   const int W = s->W;
@@ -451,6 +452,7 @@ void antinoise_batch(or_sum* s, int C, const or_sum* const* e, const double* q, 
   Map out = o0;
   for (const auto& kv : o1) out[kv.first] += kv.second;
   if (order == 2) {
+    if (eps1 > 0.0) threshold(o1, eps1);
     double a2 = 0.0;
     for (int c = 0; c < C; ++c) {
       const double a = q[c] / (1.0 - q[c]);
@@ -553,8 +555,9 @@ void or_truncate(or_sum* s, double eps, int64_t max_terms) { truncate(s, eps, ma
 
 void or_antinoise(or_sum* s, const or_sum* eprime, double q) { antinoise(s, eprime, q); }
 
-void or_antinoise_batch(or_sum* s, int C, const or_sum* const* eprimes, const double* q, int order) {
-  antinoise_batch(s, C, eprimes, q, order);
+void or_antinoise_batch(or_sum* s, int C, const or_sum* const* eprimes, const double* q, int order,
+                        double eps1) {
+  antinoise_batch(s, C, eprimes, q, order, eps1);
 }
 
 void or_antinoise_topk(or_sum* s, const or_sum* eprime, double q, int64_t k) {

@@ -66,8 +66,10 @@ void    or_antinoise(or_sum* s, const or_sum* eprime, double q);
  * |alpha||beta_i||beta_j| (Appendix B's heuristic conjugation); ties with the k-th kept. */
 void    or_antinoise_topk(or_sum* s, const or_sum* eprime, double q, int64_t k);
 /* A batch of C commuting antinoise maps to first (order 1) or second (order 2) order in
- * the number of errors (Appendix C); exact for C = 1; no truncation. */
-void    or_antinoise_batch(or_sum* s, int C, const or_sum* const* eprimes, const double* q, int order);
+ * the number of errors (Appendix C); exact for C = 1; the second-order pass takes the
+ * first-order part with |c| < eps1 dropped; no other truncation. */
+void    or_antinoise_batch(or_sum* s, int C, const or_sum* const* eprimes, const double* q, int order,
+                           double eps1);
 
 /* One circuit layer with the truncation schedule of the propagation:
  *   [noise if !noise_after_gates] ; gates (dir = +1: reverse list order, U^dag P U;

@@ -1940,7 +1940,8 @@ struct Engine final : EngineBase {
 
   // A batch of commuting antinoise maps to first or second order in the number of errors
   // (Appendix C): with a_c = q_c / (1 - q_c), O0 = O prod (1 - q_c), O1 = sum a_c C_c(O0),
-  // O2 = 1/2 sum (a_c C_c(O1) - a_c^2 O0); O becomes O0 + O1 (+ O2), then eps and the cap.
+  // O2 = 1/2 sum (a_c C_c(O1') - a_c^2 O0) with O1' = O1 without its terms below eps (the
+  // second pass's input only); O becomes O0 + O1 (+ O2), then eps and the cap.
   void antinoise_batch(const std::vector<const EngineBase*>& ebs, const double* q, int order) override {
     std::vector<const Engine*> es;
     for (const EngineBase* b : ebs) {
@@ -1965,10 +1966,11 @@ struct Engine final : EngineBase {
     }
     std::vector<ExpItem> first;
     for (size_t c = 0; c < es.size(); ++c) first.push_back({o, N, es[c], a[c] * p0, 0.0});
-    const uint64_t m1 = merge_expansion(expand_items(first), 0.0);   // O1, exact zeros dropped
+    const uint64_t m1 = merge_expansion(expand_items(first), obs->trunc.eps);   // O1'
     tmp.swap(sa);
     const Terms<CT> t1 = tmp.view();
-    std::vector<ExpItem> second{{o, N, nullptr, 0.0, p0 * (1.0 - 0.5 * a2)}, {t1, m1, nullptr, 0.0, 1.0}};
+    std::vector<ExpItem> second{{o, N, nullptr, 0.0, p0 * (1.0 - 0.5 * a2)}};
+    for (size_t c = 0; c < es.size(); ++c) second.push_back({o, N, es[c], a[c] * p0, 0.0});   // O1 in full
     for (size_t c = 0; c < es.size(); ++c) second.push_back({t1, m1, es[c], 0.5 * a[c], 0.0});
     finish_expansion(expand_items(second));
   }

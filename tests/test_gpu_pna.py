@@ -253,18 +253,19 @@ def test_pna_topk_unlimited_equals_exact(pp, ctx):
 # --------------------------------------------------------------------------------------
 # Batches of maps expanded in the number of errors (Appendix C).
 # --------------------------------------------------------------------------------------
-@pytest.mark.parametrize("n,m,ks,order", [
-    (56, 1500, [3, 7, 1, 12], 1),
-    (56, 1500, [3, 7, 1, 12], 2),
-    (128, 600, [5, 9, 2], 2),
-    (56, 800, [4, 0, 6], 1),
+@pytest.mark.parametrize("n,m,ks,order,eps", [
+    (56, 1500, [3, 7, 1, 12], 1, 0.0),
+    (56, 1500, [3, 7, 1, 12], 2, 0.0),
+    (56, 1500, [3, 7, 1, 12], 2, 1e-4),
+    (128, 600, [5, 9, 2], 2, 0.0),
+    (56, 800, [4, 0, 6], 1, 0.0),
 ])
-def test_antinoise_batch_random(pp, ctx, orc, n, m, ks, order):
-    log(f"antinoise batch n={n} |O|={m} |E'|={ks} order={order}")
+def test_antinoise_batch_random(pp, ctx, orc, n, m, ks, order, eps):
+    log(f"antinoise batch n={n} |O|={m} |E'|={ks} order={order} eps={eps}")
     o = W.random_pauli_sum(n, m, seed=7 * n + m)
     es = [W.random_pauli_sum(n, k, seed=11 * n + k + 3 * i) if k else None for i, k in enumerate(ks)]
     qs = [-0.004 * (i + 1) for i in range(len(ks))]
-    g = pp.Observable.from_sum(ctx, o)
+    g = pp.Observable.from_sum(ctx, o, eps=eps)
     gis = [pp.Observable.from_sum(ctx, e) if e is not None else
            pp.Observable(ctx, n, np.zeros((0, W.n_words(n)), np.uint64), np.zeros((0, W.n_words(n)), np.uint64), np.zeros(0))
            for e in es]
@@ -273,8 +274,9 @@ def test_antinoise_batch_random(pp, ctx, orc, n, m, ks, order):
     ris = [orc.OracleSum.from_sum(e) if e is not None else
            orc.OracleSum(n, np.zeros((0, W.n_words(n)), np.uint64), np.zeros((0, W.n_words(n)), np.uint64), np.zeros(0))
            for e in es]
-    r.antinoise_batch(ris, qs, order)
-    rep = compare_sums(g.as_dict(), r.as_dict(), context="antinoise batch")
+    r.antinoise_batch(ris, qs, order, eps)
+    r.truncate(eps, 0)
+    rep = compare_sums(g.as_dict(), r.as_dict(), thresholds=[eps], context="antinoise batch")
     log(f"  {rep}")
     assert abs(g.expectation() - r.expectation()) < 1e-10
     g.destroy()
