@@ -132,6 +132,14 @@ pp_status pp_create_observable(pp_ctx* ctx, int n_qubits, int64_t n_terms, const
                                const uint64_t* z, const double* coeff, pp_precision precision,
                                pp_mode mode, pp_trunc trunc, pp_obs** out);
 
+/* Replace the terms of an existing observable, as pp_create_observable would set them
+ * (duplicates summed, exact zeros dropped, tags zero), keeping its context, qubit count,
+ * precision, mode, truncation and device buffers.  For callers that propagate many small
+ * sums in turn (the forward-evolved errors of PNA) without creating and freeing an
+ * observable each time.  Arguments and errors as pp_create_observable's; on an error the
+ * previous terms may be lost (the observable then holds no terms). */
+pp_status pp_set_terms(pp_obs* obs, int64_t n_terms, const uint64_t* x, const uint64_t* z, const double* coeff);
+
 /* Propagate through one layer (gates, then or preceded by, a Pauli-Lindblad map):
  * rotation branching per gate with the cos/sin split (Eq. evolve_gate and its backward
  * form), duplicate strings merged after every gate, and after every non-Clifford gate

@@ -2340,6 +2340,22 @@ pp_status pp_create_observable(pp_ctx* ctx, int n_qubits, int64_t n_terms, const
   return PP_OK;
 }
 
+pp_status pp_set_terms(pp_obs* obs, int64_t n_terms, const uint64_t* x, const uint64_t* z, const double* coeff) {
+  if (!obs) { g_last_error = "NULL argument"; return PP_ERR_INVALID; }
+  if (obs->broken) { g_last_error = "observable is unusable after an earlier device error"; return PP_ERR_INVALID; }
+  if (n_terms < 0 || n_terms >= (1LL << 31)) { g_last_error = "n_terms out of range"; return PP_ERR_INVALID; }
+  if (n_terms > 0 && (!x || !z || !coeff)) { g_last_error = "NULL term array"; return PP_ERR_INVALID; }
+  if (n_terms > 0 && !strings_ok(obs->n_qubits, obs->W, n_terms, x, z)) { g_last_error = "string bits above n_qubits"; return PP_ERR_INVALID; }
+  for (int64_t i = 0; i < n_terms; ++i)
+    if (!std::isfinite(coeff[i])) { g_last_error = "non-finite coefficient"; return PP_ERR_INVALID; }
+  const pp_status s = guarded([&] {
+    HIPCHK(hipSetDevice(obs->ctx->device));
+    obs->eng->create(n_terms, x, z, coeff);
+  });
+  if (s == PP_ERR_DEVICE || s == PP_ERR_OOM) obs->broken = true;
+  return s;
+}
+
 pp_status pp_apply_layer(pp_obs* obs, const pp_layer* L) {
   if (!obs || !L) { g_last_error = "NULL argument"; return PP_ERR_INVALID; }
   if (obs->broken) { g_last_error = "observable is unusable after an earlier device error"; return PP_ERR_INVALID; }

@@ -107,6 +107,8 @@ def lib():
         L.pp_create_observable.argtypes = [C.c_void_p, C.c_int, C.c_int64, _u64p, _u64p, _f64p, C.c_int, C.c_int,
                                            pp_trunc, C.POINTER(C.c_void_p)]
         L.pp_create_observable.restype = C.c_int
+        L.pp_set_terms.argtypes = [C.c_void_p, C.c_int64, _u64p, _u64p, _f64p]
+        L.pp_set_terms.restype = C.c_int
         L.pp_apply_layer.argtypes = [C.c_void_p, C.POINTER(pp_layer)]
         L.pp_apply_layer.restype = C.c_int
         L.pp_truncate.argtypes = [C.c_void_p, C.c_double, C.c_int64]
@@ -297,6 +299,13 @@ class Observable:
         (``pp_apply_antinoise_topk``)."""
         _check(lib().pp_apply_antinoise_topk(self._h, eprime._h, float(q), int(max_products)))
 
+    def set_terms(self, x, z, c):
+        """Replace the terms, keeping the device buffers (``pp_set_terms``)."""
+        xw = _words(x, self.W)
+        zw = _words(z, self.W)
+        cc = np.ascontiguousarray(np.asarray(c, dtype=np.float64).reshape(-1))
+        _check(lib().pp_set_terms(self._h, cc.shape[0], _ptr(xw, _u64p), _ptr(zw, _u64p), _ptr(cc, _f64p)))
+
     def truncate(self, eps: float, max_terms: int = 0):
         _check(lib().pp_truncate(self._h, float(eps), int(max_terms)))
 
@@ -420,15 +429,20 @@ def antinoise_q(lam: float) -> float:
 
 
 def propagated_error(ctx: Context, circuit, t: int, k: int, eps_fwd: float = 0.0, max_terms_fwd: int = 0,
-                     precision: str = "f64") -> Observable:
+                     precision: str = "f64", into: Optional[Observable] = None) -> Observable:
     """E' = U E U^dag for generator k of layer t's noise: E carried forward in time
-    through the gates of layers t+1..M (Section II), on the device."""
+    through the gates of layers t+1..M (Section II), on the device.  With `into` (an
+    observable of the same qubit count, precision, eps_fwd and cap) its buffers are reused."""
     W = (circuit.n_qubits + 63) // 64
     layer = circuit.layers[t]
     ex = _words(layer.ex, W)[k:k + 1]
     ez = _words(layer.ez, W)[k:k + 1]
-    e = Observable(ctx, circuit.n_qubits, ex, ez, np.ones(1), precision=precision, eps=eps_fwd,
-                   max_terms=max_terms_fwd)
+    if into is not None:
+        e = into
+        e.set_terms(ex, ez, np.ones(1))
+    else:
+        e = Observable(ctx, circuit.n_qubits, ex, ez, np.ones(1), precision=precision, eps=eps_fwd,
+                       max_terms=max_terms_fwd)
     for later in circuit.layers[t + 1:]:
         e.apply_layer(later, PP_FORWARD, with_noise=False)
     return e
@@ -450,33 +464,30 @@ def pna(ctx: Context, circuit, observable, eps: float = 0.0, max_terms: int = 0,
     number of errors and merged once (Appendix C).
     """
     obs = Observable.from_sum(ctx, observable, precision=precision, eps=eps, max_terms=max_terms)
-    if batch > 1:
+    n, W = circuit.n_qubits, (circuit.n_qubits + 63) // 64
+    empty = np.zeros((0, W), np.uint64)
+    # the evolved errors live in a pool of observables whose buffers are reused
+    pool = [Observable(ctx, n, empty, empty, np.zeros(0), precision=precision, eps=eps_fwd, max_terms=max_terms_fwd)
+            for _ in range(max(1, batch))]
+    try:
         for t, layer in enumerate(circuit.layers):
             lam = np.asarray(layer.lam, np.float64)
-            for k0 in range(0, layer.n_gen, batch):
-                ks = range(k0, min(k0 + batch, layer.n_gen))
-                es = [propagated_error(ctx, circuit, t, k, eps_fwd, max_terms_fwd, precision) for k in ks]
-                try:
+            step = max(1, batch)
+            for k0 in range(0, layer.n_gen, step):
+                ks = range(k0, min(k0 + step, layer.n_gen))
+                es = [propagated_error(ctx, circuit, t, k, eps_fwd, max_terms_fwd, precision, into=pool[i])
+                      for i, k in enumerate(ks)]
+                if batch > 1:
                     obs.apply_antinoise_batch(es, [antinoise_q(lam[k]) for k in ks], batch_order)
-                finally:
-                    for e in es:
-                        e.destroy()
+                elif max_products > 0:
+                    obs.apply_antinoise_topk(es[0], antinoise_q(lam[k0]), max_products)
+                else:
+                    obs.apply_antinoise(es[0], antinoise_q(lam[k0]))
                 if on_map:
                     on_map(t, ks[-1], obs)
-        return obs
-    for t, layer in enumerate(circuit.layers):
-        lam = np.asarray(layer.lam, np.float64)
-        for k in range(layer.n_gen):
-            e = propagated_error(ctx, circuit, t, k, eps_fwd, max_terms_fwd, precision)
-            try:
-                if max_products > 0:
-                    obs.apply_antinoise_topk(e, antinoise_q(lam[k]), max_products)
-                else:
-                    obs.apply_antinoise(e, antinoise_q(lam[k]))
-            finally:
-                e.destroy()
-            if on_map:
-                on_map(t, k, obs)
+    finally:
+        for e in pool:
+            e.destroy()
     return obs
 
 

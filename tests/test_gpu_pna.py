@@ -313,3 +313,21 @@ def test_antinoise_batch_of_one_is_exact(pp, ctx):
     compare_sums(a.as_dict(), b.as_dict(), rtol=1e-14, context="batch of one vs exact")
     for h in (a, b, ge):
         h.destroy()
+
+
+def test_set_terms_reuses_an_observable(pp, ctx):
+    """An observable refilled with pp_set_terms behaves as a fresh one: larger then smaller
+    sums, duplicates merged, then propagated through a Clifford layer and its noise."""
+    n = 56
+    wl = W.named_workload("tfim7x8_pna", steps=1)
+    reused = pp.Observable(ctx, n, np.zeros((0, 1), np.uint64), np.zeros((0, 1), np.uint64), np.zeros(0), eps=1e-6)
+    for m, seed in ((3000, 1), (40, 2), (0, 3), (700, 4)):
+        ps = W.random_pauli_sum(n, m, seed=seed)
+        reused.set_terms(ps.x, ps.z, ps.c)
+        fresh = pp.Observable.from_sum(ctx, ps, eps=1e-6)
+        assert reused.as_dict() == fresh.as_dict()
+        for h in (reused, fresh):
+            h.apply_layer(wl.circuit.layers[0], pp.PP_FORWARD, with_noise=True)   # Clifford ZZ + noise
+        assert reused.as_dict() == fresh.as_dict()
+        fresh.destroy()
+    reused.destroy()
