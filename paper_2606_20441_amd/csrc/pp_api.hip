@@ -1848,35 +1848,7 @@ struct Engine final : EngineBase {
     const auto* e = dynamic_cast<const Engine*>(eb);
     if (!e) throw_fail(PP_ERR_UNSUPPORTED, "E' must have the same word count, precision and mode as O");
     if (N == 0) return;
-    const uint64_t K = e->N;
-    if (K > kMaxAntinoiseTerms)
-      throw_fail(PP_ERR_UNSUPPORTED, "E' has " + std::to_string(K) + " terms; at most " +
-                                         std::to_string(kMaxAntinoiseTerms) + " are supported");
-    const uint64_t S = 1 + K * (K - (K > 0)) / 2;
-    const uint64_t total = N * S;
-    if (total >= (1ULL << 31))
-      throw_fail(PP_ERR_UNSUPPORTED, "antinoise expansion of " + std::to_string(total) + " terms exceeds 2^31 - 1");
-    std::vector<uint32_t> pr;
-    pr.reserve(S);
-    for (uint32_t a = 0; a < K; ++a)
-      for (uint32_t b = a + 1; b < K; ++b) pr.push_back(a | (b << 16));
-    pr.push_back(0);   // never read; keeps the upload non-empty
-    pair_d.ensure(pr.size() * 4);
-    HIPCHK(hipMemcpyAsync(pair_d.p, pr.data(), pr.size() * 4, hipMemcpyHostToDevice, st));
-    sa.ensure(total);
-    u32b.ensure(total * 4 + 64);
-    uint32_t* keep = u32b.as<uint32_t>();
-    const Terms<CT> in = cur.view(), ev = e->cur.view(), out = sa.view();
-    const uint32_t* pairs = pair_d.as<uint32_t>();
-    const uint64_t n = N;
-    const unsigned grid = (unsigned)std::min<uint64_t>(cdiv(total, 256), 1u << 20);
-    ctx->run("antinoise_expand", kTermBytes * (double)(n + total) + 4.0 * total, (double)total, [&] {
-      hipLaunchKernelGGL((k_expand_antinoise<W, CT, ORD>), dim3(grid), dim3(256), 0, st, in, n, ev, (uint32_t)K,
-                         pairs, S, q, 1.0 - q, out, keep);
-    });
-    ctx->check_launch();
-    sync();   // the pair table's host source goes out of scope
-    finish_expansion(total);
+    finish_expansion(expand_items({{cur.view(), N, e, q, 1.0 - q}}));
   }
 
   // One expansion of a batch: `scale` C(X) (scale E' X E') for an E', or id X alone (e
