@@ -1637,15 +1637,19 @@ struct Engine final : EngineBase {
     if (n == 0) return;
     const uint64_t un = (uint64_t)n;
     sa.ensure(un);
-    std::vector<uint64_t> plane(un);
+    // all planes staged at once (x planes, then z planes), one wait after the copies
+    std::vector<uint64_t> planes(2 * (size_t)W * un);
     const Terms<CT> t = sa.view();
+    for (int w = 0; w < W; ++w)
+      for (uint64_t i = 0; i < un; ++i) {
+        planes[(size_t)w * un + i] = x[i * W + w];
+        planes[(size_t)(W + w) * un + i] = z[i * W + w];
+      }
     for (int w = 0; w < W; ++w) {
-      for (uint64_t i = 0; i < un; ++i) plane[i] = x[i * W + w];
-      HIPCHK(hipMemcpyAsync(t.x + (size_t)w * t.stride, plane.data(), un * 8, hipMemcpyHostToDevice, st));
-      sync();
-      for (uint64_t i = 0; i < un; ++i) plane[i] = z[i * W + w];
-      HIPCHK(hipMemcpyAsync(t.z + (size_t)w * t.stride, plane.data(), un * 8, hipMemcpyHostToDevice, st));
-      sync();
+      HIPCHK(hipMemcpyAsync(t.x + (size_t)w * t.stride, planes.data() + (size_t)w * un, un * 8,
+                            hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(t.z + (size_t)w * t.stride, planes.data() + (size_t)(W + w) * un, un * 8,
+                            hipMemcpyHostToDevice, st));
     }
     f64_d.ensure(un * 8 + 64);
     HIPCHK(hipMemcpyAsync(f64_d.p, c, un * 8, hipMemcpyHostToDevice, st));
@@ -1656,7 +1660,12 @@ struct Engine final : EngineBase {
     });
     ctx->check_launch();
     if (ORD) HIPCHK(hipMemsetAsync(t.o, 0, un, st));
-    sync();
+    sync();   // the staged planes go out of scope
+    if (un == 1) {   // one term: already in canonical order; only an exact zero is dropped
+      cur.swap(sa);
+      N = c[0] != 0.0 && (CT)c[0] != (CT)0 ? 1 : 0;
+      return;
+    }
     canonical_sort(sa, sb, un);
     const uint64_t m = merge_sorted(sa, sb, un, 0.0, nullptr);
     cur.swap(sa);
