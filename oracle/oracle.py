@@ -126,7 +126,7 @@ class OracleSum:
         _lib().or_truncate(self._h, float(eps), int(max_terms))
 
     def antinoise(self, eprime: "OracleSum", q: float) -> None:
-        """O -> (1 - q) O + q E' O E' (Section II, Eq. applyantinoise); no truncation."""
+        """O -> (1 - q) O + q E' O E' (Section I.A, Eq. applyantinoise); no truncation."""
         _lib().or_antinoise(self._h, eprime._h, float(q))
 
     def antinoise_batch(self, eprimes, qs, order: int = 1, eps1: float = 0.0) -> None:
@@ -245,7 +245,7 @@ def noise_canceling(circuit, observable, eps: float = 0.0, max_terms: int = 0,
 
 
 def noisy_evaluation(circuit, obs: OracleSum, eps: float = 0.0, max_terms: int = 0) -> float:
-    """Tr[O~ rho_noisy] by noisy Pauli propagation (Section II's check that the mitigated
+    """Tr[O~ rho_noisy] by noisy Pauli propagation (Section III's check that the mitigated
     observable recovers the ideal value): C_noisy = N_M G_M .. N_1 G_1 (noise after every
     layer's gates), so its adjoint applies, from m = M down to 1, the channel N_m itself
     (a Pauli channel is self-adjoint) and then G_m^dag.  Changes `obs` in place."""
@@ -263,7 +263,7 @@ def antinoise_q(lam: float) -> float:
 
 def propagated_error(circuit, t: int, k: int, eps_fwd: float = 0.0, max_terms_fwd: int = 0) -> OracleSum:
     """E'_{t,k} = U E U^dag: generator k of layer t's noise carried through the gates of
-    layers t+1..M, forward in time (Section II; truncation per non-Clifford gate)."""
+    layers t+1..M, forward in time (Section I.A, Eq. channel_prop; truncation per non-Clifford gate)."""
     layer = circuit.layers[t]
     W = (circuit.n_qubits + 63) // 64
     ex = np.asarray(layer.ex, np.uint64).reshape(-1, W)[k:k + 1]
@@ -276,7 +276,7 @@ def propagated_error(circuit, t: int, k: int, eps_fwd: float = 0.0, max_terms_fw
 
 def pna(circuit, observable, eps: float = 0.0, max_terms: int = 0, eps_fwd: float = 0.0,
         max_terms_fwd: int = 0, max_products: int = 0, batch: int = 1, batch_order: int = 1) -> OracleSum:
-    """Propagated noise absorption (Section II).  The hardware circuit is
+    """Propagated noise absorption (Section I.A).  The hardware circuit is
     C_noisy = N_M G_M .. N_1 G_1.  Writing each ideal layer as N_t^{-1} N_t G_t and carrying
     the inverse maps to the end one at a time, from t = 1 up, through the later gates only,
     gives C_ideal = N'_1^{-1} .. N'_M^{-1} C_noisy, where N'_t^{-1} applies, for every

@@ -122,7 +122,8 @@ int angle_cos_sin(double theta, double* c, double* s) {
     *s = cs[m][1];
     return 1;
   }
-  ::sincos(theta, s, c);   // the C library's sincos (what an optimising compiler makes of cos + sin)
+  *c = std::cos(theta);
+  *s = std::sin(theta);
   return 0;
 }
 
@@ -206,39 +207,12 @@ void noise(or_sum* s, int n_gen, const uint64_t* ex, const uint64_t* ez, const d
   }
   const int W = s->W;
   if (mode == 0) {
-    // Eq. evolve_noise for every generator of the layer: P -> prod_{k: <P,E_k>=1} f_k P.
-    // The layer's channel is a composition of local channels (Section I, the noise
-    // model): the generators acting on one qubit or one pair, consecutive in the list.
-    // The product is taken channel by channel -- inside a run of consecutive generators
-    // with the same support, then over the runs in list order.  Identity generators
-    // commute with every string and are left out.
-    std::vector<int> gens, run_start;
-    std::vector<uint64_t> prev(2 * (size_t)W, 0);
-    for (int k = 0; k < n_gen; ++k) {
-      std::vector<uint64_t> sup(2 * (size_t)W, 0);
-      bool any = false;
-      for (int w = 0; w < W; ++w) {
-        const uint64_t m = ex[(size_t)k * W + w] | ez[(size_t)k * W + w];
-        sup[w] = m;
-        any = any || m != 0;
-      }
-      if (!any) continue;
-      run_start.push_back(gens.empty() || sup != prev ? 1 : 0);
-      gens.push_back(k);
-      prev = sup;
-    }
+    // The layer's channel is the composition of its local channels, one per generator
+    // (Section I, the noise model), so Eq. evolve_noise is applied generator by generator in
+    // list order: an anticommuting P is multiplied by that generator's f_k.
     for (auto& kv : s->m) {
-      double prod = 1.0, run = 1.0;
-      for (size_t j = 0; j < gens.size(); ++j) {
-        if (run_start[j] && j > 0) {
-          prod *= run;
-          run = 1.0;
-        }
-        const int k = gens[j];
-        if (anticommutes(kv.first, ex + (size_t)k * W, ez + (size_t)k * W, W)) run *= f[k];
-      }
-      prod *= run;
-      kv.second *= prod;
+      for (int k = 0; k < n_gen; ++k)
+        if (anticommutes(kv.first, ex + (size_t)k * W, ez + (size_t)k * W, W)) kv.second *= f[k];
     }
     return;
   }
@@ -308,7 +282,7 @@ int pauli_mul(const Key& a, const Key& b, int W, Key* c) {
   return ((e % 4) + 4) % 4;
 }
 
-// Propagated antinoise absorbed into the observable (Section II, Eq. applyantinoise): the
+// Propagated antinoise absorbed into the observable (Section I.A, Eq. applyantinoise): the
 // inverse map of one generator, carried to the end of the circuit, applies the evolved
 // error E' = sum_a e_a P_a with quasi-probability q, so O -> (1 - q) O + q E' O E'.
 // E' O E' is written out as the plain sum over ordered pairs (a, b) of e_a e_b P_a P P_b
@@ -595,9 +569,13 @@ or_sum* or_noise_canceling(const or_sum* obs, int n_layers, const int* n_gates, 
                 theta + g_off[m], dir, with_noise ? n_gen[m] : 0, ex + e_off[m] * W,
                 ez + e_off[m] * W, lambda + e_off[m], +1, 1, eps, max_terms, mode, max_order);
   };
-  for (int m = n_layers - 1; m >= 1; --m) layer(m, +1, true, false);  // G_M^dag .. G_2^dag
-  layer(0, -1, false, true);                                          // N_1^{-1}
-  for (int m = 1; m < n_layers; ++m) layer(m, -1, true, true);        // G_m, then N_m^{-1}
+  // The sine-order mode expands D over every gate of C_ideal, the first layer's included
+  // (the Euclid appendix's diagrams run over j = 1..N in both halves), so it keeps the
+  // G_1^dag G_1 pair: with a cut on the number of sines its two halves no longer cancel.
+  const int first = mode == 2 ? 0 : 1;
+  for (int m = n_layers - 1; m >= first; --m) layer(m, +1, true, false);  // G_M^dag .. G_2^dag (.. G_1^dag)
+  layer(0, -1, first == 0, true);                                         // (G_1, then) N_1^{-1}
+  for (int m = 1; m < n_layers; ++m) layer(m, -1, true, true);            // G_m, then N_m^{-1}
   return s;
 }
 

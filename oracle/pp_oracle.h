@@ -50,16 +50,17 @@ void    or_export(const or_sum* s, uint64_t* x, uint64_t* z, double* c, uint8_t*
 int     or_rotate(or_sum* s, const uint64_t* rx, const uint64_t* rz, double theta, int dir);
 
 /* One Pauli-Lindblad layer (all generators), no truncation.  sign = +1 applies the
- * inverse map, sign = -1 the channel itself.  mode 0: multiply by the full product of
- * Pauli fidelities; mode 1: expand the product in the anticommuting generators'
- * (f_k - 1) and keep total order <= max_order, tagging each term with its order. */
+ * inverse map, sign = -1 the channel itself.  mode 0: the local channels one after the
+ * other in list order, each multiplying an anticommuting string by its f_k; mode 1: expand
+ * the product in the anticommuting generators' (f_k - 1) and keep total order <= max_order,
+ * tagging each term with its order. */
 void    or_noise(or_sum* s, int n_gen, const uint64_t* ex, const uint64_t* ez,
                  const double* lambda, int sign, int mode, int max_order);
 
 /* Drop |c| < eps; then, if more than max_terms remain (max_terms > 0), keep the
  * max_terms largest |c| (ties: smaller canonical key first). */
 void    or_truncate(or_sum* s, double eps, int64_t max_terms);
-/* O -> (1 - q) O + q E' O E' for E' = eprime (Section II, Eq. applyantinoise); exact zeros
+/* O -> (1 - q) O + q E' O E' for E' = eprime (Section I.A, Eq. applyantinoise); exact zeros
  * dropped, no other truncation.  eprime must have the same qubit count. */
 void    or_antinoise(or_sum* s, const or_sum* eprime, double q);
 /* As or_antinoise, with E' O E' limited to the products P_i P P_j of the k largest
@@ -88,7 +89,10 @@ void    or_apply_layer(or_sum* s, int n_gates, const uint64_t* gx, const uint64_
  * N_m, m = 1..M, arrays concatenated over layers):
  *   O~ = N_M^{-1} G_M ... N_2^{-1} G_2 N_1^{-1} G_2^dag ... G_M^dag (O)
  * i.e. backward (Heisenberg) through G_M..G_2, then N_1^{-1}, then for m = 2..M forward
- * through G_m and N_m^{-1}.  Truncation as in or_apply_layer, per layer call. */
+ * through G_m and N_m^{-1}.  In mode 2 (sine order) the first layer's pair is kept:
+ * backward through G_M..G_1, then forward through G_1 and N_1^{-1}, then as above (the
+ * Euclid appendix expands D over every gate of C_ideal).  Truncation as in
+ * or_apply_layer, per layer call. */
 or_sum* or_noise_canceling(const or_sum* obs, int n_layers, const int* n_gates,
                            const uint64_t* gx, const uint64_t* gz, const double* theta,
                            const int* n_gen, const uint64_t* ex, const uint64_t* ez,

@@ -1,4 +1,4 @@
-"""GPU parity of propagated noise absorption (Section II, Eq. applyantinoise).
+"""GPU parity of propagated noise absorption (Section I.A, Eq. applyantinoise).
 
 ``pp_apply_antinoise`` through the C ABI against the FP64 reference's plain double sum over
 ordered pairs, on random sums at one, two and four words per string; then whole PNA runs

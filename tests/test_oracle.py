@@ -436,7 +436,7 @@ def test_layer_truncation_schedule_against_brute_force(oracle_lib):
 
 
 # --------------------------------------------------------------------------------------
-# Propagated noise absorption (Section II, Eq. applyantinoise; Appendix D panel b).
+# Propagated noise absorption (Section I.A, Eq. applyantinoise; Appendix D panel b).
 # --------------------------------------------------------------------------------------
 def _small_random_circuit(n, n_layers, n_gates, n_gen, seed, clifford=False):
     rng = np.random.default_rng(seed)
@@ -521,7 +521,7 @@ def test_pna_recovers_ideal_and_equals_deconvolution(oracle_lib, case):
 
 def test_pna_clifford_closed_form(oracle_lib):
     """Clifford circuit: every E' is one Pauli and O~ = O prod (1 - 2 q) over the errors
-    whose E' anticommutes with O (Section III's sampling-cost argument); E' from explicit
+    whose E' anticommutes with O (Appendix A's sampling-cost argument); E' from explicit
     matrices."""
     B = _brute()
     n = 4
@@ -569,27 +569,21 @@ def test_pna_threshold_and_cap_after_every_update(oracle_lib):
 # --------------------------------------------------------------------------------------
 # Heuristic conjugation (Appendix B): E' O E' limited to the most significant products.
 # --------------------------------------------------------------------------------------
-def _priority_queue_conjugation(n, a, b, k):
-    """The appendix's search, on explicit matrices: both operators sorted by |coefficient|,
-    index triplets (i, s, j) popped from a max-queue by |beta_i alpha_s beta_j|, the three
-    neighbours of each popped triplet pushed once, until k products are taken."""
-    import heapq
+def _top_products_conjugation(n, a, b, k):
+    """E' O E' restricted to its k most significant products, from the definition on
+    explicit matrices: every ordered triplet (i, s, j) of an E' term, an O term and an E'
+    term is listed with mu = |beta_i alpha_s beta_j|, the list is sorted by mu, and the
+    products beta_i alpha_s beta_j P_i P_s P_j of the first k are summed (callers pick k
+    where no tie straddles the cut)."""
     B = _brute()
-    oa = sorted(range(len(a.c)), key=lambda t: -abs(a.c[t]))
-    ob = sorted(range(len(b.c)), key=lambda t: -abs(b.c[t]))
-    pa = [(a.c[t], B.PauliOp(n, a.x[t], a.z[t]).matrix()) for t in oa]
-    pb = [(b.c[t], B.PauliOp(n, b.x[t], b.z[t]).matrix()) for t in ob]
-    M, N = len(pb), len(pa)
-    mag = lambda i, s, j: abs(pb[i][0] * pa[s][0] * pb[j][0])
-    heap, seen, out, taken = [(-mag(0, 0, 0), (0, 0, 0))], {(0, 0, 0)}, 0, 0
-    while heap and taken < k:
-        _, (i, s, j) = heapq.heappop(heap)
+    pa = [(a.c[t], B.PauliOp(n, a.x[t], a.z[t]).matrix()) for t in range(len(a.c))]
+    pb = [(b.c[t], B.PauliOp(n, b.x[t], b.z[t]).matrix()) for t in range(len(b.c))]
+    trip = [(abs(pb[i][0] * pa[s][0] * pb[j][0]), i, s, j)
+            for i in range(len(pb)) for s in range(len(pa)) for j in range(len(pb))]
+    trip.sort(key=lambda t: -t[0])
+    out = 0
+    for _, i, s, j in trip[:k]:
         out = out + pb[i][0] * pa[s][0] * pb[j][0] * (pb[i][1] @ pa[s][1] @ pb[j][1])
-        taken += 1
-        for nb in ((i + 1, s, j), (i, s + 1, j), (i, s, j + 1)):
-            if nb[0] < M and nb[1] < N and nb[2] < M and nb not in seen:
-                seen.add(nb)
-                heapq.heappush(heap, (-mag(*nb), nb))
     return out
 
 
@@ -609,9 +603,10 @@ def test_antinoise_topk_all_products_is_exact(oracle_lib):
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
-def test_antinoise_topk_against_priority_queue(oracle_lib, seed):
-    """Wherever no tie straddles the cut, the kept products are the ones the appendix's
-    priority-queue search pops; the update is compared on explicit 2^n matrices."""
+def test_antinoise_topk_against_definition(oracle_lib, seed):
+    """Wherever no tie straddles the cut, the kept products are the k most significant
+    triplets of the definition (Appendix B: the products with the largest
+    |beta_i alpha beta_j|); the update is compared on explicit 2^n matrices."""
     B = _brute()
     n = 3
     e = W.random_pauli_sum(n, 5, seed=40 + seed, allow_duplicates=False)
@@ -624,7 +619,7 @@ def test_antinoise_topk_against_priority_queue(oracle_lib, seed):
     for k in ks[:: max(1, len(ks) // 12)]:
         got = oracle_lib.OracleSum.from_sum(o)
         got.antinoise_topk(oracle_lib.OracleSum.from_sum(e), q, k)
-        m = (1 - q) * om + q * _priority_queue_conjugation(n, o, e, k)
+        m = (1 - q) * om + q * _top_products_conjugation(n, o, e, k)
         want = _dict_from_decomp(B.pauli_decompose(m, n, tol=1e-14), n)
         _assert_same_sum(_oracle_dict(got), want, 1e-13)
 
@@ -651,8 +646,9 @@ def test_antinoise_topk_keeps_ties_with_the_cut(oracle_lib):
 # --------------------------------------------------------------------------------------
 def _sine_series(circuit, obs_matrix, K):
     """D O as a polynomial in a formal s that multiplies every non-Clifford sine, on
-    explicit matrices and in the propagation's order (backward through G_M .. G_2, the first
-    layer's inverse noise, then forward through G_m and N_m^{-1}); coefficients of s^0..s^K.
+    explicit matrices and in the propagation's order (backward through G_M .. G_1, forward
+    through G_1 and the first layer's inverse noise, then forward through G_m and N_m^{-1};
+    the G_1 pair is kept, as in the Euclid appendix's diagrams); coefficients of s^0..s^K.
     A rotation splits M into the parts commuting (Mc) and anticommuting (Ma) with R:
     U M U^dag = Mc + cos Ma - sin (i R Ma), U^dag M U = Mc + cos Ma + sin (i R Ma)."""
     B = _brute()
@@ -678,10 +674,12 @@ def _sine_series(circuit, obs_matrix, K):
         return out
 
     poly = [obs_matrix.copy()] + [np.zeros_like(obs_matrix) for _ in range(K)]
-    for gates, gens, lam in reversed(layers[1:]):
+    for gates, gens, lam in reversed(layers):
         for r, th in reversed(gates):
             poly = gate(poly, r, th, +1)
     g0 = layers[0]
+    for r, th in g0[0]:
+        poly = gate(poly, r, th, -1)
     if g0[1]:
         poly = [B.channel(m, g0[1], g0[2], -1) for m in poly]
     for gates, gens, lam in layers[1:]:
@@ -690,6 +688,96 @@ def _sine_series(circuit, obs_matrix, K):
         if gens:
             poly = [B.channel(m, gens, lam, -1) for m in poly]
     return poly
+
+
+def _anti(a, b):
+    """Symplectic product of two strings given as (x, z) integer masks."""
+    return bin((a[0] & b[1]) ^ (a[1] & b[0])).count("1") & 1
+
+
+def test_sine_order_against_euclid_diagrams(oracle_lib):
+    """Tags 0, 1 and 2 of the sine-order propagation against the Euclid appendix's diagram
+    coefficients, written out from Eq. line-term, Eq. Z-term, Eq. Zprime-term and
+    Eq. bubble-term with exact noise factors 1 + eps = 1/f and j running over every gate of
+    C_ideal, the first included.  The circuit has one gate per node; node j is the paper's
+    Lambda_j then U_j, so Lambda_1 is the identity and the channel after gate j is
+    Lambda_{j+1}.  The generators are distinct, so the only order-2 paths back to O are the
+    bubbles.  The first gate is non-Clifford and anticommutes with O: a propagation that
+    dropped the G_1 pair would miss cos^2 theta_1 in the line term and the bubble Omega_1."""
+    B = _brute()
+    n = 3
+    gates = [({0: "X"}, 0.35), ({0: "Z", 1: "Z"}, -0.5), ({1: "Y", 2: "X"}, 0.6), ({0: "Z", 2: "Z"}, 0.42),
+             ({2: "X"}, -0.27)]
+    N = len(gates)
+    rng = np.random.default_rng(3)
+    labels = [{0: "X"}, {1: "Z"}, {0: "Y", 2: "Z"}, {1: "X", 2: "X"}, {2: "Y"}, {0: "Z", 1: "Y"}]
+    layers = []
+    for m in range(N):
+        gens = [] if m == N - 1 else [(ops, float(rng.uniform(0.01, 0.05))) for ops in labels]
+        layers.append(W.make_layer(n, [gates[m]], gens))
+    circ = W.Circuit(n, layers)
+    c_o = 0.8
+    obs = W.pauli_sum(n, [({0: "Z", 2: "Y"}, c_o)])
+
+    def mask(ops):
+        x, z = W.pauli_masks(n, ops)
+        return int(x[0]), int(z[0])
+
+    O = mask({0: "Z", 2: "Y"})
+    P = [mask(ops) for ops, _ in gates]
+    th = [t for _, t in gates]
+    mul = lambda a, b: (a[0] ^ b[0], a[1] ^ b[1])
+    # 1 + eps_k^Q = 1/f_k^Q for node k = 1..N (Lambda_1 = identity, Lambda_k = channel after gate k-1)
+    def ope(k, q):
+        if k == 1:
+            return 1.0
+        layer = layers[k - 2]
+        f = 1.0
+        for g in range(layer.n_gen):
+            e = (int(layer.ex[g, 0]), int(layer.ez[g, 0]))
+            if _anti(q, e):
+                f *= math.exp(2.0 * float(layer.lam[g]))
+        return f
+    cos, sin = math.cos, math.sin
+    prod = lambda it: math.prod(list(it))
+    J = range(1, N + 1)
+    pj = lambda j: P[j - 1]
+    tj = lambda j: th[j - 1]
+    # Eq. line-term
+    line = prod(cos(tj(j)) ** 2 for j in J if _anti(pj(j), O)) * prod(ope(j, O) for j in J)
+    # Eq. Z-term and Eq. Zprime-term, as operators i (...) P_j O and -i (...) P_j O
+    om = B.pauli_sum_matrix(n, obs.x, obs.z, obs.c)
+    step_op = np.zeros_like(om)
+    bubbles = 0.0
+    for j in J:
+        if not _anti(pj(j), O):
+            continue
+        q = mul(pj(j), O)
+        later_o = prod(cos(tj(k)) for k in J if k > j and _anti(pj(k), O))
+        later_q = prod(cos(tj(k)) for k in J if k > j and _anti(pj(k), q))
+        z_dir = (cos(tj(j)) * sin(tj(j)) * later_o * later_q
+                 * prod(cos(tj(k)) ** 2 for k in J if k < j and _anti(pj(k), q)) * prod(ope(k, q) for k in J))
+        z_inv = (cos(tj(j)) * sin(tj(j)) * later_o * later_q
+                 * prod(cos(tj(k)) ** 2 for k in J if k < j and _anti(pj(k), O))
+                 * prod(ope(k, q) for k in J if k > j) * prod(ope(k, O) for k in J if k <= j))
+        pm = B.PauliOp(n, np.array([pj(j)[0]], np.uint64), np.array([pj(j)[1]], np.uint64)).matrix()
+        step_op = step_op + (1j * z_dir - 1j * z_inv) * (pm @ om)
+        # Eq. bubble-term
+        bubbles += (sin(tj(j)) ** 2 * prod(cos(tj(k)) ** 2 for k in J if k > j and _anti(pj(k), O))
+                    * prod(ope(k, O) for k in J if k > j)
+                    * prod(cos(tj(k)) ** 2 for k in J if k < j and _anti(pj(k), q))
+                    * prod(ope(k, q) for k in J if k <= j))
+    assert _anti(P[0], O) and abs(sin(th[0])) > 0.3
+    res = oracle_lib.noise_canceling(circ, obs, mode="sine_order", max_order=2).as_dict()
+    okey = ((O[0],), (O[1],))
+    tag = lambda t: {(k[0], k[1]): v for k, v in res.items() if k[2] == t}
+    _assert_same_sum(tag(0), {okey: c_o * line}, 1e-14)
+    want1 = _dict_from_decomp(B.pauli_decompose(step_op, n, tol=1e-14), n)
+    assert len(want1) >= 3
+    _assert_same_sum(tag(1), want1, 1e-14)
+    assert abs(tag(2)[okey] - c_o * bubbles) < 1e-14
+    only0 = oracle_lib.noise_canceling(circ, obs, mode="sine_order", max_order=0).as_dict()
+    assert set(only0) == {(okey[0], okey[1], 0)} and abs(only0[(okey[0], okey[1], 0)] - c_o * line) < 1e-14
 
 
 def test_sine_split_matches_conjugation(oracle_lib):
@@ -782,6 +870,25 @@ def test_antinoise_batch_against_matrices(oracle_lib):
         s.antinoise_batch(es, qs, order)
         _assert_same_sum(_oracle_dict(s), _dict_from_decomp(B.pauli_decompose(want, n, tol=1e-14), n), 1e-13)
     assert np.abs(exact - (o0 + o1 + o2)).max() < 0.2 * np.abs(exact - (o0 + o1)).max()
+    # The second pass's input O1' is O1 without its Pauli terms below eps1; O1 itself enters
+    # the result in full.  eps1 sits inside the spread of O1's coefficients, so some of them
+    # are dropped and some kept.
+    d1 = B.pauli_decompose(o1, n, tol=0.0)
+    mags = sorted(abs(v) for v in d1.values() if abs(v) > 1e-15)
+    # the middle of the widest relative gap in the middle half of the magnitudes, so no
+    # coefficient lies near eps1 and rounding cannot decide its side
+    lo, hi = len(mags) // 4, 3 * len(mags) // 4
+    g = max(range(lo, hi), key=lambda i: mags[i + 1] / mags[i])
+    assert mags[g + 1] > 1.01 * mags[g]
+    eps1 = math.sqrt(mags[g] * mags[g + 1])
+    kept = {k: v for k, v in d1.items() if abs(v) >= eps1}
+    o1p = sum(v * B.PauliOp(n, np.array([k[0]], np.uint64), np.array([k[1]], np.uint64)).matrix()
+              for k, v in kept.items())
+    o2p = 0.5 * sum(ac * conj(o1p, em) - ac * ac * o0 for ac, em in zip(a, mats))
+    s = oracle_lib.OracleSum.from_sum(obs)
+    s.antinoise_batch(es, qs, 2, eps1)
+    _assert_same_sum(_oracle_dict(s), _dict_from_decomp(B.pauli_decompose(o0 + o1 + o2p, n, tol=1e-14), n), 1e-13)
+    assert np.abs(o2p - o2).max() > 1e-6   # the threshold changed the second-order part
     one = oracle_lib.OracleSum.from_sum(obs)
     one.antinoise_batch(es[:1], qs[:1], 1)
     ref = oracle_lib.OracleSum.from_sum(obs)
