@@ -200,7 +200,7 @@ def noisy_check(ctx, wl, precision):
 
 
 def pna_check(ctx, cpu: bool, prefix_maps: int = 300, topk=(), batches=()):
-    """Propagated noise absorption (Section II) on the same 7x8 lattice, angles and noise
+    """Propagated noise absorption (Section I.A) on the same 7x8 lattice, angles and noise
     as the headline workload at 2 Trotter steps (4 layers, 4164 generators): every
     generator's error propagated forward through the later gates on the device (threshold
     1e-4), then absorbed into O (threshold 1e-5), one update per generator.  Timed whole,
@@ -277,7 +277,7 @@ def pna_check(ctx, cpu: bool, prefix_maps: int = 300, topk=(), batches=()):
         gg = pp.Observable.from_sum(ctx, wl.observable, eps=eps)
         for t, k in maps:
             e = pp.propagated_error(ctx, circ, t, k, eps_fwd)
-            gg.apply_antinoise(e, pp.antinoise_q(circ.layers[t].lam[k]))
+            gg.apply_antinoise(e, circ.layers[t].lam[k])
             e.destroy()
         torch.cuda.synchronize()
         t_gpu = time.perf_counter() - t0
@@ -296,7 +296,7 @@ def sine_order_check(ctx, wl, orders):
     in the Clifford interaction picture, for each tag limit K: time, term count and <O~>."""
     import torch
     from paper_2606_20441_amd import pp
-    ip = pp.interaction_picture(wl.circuit)
+    ip = wl.circuit   # the library writes it in the interaction picture
     out = []
     for K in orders:
         torch.cuda.synchronize()

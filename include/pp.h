@@ -66,10 +66,13 @@ typedef enum { PP_F64 = 0, PP_F32_KAHAN = 1 } pp_precision;
  * kappa = k + 2p of the Euclid appendix (k steps and p bubbles, one sine per step): the
  * sin child of a non-Clifford rotation gets tag + 1 and is dropped above max_order
  * (0..250), Clifford rotations do not count, the noise rescales as in PP_MODE_GREEDY, and
- * terms merge by (string, tag).  Every gate takes the per-gate sort-and-merge path.  The
- * caller writes the circuit in the Clifford interaction picture (each angle split into a
- * multiple of pi/2 and a residual of at most pi/4) so that every counted sine is at most
- * 1/sqrt 2; <O~> sums all tags. */
+ * terms merge by (string, tag).  Every gate takes the per-gate sort-and-merge path.
+ * pp_apply_layer writes each layer in the Clifford interaction picture of the Euclid
+ * appendix before propagating: a rotation by theta becomes the exact Clifford rotation by
+ * the nearest multiple k pi/2 followed by one by the residual theta - k pi/2 (at most pi/4,
+ * so every counted sine is at most 1/sqrt 2); whole turns are dropped.  <O~> sums all tags.
+ * The Euclid appendix expands D over every gate of C_ideal, the first layer's included, so
+ * a caller building D in this mode keeps the G_1^dag G_1 pair. */
 typedef enum { PP_MODE_GREEDY = 0, PP_MODE_ERROR_ORDER = 1, PP_MODE_SINE_ORDER = 2 } pp_mode;
 
 /* Direction of a gate layer.  PP_HEISENBERG: P -> U^dag P U = cos P + sin (i R P) for
@@ -150,18 +153,21 @@ pp_status pp_set_terms(pp_obs* obs, int64_t n_terms, const uint64_t* x, const ui
  * (string, order) and the max_terms cap. */
 pp_status pp_apply_layer(pp_obs* obs, const pp_layer* layer);
 
-/* Absorb one propagated antinoise map into the observable (Section II, Eq.
+/* Absorb one propagated antinoise map into the observable (Section I.A, Eq.
  * applyantinoise): O -> (1 - q) O + q E' O E'.  E' = sum_a e_a P_a is the observable
  * `eprime`, normally one noise generator E evolved to the end of the circuit, U E U^dag
- * (pp_apply_layer with PP_FORWARD over the later layers, noise off); q is the inverse
- * map's quasi-probability (1 - e^{2 lambda})/2 <= 0, though any finite q is accepted.
+ * (Eq. channel_prop; pp_apply_layer with PP_FORWARD over the later layers, noise off).
+ * lambda is that generator's strength (finite, 0 <= lambda <= 300, else PP_ERR_INVALID);
+ * the library takes the inverse map's quasi-probability q = (1 - e^{2 lambda})/2 <= 0
+ * (Section I: the channel applies E with probability (1 - e^{-2 lambda})/2, the inverse
+ * negates lambda).
  * Each term of O expands into 1 + K(K-1)/2 strings for K = |E'| (P itself, and one string
  * per unordered pair of E' terms), duplicates are merged, then |c| < eps and the max_terms
  * cap of obs's pp_trunc are applied; eprime is not changed.  Both observables must share
  * the context, qubit count and precision (PP_ERR_INVALID otherwise) and be in
  * PP_MODE_GREEDY (PP_ERR_UNSUPPORTED otherwise).  PP_ERR_UNSUPPORTED as well when
  * K > 4096 or the expansion exceeds 2^31 - 1 strings; obs is then unchanged. */
-pp_status pp_apply_antinoise(pp_obs* obs, const pp_obs* eprime, double q);
+pp_status pp_apply_antinoise(pp_obs* obs, const pp_obs* eprime, double lambda);
 
 /* A batch of n_maps commuting antinoise maps (e.g. generators of one layer) absorbed at
  * once, expanded in the number of errors (Appendix C): with a_c = q_c / (1 - q_c) and
@@ -170,11 +176,12 @@ pp_status pp_apply_antinoise(pp_obs* obs, const pp_obs* eprime, double q);
  * obs's eps (the second pass's input only); O becomes O0 + O1 (+ O2), then |c| < eps and
  * the max_terms cap of obs's pp_trunc apply.  Exact for n_maps = 1; the error of a
  * batch is of order (q C)^2 (order 1) or (q C)^3 (order 2).  eprimes: n_maps observables
- * sharing O's context, qubit count and precision, in PP_MODE_GREEDY; q: n_maps finite
- * values != 1 (host array).  All maps of the batch are expanded into one buffer and merged
+ * sharing O's context, qubit count and precision, in PP_MODE_GREEDY; lambda: the n_maps
+ * generators' strengths (host array, each as for pp_apply_antinoise), q_c taken from
+ * lambda_c as there.  All maps of the batch are expanded into one buffer and merged
  * once, instead of one sort per map.  Errors as pp_apply_antinoise (PP_ERR_INVALID for
  * n_maps < 1 or order not 1 or 2). */
-pp_status pp_apply_antinoise_batch(pp_obs* obs, const pp_obs* const* eprimes, const double* q, int n_maps,
+pp_status pp_apply_antinoise_batch(pp_obs* obs, const pp_obs* const* eprimes, const double* lambda, int n_maps,
                                    int order);
 
 /* As pp_apply_antinoise, with E' O E' approximated by its most significant products
@@ -186,7 +193,7 @@ pp_status pp_apply_antinoise_batch(pp_obs* obs, const pp_obs* const* eprimes, co
  * |O| K^2, gives pp_apply_antinoise's result.  Only the kept products are expanded, so
  * the 2^31 - 1 limit applies to |O| + (kept unordered pairs); other arguments and errors
  * as pp_apply_antinoise. */
-pp_status pp_apply_antinoise_topk(pp_obs* obs, const pp_obs* eprime, double q, int64_t max_products);
+pp_status pp_apply_antinoise_topk(pp_obs* obs, const pp_obs* eprime, double lambda, int64_t max_products);
 
 /* Explicit greedy truncation: drop |c| < eps, then keep the max_terms largest |c|
  * (0 = no cap; ties to the smaller canonical key).  E.g. the K_M leading terms of

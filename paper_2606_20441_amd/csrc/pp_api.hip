@@ -209,8 +209,8 @@ bool angle_cos_sin(double theta, double* c, double* s) {
     *s = ss[k];
     return true;
   }
-  // one call for both: the C library's sincos (a separate cos call can differ in the last bit)
-  ::sincos(theta, s, c);
+  *c = std::cos(theta);
+  *s = std::sin(theta);
   return false;
 }
 
@@ -1694,7 +1694,37 @@ struct Engine final : EngineBase {
   // Sine-order mode: greedy noise, and every gate through the per-gate path, whose
   // expansion counts the sines of non-Clifford gates in the tag; threshold and cap after
   // every non-Clifford gate.
-  void sine_order_layer(const pp_layer* L) {
+  void sine_order_layer(const pp_layer* L0) {
+    // The Clifford interaction picture of the Euclid appendix: a rotation by theta about R
+    // becomes the exact Clifford rotation by the nearest multiple k pi/2 (first; the two
+    // commute) and one by the residual theta - k pi/2, |residual| <= pi/4, so every sine the
+    // tag counts is at most 1/sqrt 2.  A whole turn (k = 0 mod 4) is a phase under
+    // conjugation and is left out; Clifford angles stay single gates.
+    std::vector<uint64_t> ipx, ipz;
+    std::vector<double> ipt;
+    const double half = M_PI / 2;
+    for (int g = 0; g < L0->n_gates; ++g) {
+      const double t = L0->theta[g];
+      const double k = std::nearbyint(t / half);
+      const double r = t - k * half;
+      std::vector<double> parts;
+      if (std::fabs(r) <= 1e-12 * half) parts = {t};
+      else if ((((long long)k % 4) + 4) % 4 == 0) parts = {r};
+      else parts = {k * half, r};
+      for (double a : parts) {
+        for (int w = 0; w < W; ++w) {
+          ipx.push_back(L0->gx[(size_t)g * W + w]);
+          ipz.push_back(L0->gz[(size_t)g * W + w]);
+        }
+        ipt.push_back(a);
+      }
+    }
+    pp_layer ip = *L0;
+    ip.n_gates = (int)ipt.size();
+    ip.gx = ipx.data();
+    ip.gz = ipz.data();
+    ip.theta = ipt.data();
+    const pp_layer* L = &ip;
     pp_layer_stats ls{};
     ls.n_in = (int64_t)N;
     auto noise = [&]() {
@@ -1850,7 +1880,7 @@ struct Engine final : EngineBase {
     if (cap > 0 && (int64_t)N > cap) cap_select((uint64_t)cap, ls);
   }
 
-  // Propagated antinoise (Section II, Eq. applyantinoise): O -> (1 - q) O + q E' O E'.
+  // Propagated antinoise (Section I.A, Eq. applyantinoise): O -> (1 - q) O + q E' O E'.
   // Every term expands into 1 + K(K-1)/2 slots (k_expand_antinoise), the slots are put in
   // canonical order and merged with the observable's eps threshold, then the cap applies.
   void antinoise(const EngineBase* eb, double q) override {
@@ -2371,14 +2401,19 @@ pp_status pp_truncate(pp_obs* obs, double eps, int64_t max_terms) {
   return s;
 }
 
-pp_status pp_apply_antinoise(pp_obs* obs, const pp_obs* eprime, double q) {
+// Quasi-probability of a generator's inverse map (Section I: the channel applies E with
+// probability (1 - e^{-2 lambda})/2 and the inverse map negates lambda): (1 - e^{2 lambda})/2.
+static double inverse_quasi_probability(double lambda) { return -0.5 * std::expm1(2.0 * lambda); }
+
+pp_status pp_apply_antinoise(pp_obs* obs, const pp_obs* eprime, double lambda) {
   if (!obs || !eprime) { g_last_error = "NULL argument"; return PP_ERR_INVALID; }
   if (obs->broken || eprime->broken) { g_last_error = "observable is unusable after an earlier device error"; return PP_ERR_INVALID; }
   if (obs->ctx != eprime->ctx) { g_last_error = "O and E' belong to different contexts"; return PP_ERR_INVALID; }
   if (obs->n_qubits != eprime->n_qubits) { g_last_error = "O and E' have different qubit counts"; return PP_ERR_INVALID; }
   if (obs->prec != eprime->prec) { g_last_error = "O and E' have different precisions"; return PP_ERR_INVALID; }
   if (obs->mode != PP_MODE_GREEDY || eprime->mode != PP_MODE_GREEDY) { g_last_error = "antinoise needs PP_MODE_GREEDY observables"; return PP_ERR_UNSUPPORTED; }
-  if (!std::isfinite(q)) { g_last_error = "q must be finite"; return PP_ERR_INVALID; }
+  if (!std::isfinite(lambda) || lambda < 0.0 || lambda > 300.0) { g_last_error = "lambda must be finite, >= 0 and <= 300"; return PP_ERR_INVALID; }
+  const double q = inverse_quasi_probability(lambda);
   const pp_status s = guarded([&] {
     HIPCHK(hipSetDevice(obs->ctx->device));
     obs->eng->antinoise(eprime->eng.get(), q);
@@ -2387,13 +2422,14 @@ pp_status pp_apply_antinoise(pp_obs* obs, const pp_obs* eprime, double q) {
   return s;
 }
 
-pp_status pp_apply_antinoise_batch(pp_obs* obs, const pp_obs* const* eprimes, const double* q, int n_maps, int order) {
-  if (!obs || !eprimes || !q) { g_last_error = "NULL argument"; return PP_ERR_INVALID; }
+pp_status pp_apply_antinoise_batch(pp_obs* obs, const pp_obs* const* eprimes, const double* lambda, int n_maps, int order) {
+  if (!obs || !eprimes || !lambda) { g_last_error = "NULL argument"; return PP_ERR_INVALID; }
   if (n_maps < 1) { g_last_error = "n_maps must be >= 1"; return PP_ERR_INVALID; }
   if (order != 1 && order != 2) { g_last_error = "order must be 1 or 2"; return PP_ERR_INVALID; }
   if (obs->broken) { g_last_error = "observable is unusable after an earlier device error"; return PP_ERR_INVALID; }
   if (obs->mode != PP_MODE_GREEDY) { g_last_error = "antinoise needs PP_MODE_GREEDY observables"; return PP_ERR_UNSUPPORTED; }
   std::vector<const EngineBase*> es;
+  std::vector<double> q((size_t)n_maps);
   for (int c = 0; c < n_maps; ++c) {
     const pp_obs* e = eprimes[c];
     if (!e) { g_last_error = "NULL E'"; return PP_ERR_INVALID; }
@@ -2403,25 +2439,27 @@ pp_status pp_apply_antinoise_batch(pp_obs* obs, const pp_obs* const* eprimes, co
       return PP_ERR_INVALID;
     }
     if (e->mode != PP_MODE_GREEDY) { g_last_error = "antinoise needs PP_MODE_GREEDY observables"; return PP_ERR_UNSUPPORTED; }
-    if (!std::isfinite(q[c]) || q[c] == 1.0) { g_last_error = "q must be finite and != 1"; return PP_ERR_INVALID; }
+    if (!std::isfinite(lambda[c]) || lambda[c] < 0.0 || lambda[c] > 300.0) { g_last_error = "lambda must be finite, >= 0 and <= 300"; return PP_ERR_INVALID; }
+    q[c] = inverse_quasi_probability(lambda[c]);
     es.push_back(e->eng.get());
   }
   const pp_status s = guarded([&] {
     HIPCHK(hipSetDevice(obs->ctx->device));
-    obs->eng->antinoise_batch(es, q, order);
+    obs->eng->antinoise_batch(es, q.data(), order);
   });
   if (s == PP_ERR_DEVICE || s == PP_ERR_OOM) obs->broken = true;
   return s;
 }
 
-pp_status pp_apply_antinoise_topk(pp_obs* obs, const pp_obs* eprime, double q, int64_t max_products) {
+pp_status pp_apply_antinoise_topk(pp_obs* obs, const pp_obs* eprime, double lambda, int64_t max_products) {
   if (!obs || !eprime) { g_last_error = "NULL argument"; return PP_ERR_INVALID; }
   if (obs->broken || eprime->broken) { g_last_error = "observable is unusable after an earlier device error"; return PP_ERR_INVALID; }
   if (obs->ctx != eprime->ctx) { g_last_error = "O and E' belong to different contexts"; return PP_ERR_INVALID; }
   if (obs->n_qubits != eprime->n_qubits) { g_last_error = "O and E' have different qubit counts"; return PP_ERR_INVALID; }
   if (obs->prec != eprime->prec) { g_last_error = "O and E' have different precisions"; return PP_ERR_INVALID; }
   if (obs->mode != PP_MODE_GREEDY || eprime->mode != PP_MODE_GREEDY) { g_last_error = "antinoise needs PP_MODE_GREEDY observables"; return PP_ERR_UNSUPPORTED; }
-  if (!std::isfinite(q)) { g_last_error = "q must be finite"; return PP_ERR_INVALID; }
+  if (!std::isfinite(lambda) || lambda < 0.0 || lambda > 300.0) { g_last_error = "lambda must be finite, >= 0 and <= 300"; return PP_ERR_INVALID; }
+  const double q = inverse_quasi_probability(lambda);
   const pp_status s = guarded([&] {
     HIPCHK(hipSetDevice(obs->ctx->device));
     obs->eng->antinoise_topk(eprime->eng.get(), q, max_products);

@@ -7,7 +7,6 @@ caching allocator.  Loading fails loudly if the library was not built.
 from __future__ import annotations
 
 import ctypes as C
-import math
 import os
 import threading
 from dataclasses import dataclass
@@ -283,21 +282,22 @@ class Observable:
         _check(lib().pp_apply_layer(self._h, C.byref(L)))
         del keep
 
-    def apply_antinoise(self, eprime: "Observable", q: float):
-        """O -> (1 - q) O + q E' O E' (``pp_apply_antinoise``)."""
-        _check(lib().pp_apply_antinoise(self._h, eprime._h, float(q)))
+    def apply_antinoise(self, eprime: "Observable", lam: float):
+        """O -> (1 - q) O + q E' O E' for a generator of strength lam, q taken by the
+        library (``pp_apply_antinoise``)."""
+        _check(lib().pp_apply_antinoise(self._h, eprime._h, float(lam)))
 
-    def apply_antinoise_batch(self, eprimes, qs, order: int = 1):
+    def apply_antinoise_batch(self, eprimes, lams, order: int = 1):
         """A batch of commuting antinoise maps to first or second order in the number of
-        errors (``pp_apply_antinoise_batch``)."""
+        errors (``pp_apply_antinoise_batch``); lams are the generators' strengths."""
         hs = (C.c_void_p * len(eprimes))(*[e._h.value if isinstance(e._h, C.c_void_p) else e._h for e in eprimes])
-        qa = np.ascontiguousarray(np.asarray(qs, np.float64))
-        _check(lib().pp_apply_antinoise_batch(self._h, hs, _ptr(qa, _f64p), len(eprimes), int(order)))
+        la = np.ascontiguousarray(np.asarray(lams, np.float64))
+        _check(lib().pp_apply_antinoise_batch(self._h, hs, _ptr(la, _f64p), len(eprimes), int(order)))
 
-    def apply_antinoise_topk(self, eprime: "Observable", q: float, max_products: int):
+    def apply_antinoise_topk(self, eprime: "Observable", lam: float, max_products: int):
         """As ``apply_antinoise`` with E' O E' limited to its most significant products
         (``pp_apply_antinoise_topk``)."""
-        _check(lib().pp_apply_antinoise_topk(self._h, eprime._h, float(q), int(max_products)))
+        _check(lib().pp_apply_antinoise_topk(self._h, eprime._h, float(lam), int(max_products)))
 
     def set_terms(self, x, z, c):
         """Replace the terms, keeping the device buffers (``pp_set_terms``)."""
@@ -341,37 +341,6 @@ class Observable:
         return {k: getattr(s, k) for k, _ in pp_layer_stats._fields_}
 
 
-def interaction_picture(circuit):
-    """Rewrite a circuit in the Clifford interaction picture (Euclid appendix): a rotation
-    by theta about R becomes a rotation by the nearest multiple of pi/2 (exact, Clifford)
-    followed by one by the remainder, |remainder| <= pi/4 (they commute).  Whole turns are a
-    phase under conjugation and are dropped; exact Clifford angles stay single gates.  Used
-    with mode="sine_order", where only the remainders' sines are counted."""
-    import copy
-    q = math.pi / 2
-    new = copy.deepcopy(circuit)
-    for layer in new.layers:
-        G = layer.n_gates
-        if G == 0:
-            continue
-        rows_x = np.asarray(layer.gx, np.uint64).reshape(G, -1)
-        rows_z = np.asarray(layer.gz, np.uint64).reshape(G, -1)
-        keep, angles = [], []
-        for g, th in enumerate(np.asarray(layer.theta, np.float64)):
-            k = int(np.rint(th / q))
-            rest = float(th) - k * q
-            exact = abs(rest) <= 1e-12 * q
-            if not exact and k % 4:
-                keep.append(g)
-                angles.append(k * q)
-            keep.append(g)
-            angles.append(float(th) if exact else rest)
-        layer.gx = rows_x[keep]
-        layer.gz = rows_z[keep]
-        layer.theta = np.asarray(angles, np.float64)
-    return new
-
-
 def noise_canceling(ctx: Context, circuit, observable, eps: float = 0.0, max_terms: int = 0,
                     mode: str = "greedy", max_order: int = 2, precision: str = "f64",
                     on_layer=None) -> Observable:
@@ -381,19 +350,24 @@ def noise_canceling(ctx: Context, circuit, observable, eps: float = 0.0, max_ter
     C_ideal C_noisy^{-1} = G_M..G_2 N_1^{-1} G_2^{-1} N_2^{-1} .. G_M^{-1} N_M^{-1} (the first
     layer's gates cancel).  Its adjoint applied to O therefore walks backward through
     G_M .. G_2 without noise (U^dag P U), applies N_1^{-1}, then for m = 2..M goes forward
-    through G_m (U P U^dag) followed by N_m^{-1}.
+    through G_m (U P U^dag) followed by N_m^{-1}.  In the sine-order mode the G_1 pair is
+    kept (backward through G_1, then forward through G_1 before N_1^{-1}): the Euclid
+    appendix expands D over every gate of C_ideal, and with a cut on the number of sines
+    the two halves of the pair no longer cancel.  The library writes that mode's layers in
+    the Clifford interaction picture itself.
     """
     obs = Observable.from_sum(ctx, observable, precision=precision, mode=mode, eps=eps, max_terms=max_terms,
                               max_order=max_order)
     layers = circuit.layers
     M = len(layers)
+    first = 0 if mode == "sine_order" else 1
     step = 0
-    for m in range(M - 1, 0, -1):
+    for m in range(M - 1, first - 1, -1):
         obs.apply_layer(layers[m], PP_HEISENBERG, with_noise=False)
         if on_layer:
             on_layer(step, "backward", m, obs)
         step += 1
-    obs.apply_layer(layers[0], PP_FORWARD, with_gates=False, noise_sign=1)
+    obs.apply_layer(layers[0], PP_FORWARD, with_gates=first == 0, noise_sign=1)
     if on_layer:
         on_layer(step, "noise", 0, obs)
     step += 1
@@ -409,7 +383,7 @@ def noisy_evaluation(circuit, obs_tilde: "Observable", on_layer=None) -> float:
     """Tr[O~ rho_noisy] by noisy Pauli propagation, with rho_noisy = C_noisy(|0><0|).
 
     This is the paper's check that propagating the mitigated observable back through the
-    noisy circuit recovers the ideal value (Section II).  C_noisy = N_M G_M .. N_1 G_1, so
+    noisy circuit recovers the ideal value (Section III).  C_noisy = N_M G_M .. N_1 G_1, so
     its adjoint on O~ walks back from m = M to 1 applying the channel N_m itself (noise
     sign -1; a Pauli channel is its own adjoint) and then G_m^dag (U^dag P U).  The
     observable keeps its own threshold and cap, and is changed in place.
@@ -422,16 +396,10 @@ def noisy_evaluation(circuit, obs_tilde: "Observable", on_layer=None) -> float:
     return obs_tilde.expectation()
 
 
-def antinoise_q(lam: float) -> float:
-    """Quasi-probability q = (1 - e^{2 lambda})/2 <= 0 of a generator's inverse map
-    (Section I: the channel applies E with probability (1 - e^{-2 lambda})/2)."""
-    return (1.0 - math.exp(2.0 * float(lam))) / 2.0
-
-
 def propagated_error(ctx: Context, circuit, t: int, k: int, eps_fwd: float = 0.0, max_terms_fwd: int = 0,
                      precision: str = "f64", into: Optional[Observable] = None) -> Observable:
     """E' = U E U^dag for generator k of layer t's noise: E carried forward in time
-    through the gates of layers t+1..M (Section II), on the device.  With `into` (an
+    through the gates of layers t+1..M (Section I.A, Eq. channel_prop), on the device.  With `into` (an
     observable of the same qubit count, precision, eps_fwd and cap) its buffers are reused."""
     W = (circuit.n_qubits + 63) // 64
     layer = circuit.layers[t]
@@ -451,7 +419,7 @@ def propagated_error(ctx: Context, circuit, t: int, k: int, eps_fwd: float = 0.0
 def pna(ctx: Context, circuit, observable, eps: float = 0.0, max_terms: int = 0, eps_fwd: float = 0.0,
         max_terms_fwd: int = 0, precision: str = "f64", on_map=None, max_products: int = 0, batch: int = 1,
         batch_order: int = 1) -> Observable:
-    """Propagated noise absorption (Section II).
+    """Propagated noise absorption (Section I.A).
 
     With C_noisy = N_M G_M .. N_1 G_1, inserting N_t^{-1} N_t after every G_t and carrying
     each inverse map to the end of the circuit, from t = 1 up and through the later gates
@@ -478,11 +446,11 @@ def pna(ctx: Context, circuit, observable, eps: float = 0.0, max_terms: int = 0,
                 es = [propagated_error(ctx, circuit, t, k, eps_fwd, max_terms_fwd, precision, into=pool[i])
                       for i, k in enumerate(ks)]
                 if batch > 1:
-                    obs.apply_antinoise_batch(es, [antinoise_q(lam[k]) for k in ks], batch_order)
+                    obs.apply_antinoise_batch(es, [lam[k] for k in ks], batch_order)
                 elif max_products > 0:
-                    obs.apply_antinoise_topk(es[0], antinoise_q(lam[k0]), max_products)
+                    obs.apply_antinoise_topk(es[0], lam[k0], max_products)
                 else:
-                    obs.apply_antinoise(es[0], antinoise_q(lam[k0]))
+                    obs.apply_antinoise(es[0], lam[k0])
                 if on_map:
                     on_map(t, ks[-1], obs)
     finally:

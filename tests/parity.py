@@ -40,3 +40,50 @@ def compare_sums(gpu: Dict[Key, float], ref: Dict[Key, float], thresholds=(), bo
 def cap_cut(ref: Dict[Key, float]) -> float:
     """Smallest kept |c| (the cap's cut value) of a capped result."""
     return min((abs(v) for v in ref.values()), default=0.0)
+
+
+def _keys(x, z, o):
+    """Rows of (x words, z words, order) as one structured array, sortable and comparable."""
+    import numpy as np
+    n, w = x.shape
+    dt = [(f"x{i}", "<u8") for i in range(w)] + [(f"z{i}", "<u8") for i in range(w)] + [("o", "u1")]
+    k = np.zeros(n, dtype=dt)
+    for i in range(w):
+        k[f"x{i}"] = x[:, i]
+        k[f"z{i}"] = z[:, i]
+    k["o"] = o
+    return k
+
+
+def compare_exports(g, r, thresholds=(), boundary: float = 1e-12, rtol: float = 1e-12, atol: float = 1e-15,
+                    context: str = "") -> dict:
+    """compare_sums for two exports (x, z, c, ord), vectorised for large sums: strings and
+    orders exact except terms within `boundary` (relative) of a truncation threshold or below
+    1e-12, shared coefficients to rtol/atol."""
+    import numpy as np
+    gk, rk = _keys(g[0], g[1], g[3]), _keys(r[0], r[1], r[3])
+    gc, rc = np.asarray(g[2], np.float64), np.asarray(r[2], np.float64)
+    common, gi, ri = np.intersect1d(gk, rk, assume_unique=True, return_indices=True)
+    only_g = np.setdiff1d(np.arange(len(gk)), gi)
+    only_r = np.setdiff1d(np.arange(len(rk)), ri)
+
+    def exempt(v):
+        a = np.abs(v)
+        ok = a <= 1e-12
+        for t in thresholds:
+            if t > 0:
+                ok |= np.abs(a - t) <= boundary * t + boundary
+        return ok
+
+    bad_g = only_g[~exempt(gc[only_g])]
+    bad_r = only_r[~exempt(rc[only_r])]
+    assert len(bad_g) == 0, f"{context}: {len(bad_g)} strings only on the GPU, e.g. |c| {np.abs(gc[bad_g[:3]])}"
+    assert len(bad_r) == 0, f"{context}: {len(bad_r)} strings missing on the GPU, e.g. |c| {np.abs(rc[bad_r[:3]])}"
+    a, b = gc[gi], rc[ri]
+    err = np.abs(a - b)
+    tol = atol + rtol * np.abs(b)
+    bad = np.nonzero(err > tol)[0]
+    assert len(bad) == 0, f"{context}: {len(bad)} coefficient mismatches, e.g. gpu {a[bad[:3]]} oracle {b[bad[:3]]}"
+    nz = b != 0
+    worst = float((err[nz] / np.abs(b[nz])).max()) if nz.any() else 0.0
+    return dict(n_gpu=len(gk), n_ref=len(rk), only_gpu=len(only_g), only_ref=len(only_r), worst_rel=worst)

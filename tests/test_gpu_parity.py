@@ -1,7 +1,9 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 CPU reference.
 
-Strings and orders are compared exactly, coefficients to ~1e-11 relative (FP64), terms within
-1e-12 of a truncation threshold are exempt, and <O> must agree within 1e-10 absolute.
+Strings and orders are compared exactly, coefficients to 1e-12 relative (FP64), terms within
+1e-12 of a truncation threshold are exempt, and <O> must agree within 1e-10 absolute.  Whole
+propagations where a cap binds are compared layer call by layer call, the reference fed the
+device's input (tests/test_gpu_fullsteps.py); the end-to-end cases here are uncapped.
 """
 import math
 import sys
@@ -85,13 +87,13 @@ def test_general_gates_one_by_one(pp, ctx, orc, n, direction):
     o = orc.OracleSum.from_sum(ps)
     g.apply_layer(layer, direction, with_noise=False)
     o.apply_layer(layer, direction, with_noise=False, eps=1e-3)
-    compare_sums(g.as_dict(), o.as_dict(), thresholds=[1e-3], rtol=0.0, atol=0.0, context="general gates")
+    compare_sums(g.as_dict(), o.as_dict(), thresholds=[1e-3], rtol=1e-12, atol=1e-15, context="general gates")
 
 
 @pytest.mark.parametrize("name,steps", [("tfim7x8_pna", 1), ("tfim8x16", 1), ("tfim3x3", 1)])
 @pytest.mark.parametrize("direction", [1, -1])
 def test_tfim_layers_exact(pp, ctx, orc, name, steps, direction):
-    """X-type and Z-type layers (fused LDS kernel) and Clifford layers, bit-exact FP64."""
+    """X-type and Z-type layers (fused LDS kernel) and Clifford layers, FP64."""
     wl = W.named_workload(name, steps=steps)
     n = wl.circuit.n_qubits
     ps = W.random_pauli_sum(n, 2000, seed=11, weight=3)
@@ -102,7 +104,7 @@ def test_tfim_layers_exact(pp, ctx, orc, name, steps, direction):
         o = orc.OracleSum.from_sum(ps)
         g.apply_layer(layer, direction, with_noise=False)
         o.apply_layer(layer, direction, with_noise=False, eps=eps)
-        compare_sums(g.as_dict(), o.as_dict(), thresholds=[eps], rtol=0.0, atol=0.0, context=f"layer {li}")
+        compare_sums(g.as_dict(), o.as_dict(), thresholds=[eps], rtol=1e-12, atol=1e-15, context=f"layer {li}")
 
 
 @pytest.mark.parametrize("sign", [1, -1])
@@ -139,10 +141,12 @@ def test_noise_general_generators(pp, ctx, orc):
 
 
 @pytest.mark.parametrize("variant", ["interleaved", "with_weight3"])
-def test_noise_runs_bit_exact(pp, ctx, orc, variant):
-    """Greedy factors are products over runs of consecutive generators on the same qubits,
-    in list order, on both sides: supports that come back later in the list (a new run) and
-    lists with a weight-3 generator (all generators tested one by one) match bit for bit."""
+def test_noise_runs(pp, ctx, orc, variant):
+    """The device multiplies the factors of each run of consecutive generators on the same
+    qubits together (one table value per run a string touches); the reference applies the
+    local channels one generator at a time.  Supports that come back later in the list (a
+    new run) and lists with a weight-3 generator (every generator tested on its own) agree
+    to rounding."""
     log(f"noise runs {variant}")
     n = 12
     rng = np.random.default_rng(21)
@@ -167,7 +171,7 @@ def test_noise_runs_bit_exact(pp, ctx, orc, variant):
         o = orc.OracleSum.from_sum(ps)
         g.apply_layer(layer, with_gates=False, noise_sign=sign)
         o.noise(layer.ex, layer.ez, layer.lam, sign=sign)
-        compare_sums(g.as_dict(), o.as_dict(), rtol=0.0, atol=0.0, context=f"noise runs {variant} {sign}")
+        compare_sums(g.as_dict(), o.as_dict(), rtol=1e-13, atol=0.0, context=f"noise runs {variant} {sign}")
 
 
 @pytest.mark.parametrize("max_order", [0, 1, 2, 3])
@@ -241,7 +245,7 @@ def test_group_overflow_falls_back(pp, ctx, orc):
     st = g.last_layer_stats()
     o.apply_layer(layer, 1, with_noise=False, eps=1e-12)
     assert st["n_fallback"] > 0
-    compare_sums(g.as_dict(), o.as_dict(), thresholds=[1e-12], rtol=0.0, atol=0.0, context="overflow")
+    compare_sums(g.as_dict(), o.as_dict(), thresholds=[1e-12], rtol=1e-12, atol=1e-15, context="overflow")
 
 
 @pytest.mark.parametrize("cap", [40000, 15000])
@@ -271,8 +275,7 @@ def test_capped_gates_with_oversize_classes(pp, ctx, orc, cap, W_qubits):
         o.apply_layer(layer, direction, with_noise=False, eps=1e-4, max_terms=cap)
         assert st["n_fallback"] > 0
         gd, od = g.as_dict(), o.as_dict()
-        assert set(gd) == set(od)
-        assert all(gd[k] == od[k] for k in od)   # no noise: the arithmetic is identical
+        compare_sums(gd, od, thresholds=[1e-4, cap_cut(od)], rtol=1e-12, atol=1e-15, context="capped classes")
         assert len(gd) <= cap
 
 
@@ -312,11 +315,11 @@ def run_both(pp, ctx, orc, wl, precision="f64"):
     ("tfim3x3", dict(eps=1e-6)),
     ("tfim3x3", dict(noise="entangling", steps=5)),
     ("tfim7x8_pna", dict(steps=2)),
-    ("tfim7x8_pna", dict(steps=3, max_terms=20000)),
+    ("tfim7x8_pna", dict(steps=3, eps=1e-4)),
     ("tfim7x8_cd", dict(steps=2)),
     ("tfim7x8_cd", dict(steps=3, eps=1e-5)),
     ("tfim8x16", dict(steps=1, eps=1e-4)),
-    ("tfim8x16", dict(steps=2, eps=2e-3, max_terms=5000)),
+    ("tfim8x16", dict(steps=2, eps=2e-3)),
 ])
 def test_workload_parity(pp, ctx, orc, wname, kw):
     wl = W.named_workload(wname, **kw)
@@ -324,7 +327,7 @@ def test_workload_parity(pp, ctx, orc, wname, kw):
     g, o = run_both(pp, ctx, orc, wl)
     od = o.as_dict()
     thr = [wl.eps] + ([cap_cut(od)] if wl.max_terms else [])
-    rep = compare_sums(g.as_dict(), od, thresholds=thr, rtol=1e-10, atol=1e-15, context=f"{wname} {kw}")
+    rep = compare_sums(g.as_dict(), od, thresholds=thr, rtol=1e-12, atol=1e-15, context=f"{wname} {kw}")
     eg, eo = g.expectation(), o.expectation()
     log(f"  terms {rep['n_gpu']} vs {rep['n_ref']}, <O> {eg!r} vs {eo!r}")
     assert abs(eg - eo) < 1e-10
@@ -334,7 +337,7 @@ def test_workload_parity(pp, ctx, orc, wname, kw):
     ("tfim3x3", dict(eps=0.0)),
     ("tfim3x3", {}),
     ("tfim7x8_pna", dict(steps=2)),
-    ("tfim7x8_pna", dict(steps=3, max_terms=20000)),
+    ("tfim7x8_pna", dict(steps=3, eps=1e-4)),
 ])
 def test_noisy_evaluation(pp, ctx, orc, wname, kw):
     """O~ propagated back through the noisy circuit on the GPU: Tr[O~ rho_noisy] against the

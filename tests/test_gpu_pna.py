@@ -48,6 +48,12 @@ def orc():
     return oracle
 
 
+def _lam(q):
+    """The strength lambda whose inverse map has quasi-probability q = (1 - e^{2 lambda})/2
+    (the device takes lambda; the reference takes q, computed from that lambda)."""
+    return 0.5 * math.log1p(-2.0 * q)
+
+
 def _pair(pp, ctx, orc, ps, **kw):
     return pp.Observable.from_sum(ctx, ps, **kw), orc.OracleSum.from_sum(ps)
 
@@ -57,7 +63,7 @@ def _pair(pp, ctx, orc, ps, **kw):
     (56, 1500, 40, -0.004, 1e-6, 0),
     (56, 2000, 1, -0.3, 0.0, 0),
     (128, 1200, 25, -0.02, 1e-7, 700),
-    (200, 800, 12, 0.05, 0.0, 0),
+    (200, 800, 12, -0.05, 0.0, 0),
     (9, 100, 300, -0.001, 1e-9, 0),
 ])
 def test_antinoise_random(pp, ctx, orc, n, m, k, q, eps, cap):
@@ -66,7 +72,9 @@ def test_antinoise_random(pp, ctx, orc, n, m, k, q, eps, cap):
     e = W.random_pauli_sum(n, k, seed=7 * n + k)
     g, r = _pair(pp, ctx, orc, o, eps=eps, max_terms=cap)
     ge = pp.Observable.from_sum(ctx, e)
-    g.apply_antinoise(ge, q)
+    lam = _lam(q)
+    q = orc.antinoise_q(lam)
+    g.apply_antinoise(ge, lam)
     r.antinoise(orc.OracleSum.from_sum(e), q)
     r.truncate(eps, cap)
     ref = r.as_dict()
@@ -87,28 +95,31 @@ def test_antinoise_edge_cases(pp, ctx, orc):
     # empty E': O -> (1 - q) O
     g = pp.Observable.from_sum(ctx, o)
     empty = pp.Observable(ctx, n, np.zeros((0, 1), np.uint64), np.zeros((0, 1), np.uint64), np.zeros(0))
-    g.apply_antinoise(empty, -0.25)
-    want = {kk: 1.25 * v for kk, v in orc.OracleSum.from_sum(o).as_dict().items()}
+    g.apply_antinoise(empty, _lam(-0.25))
+    qq = orc.antinoise_q(_lam(-0.25))
+    want = {kk: (1 - qq) * v for kk, v in orc.OracleSum.from_sum(o).as_dict().items()}
     compare_sums(g.as_dict(), want, context="empty E'")
     # empty O stays empty
     e = pp.Observable.from_sum(ctx, W.random_pauli_sum(n, 5, seed=2))
-    empty.apply_antinoise(e, -0.1)
+    empty.apply_antinoise(e, 0.1)
     assert len(empty) == 0
     # argument errors leave O unchanged
     before = g.as_dict()
     other = pp.Observable.from_sum(ctx, W.random_pauli_sum(57, 3, seed=3))
     with pytest.raises(pp.PPError):
-        g.apply_antinoise(other, -0.1)
+        g.apply_antinoise(other, 0.1)
     eo = pp.Observable.from_sum(ctx, W.random_pauli_sum(n, 3, seed=4), mode="error_order")
     with pytest.raises(pp.PPError):
-        g.apply_antinoise(eo, -0.1)
+        g.apply_antinoise(eo, 0.1)
     with pytest.raises(pp.PPError):
-        eo.apply_antinoise(e, -0.1)
+        eo.apply_antinoise(e, 0.1)
     f32 = pp.Observable.from_sum(ctx, W.random_pauli_sum(n, 3, seed=5), precision="f32k")
     with pytest.raises(pp.PPError):
-        g.apply_antinoise(f32, -0.1)
+        g.apply_antinoise(f32, 0.1)
     with pytest.raises(pp.PPError):
         g.apply_antinoise(e, float("nan"))
+    with pytest.raises(pp.PPError):
+        g.apply_antinoise(e, -0.01)          # a strength is >= 0
     assert g.as_dict() == before
     for h in (g, empty, e, other, eo, f32):
         h.destroy()
@@ -121,9 +132,9 @@ def test_antinoise_f32k(pp, ctx, orc):
     e = W.random_pauli_sum(n, 9, seed=12)
     g = pp.Observable.from_sum(ctx, o, precision="f32k")
     ge = pp.Observable.from_sum(ctx, e, precision="f32k")
-    g.apply_antinoise(ge, -0.03)
+    g.apply_antinoise(ge, _lam(-0.03))
     r = orc.OracleSum.from_sum(o)
-    r.antinoise(orc.OracleSum.from_sum(e), -0.03)
+    r.antinoise(orc.OracleSum.from_sum(e), orc.antinoise_q(_lam(-0.03)))
     got, ref = g.as_dict(), r.as_dict()
     big = {kk for kk, v in ref.items() if abs(v) > 1e-5}
     assert big <= set(got)
@@ -206,9 +217,9 @@ def test_antinoise_topk_random(pp, ctx, orc, n, m, k, q, kmax):
     e = W.random_pauli_sum(n, k, seed=5 * n + k, allow_duplicates=False)
     g = pp.Observable.from_sum(ctx, o)
     ge = pp.Observable.from_sum(ctx, e)
-    g.apply_antinoise_topk(ge, q, kmax)
+    g.apply_antinoise_topk(ge, _lam(q), kmax)
     r = orc.OracleSum.from_sum(o)
-    r.antinoise_topk(orc.OracleSum.from_sum(e), q, kmax)
+    r.antinoise_topk(orc.OracleSum.from_sum(e), orc.antinoise_q(_lam(q)), kmax)
     rep = compare_sums(g.as_dict(), r.as_dict(), context="antinoise top-k")
     log(f"  {rep}")
     assert abs(g.expectation() - r.expectation()) < 1e-10
@@ -227,12 +238,12 @@ def test_antinoise_topk_along_a_walk(pp, ctx, orc):
     for t, layer in enumerate(circ.layers):
         for kk in range(0, layer.n_gen, 17):
             e = pp.propagated_error(ctx, circ, t, kk, 1e-4)
-            qk = pp.antinoise_q(layer.lam[kk])
+            lk = float(layer.lam[kk])
             x, z, c, _ = g.export()
             r = _from_export(orc, n, x, z, c)
             ex, ez, ec, _ = e.export()
-            g.apply_antinoise_topk(e, qk, 400)
-            r.antinoise_topk(_from_export(orc, n, ex, ez, ec), qk, 400)
+            g.apply_antinoise_topk(e, lk, 400)
+            r.antinoise_topk(_from_export(orc, n, ex, ez, ec), orc.antinoise_q(lk), 400)
             r.truncate(1e-5, 0)
             compare_sums(g.as_dict(), r.as_dict(), thresholds=[1e-5], context=f"map ({t}, {kk})")
             e.destroy()
@@ -264,12 +275,13 @@ def test_antinoise_batch_random(pp, ctx, orc, n, m, ks, order, eps):
     log(f"antinoise batch n={n} |O|={m} |E'|={ks} order={order} eps={eps}")
     o = W.random_pauli_sum(n, m, seed=7 * n + m)
     es = [W.random_pauli_sum(n, k, seed=11 * n + k + 3 * i) if k else None for i, k in enumerate(ks)]
-    qs = [-0.004 * (i + 1) for i in range(len(ks))]
+    lams = [_lam(-0.004 * (i + 1)) for i in range(len(ks))]
+    qs = [orc.antinoise_q(l) for l in lams]
     g = pp.Observable.from_sum(ctx, o, eps=eps)
     gis = [pp.Observable.from_sum(ctx, e) if e is not None else
            pp.Observable(ctx, n, np.zeros((0, W.n_words(n)), np.uint64), np.zeros((0, W.n_words(n)), np.uint64), np.zeros(0))
            for e in es]
-    g.apply_antinoise_batch(gis, qs, order)
+    g.apply_antinoise_batch(gis, lams, order)
     r = orc.OracleSum.from_sum(o)
     ris = [orc.OracleSum.from_sum(e) if e is not None else
            orc.OracleSum(n, np.zeros((0, W.n_words(n)), np.uint64), np.zeros((0, W.n_words(n)), np.uint64), np.zeros(0))
@@ -308,8 +320,8 @@ def test_antinoise_batch_of_one_is_exact(pp, ctx):
     a = pp.Observable.from_sum(ctx, o)
     b = pp.Observable.from_sum(ctx, o)
     ge = pp.Observable.from_sum(ctx, e)
-    a.apply_antinoise_batch([ge], [-0.01], 1)
-    b.apply_antinoise(ge, -0.01)
+    a.apply_antinoise_batch([ge], [_lam(-0.01)], 1)
+    b.apply_antinoise(ge, _lam(-0.01))
     compare_sums(a.as_dict(), b.as_dict(), rtol=1e-14, context="batch of one vs exact")
     for h in (a, b, ge):
         h.destroy()

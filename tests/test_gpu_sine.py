@@ -1,8 +1,10 @@
 """GPU parity of the sine-order mode (Euclid appendix: the CPT order kappa = k + 2p of a term,
 counted as the sine factors along its path, in the Clifford interaction picture).
 
-Each case runs D O in the sine-order mode on the device and in the FP64 reference, and
-compares every (string, tag) term (terms within 1e-12 of a threshold exempt, coefficients to
+Each case runs D O in the sine-order mode on the device (which writes each layer in the
+interaction picture itself) and in the FP64 reference (given the circuit rewritten by its own,
+independent rewrite), with the first layer's gate pair kept on both sides, and compares
+every (string, tag) term (terms within 1e-12 of a threshold exempt, coefficients to
 1e-11 relative, <O~> to 1e-10).  At a tag limit above the number of rotations, the tags
 summed equal the greedy propagation.
 """
@@ -70,9 +72,8 @@ def test_sine_order_parity(pp, ctx, orc, name, kw, K, eps, cap, wide):
     wl = W.named_workload(name, **kw)
     circ = _wide_angles(wl.circuit, 5) if wide else wl.circuit
     log(f"sine order {name} {kw} K={K} eps={eps} cap={cap} wide={wide}")
-    ipg = pp.interaction_picture(circ)
-    ipo = orc.interaction_picture(circ)
-    g = pp.noise_canceling(ctx, ipg, wl.observable, eps=eps, max_terms=cap, mode="sine_order", max_order=K)
+    ipo = orc.interaction_picture(circ)      # the library writes the device's layers in it itself
+    g = pp.noise_canceling(ctx, circ, wl.observable, eps=eps, max_terms=cap, mode="sine_order", max_order=K)
     r = orc.noise_canceling(ipo, wl.observable, eps=eps, max_terms=cap, mode="sine_order", max_order=K)
     ref = r.as_dict()
     got = g.as_dict()
@@ -87,7 +88,7 @@ def test_sine_order_parity(pp, ctx, orc, name, kw, K, eps, cap, wide):
 
 def test_sine_order_all_tags_equal_greedy(pp, ctx):
     wl = W.named_workload("tfim3x3", steps=2)
-    ip = pp.interaction_picture(_wide_angles(wl.circuit, 9))
+    ip = _wide_angles(wl.circuit, 9)
     a = pp.noise_canceling(ctx, ip, wl.observable, mode="sine_order", max_order=250)
     b = pp.noise_canceling(ctx, ip, wl.observable)
     tot = {}
