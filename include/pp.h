@@ -205,6 +205,17 @@ pp_status pp_truncate(pp_obs* obs, double eps, int64_t max_terms);
  * NULL for |0...0>.  In PP_MODE_ERROR_ORDER all orders are summed. */
 pp_status pp_expectation(pp_obs* obs, const uint64_t* basis, double* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): pp_expectation without any allocation.
+ * Same arguments, result and errors as pp_expectation, up to the order of the FP64 sum (the
+ * terms' storage order here, canonical order there: the two differ by rounding only).  The
+ * block partials live in a fixed device array of 2080 doubles (16.6 KB) per GPU, held until
+ * the process ends; the workgroups stride over the terms, so an observable of any size fits
+ * in it.  Every call on one GPU shares that array: calls that overlap on one GPU (several
+ * host threads, or several streams) race and must be serialised by the caller.  The array's
+ * address is taken when the first context is created on a device. */
+pp_status pp_expectation_noalloc(pp_obs* obs, const uint64_t* basis, double* out);
+
 /* Current number of terms (distinct (string, order) entries). */
 pp_status pp_size(pp_obs* obs, int64_t* out);
 

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -54,6 +55,39 @@ inline uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 inline int ceil_log2(uint64_t v) { int k = 0; while ((1ULL << k) < v) ++k; return k; }
 inline int floor_log2(uint64_t v) { int k = 0; while ((2ULL << k) <= v) ++k; return k; }
 
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// Scratch of the allocation-free expectation (pp_expectation_noalloc): one FP64 partial per
+// workgroup of k_expect (at most kNoAllocBlocks) and the reduced value after them.  Each GPU
+// the library runs on holds its own copy until the process ends.  Host code never passes the
+// array's name to a kernel: it uses the device address that hipGetSymbolAddress returned for
+// the current device when a context was created there (scratch_of).
+// ---------------------------------------------------------------------------------------------
+constexpr unsigned kNoAllocBlocks = 2048;
+static __device__ __align__(256) double scratch[kNoAllocBlocks + 32];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_addr;   // per device ordinal, set by pp_ctx_create
+
+// Record this device's address of `scratch` (the device must be current).  Called once per
+// device, at the first context created on it.
+void register_scratch(int device, int count) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_addr.size() < count) g_scratch_addr.resize((size_t)count, nullptr);
+  if (g_scratch_addr[(size_t)device]) return;
+  void* p = nullptr;
+  HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) throw_fail(PP_ERR_DEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+  g_scratch_addr[(size_t)device] = (double*)p;
+}
+
+double* scratch_of(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || (size_t)device >= g_scratch_addr.size()) return nullptr;
+  return g_scratch_addr[(size_t)device];
+}
 }  // namespace
 
 // ---------------------------------------------------------------------------------------------
@@ -259,6 +293,7 @@ struct EngineBase {
   virtual void antinoise_topk(const EngineBase* eprime, double q, int64_t k) = 0;
   virtual void antinoise_batch(const std::vector<const EngineBase*>& eprimes, const double* q, int order) = 0;
   virtual double expectation(const uint64_t* basis) = 0;
+  virtual double expectation_noalloc(const uint64_t* basis, double* dev_scratch) = 0;
   virtual void export_terms(uint64_t* x, uint64_t* z, double* c, uint8_t* o) = 0;
   virtual uint64_t size() const = 0;
 };
@@ -2167,6 +2202,32 @@ struct Engine final : EngineBase {
     return v;
   }
 
+  // <b|O|b> with no allocation: k_expect over all N slots (it skips non-diagonal strings)
+  // with its workgroup partials in the caller-given device scratch, the reduction into the
+  // slot after them, and one copy to the context's pinned host word.  The sum runs in the
+  // terms' storage order, so it can differ from expectation()'s canonical-order sum by
+  // rounding.  No instrumentation (which would allocate events).
+  double expectation_noalloc(const uint64_t* basis, double* dev_scratch) override {
+    GroupMask b;
+    for (int w = 0; w < PP_MAXW; ++w) { b.mx[w] = 0; b.mz[w] = 0; }
+    if (basis)
+      for (int w = 0; w < W; ++w) b.mz[w] = basis[w];
+    const uint64_t n = N;
+    const unsigned nb = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(kNoAllocBlocks, cdiv(n, 256)));
+    double* part = dev_scratch;
+    double* outd = dev_scratch + kNoAllocBlocks;
+    const Terms<CT> t = cur.view();
+    hipLaunchKernelGGL((k_expect<W, CT>), dim3(nb), dim3(256), 0, st, t, n, b, part);
+    ctx->check_launch();
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, st, (const double*)part, (int)nb, outd);
+    ctx->check_launch();
+    HIPCHK(hipMemcpyAsync(ctx->pinned, outd, 8, hipMemcpyDeviceToHost, st));
+    sync();
+    double v = 0.0;
+    std::memcpy(&v, ctx->pinned, 8);
+    return v;
+  }
+
   void export_terms(uint64_t* x, uint64_t* z, double* c, uint8_t* o) override {
     if (N == 0) return;
     const uint64_t n = N;
@@ -2282,6 +2343,7 @@ pp_status pp_ctx_create(int device, void* hip_stream, pp_alloc_fn alloc, pp_rele
     HIPCHK(hipGetDeviceCount(&count));
     if (device < 0 || device >= count) throw_fail(PP_ERR_INVALID, "device index out of range");
     HIPCHK(hipSetDevice(device));
+    register_scratch(device, count);
     auto* c = new pp_ctx;
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
@@ -2475,6 +2537,20 @@ pp_status pp_expectation(pp_obs* obs, const uint64_t* basis, double* out) {
   const pp_status s = guarded([&] {
     HIPCHK(hipSetDevice(obs->ctx->device));
     *out = obs->eng->expectation(basis);
+  });
+  if (s == PP_ERR_DEVICE || s == PP_ERR_OOM) obs->broken = true;
+  return s;
+}
+
+pp_status pp_expectation_noalloc(pp_obs* obs, const uint64_t* basis, double* out) {
+  if (!obs || !out) { g_last_error = "NULL argument"; return PP_ERR_INVALID; }
+  if (obs->broken) { g_last_error = "observable is unusable after an earlier device error"; return PP_ERR_INVALID; }
+  if (basis && !strings_ok(obs->n_qubits, obs->W, 1, basis, basis)) { g_last_error = "basis bits above n_qubits"; return PP_ERR_INVALID; }
+  double* scr = scratch_of(obs->ctx->device);
+  if (!scr) { g_last_error = "no scratch address recorded for this device"; return PP_ERR_DEVICE; }
+  const pp_status s = guarded([&] {
+    HIPCHK(hipSetDevice(obs->ctx->device));
+    *out = obs->eng->expectation_noalloc(basis, scr);
   });
   if (s == PP_ERR_DEVICE || s == PP_ERR_OOM) obs->broken = true;
   return s;

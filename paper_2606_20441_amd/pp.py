@@ -86,7 +86,7 @@ def _release_all():
             pass
 
 EXPORTED = ["pp_ctx_create", "pp_ctx_destroy", "pp_create_observable", "pp_apply_layer", "pp_truncate",
-            "pp_expectation", "pp_size", "pp_export", "pp_destroy", "pp_last_error", "pp_timing_enable",
+            "pp_expectation", "pp_expectation_noalloc", "pp_size", "pp_export", "pp_destroy", "pp_last_error", "pp_timing_enable",
             "pp_timing_read", "pp_last_layer_stats"]
 
 
@@ -120,6 +120,8 @@ def lib():
         L.pp_truncate.restype = C.c_int
         L.pp_expectation.argtypes = [C.c_void_p, _u64p, _f64p]
         L.pp_expectation.restype = C.c_int
+        L.pp_expectation_noalloc.argtypes = [C.c_void_p, _u64p, _f64p]
+        L.pp_expectation_noalloc.restype = C.c_int
         L.pp_size.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
         L.pp_size.restype = C.c_int
         L.pp_export.argtypes = [C.c_void_p, _u64p, _u64p, _f64p, _u8p]
@@ -164,6 +166,7 @@ class Context:
         self.limit_bytes = limit_bytes
         self.live_bytes = 0
         self.peak_bytes = 0
+        self.n_allocs = 0
         self._sizes = {}
         if torch_allocator:
             dev = torch.device("cuda", device)
@@ -178,6 +181,7 @@ class Context:
                 except Exception:
                     return None
                 self._sizes[p] = nbytes
+                self.n_allocs += 1
                 self.live_bytes += nbytes
                 self.peak_bytes = max(self.peak_bytes, self.live_bytes)
                 return p
@@ -313,6 +317,13 @@ class Observable:
         out = C.c_double()
         b = None if basis is None else _words(basis, self.W).reshape(-1)
         _check(lib().pp_expectation(self._h, _ptr(b, _u64p), C.byref(out)))
+        return float(out.value)
+
+    def expectation_noalloc(self, basis=None) -> float:
+        """<b|O|b> without any device allocation (``pp_expectation_noalloc``)."""
+        out = C.c_double()
+        b = None if basis is None else _words(basis, self.W).reshape(-1)
+        _check(lib().pp_expectation_noalloc(self._h, _ptr(b, _u64p), C.byref(out)))
         return float(out.value)
 
     def __len__(self) -> int:
