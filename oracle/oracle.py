@@ -275,7 +275,8 @@ def propagated_error(circuit, t: int, k: int, eps_fwd: float = 0.0, max_terms_fw
 
 
 def pna(circuit, observable, eps: float = 0.0, max_terms: int = 0, eps_fwd: float = 0.0,
-        max_terms_fwd: int = 0, max_products: int = 0, batch: int = 1, batch_order: int = 1) -> OracleSum:
+        max_terms_fwd: int = 0, max_products: int = 0, batch: int = 1, batch_order: int = 1,
+        fwd_cap: str = "gate") -> OracleSum:
     """Propagated noise absorption (Section I.A).  The hardware circuit is
     C_noisy = N_M G_M .. N_1 G_1.  Writing each ideal layer as N_t^{-1} N_t G_t and carrying
     the inverse maps to the end one at a time, from t = 1 up, through the later gates only,
@@ -287,20 +288,33 @@ def pna(circuit, observable, eps: float = 0.0, max_terms: int = 0, eps_fwd: floa
     commute).  After every update |c| < eps is dropped and the cap applied.  With
     max_products > 0, E' O E' keeps only that many most significant products (Appendix B).
     With batch > 1, a layer's maps are taken batch at a time, each batch expanded to
-    batch_order in the number of errors (Appendix C), then truncated once."""
+    batch_order in the number of errors (Appendix C), then truncated once.
+    fwd_cap="gate": each E' keeps its max_terms_fwd largest terms after every non-Clifford
+    gate of its propagation; "final": only the eps_fwd threshold during the propagation, and
+    the max_terms_fwd largest terms of the evolved E' kept once, before it is absorbed."""
+    if fwd_cap not in ("gate", "final"):
+        raise ValueError("fwd_cap must be 'gate' or 'final'")
+
+    def evolved(t, k):
+        if fwd_cap == "gate":
+            return propagated_error(circuit, t, k, eps_fwd, max_terms_fwd)
+        e = propagated_error(circuit, t, k, eps_fwd, 0)
+        e.truncate(0.0, max_terms_fwd)
+        return e
+
     o = observable.clone() if isinstance(observable, OracleSum) else OracleSum.from_sum(observable)
     if batch > 1:
         for t, layer in enumerate(circuit.layers):
             lam = np.asarray(layer.lam, np.float64)
             for k0 in range(0, layer.n_gen, batch):
                 ks = range(k0, min(k0 + batch, layer.n_gen))
-                es = [propagated_error(circuit, t, k, eps_fwd, max_terms_fwd) for k in ks]
+                es = [evolved(t, k) for k in ks]
                 o.antinoise_batch(es, [antinoise_q(float(lam[k])) for k in ks], batch_order, eps)
                 o.truncate(eps, max_terms)
         return o
     for t, layer in enumerate(circuit.layers):
         for k in range(layer.n_gen):
-            e = propagated_error(circuit, t, k, eps_fwd, max_terms_fwd)
+            e = evolved(t, k)
             qk = antinoise_q(float(np.asarray(layer.lam)[k]))
             if max_products > 0:
                 o.antinoise_topk(e, qk, max_products)

@@ -322,14 +322,17 @@ void antinoise(or_sum* s, const or_sum* e, double q) {
   s->m.swap(out);
 }
 
-// Approximate conjugation by the most significant products (Appendix B, Algorithm
-// heuristic-conjugation): of the products P_i P P_j over ordered index triplets
-// (i, term of O, j), only those with the k largest magnitudes mu = |alpha| (|beta_i|
-// |beta_j|) enter E' O E'.  Reading for ties: every product whose mu equals the k-th
-// largest is kept as well, so two orders of one pair (equal mu) are never split and the
-// result stays Hermitian; without a tie at the cut this is the set the paper's
-// priority-queue search pops.  k <= 0, or k at least the number of triplets, keeps all.
-// Written as the definition: every triplet's mu, sorted, the k-th taken as the cut.
+// Approximate conjugation by the most significant products (Appendix B, the heuristic
+// conjugation of large Pauli sums): E' O E' is a sum of products P_a P P_b over index
+// triplets (a, term of O, b) with magnitudes mu = |c| (|e_a| |e_b|).  Reading used here:
+// the products with a = b (P_a P P_a = +-P), which together with (1 - q) O make up the
+// part of the update that leaves every term on its own string (for an E' of unit weight,
+// exactly O where E' commutes with it; compare the commutator form of Appendix A), are
+// always kept; the limit applies to the triplets with a != b, of which the k largest mu
+// are kept, every triplet tied with the k-th as well (both orders of a pair have equal mu,
+// so they stay together and the result is Hermitian).  k <= 0, or k at least the number of
+// such triplets, keeps all: the exact update.  Written as the definition: every off-diagonal
+// triplet's mu, sorted, the k-th taken as the cut.
 void antinoise_topk(or_sum* s, const or_sum* e, double q, int64_t k) {
   if (e->W != s->W || e->n != s->n) fail("E' and O must have the same qubit count");
   if (!std::isfinite(q)) fail("q must be finite");
@@ -337,13 +340,14 @@ void antinoise_topk(or_sum* s, const or_sum* e, double q, int64_t k) {
   std::vector<std::pair<Key, double>> ev(e->m.begin(), e->m.end());
   std::vector<std::pair<Key, double>> ov(s->m.begin(), s->m.end());
   double cut = 0.0;
-  const uint64_t n_trip = (uint64_t)ov.size() * ev.size() * ev.size();
+  const uint64_t n_trip = (uint64_t)ov.size() * ev.size() * (ev.size() ? ev.size() - 1 : 0);
   if (k > 0 && (uint64_t)k < n_trip) {
     std::vector<double> mu;
     mu.reserve(n_trip);
     for (const auto& p : ov)
-      for (const auto& a : ev)
-        for (const auto& b : ev) mu.push_back(std::fabs(p.second) * (std::fabs(a.second) * std::fabs(b.second)));
+      for (size_t a = 0; a < ev.size(); ++a)
+        for (size_t b = 0; b < ev.size(); ++b)
+          if (a != b) mu.push_back(std::fabs(p.second) * (std::fabs(ev[a].second) * std::fabs(ev[b].second)));
     std::sort(mu.begin(), mu.end(), [](double x, double y) { return x > y; });
     cut = mu[(size_t)k - 1];
   }
@@ -354,9 +358,11 @@ void antinoise_topk(or_sum* s, const or_sum* e, double q, int64_t k) {
     const Key& p = kv.first;
     const double c = kv.second;
     acc[p] += (1.0 - q) * c;
-    for (const auto& ea : ev) {
-      for (const auto& eb : ev) {
-        if (!(std::fabs(c) * (std::fabs(ea.second) * std::fabs(eb.second)) >= cut)) continue;
+    for (size_t a = 0; a < ev.size(); ++a) {
+      for (size_t b = 0; b < ev.size(); ++b) {
+        const auto& ea = ev[a];
+        const auto& eb = ev[b];
+        if (a != b && !(std::fabs(c) * (std::fabs(ea.second) * std::fabs(eb.second)) >= cut)) continue;
         Key t, r;
         const int k1 = pauli_mul(ea.first, p, W, &t);
         const int k2 = pauli_mul(t, eb.first, W, &r);

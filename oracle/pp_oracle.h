@@ -63,8 +63,9 @@ void    or_truncate(or_sum* s, double eps, int64_t max_terms);
 /* O -> (1 - q) O + q E' O E' for E' = eprime (Section I.A, Eq. applyantinoise); exact zeros
  * dropped, no other truncation.  eprime must have the same qubit count. */
 void    or_antinoise(or_sum* s, const or_sum* eprime, double q);
-/* As or_antinoise, with E' O E' limited to the products P_i P P_j of the k largest
- * |alpha||beta_i||beta_j| (Appendix B's heuristic conjugation); ties with the k-th kept. */
+/* As or_antinoise, with E' O E' limited to the products P_i P P_j (i != j) of the k largest
+ * |alpha||beta_i||beta_j| (Appendix B's heuristic conjugation); ties with the k-th kept; the
+ * products with i = j (P_i P P_i = +-P) are always kept. */
 void    or_antinoise_topk(or_sum* s, const or_sum* eprime, double q, int64_t k);
 /* A batch of C commuting antinoise maps to first (order 1) or second (order 2) order in
  * the number of errors (Appendix C); exact for C = 1; the second-order pass takes the

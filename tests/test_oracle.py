@@ -570,25 +570,31 @@ def test_pna_threshold_and_cap_after_every_update(oracle_lib):
 # Heuristic conjugation (Appendix B): E' O E' limited to the most significant products.
 # --------------------------------------------------------------------------------------
 def _top_products_conjugation(n, a, b, k):
-    """E' O E' restricted to its k most significant products, from the definition on
-    explicit matrices: every ordered triplet (i, s, j) of an E' term, an O term and an E'
-    term is listed with mu = |beta_i alpha_s beta_j|, the list is sorted by mu, and the
-    products beta_i alpha_s beta_j P_i P_s P_j of the first k are summed (callers pick k
-    where no tie straddles the cut)."""
+    """E' O E' with its off-diagonal products limited to the k most significant, from the
+    definition on explicit matrices: every ordered triplet (i, s, j) with i != j of an E'
+    term, an O term and an E' term is listed with mu = |beta_i alpha_s beta_j|, the list is
+    sorted by mu, and the products beta_i alpha_s beta_j P_i P_s P_j of the first k are
+    summed with every diagonal product (i = j) (callers pick k where no tie straddles the
+    cut)."""
     B = _brute()
     pa = [(a.c[t], B.PauliOp(n, a.x[t], a.z[t]).matrix()) for t in range(len(a.c))]
     pb = [(b.c[t], B.PauliOp(n, b.x[t], b.z[t]).matrix()) for t in range(len(b.c))]
     trip = [(abs(pb[i][0] * pa[s][0] * pb[j][0]), i, s, j)
-            for i in range(len(pb)) for s in range(len(pa)) for j in range(len(pb))]
+            for i in range(len(pb)) for s in range(len(pa)) for j in range(len(pb)) if i != j]
     trip.sort(key=lambda t: -t[0])
     out = 0
     for _, i, s, j in trip[:k]:
         out = out + pb[i][0] * pa[s][0] * pb[j][0] * (pb[i][1] @ pa[s][1] @ pb[j][1])
+    for i in range(len(pb)):
+        for s in range(len(pa)):
+            out = out + pb[i][0] * pa[s][0] * pb[i][0] * (pb[i][1] @ pa[s][1] @ pb[i][1])
     return out
 
 
 def _mus(a, b):
-    return sorted((abs(ca) * (abs(bi) * abs(bj)) for ca in a.c for bi in b.c for bj in b.c), reverse=True)
+    """Magnitudes of the off-diagonal triplets (i != j), largest first."""
+    return sorted((abs(ca) * (abs(b.c[i]) * abs(b.c[j])) for ca in a.c for i in range(len(b.c))
+                   for j in range(len(b.c)) if i != j), reverse=True)
 
 
 def test_antinoise_topk_all_products_is_exact(oracle_lib):
@@ -596,7 +602,7 @@ def test_antinoise_topk_all_products_is_exact(oracle_lib):
     o = W.random_pauli_sum(5, 20, seed=32, allow_duplicates=False)
     want = oracle_lib.OracleSum.from_sum(o)
     want.antinoise(oracle_lib.OracleSum.from_sum(e), -0.02)
-    for k in (0, 6 * 6 * 20, 10 ** 9):
+    for k in (0, 6 * 5 * 20, 10 ** 9):
         got = oracle_lib.OracleSum.from_sum(o)
         got.antinoise_topk(oracle_lib.OracleSum.from_sum(e), -0.02, k)
         _assert_same_sum(_oracle_dict(got), _oracle_dict(want), 1e-15)
@@ -605,8 +611,9 @@ def test_antinoise_topk_all_products_is_exact(oracle_lib):
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_antinoise_topk_against_definition(oracle_lib, seed):
     """Wherever no tie straddles the cut, the kept products are the k most significant
-    triplets of the definition (Appendix B: the products with the largest
-    |beta_i alpha beta_j|); the update is compared on explicit 2^n matrices."""
+    off-diagonal triplets of the definition (Appendix B: the products with the largest
+    |beta_i alpha beta_j|) and every diagonal one; the update is compared on explicit 2^n
+    matrices."""
     B = _brute()
     n = 3
     e = W.random_pauli_sum(n, 5, seed=40 + seed, allow_duplicates=False)
@@ -622,6 +629,25 @@ def test_antinoise_topk_against_definition(oracle_lib, seed):
         m = (1 - q) * om + q * _top_products_conjugation(n, o, e, k)
         want = _dict_from_decomp(B.pauli_decompose(m, n, tol=1e-14), n)
         _assert_same_sum(_oracle_dict(got), want, 1e-13)
+
+
+def test_antinoise_topk_keeps_commuting_terms(oracle_lib):
+    """A term that commutes with every term of an E' of unit weight (sum e_a^2 = 1) is left
+    unchanged by the exact update, (1 - q) + q sum e_a^2 = 1, and by the product-limited one
+    for every k: the diagonal products that cancel (1 - q) are never cut, so a long walk of
+    limited updates cannot inflate O by (1 - q) per map."""
+    n = 4
+    e_terms = [({0: "Z"}, 0.6), ({1: "Z", 2: "Z"}, 0.48), ({0: "Z", 3: "Z"}, 0.64)]
+    e = W.pauli_sum(n, e_terms)
+    assert abs(float(np.sum(e.c ** 2)) - 1.0) < 1e-12
+    o = W.pauli_sum(n, [({0: "Z", 1: "Z"}, 0.7), ({0: "X", 2: "Y"}, -0.3)])
+    key = None
+    for k in (1, 2, 3, 5, 0):
+        s = oracle_lib.OracleSum.from_sum(o)
+        s.antinoise_topk(oracle_lib.OracleSum.from_sum(e), -0.2, k)
+        d = s.as_dict()
+        key = next(kk for kk in d if kk[0] == (0,) and kk[1] == (3,))   # Z0 Z1 commutes with every E' term
+        assert abs(d[key] - 0.7) < 1e-15, (k, d[key])
 
 
 def test_antinoise_topk_keeps_ties_with_the_cut(oracle_lib):
