@@ -186,13 +186,16 @@ pp_status pp_apply_antinoise_batch(pp_obs* obs, const pp_obs* const* eprimes, co
 
 /* As pp_apply_antinoise, with E' O E' approximated by its most significant products
  * (Appendix B, the heuristic conjugation of large Pauli sums): of the products P_a P P_b
- * over ordered triplets (a, term of O, b), only those whose magnitude
+ * with a != b over ordered triplets (a, term of O, b), only those whose magnitude
  * |c_P| (|e_a| |e_b|) is among the max_products largest enter; every product tied with
  * the max_products-th is kept as well, so both orders of a pair stay together and the
- * result is Hermitian.  The (1 - q) O part is exact.  max_products <= 0, or at least
- * |O| K^2, gives pp_apply_antinoise's result.  Only the kept products are expanded, so
- * the 2^31 - 1 limit applies to |O| + (kept unordered pairs); other arguments and errors
- * as pp_apply_antinoise. */
+ * result is Hermitian.  The (1 - q) O part and the products with a = b (P_a P P_a = +-P,
+ * which cancel (1 - q) on terms that commute with E') are exact, so a walk of limited
+ * updates does not inflate O.  max_products <= 0, or at least |O| K (K - 1), gives
+ * pp_apply_antinoise's result.  The pair magnitudes are sorted on the device; K <= 16384
+ * (PP_ERR_UNSUPPORTED otherwise).  Only the kept products are expanded, so the 2^31 - 1
+ * limit applies to |O| + (kept unordered pairs); other arguments and errors as
+ * pp_apply_antinoise. */
 pp_status pp_apply_antinoise_topk(pp_obs* obs, const pp_obs* eprime, double lambda, int64_t max_products);
 
 /* Explicit greedy truncation: drop |c| < eps, then keep the max_terms largest |c|
@@ -238,8 +241,12 @@ typedef struct {
   char name[48];
   int64_t launches;
   double total_ms;
-  double algo_bytes;     /* bytes the method must move for the launches' work */
+  double algo_bytes;     /* terms loaded plus terms written by the launches, times the term
+                            size: one read and one write of what each pass handled */
   double items;          /* terms processed (term-updates for layer kernels) */
+  double layer_bytes;    /* the launches' share of their layer calls' algorithmic bytes
+                            (N_in + N_out) B: algo_bytes / G for the passes of a layer whose G
+                            gates run one pass each, algo_bytes otherwise */
 } pp_kernel_stat;
 
 pp_status pp_timing_enable(pp_ctx* ctx, int enable);

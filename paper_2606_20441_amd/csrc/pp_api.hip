@@ -104,13 +104,16 @@ struct pp_ctx {
   struct Pending {
     std::string name;
     hipEvent_t a, b;
-    double bytes, items;
+    double bytes, items, share;
   };
   std::vector<Pending> pending;
   struct Acc {
     int64_t launches = 0;
-    double ms = 0, bytes = 0, items = 0;
+    double ms = 0, bytes = 0, items = 0, layer_bytes = 0;
   };
+  // Share of its layer call's algorithmic bytes (N_in + N_out) B that one pass of the
+  // current kernel stands for: 1 / G while a layer's G gates run one pass each, else 1.
+  double pass_share = 1.0;
   std::map<std::string, Acc> acc;
   std::vector<hipEvent_t> evfree;
 
@@ -148,7 +151,7 @@ struct pp_ctx {
       f();
       return -1;
     }
-    Pending p{name, ev(), ev(), bytes, items};
+    Pending p{name, ev(), ev(), bytes, items, pass_share};
     HIPCHK(hipEventRecord(p.a, stream));
     f();
     HIPCHK(hipEventRecord(p.b, stream));
@@ -165,6 +168,7 @@ struct pp_ctx {
       a.launches += 1;
       a.ms += ms;
       a.bytes += p.bytes;
+      a.layer_bytes += p.bytes * p.share;
       a.items += p.items;
       evfree.push_back(p.a);
       evfree.push_back(p.b);
@@ -272,7 +276,9 @@ const std::vector<uint32_t>& hash_tables() {
   return t;
 }
 
-constexpr uint64_t kMaxAntinoiseTerms = 4096;   // E' terms per antinoise update (16-bit pair indices)
+constexpr uint64_t kMaxAntinoiseTerms = 1ULL << 20;   // E' terms per antinoise update
+constexpr uint64_t kExpandSlab = 1ULL << 27;          // expansion slots handled at once
+constexpr uint64_t kMaxTopkTerms = 1ULL << 14;        // E' terms of a product-limited update (pairs sorted on the device)
 
 struct HostGate {
   GateDev g;
@@ -330,7 +336,7 @@ struct Engine final : EngineBase {
   TBuf<CT, ORD> gb;              // boundary candidates of a cap
   Buf u32a, u32b, u32c, scan_scr, tiles, gates_d, sup_d, tab_d, drun_d, dm_d, dval_d, cnt_d, ovf_d, partial_d, f64_d, span_d, htab_d, lstat_d;
   Buf hscr_d, tr_s0, tr_l0, tr_s1, tr_l1, g1_d, g1_ovf, g1_base, g1_base2;   // per-gate tile path
-  Buf rl0, rl1, rl2, ovl1, ovl2, tf_flag, tf_pos, tf_list, g1_io, g1_tab, g1_tabmeta, win_hist_d, pair_d, topk_d, topk_off;
+  Buf rl0, rl1, rl2, ovl1, ovl2, tf_flag, tf_pos, tf_list, g1_io, g1_tab, g1_tabmeta, win_hist_d, qlist_d, topk_d, topk_off;
   double growth[4] = {4.0, 4.0, 2.0, 3.0};
   double tile_target[4] = {80.0, 80.0, 80.0, 64.0};   // level-0 (one-wavefront) tile targets
   uint64_t last_ntiles = 1, last_ovf_tiles = 0;
@@ -340,7 +346,7 @@ struct Engine final : EngineBase {
     for (auto* t : {&ta, &tb}) { t->mem.ctx = ctx; t->W = W; }
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &drun_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
                    &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hscr_d, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &rl0, &rl1, &rl2, &ovl1, &ovl2,
-                   &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d, &pair_d, &topk_d, &topk_off})
+                   &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d, &qlist_d, &topk_d, &topk_off})
       b->ctx = ctx;
     cnt_d.ensure(256);
     span_d.ensure(256);
@@ -353,7 +359,7 @@ struct Engine final : EngineBase {
     for (auto* t : {&ta, &tb}) t->mem.release();
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &drun_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
                    &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hscr_d, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &rl0, &rl1, &rl2, &ovl1, &ovl2,
-                   &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d, &pair_d, &topk_d, &topk_off})
+                   &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d, &qlist_d, &topk_d, &topk_off})
       b->release();
   }
 
@@ -576,6 +582,8 @@ struct Engine final : EngineBase {
     std::vector<uint8_t> drun;
     std::vector<uint64_t> dm;
     std::vector<double> dval;
+    std::vector<int32_t> qoff;    // greedy: supports listed per qubit (CSR), see NoiseDev
+    std::vector<uint32_t> qent;
     int np = 1;
   };
 
@@ -679,6 +687,19 @@ struct Engine final : EngineBase {
         }
         hn.sup.push_back(sd);
       }
+      // per-qubit lists: every run under its first qubit, two-qubit runs also under their
+      // second qubit (flagged; taken there only when the first qubit is the identity)
+      const int nq = obs->n_qubits;
+      std::vector<std::vector<uint32_t>> per(nq);
+      for (size_t si = 0; si < order.size(); ++si) {
+        per[order[si].first].push_back((uint32_t)si);
+        if (order[si].second >= 0) per[order[si].second].push_back((uint32_t)si | 0x80000000u);
+      }
+      hn.qoff.assign(1, 0);
+      for (int q = 0; q < nq; ++q) {
+        for (uint32_t e : per[q]) hn.qent.push_back(e);
+        hn.qoff.push_back((int32_t)hn.qent.size());
+      }
       return hn;
     }
     std::map<std::pair<int, int>, std::vector<int>> by_sup;
@@ -739,6 +760,21 @@ struct Engine final : EngineBase {
     nd.drun = hn.drun.empty() ? nullptr : drun_d.as<uint8_t>();
     nd.dm = dm_d.as<uint64_t>();
     nd.dval = dval_d.as<double>();
+    nd.nq = 0;
+    nd.nqent = 0;
+    nd.qoff = nullptr;
+    nd.qent = nullptr;
+    if (!hn.qoff.empty()) {
+      nd.nq = (int)hn.qoff.size() - 1;
+      nd.nqent = (int)hn.qent.size();
+      qlist_d.ensure(hn.qoff.size() * 4 + hn.qent.size() * 4 + 64);
+      HIPCHK(hipMemcpyAsync(qlist_d.p, hn.qoff.data(), hn.qoff.size() * 4, hipMemcpyHostToDevice, st));
+      if (!hn.qent.empty())
+        HIPCHK(hipMemcpyAsync((char*)qlist_d.p + hn.qoff.size() * 4, hn.qent.data(), hn.qent.size() * 4,
+                              hipMemcpyHostToDevice, st));
+      nd.qoff = qlist_d.as<int32_t>();
+      nd.qent = (const uint32_t*)((const char*)qlist_d.p + hn.qoff.size() * 4);
+    }
     // The uploads above are ordered on the stream before the kernels that read them; the
     // host vectors are synchronous copies' sources, so wait for them before returning.
     sync();
@@ -1257,7 +1293,7 @@ struct Engine final : EngineBase {
   // the copy of its bins to the host.
   uint64_t win_lo = 0;
   int win_sh = 0;
-  void win_hist_launch(const CT* c, uint64_t n) {
+  void win_hist_launch(const CT* c, uint64_t n, const TileView* tv = nullptr) {
     win_sh = hint_shift;
     const uint64_t half = 1024ULL << win_sh;
     win_lo = hint_key > half ? ((hint_key - half) >> win_sh) << win_sh : 0ULL;
@@ -1268,13 +1304,22 @@ struct Engine final : EngineBase {
     const uint64_t lo = win_lo;
     const int sh = win_sh;
     ctx->run("cap_hist", sizeof(CT) * (double)n, (double)n, [&] {
-      hipLaunchKernelGGL((k_abs_hist_win<CT>), dim3(nbh), dim3(256), 0, st, c, n, lo, sh, hist);
+      if (tv)
+        hipLaunchKernelGGL((k_abs_hist_win_tiles<CT>), dim3(tile_grid(*tv)), dim3(256), 0, st, c, *tv, lo, sh, hist);
+      else
+        hipLaunchKernelGGL((k_abs_hist_win<CT>), dim3(nbh), dim3(256), 0, st, c, n, lo, sh, hist);
     });
     ctx->check_launch();
     HIPCHK(hipMemcpyAsync((char*)ctx->pinned + kPinWin, hist, 2049 * 4, hipMemcpyDeviceToHost, st));
   }
 
-  CutDev cap_cut(uint64_t K, uint64_t n) {
+  // Grid of the tile sweeps: four tiles per wavefront, four wavefronts per workgroup.
+  static unsigned tile_grid(const TileView& tv) {   // sixteen tiles per wavefront at first
+    return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(4096, cdiv(tv.ntiles, 64)));
+  }
+
+  // tv: the buffer is tiled (only the tiles' live ranges hold terms), else n dense slots.
+  CutDev cap_cut(uint64_t K, uint64_t n, const TileView* tv = nullptr) {
     constexpr uint32_t kGather = 4096;
     const int KB = sizeof(CT) == 8 ? 63 : 31;
     uint64_t prefix = 0, pmask = 0, need = K, count_eq = 0;
@@ -1288,7 +1333,7 @@ struct Engine final : EngineBase {
     if (hint_valid) {
       // The window's bins are the key prefixes above bit `shift`, so a hit continues the
       // radix passes below it; a miss falls back to the passes from the top.
-      win_hist_launch(c, n);
+      win_hist_launch(c, n, tv);
       sync();
       const int sh = win_sh;
       const uint64_t lo = win_lo;
@@ -1319,7 +1364,11 @@ struct Engine final : EngineBase {
       const int bins = 1 << bits;
       HIPCHK(hipMemsetAsync(hist, 0, bins * 4, st));
       ctx->run("cap_hist", sizeof(CT) * (double)n, (double)n, [&] {
-        hipLaunchKernelGGL((k_abs_hist<CT>), dim3(nbh), dim3(256), 0, st, c, n, shift, bits, pmask, prefix, hist);
+        if (tv)
+          hipLaunchKernelGGL((k_abs_hist_tiles<CT>), dim3(tile_grid(*tv)), dim3(256), 0, st, c, *tv, shift, bits, pmask,
+                             prefix, hist);
+        else
+          hipLaunchKernelGGL((k_abs_hist<CT>), dim3(nbh), dim3(256), 0, st, c, n, shift, bits, pmask, prefix, hist);
       });
       ctx->check_launch();
       HIPCHK(hipMemcpyAsync(ctx->pinned, hist, bins * 4, hipMemcpyDeviceToHost, st));
@@ -1347,8 +1396,12 @@ struct Engine final : EngineBase {
     const Terms<CT> t = cur.view(), g = gb.view();
     const uint64_t gcap = gb.cap;
     ctx->run("cap_gather", 0, (double)n, [&] {
-      hipLaunchKernelGGL((k_gather_bucket<W, CT, ORD>), grid1(n), dim3(256), 0, st, t, n, pmask, prefix, g, gcap,
-                         cntd);
+      if (tv)
+        hipLaunchKernelGGL((k_gather_bucket_tiles<W, CT, ORD>), dim3(tile_grid(*tv)), dim3(256), 0, st, t, *tv, pmask,
+                           prefix, g, gcap, cntd);
+      else
+        hipLaunchKernelGGL((k_gather_bucket<W, CT, ORD>), grid1(n), dim3(256), 0, st, t, n, pmask, prefix, g, gcap,
+                           cntd);
     });
     ctx->check_launch();
     const CutDev cut = rank_bucket(g, count_eq, need);   // its copies wait for the gather
@@ -1358,7 +1411,8 @@ struct Engine final : EngineBase {
   }
 
   // Drop the terms a cut removes (and exact zeros) from cur (N slots).
-  void apply_cut(const CutDev& cut, pp_layer_stats& ls) {
+  // tv: cur is tiled over its first N slots (only the tiles' live ranges hold terms).
+  void apply_cut(const CutDev& cut, pp_layer_stats& ls, const TileView* tv = nullptr) {
     if (N == 0) return;
     u32b.ensure(N * 4 + 64);
     uint32_t* keep = u32b.as<uint32_t>();
@@ -1366,8 +1420,12 @@ struct Engine final : EngineBase {
     HIPCHK(hipMemsetAsync(dd, 0, 8, st));
     const Terms<CT> t = cur.view();
     const uint64_t n = N;
+    if (tv) HIPCHK(hipMemsetAsync(keep, 0, n * 4, st));
     ctx->run("cut_flags", 0, (double)n, [&] {
-      hipLaunchKernelGGL((k_cut_keep<W, CT, ORD>), gridb(n), dim3(256), 0, st, t, n, cut, keep, dd);
+      if (tv)
+        hipLaunchKernelGGL((k_cut_keep_tiles<W, CT, ORD>), dim3(tile_grid(*tv)), dim3(256), 0, st, t, *tv, cut, keep, dd);
+      else
+        hipLaunchKernelGGL((k_cut_keep<W, CT, ORD>), gridb(n), dim3(256), 0, st, t, n, cut, keep, dd);
     });
     ctx->check_launch();
     compact_cur(keep);
@@ -1495,6 +1553,12 @@ struct Engine final : EngineBase {
   // the cut of the last gate is applied when the next pass loads the tile.
   void gate_by_gate(const std::vector<GateDev>& gates, int kind, double eps, uint64_t cap, pp_layer_stats& ls) {
     const GroupMask gm = invariant_mask(gates, kind);
+    // each gate's pass over the tiles carries 1 / G of the layer's read-once, write-once bytes
+    struct ShareGuard {
+      pp_ctx* c;
+      ~ShareGuard() { c->pass_share = 1.0; }
+    } share_guard{ctx};
+    ctx->pass_share = 1.0 / (double)std::max<size_t>(1, gates.size());
     bool need_tiles = true;
     CutDev cut{};   // the pending cut (cut.has = 0: none)
     uint64_t extent = N;      // slots of cur that hold terms or zeros
@@ -1502,11 +1566,14 @@ struct Engine final : EngineBase {
     g1_d.ensure(sizeof(G1Counters) + 64);
     G1Counters* cd = g1_d.as<G1Counters>();
     double* dropd = &cd->drop[0];
+    bool tiled = false;       // cur holds tiles (live ranges tr_s0/tr_l0 of g1_ntiles tiles)
     auto densify = [&]() {   // apply a pending cut and squeeze out the unused slots
       N = extent;
-      apply_cut(cut, ls);
+      const TileView tv{tr_s0.as<uint32_t>(), tr_l0.as<uint32_t>(), (uint32_t)g1_ntiles};
+      apply_cut(cut, ls, tiled ? &tv : nullptr);
       cut.has = 0;
       extent = N;
+      tiled = false;
     };
     for (size_t gi = 0; gi < gates.size() && N > 0; ++gi) {
       const GateDev& G = gates[gi];
@@ -1650,13 +1717,15 @@ struct Engine final : EngineBase {
       std::swap(tr_l0, tr_l1);
       std::swap(g1_base, g1_base2);
       extent = out_extent;
+      tiled = true;
       for (double v : dsl) ls.dropped_l1 += v;
       N = next_extent / 2 + giant_terms;
       out_extent = next_extent;
       ls.n_peak = std::max<int64_t>(ls.n_peak, (int64_t)N);
       cut.has = 0;
       if (!G.clifford && cap > 0 && N > cap) {
-        cut = cap_cut(cap, extent);
+        const TileView tv{tr_s0.as<uint32_t>(), tr_l0.as<uint32_t>(), (uint32_t)ntiles};
+        cut = cap_cut(cap, extent, &tv);
         ls.n_capped += (int64_t)(N - cap);
         N = cap;
       }
@@ -1922,7 +1991,44 @@ struct Engine final : EngineBase {
     const auto* e = dynamic_cast<const Engine*>(eb);
     if (!e) throw_fail(PP_ERR_UNSUPPORTED, "E' must have the same word count, precision and mode as O");
     if (N == 0) return;
-    finish_expansion(expand_items({{cur.view(), N, e, q, 1.0 - q}}));
+    const uint64_t S = slots_per_term(e->N);
+    if (N * S < kExpandSlab) {
+      finish_expansion(expand_items({{cur.view(), N, e, q, 1.0 - q}}));
+      return;
+    }
+    // Larger than one slab: the map is linear in O, so O is expanded a chunk of terms at a
+    // time; each chunk's expansion is merged without a threshold and appended to alt, and
+    // the concatenation is merged once more with the threshold, then capped.
+    const uint64_t chunk = std::max<uint64_t>(1, kExpandSlab / S);
+    uint64_t acc = 0;
+    for (uint64_t i0 = 0; i0 < N; i0 += chunk) {
+      const uint64_t n = std::min<uint64_t>(chunk, N - i0);
+      Terms<CT> part = cur.view();   // planes keep cur's stride; the chunk starts at term i0
+      part.x = cur.view().x + i0;
+      part.z = cur.view().z + i0;
+      part.c = cur.view().c + i0;
+      if (ORD) part.o = cur.view().o + i0;
+      const uint64_t m = merge_expansion(expand_items({{part, n, e, q, 1.0 - q}}), 0.0);
+      grow_keep(alt, acc + m, acc);
+      const Terms<CT> from = sa.view(), to = alt.view();
+      ctx->run("copy", 0, (double)m, [&] {
+        hipLaunchKernelGGL((k_copy<W, CT, ORD>), grid1(m), dim3(256), 0, st, from, 0, to, acc, m);
+      });
+      ctx->check_launch();
+      acc += m;
+    }
+    sa.ensure(std::max<uint64_t>(acc, 1));
+    u32b.ensure(acc * 4 + 64);
+    {
+      const Terms<CT> from = alt.view(), to = sa.view();
+      ctx->run("copy", 0, (double)acc, [&] {
+        hipLaunchKernelGGL((k_copy<W, CT, ORD>), grid1(acc), dim3(256), 0, st, from, 0, to, 0, acc);
+      });
+      ctx->check_launch();
+      hipLaunchKernelGGL(k_fill_u32, grid1(acc), dim3(256), 0, st, u32b.as<uint32_t>(), acc, 1u);
+      ctx->check_launch();
+    }
+    finish_expansion(acc);
   }
 
   // One expansion of a batch: `scale` C(X) (scale E' X E') for an E', or id X alone (e
@@ -1936,26 +2042,22 @@ struct Engine final : EngineBase {
 
   // Writes every item's slots at consecutive offsets of sa (flags in u32b); returns the
   // slot count.  Pair tables of all items go up in one copy.
+  // Slots per term of an expansion by an E' of K terms: P itself and one per unordered pair.
+  static uint64_t slots_per_term(uint64_t K) { return 1 + (K ? K * (K - 1) / 2 : 0); }
+
   uint64_t expand_items(const std::vector<ExpItem>& items) {
-    std::vector<uint64_t> S(items.size()), off(items.size() + 1, 0), poff(items.size(), 0);
-    std::vector<uint32_t> pr;
+    std::vector<uint64_t> S(items.size()), off(items.size() + 1, 0);
     for (size_t i = 0; i < items.size(); ++i) {
       const uint64_t K = items[i].e ? items[i].e->N : 0;
       if (K > kMaxAntinoiseTerms)
         throw_fail(PP_ERR_UNSUPPORTED, "E' has " + std::to_string(K) + " terms; at most " +
                                            std::to_string(kMaxAntinoiseTerms) + " are supported");
-      S[i] = 1 + (K ? K * (K - 1) / 2 : 0);
+      S[i] = slots_per_term(K);
       off[i + 1] = off[i] + items[i].n * S[i];
       if (off[i + 1] >= (1ULL << 31))
         throw_fail(PP_ERR_UNSUPPORTED, "antinoise expansion exceeds 2^31 - 1 terms");
-      poff[i] = pr.size();
-      for (uint32_t a = 0; a < K; ++a)
-        for (uint32_t b = a + 1; b < K; ++b) pr.push_back(a | (b << 16));
     }
-    pr.push_back(0);
     const uint64_t total = off.back();
-    pair_d.ensure(pr.size() * 4);
-    HIPCHK(hipMemcpyAsync(pair_d.p, pr.data(), pr.size() * 4, hipMemcpyHostToDevice, st));
     sa.ensure(std::max<uint64_t>(total, 1));
     u32b.ensure(total * 4 + 64);
     uint32_t* keep = u32b.as<uint32_t>();
@@ -1970,17 +2072,15 @@ struct Engine final : EngineBase {
       if (ORD) o.o += off[i];
       const Terms<CT> ev = it.e ? it.e->cur.view() : it.in;
       const uint32_t K = it.e ? (uint32_t)it.e->N : 0u;
-      const uint32_t* pairs = pair_d.as<uint32_t>() + poff[i];
       const uint64_t cnt = it.n * S[i];
       const unsigned grid = (unsigned)std::min<uint64_t>(cdiv(cnt, 256), 1u << 20);
       const double q = it.e ? it.scale : 0.0;
       ctx->run("antinoise_expand", kTermBytes * (double)(it.n + cnt) + 4.0 * cnt, (double)cnt, [&] {
-        hipLaunchKernelGGL((k_expand_antinoise<W, CT, ORD>), dim3(grid), dim3(256), 0, st, it.in, it.n, ev, K, pairs,
-                           S[i], q, it.id, o, keep + off[i]);
+        hipLaunchKernelGGL((k_expand_antinoise<W, CT, ORD>), dim3(grid), dim3(256), 0, st, it.in, it.n, ev, K, S[i], q,
+                           it.id, o, keep + off[i]);
       });
       ctx->check_launch();
     }
-    sync();   // the pair tables' host source goes out of scope
     return total;
   }
 
@@ -2068,47 +2168,51 @@ struct Engine final : EngineBase {
     if (!e) throw_fail(PP_ERR_UNSUPPORTED, "E' must have the same word count, precision and mode as O");
     if (N == 0) return;
     const uint64_t K = e->N;
-    if (K > kMaxAntinoiseTerms)
+    if (K > kMaxTopkTerms)
       throw_fail(PP_ERR_UNSUPPORTED, "E' has " + std::to_string(K) + " terms; at most " +
-                                         std::to_string(kMaxAntinoiseTerms) + " are supported");
-    if (kmax <= 0 || (uint64_t)kmax >= N * K * K) {
+                                         std::to_string(kMaxTopkTerms) + " are supported with a product limit");
+    if (K < 2 || kmax <= 0 || (uint64_t)kmax >= N * K * (K - 1)) {
       antinoise(eb, q);
       return;
     }
-    // pairs a <= b of E' (in device order), largest |e_a| |e_b| first
-    std::vector<CT> ec(K);
-    HIPCHK(hipMemcpyAsync(ec.data(), e->cur.view().c, K * sizeof(CT), hipMemcpyDeviceToHost, st));
-    sync();
-    const uint64_t P = K * (K + 1) / 2;
-    std::vector<std::pair<double, uint32_t>> pr;
-    pr.reserve(P);
-    for (uint32_t a = 0; a < K; ++a)
-      for (uint32_t b = a; b < K; ++b)
-        pr.push_back({std::fabs((double)ec[a]) * std::fabs((double)ec[b]), a | (b << 16)});
-    std::sort(pr.begin(), pr.end(), [](const std::pair<double, uint32_t>& x, const std::pair<double, uint32_t>& y) {
-      return x.first > y.first || (x.first == y.first && x.second < y.second);
-    });
-    // one upload: pm[P] doubles, cw[P + 1] u64, tau (one double), the slot total (u64,
-    // zero), pidx[P] u32
-    const size_t o_cw = P * 8, o_tau = o_cw + (P + 1) * 8, o_sum = o_tau + 8, o_idx = o_sum + 8;
-    std::vector<char> host(o_idx + P * 4, 0);
-    double* pm = (double*)host.data();
-    uint64_t* cw = (uint64_t*)(host.data() + o_cw);
-    uint32_t* pidx = (uint32_t*)(host.data() + o_idx);
-    cw[0] = 0;
-    for (uint64_t p = 0; p < P; ++p) {
-      pm[p] = pr[p].first;
-      pidx[p] = pr[p].second;
-      const bool diag = (pr[p].second & 0xffffu) == (pr[p].second >> 16);
-      cw[p + 1] = cw[p] + (diag ? 1 : 2);
+    // pairs a < b of E' (the limited products; a = b are always kept), largest |e_a| |e_b|
+    // first: keys generated, put in canonical order and tabulated on the device
+    const uint64_t P = K * (K - 1) / 2;
+    ta.ensure(P);
+    tb.ensure(P);
+    {
+      const Terms<double> kt = ta.view();
+      const CT* ecd = e->cur.view().c;
+      const unsigned grid = (unsigned)std::min<uint64_t>(cdiv(P, 256), 1u << 20);
+      ctx->run("topk_pairs", 0, (double)P, [&] {
+        hipLaunchKernelGGL((k_pair_keys<W, CT>), dim3(grid), dim3(256), 0, st, ecd, K, P, kt);
+      });
+      ctx->check_launch();
     }
-    topk_d.ensure(host.size());
-    HIPCHK(hipMemcpyAsync(topk_d.p, host.data(), host.size(), hipMemcpyHostToDevice, st));
+    canonical_sort(ta, tb, P);
+    // tables: pm[P] doubles, cw[P + 1] u64, tau (one double), the slot total (u64), pidx[P]
+    // u64, the weights w[P] u32 (scanned in place)
+    const size_t o_cw = P * 8, o_tau = o_cw + (P + 1) * 8, o_sum = o_tau + 8, o_idx = o_sum + 8, o_w = o_idx + P * 8;
+    topk_d.ensure(o_w + P * 4 + 64);
+    double* pm_w = (double*)topk_d.p;
+    uint64_t* cw_w = (uint64_t*)((char*)topk_d.p + o_cw);
+    uint64_t* pidx_w = (uint64_t*)((char*)topk_d.p + o_idx);
+    uint32_t* w_w = (uint32_t*)((char*)topk_d.p + o_w);
+    HIPCHK(hipMemsetAsync((char*)topk_d.p + o_tau, 0, 16, st));
+    {
+      const Terms<double> srt = ta.view();
+      hipLaunchKernelGGL(k_pair_tables, grid1(P), dim3(256), 0, st, srt, P, pm_w, pidx_w, w_w);
+      ctx->check_launch();
+      scan_u32(w_w, P);
+      hipLaunchKernelGGL(k_pair_cw, grid1(P), dim3(256), 0, st, (const uint32_t*)w_w, (const uint64_t*)pidx_w, P,
+                         cw_w);
+      ctx->check_launch();
+    }
     const double* pm_d = (const double*)topk_d.p;
     const uint64_t* cw_d = (const uint64_t*)((char*)topk_d.p + o_cw);
     double* tau_d = (double*)((char*)topk_d.p + o_tau);
     unsigned long long* sum_d = (unsigned long long*)((char*)topk_d.p + o_sum);
-    const uint32_t* pidx_d = (const uint32_t*)((char*)topk_d.p + o_idx);
+    const uint64_t* pidx_d = (const uint64_t*)((char*)topk_d.p + o_idx);
     const CT* c = cur.view().c;
     const uint64_t n = N;
     ctx->run("topk_cut", 0, (double)n, [&] {
@@ -2126,7 +2230,7 @@ struct Engine final : EngineBase {
     });
     ctx->check_launch();
     HIPCHK(hipMemcpyAsync(ctx->pinned, sum_d, 8, hipMemcpyDeviceToHost, st));
-    sync();   // also: the upload's host source goes out of scope
+    sync();
     uint64_t total = 0;
     std::memcpy(&total, ctx->pinned, 8);
     if (total >= (1ULL << 31))
@@ -2140,8 +2244,8 @@ struct Engine final : EngineBase {
     const uint32_t* offc = topk_off.as<uint32_t>();
     const unsigned grid = (unsigned)std::min<uint64_t>(cdiv(total, 256), 1u << 20);
     ctx->run("antinoise_topk_expand", kTermBytes * (double)(n + total) + 4.0 * total, (double)total, [&] {
-      hipLaunchKernelGGL((k_expand_topk<W, CT, ORD>), dim3(grid), dim3(256), 0, st, in, n, offc, total, ev, pidx_d,
-                         q, out, keep);
+      hipLaunchKernelGGL((k_expand_topk<W, CT, ORD>), dim3(grid), dim3(256), 0, st, in, n, offc, total, ev,
+                         (uint32_t)K, pidx_d, q, out, keep);
     });
     ctx->check_launch();
     finish_expansion(total);
@@ -2602,6 +2706,7 @@ int pp_timing_read(pp_ctx* ctx, pp_kernel_stat* out, int cap, int reset) {
         k.total_ms = kv.second.ms;
         k.algo_bytes = kv.second.bytes;
         k.items = kv.second.items;
+        k.layer_bytes = kv.second.layer_bytes;
       }
       ++n;
     }

@@ -51,6 +51,13 @@ struct NoiseDev {
   const uint64_t* dm;       // direct generators: [ndirect][2W]
   const double* dval;       // greedy: fidelity factor; error order: max_order powers of x_k
   const uint8_t* drun;      // greedy, direct generators: 1 where a run on new qubits starts
+  // greedy mode: the supports listed per qubit (CSR over n qubits; entry = support index,
+  // top bit set when the qubit is the support's second one), so that a string visits only
+  // the supports on its non-identity qubits; null when not built
+  int nq;                   // qubits with lists (0: none)
+  int nqent;
+  const int32_t* qoff;      // [nq + 1]
+  const uint32_t* qent;     // [nqent]
 };
 
 __device__ __forceinline__ int popc64(uint64_t v) { return __popcll(v); }

@@ -76,15 +76,14 @@ struct Gate1Args {
   unsigned long long* io;       // [2][kDropSlots]: terms loaded / written by completed tiles
 };
 
-// A tile handed to another path: its output region is left empty (c = 0, length 0).
+// A tile handed to another path: its output range is left empty (length 0).
 template <class CT>
 __device__ void zero_region(const Gate1Args<CT>& a, uint32_t tile, uint32_t n0) {
-  const uint64_t base = a.o_base[tile];
+  (void)n0;
   if (threadIdx.x == 0) {
-    a.o_start[tile] = (uint32_t)base;
+    a.o_start[tile] = (uint32_t)a.o_base[tile];
     a.o_len[tile] = 0;
   }
-  for (uint64_t i = base + threadIdx.x; i < base + 2ULL * n0; i += blockDim.x) a.out.c[i] = (CT)0;
 }
 
 // A tile copied through with only the pending cut applied (order kept).
@@ -138,7 +137,6 @@ __device__ void pass_through(const Gate1Args<CT>& a, uint32_t tile, uint32_t t0,
     atomicAdd(&a.io[blockIdx.x % kDropSlots], (unsigned long long)n0);
     atomicAdd(&a.io[kDropSlots + blockIdx.x % kDropSlots], (unsigned long long)total);
   }
-  for (uint64_t i = base + total + tid; i < base + 2ULL * n0; i += BLOCK) a.out.c[i] = (CT)0;
   uint64_t dst = base + before + incl - cnt;
   for (uint32_t i = lo; i < hi; ++i) {
     const uint64_t src = (uint64_t)t0 + i;
@@ -287,11 +285,17 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
       __syncthreads();
 
       // ---- stage, cut, insert ----------------------------------------------------------------
-      uint32_t hh[R];   // key hashes of this thread's terms
+      // Only strings that anticommute with the gate branch, and a partner iRP anticommutes
+      // too, so only they enter the table (and need a hash); with a Clifford angle no
+      // partner is looked up at all.
+      const bool pairs = cs != 0.0 && snd != 0.0;
+      uint32_t hh[R];   // key hashes of this thread's anticommuting terms
+      bool an[R];       // anticommutes with the gate
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const uint32_t i = (uint32_t)r * BLOCK + tid;
-        hh[r] = key_hash<W>(cur.x[r], cur.z[r]);
+        an[r] = anticommutes<W>(cur.x[r], cur.z[r], m) != 0;
+        hh[r] = an[r] ? key_hash<W>(cur.x[r], cur.z[r]) : 0u;
         if (i >= n0) continue;
 #pragma unroll
         for (int w = 0; w < W; ++w) { sx[w][i] = cur.x[r][w]; sz[w][i] = cur.z[r][w]; }
@@ -303,7 +307,7 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
         }
         sh[i] = hh[r];
         sc[i] = cur.c[r];
-        if (cur.c[r] != (CT)0) {
+        if (pairs && an[r] && cur.c[r] != (CT)0) {
           uint32_t slot = (hh[r] ^ (cur.o[r] * 0x9e3779b9u)) & (H - 1);
           while (atomicCAS(&hidx[slot], EMPTY, i) != EMPTY) slot = (slot + 1) & (H - 1);
         }
@@ -316,7 +320,7 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
         const uint32_t i = (uint32_t)r * BLOCK + tid;
         const double ci = (double)cur.c[r];
         if (i >= n0 || ci == 0.0) continue;
-        if (!anticommutes<W>(cur.x[r], cur.z[r], m)) {
+        if (!an[r]) {
           // untouched, but the threshold after a non-Clifford gate covers every term
           if (fabs(ci) < thr) { lost += fabs(ci); sc[i] = (CT)0; }
           continue;
@@ -438,8 +442,9 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
           for (int r = 0; r < R; ++r) pre[r] = s_slice[r * NW + wv];
           total = s_total;
         }
-        // the tile's output region holds 2 * n0 slots (a gate at most doubles a tile); unused
-        // slots get a zero coefficient so that sweeps over the whole buffer skip them
+        // the tile's output region holds 2 * n0 slots (a gate at most doubles a tile); the
+        // slots after its `total` survivors are left unused (every later sweep reads the
+        // tile ranges, never the whole buffer)
         if (tid == 0) {
           a.o_start[tile] = (uint32_t)base;
           a.o_len[tile] = total;
@@ -447,7 +452,6 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
           acc_in += n0;
           acc_out += total;
         }
-        for (uint64_t i = base + total + tid; i < base + 2ULL * n0; i += BLOCK) a.out.c[i] = (CT)0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           if (!((bal[r] >> lane) & 1ULL)) continue;
@@ -648,7 +652,6 @@ __global__ void __launch_bounds__(1024) k_gate1_big(Gate1Args<CT> a, uint32_t* t
     written += total;
     __syncthreads();
   }
-  for (uint64_t i = base + written + tid; i < base + 2ULL * n0; i += BLOCK) o.c[i] = (CT)0;
   for (int d = 32; d >= 1; d >>= 1) lost += __shfl_xor(lost, d, 64);
   if (lane == 0) s_drop[tid >> 6] = lost;
   __syncthreads();
@@ -739,6 +742,141 @@ __global__ void k_gather_bucket(Terms<CT> t, uint64_t n, uint64_t pmask, uint64_
   for (int w = 0; w < W; ++w) { g.x[w * g.stride + j] = t.x[w * t.stride + i]; g.z[w * g.stride + j] = t.z[w * t.stride + i]; }
   g.c[j] = t.c[i];
   if (ORD) g.o[j] = t.o[i];
+}
+
+// ------------------------------------------------------------------------------------------
+// Sweeps over the live slots of a tiled buffer.  Between the gates of a run, tile t holds its
+// terms in slots [start[t], start[t] + len[t]) of its own output region; the rest of the
+// region is unused and never read, so these sweeps walk the tile ranges instead of the
+// whole buffer.
+// ------------------------------------------------------------------------------------------
+struct TileView {
+  const uint32_t* start;
+  const uint32_t* len;
+  uint32_t ntiles;
+};
+
+// Call f(slot, key) with the |c| key of every live slot.  A wavefront takes sixteen
+// consecutive tiles: lanes 0..15 load their ranges in one request, the sixteen ranges are
+// read into scalar registers (readlane, before any branch: a shuffle from a lane that a
+// branch has switched off returns 0), and the first 128 keys of all sixteen tiles are loaded
+// (32 loads in flight per lane) before any is used; the rest of tiles longer than 128
+// follows in a loop.
+template <class CT, class F>
+__device__ __forceinline__ void tile_visit(const CT* c, const TileView tv, F&& f) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint32_t nw = (gridDim.x * blockDim.x) >> 6;
+  for (uint64_t t0 = (uint64_t)wave * 16; t0 < tv.ntiles; t0 += (uint64_t)nw * 16) {
+    uint32_t my_s = 0, my_l = 0;
+    if (lane < 16 && t0 + lane < tv.ntiles) {
+      my_s = tv.start[t0 + lane];
+      my_l = tv.len[t0 + lane];
+    }
+    uint32_t ts[16], tl[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      ts[u] = (uint32_t)__builtin_amdgcn_readlane((int)my_s, u);
+      tl[u] = (uint32_t)__builtin_amdgcn_readlane((int)my_l, u);
+    }
+    uint64_t k[2][16];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const uint32_t i = (uint32_t)lane + 64u * r;
+        k[r][u] = i < tl[u] ? abs_key<CT>(c[(uint64_t)ts[u] + i]) : 0ULL;
+      }
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (k[r][u]) f((uint64_t)ts[u] + (uint64_t)lane + 64u * r, k[r][u]);
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      for (uint32_t i = 128 + lane; i < tl[u]; i += 64) {
+        const uint64_t kk = abs_key<CT>(c[(uint64_t)ts[u] + i]);
+        if (kk) f((uint64_t)ts[u] + i, kk);
+      }
+  }
+}
+
+// As k_abs_hist_win over the live slots of the tiles.
+template <class CT>
+__global__ void __launch_bounds__(256) k_abs_hist_win_tiles(const CT* c, TileView tv, uint64_t lo, int shift,
+                                                            uint32_t* hist) {
+  __shared__ uint32_t h[2049];
+  for (int b = threadIdx.x; b < 2049; b += 256) h[b] = 0;
+  __syncthreads();
+  uint32_t above = 0;   // most keys lie above a window near the cut: counted in a register
+  tile_visit<CT>(c, tv, [&](uint64_t, uint64_t k) {
+    if (k >= lo) {
+      const uint64_t d = (k - lo) >> shift;
+      if (d >= 2048) ++above;
+      else atomicAdd(&h[d], 1u);
+    }
+  });
+  for (int d = 32; d >= 1; d >>= 1) above += __shfl_xor(above, d, 64);
+  if ((threadIdx.x & 63) == 0 && above) atomicAdd(&h[2048], above);
+  __syncthreads();
+  for (int b = threadIdx.x; b < 2049; b += 256)
+    if (h[b]) atomicAdd(&hist[b], h[b]);
+}
+
+// As k_abs_hist over the live slots of the tiles.
+template <class CT>
+__global__ void __launch_bounds__(256) k_abs_hist_tiles(const CT* c, TileView tv, int shift, int bits, uint64_t pmask,
+                                                        uint64_t prefix, uint32_t* hist) {
+  __shared__ uint32_t h[2048];
+  const int bins = 1 << bits;
+  for (int b = threadIdx.x; b < bins; b += 256) h[b] = 0;
+  __syncthreads();
+  tile_visit<CT>(c, tv, [&](uint64_t, uint64_t k) {
+    if ((k & pmask) == prefix) atomicAdd(&h[(k >> shift) & (uint64_t)(bins - 1)], 1u);
+  });
+  __syncthreads();
+  for (int b = threadIdx.x; b < bins; b += 256)
+    if (h[b]) atomicAdd(&hist[b], h[b]);
+}
+
+// As k_gather_bucket over the live slots of the tiles (the candidates are few: one atomic
+// each).
+template <int W, class CT, bool ORD>
+__global__ void k_gather_bucket_tiles(Terms<CT> t, TileView tv, uint64_t pmask, uint64_t prefix, Terms<CT> g,
+                                      uint64_t gcap, uint32_t* cnt) {
+  tile_visit<CT>(t.c, tv, [&](uint64_t i, uint64_t key) {
+    if ((key & pmask) != prefix) return;
+    const CT v = t.c[i];
+    const uint64_t j = atomicAdd(cnt, 1u);
+    if (j >= gcap) return;
+#pragma unroll
+    for (int w = 0; w < W; ++w) { g.x[w * g.stride + j] = t.x[w * t.stride + i]; g.z[w * g.stride + j] = t.z[w * t.stride + i]; }
+    g.c[j] = v;
+    if (ORD) g.o[j] = t.o[i];
+  });
+}
+
+// keep[i] = 1 for the live slots that survive the pending cut (the caller clears keep over
+// the whole buffer first, so unused slots stay 0).
+template <int W, class CT, bool ORD>
+__global__ void k_cut_keep_tiles(Terms<CT> t, TileView tv, CutDev cut, uint32_t* keep, double* dropped) {
+  double lost = 0.0;
+  tile_visit<CT>(t.c, tv, [&](uint64_t i, uint64_t key) {
+    bool k = true;
+    if (cut.has) {
+      if (key != cut.val) {
+        k = key > cut.val;
+      } else {
+        uint64_t kx[W], kz[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) { kx[w] = t.x[w * t.stride + i]; kz[w] = t.z[w * t.stride + i]; }
+        k = canon_le<W>(kx, kz, ORD ? t.o[i] : 0u, cut);
+      }
+    }
+    if (k) keep[i] = 1u;
+    else lost += fabs((double)t.c[i]);
+  });
+  add_dropped(lost, dropped);
 }
 
 }  // namespace pp

@@ -157,17 +157,46 @@ __device__ __forceinline__ void noise_sums(const uint64_t* px, const uint64_t* p
 // factor indices in per-pattern slots (padding points at a 1.0, an exact no-op);
 // generators handled directly come after them.
 template <int W>
+__device__ __forceinline__ uint32_t support_pattern(const uint64_t* px, const uint64_t* pz, const SupportDev& sp) {
+  uint32_t pat = (uint32_t)((pick<W>(px, sp.w0) >> sp.b0) & 1u) | (uint32_t)(((pick<W>(pz, sp.w0) >> sp.b0) & 1u) << 1);
+  if (sp.w1 >= 0)
+    pat |= (uint32_t)(((pick<W>(px, sp.w1) >> sp.b1) & 1u) << 2) | (uint32_t)(((pick<W>(pz, sp.w1) >> sp.b1) & 1u) << 3);
+  return pat;
+}
+
+// qoff/qent: the supports listed per qubit (NoiseDev), or null to visit every support.
+template <int W>
 __device__ __forceinline__ double noise_factor(const uint64_t* px, const uint64_t* pz, const double* tab,
-                                               const SupportDev* sup, const NoiseDev& nd) {
-  // Greedy mode: the product over runs of generators on the same qubits, in list order, of
-  // each run's product for the string's local pattern (pattern 0: exactly 1.0, skipped).
+                                               const SupportDev* sup, const int32_t* qoff, const uint32_t* qent,
+                                               const NoiseDev& nd) {
+  // Greedy mode: the product over runs of generators on the same qubits of each run's
+  // product for the string's local pattern (pattern 0: exactly 1.0, skipped).  Only runs
+  // on the string's non-identity qubits can differ from 1: with the per-qubit lists the
+  // string visits just those, each once (a two-qubit run at its first qubit when that one
+  // is set, else at its second), in qubit order.
   double prod = 1.0;
-  for (int s = 0; s < nd.nsup; ++s) {
-    const SupportDev sp = sup[s];
-    uint32_t pat = (uint32_t)((pick<W>(px, sp.w0) >> sp.b0) & 1u) | (uint32_t)(((pick<W>(pz, sp.w0) >> sp.b0) & 1u) << 1);
-    if (sp.w1 >= 0)
-      pat |= (uint32_t)(((pick<W>(px, sp.w1) >> sp.b1) & 1u) << 2) | (uint32_t)(((pick<W>(pz, sp.w1) >> sp.b1) & 1u) << 3);
-    if (pat) prod *= tab[sp.table + (int)pat];
+  if (qoff) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      uint64_t live = px[w] | pz[w];
+      while (live) {
+        const int q = 64 * w + (int)__builtin_ctzll(live);
+        live &= live - 1;
+        if (q >= nd.nq) break;
+        for (int e = qoff[q]; e < qoff[q + 1]; ++e) {
+          const uint32_t en = qent[e];
+          const SupportDev sp = sup[en & 0x7fffffffu];
+          if ((en >> 31) && (((pick<W>(px, sp.w0) | pick<W>(pz, sp.w0)) >> sp.b0) & 1u)) continue;
+          prod *= tab[sp.table + (int)support_pattern<W>(px, pz, sp)];
+        }
+      }
+    }
+  } else {
+    for (int s = 0; s < nd.nsup; ++s) {
+      const SupportDev sp = sup[s];
+      const uint32_t pat = support_pattern<W>(px, pz, sp);
+      if (pat) prod *= tab[sp.table + (int)pat];
+    }
   }
   if (nd.ndirect > 0) {
     double run = 1.0;
@@ -657,7 +686,7 @@ __global__ void __launch_bounds__(BLOCK) k_layer(LayerArgs<CT> a) {
         if (c == 0.0) continue;
         uint64_t kx[W], kz[W];
         load_key(i, kx, kz);
-        sc[i] = (CT)(c * noise_factor<W>(kx, kz, nd.tab, nd.sup, nd));
+        sc[i] = (CT)(c * noise_factor<W>(kx, kz, nd.tab, nd.sup, nd.qoff, nd.qent, nd));
       }
       __syncthreads();
     } else if (ORD) {
@@ -813,14 +842,28 @@ __global__ void k_tile_starts(const uint32_t* bnd, uint32_t nb, uint64_t n, uint
 // ------------------------------------------------------------------------------------------
 // Bytes of LDS a noise descriptor needs when staged (table, then supports).
 inline size_t noise_lds_bytes(const NoiseDev& nd) {
-  return (size_t)nd.ntab * sizeof(double) + (size_t)nd.nsup * sizeof(SupportDev);
+  return (size_t)nd.ntab * sizeof(double) + (size_t)nd.nsup * sizeof(SupportDev) +
+         (nd.nq ? (size_t)(nd.nq + 1) * 4 + (size_t)nd.nqent * 4 : 0);
 }
 constexpr size_t kNoiseLdsMax = 64 * 1024;
 
-// LDS layout of a staged noise descriptor: tab (doubles), then supports.
+// LDS layout of a staged noise descriptor: tab (doubles), supports, then (when built) the
+// per-qubit support lists.
 __device__ __forceinline__ void stage_noise(const NoiseDev& nd, double* stab, SupportDev* ssup) {
   for (int j = threadIdx.x; j < nd.ntab; j += blockDim.x) stab[j] = nd.tab[j];
   for (int j = threadIdx.x; j < nd.nsup; j += blockDim.x) ssup[j] = nd.sup[j];
+  if (nd.nq) {
+    int32_t* qo = (int32_t*)(ssup + nd.nsup);
+    uint32_t* qe = (uint32_t*)(qo + nd.nq + 1);
+    for (int j = threadIdx.x; j <= nd.nq; j += blockDim.x) qo[j] = nd.qoff[j];
+    for (int j = threadIdx.x; j < nd.nqent; j += blockDim.x) qe[j] = nd.qent[j];
+  }
+}
+__device__ __forceinline__ const int32_t* staged_qoff(const NoiseDev& nd, const SupportDev* ssup) {
+  return nd.nq ? (const int32_t*)(ssup + nd.nsup) : nullptr;
+}
+__device__ __forceinline__ const uint32_t* staged_qent(const NoiseDev& nd, const SupportDev* ssup) {
+  return nd.nq ? (const uint32_t*)((const int32_t*)(ssup + nd.nsup) + nd.nq + 1) : nullptr;
 }
 
 // A layer made only of Clifford rotations maps every string to one string (no merging):
@@ -856,7 +899,7 @@ __global__ void __launch_bounds__(1024) k_clifford(Terms<CT> t, uint64_t n, cons
         for (int w = 0; w < W; ++w) { kx[w] ^= m[w]; kz[w] ^= m[W + w]; }
       }
     }
-    if (has_noise) c = c * noise_factor<W>(kx, kz, stab, ssup, nd);
+    if (has_noise) c = c * noise_factor<W>(kx, kz, stab, ssup, staged_qoff(nd, ssup), staged_qent(nd, ssup), nd);
 #pragma unroll
     for (int w = 0; w < W; ++w) { t.x[w * t.stride + i] = kx[w]; t.z[w * t.stride + i] = kz[w]; }
     t.c[i] = (CT)c;
@@ -875,7 +918,7 @@ __global__ void __launch_bounds__(1024) k_noise_greedy(Terms<CT> t, uint64_t n, 
 #pragma unroll
     for (int w = 0; w < W; ++w) { kx[w] = t.x[w * t.stride + i]; kz[w] = t.z[w * t.stride + i]; }
     const double c = (double)t.c[i];
-    t.c[i] = (CT)(c * noise_factor<W>(kx, kz, stab, ssup, nd));
+    t.c[i] = (CT)(c * noise_factor<W>(kx, kz, stab, ssup, staged_qoff(nd, ssup), staged_qent(nd, ssup), nd));
   }
 }
 

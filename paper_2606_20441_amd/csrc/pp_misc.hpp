@@ -118,20 +118,36 @@ __device__ __forceinline__ int herm_mul_phase(const uint64_t* ax, const uint64_t
   return k & 3;
 }
 
-// Expansion of one propagated antinoise map (Section II, Eq. applyantinoise):
+// Pair p (0-based) of the K(K-1)/2 unordered pairs a < b listed row by row (a = 0: b = 1..K-1,
+// then a = 1, ...): row a starts at a (2K - a - 1) / 2.  The row comes from the quadratic's
+// root in FP64 and is then corrected to the exact integer row, so any K below 2^26 works.
+__device__ __forceinline__ void pair_of_index(uint64_t p, uint64_t K, uint32_t& a, uint32_t& b) {
+  auto start = [&](uint64_t r) { return r * (2 * K - r - 1) / 2; };
+  const double t = 2.0 * (double)K - 1.0;
+  const double disc = t * t - 8.0 * (double)p;
+  int64_t r = (int64_t)floor((t - sqrt(disc > 0.0 ? disc : 0.0)) * 0.5);
+  if (r < 0) r = 0;
+  if (r > (int64_t)K - 2) r = (int64_t)K - 2;
+  while (r > 0 && start((uint64_t)r) > p) --r;
+  while ((uint64_t)r + 1 < K - 1 && start((uint64_t)r + 1) <= p) ++r;
+  a = (uint32_t)r;
+  b = (uint32_t)(r + 1 + (int64_t)(p - start((uint64_t)r)));
+}
+
+// Expansion of one propagated antinoise map (Section I.A, Eq. applyantinoise):
 // O -> id O + q E' O E' with E' = sum_a e_a P_a (K terms, in `e`; id = 1 - q for one map,
 // other values for the terms of a batch).  Term i of O owns S = 1 + K(K-1)/2 consecutive
 // output slots:
 //  * slot 0: P_i with c_i [id + q sum_a e_a^2 (-1)^{<P_a, P_i>}]  (P_a P P_a = +-P);
-//  * slot 1 + j, pair (a, b) = pairs[j] with a < b: the two orders are adjoints of each
-//    other, so P_a P P_b + P_b P P_a = 2 Re(i^k) R for P_a P P_b = i^k R: 2 q e_a e_b c_i
+//  * slot 1 + j, pair (a, b) = pair_of_index(j) with a < b: the two orders are adjoints of
+//    each other, so P_a P P_b + P_b P P_a = 2 Re(i^k) R for P_a P P_b = i^k R: 2 q e_a e_b c_i
 //    times +1 (k = 0) or -1 (k = 2), and 0 for odd k.
 // keep[t] flags the nonzero slots, which are compacted before the canonical sort.
 // Grid-stride over n * S slots, so consecutive threads write consecutive slots of every
 // plane.
 template <int W, class CT, bool ORD>
-__global__ void k_expand_antinoise(Terms<CT> in, uint64_t n, Terms<CT> e, uint32_t K, const uint32_t* pairs,
-                                   uint64_t S, double q, double id, Terms<CT> out, uint32_t* keep) {
+__global__ void k_expand_antinoise(Terms<CT> in, uint64_t n, Terms<CT> e, uint32_t K, uint64_t S, double q,
+                                   double id, Terms<CT> out, uint32_t* keep) {
   const uint64_t total = n * S;
   for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (uint64_t)gridDim.x * blockDim.x) {
@@ -159,8 +175,8 @@ __global__ void k_expand_antinoise(Terms<CT> in, uint64_t n, Terms<CT> e, uint32
       }
       v = c * (id + q * s);
     } else {
-      const uint32_t pr = pairs[j - 1];
-      const uint32_t a = pr & 0xffffu, b = pr >> 16;
+      uint32_t a, b;
+      pair_of_index(j - 1, K, a, b);
       uint64_t ax[W], az[W], bx[W], bz[W], tx[W], tz[W];
 #pragma unroll
       for (int w = 0; w < W; ++w) {
@@ -191,6 +207,50 @@ __global__ void k_expand_antinoise(Terms<CT> in, uint64_t n, Terms<CT> e, uint32
 }
 
 // ---- most significant products only (Appendix B, heuristic conjugation) --------------------
+// The K(K-1)/2 unordered pairs a < b of E' (the products limited; the products with a = b
+// are always kept) get the sort key x = ~bits(|e_a| |e_b|) (non-negative doubles order like
+// their bit patterns, so ascending keys are descending magnitudes) and z = a << 32 | b, then
+// are put in canonical order by the library's radix sort.
+template <int W, class CT>
+__global__ void k_pair_keys(const CT* ec, uint64_t K, uint64_t P, Terms<double> out) {
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t a, b;
+    pair_of_index(p, K, a, b);
+    const double m = fabs((double)ec[a]) * fabs((double)ec[b]);
+    out.x[p] = ~(uint64_t)__double_as_longlong(m);
+    out.z[p] = ((uint64_t)a << 32) | b;
+#pragma unroll
+    for (int w = 1; w < W; ++w) {
+      out.x[(size_t)w * out.stride + p] = 0;
+      out.z[(size_t)w * out.stride + p] = 0;
+    }
+    out.c[p] = 0.0;
+    out.o[p] = 0;
+  }
+}
+
+// From the sorted pairs: magnitudes pm[p], indices pidx[p] = a << 32 | b, and each pair's
+// weight w[p] (its ordered triplets per term: 1 for a = b, 2 otherwise).
+__global__ void k_pair_tables(Terms<double> srt, uint64_t P, double* pm, uint64_t* pidx, uint32_t* w) {
+  const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const uint64_t z = srt.z[p];
+  pm[p] = __longlong_as_double((long long)~srt.x[p]);
+  pidx[p] = z;
+  w[p] = (z >> 32) == (z & 0xffffffffULL) ? 1u : 2u;
+}
+
+// cw[p] = weights before pair p (ws: their exclusive scan), cw[P] = all of them.
+__global__ void k_pair_cw(const uint32_t* ws, const uint64_t* pidx, uint64_t P, uint64_t* cw) {
+  const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  cw[p] = ws[p];
+  if (p == P - 1) {
+    const uint64_t z = pidx[p];
+    cw[P] = (uint64_t)ws[p] + ((z >> 32) == (z & 0xffffffffULL) ? 1u : 2u);
+  }
+}
+
 // Unordered pairs p = (a <= b) of E' terms are sorted on the host by pm[p] = |e_a| |e_b|,
 // largest first; cw[p] = sum of the pair weights before p (1 for a = b, 2 otherwise: the
 // number of ordered triplets).  A triplet's magnitude is mu = |c_s| pm[p], non-increasing
@@ -251,11 +311,12 @@ __global__ void k_topk_lens(const CT* c, uint64_t n, const double* pm, uint32_t 
 }
 
 // Expansion with the kept pairs only.  off[s] = first slot of term s (exclusive scan of
-// lens).  Slot 0 of a term: (1 - q) c P.  Pair (a, a): q e_a^2 c (-1)^{<P_a, P>} on P.  Pair
-// (a, b), a < b: both orders, 2 Re(i^k) q e_a e_b c on R for P_a P P_b = i^k R.
+// lens).  Slot 0 of a term: P with c [(1 - q) + q sum_a e_a^2 (-1)^{<P_a, P>}] (every
+// diagonal product, as in the exact update).  Pair (a, b), a < b: both orders,
+// 2 Re(i^k) q e_a e_b c on R for P_a P P_b = i^k R.
 template <int W, class CT, bool ORD>
 __global__ void k_expand_topk(Terms<CT> in, uint64_t n, const uint32_t* off, uint64_t total, Terms<CT> e,
-                              const uint32_t* pidx, double q, Terms<CT> out, uint32_t* keep) {
+                              uint32_t K, const uint64_t* pidx, double q, Terms<CT> out, uint32_t* keep) {
   for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (uint64_t)gridDim.x * blockDim.x) {
     uint64_t lo = 0, hi = n;   // last s with off[s] <= t
@@ -276,10 +337,19 @@ __global__ void k_expand_topk(Terms<CT> in, uint64_t n, const uint32_t* off, uin
     const double c = (double)in.c[i];
     double v;
     if (j == 0) {
-      v = (1.0 - q) * c;
+      double sd = 0.0;
+      for (uint32_t a = 0; a < K; ++a) {
+        int par = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+          par += popc64(e.x[(size_t)w * e.stride + a] & pz[w]) + popc64(e.z[(size_t)w * e.stride + a] & px[w]);
+        const double ea = (double)e.c[a];
+        sd += (par & 1) ? -ea * ea : ea * ea;
+      }
+      v = c * ((1.0 - q) + q * sd);
     } else {
-      const uint32_t pr = pidx[j - 1];
-      const uint32_t a = pr & 0xffffu, b = pr >> 16;
+      const uint64_t pr = pidx[j - 1];
+      const uint32_t a = (uint32_t)(pr >> 32), b = (uint32_t)pr;
       uint64_t ax[W], az[W], bx[W], bz[W], tx[W], tz[W];
 #pragma unroll
       for (int w = 0; w < W; ++w) {

@@ -49,7 +49,7 @@ class pp_layer(C.Structure):
 
 class pp_kernel_stat(C.Structure):
     _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("total_ms", C.c_double),
-                ("algo_bytes", C.c_double), ("items", C.c_double)]
+                ("algo_bytes", C.c_double), ("items", C.c_double), ("layer_bytes", C.c_double)]
 
 
 class pp_layer_stats(C.Structure):
@@ -223,7 +223,8 @@ class Context:
         arr = (pp_kernel_stat * max(n, 1))()
         lib().pp_timing_read(self._h, arr, n, int(reset))
         return [dict(name=arr[i].name.decode(), launches=int(arr[i].launches), total_ms=float(arr[i].total_ms),
-                     algo_bytes=float(arr[i].algo_bytes), items=float(arr[i].items)) for i in range(n)]
+                     algo_bytes=float(arr[i].algo_bytes), items=float(arr[i].items),
+                     layer_bytes=float(arr[i].layer_bytes)) for i in range(n)]
 
 
 class Observable:
@@ -427,9 +428,92 @@ def propagated_error(ctx: Context, circuit, t: int, k: int, eps_fwd: float = 0.0
     return e
 
 
+TAG_QUBITS = 8   # extra qubits that carry a generator's index in a batched forward propagation
+
+
+class _GateLayer:
+    """A layer's gates only, as pp_apply_layer reads them (no noise)."""
+
+    def __init__(self, gx, gz, theta):
+        self.gx, self.gz, self.theta = gx, gz, theta
+        self.ex = self.ez = np.zeros((0, gx.shape[1]), np.uint64)
+        self.lam = np.zeros(0)
+
+    @property
+    def n_gates(self) -> int:
+        return int(self.theta.shape[0])
+
+    @property
+    def n_gen(self) -> int:
+        return 0
+
+
+def _widened_gates(circuit, n_total: int):
+    """The circuit's gate layers written on n_total >= n qubits (the extra qubits untouched)."""
+    W, Wt = (circuit.n_qubits + 63) // 64, (n_total + 63) // 64
+    out = []
+    for layer in circuit.layers:
+        G = layer.n_gates
+        gx = np.zeros((G, Wt), np.uint64)
+        gz = np.zeros((G, Wt), np.uint64)
+        if G:
+            gx[:, :W] = _words(layer.gx, W)
+            gz[:, :W] = _words(layer.gz, W)
+        out.append(_GateLayer(gx, gz, np.ascontiguousarray(layer.theta, np.float64)))
+    return out
+
+
+def evolved_errors(ctx: Context, circuit, t: int, ks, eps_fwd: float = 0.0, precision: str = "f64",
+                   widened=None):
+    """E'_k = U E_k U^dag for the generators ks (at most 2^TAG_QUBITS of them) of layer t's
+    noise, carried forward together through the gates of layers t+1..M (Section I.A,
+    Eq. channel_prop) in one propagation on the device: generator ks[j] enters as
+    E_{ks[j]} (x) Z^j on TAG_QUBITS extra qubits that no gate touches, so the strings of
+    different generators never merge and each term keeps its generator's index; the
+    threshold eps_fwd follows every non-Clifford gate, as for one generator alone.  Returns
+    {k: (x, z, c)} with the extra qubits removed."""
+    n = circuit.n_qubits
+    nt = n + TAG_QUBITS
+    W, Wt = (n + 63) // 64, (nt + 63) // 64
+    ks = list(ks)
+    assert len(ks) <= (1 << TAG_QUBITS)
+    layer = circuit.layers[t]
+    ex = _words(layer.ex, W)
+    ez = _words(layer.ez, W)
+    x0 = np.zeros((len(ks), Wt), np.uint64)
+    z0 = np.zeros((len(ks), Wt), np.uint64)
+    x0[:, :W] = ex[ks]
+    z0[:, :W] = ez[ks]
+    for j in range(len(ks)):
+        for b in range(TAG_QUBITS):
+            if (j >> b) & 1:
+                q = n + b
+                z0[j, q // 64] |= np.uint64(1) << np.uint64(q % 64)
+    if widened is None:
+        widened = _widened_gates(circuit, nt)
+    e = Observable(ctx, nt, x0, z0, np.ones(len(ks)), precision=precision, eps=eps_fwd)
+    try:
+        for later in widened[t + 1:]:
+            e.apply_layer(later, PP_FORWARD, with_noise=False)
+        x, z, c, _ = e.export()
+    finally:
+        e.destroy()
+    tag = np.zeros(len(c), np.int64)
+    for b in range(TAG_QUBITS):
+        q = n + b
+        bit = (z[:, q // 64] >> np.uint64(q % 64)) & np.uint64(1)
+        tag |= bit.astype(np.int64) << b
+        z[:, q // 64] &= ~(np.uint64(1) << np.uint64(q % 64))
+    x, z = np.ascontiguousarray(x[:, :W]), np.ascontiguousarray(z[:, :W])
+    order = np.argsort(tag, kind="stable")
+    bounds = np.searchsorted(tag[order], np.arange(len(ks) + 1))
+    return {k: (x[order[bounds[j]:bounds[j + 1]]], z[order[bounds[j]:bounds[j + 1]]], c[order[bounds[j]:bounds[j + 1]]])
+            for j, k in enumerate(ks)}
+
+
 def pna(ctx: Context, circuit, observable, eps: float = 0.0, max_terms: int = 0, eps_fwd: float = 0.0,
         max_terms_fwd: int = 0, precision: str = "f64", on_map=None, max_products: int = 0, batch: int = 1,
-        batch_order: int = 1) -> Observable:
+        batch_order: int = 1, forward: str = "batched") -> Observable:
     """Propagated noise absorption (Section I.A).
 
     With C_noisy = N_M G_M .. N_1 G_1, inserting N_t^{-1} N_t after every G_t and carrying
@@ -441,21 +525,43 @@ def pna(ctx: Context, circuit, observable, eps: float = 0.0, max_terms: int = 0,
     many most significant products (Appendix B's heuristic conjugation).  With batch > 1 a
     layer's maps are absorbed `batch` at a time, each batch expanded to `batch_order` in the
     number of errors and merged once (Appendix C).
+
+    forward="batched" carries up to 2^TAG_QUBITS generators of a layer forward in one
+    propagation (evolved_errors), with the threshold eps_fwd after every non-Clifford gate;
+    each E' is then cut to its max_terms_fwd largest terms once, on the device, before it is
+    absorbed.  forward="each" propagates every generator on its own with eps_fwd and the
+    max_terms_fwd cap after every non-Clifford gate.
     """
+    if forward not in ("batched", "each"):
+        raise ValueError("forward must be 'batched' or 'each'")
     obs = Observable.from_sum(ctx, observable, precision=precision, eps=eps, max_terms=max_terms)
     n, W = circuit.n_qubits, (circuit.n_qubits + 63) // 64
     empty = np.zeros((0, W), np.uint64)
     # the evolved errors live in a pool of observables whose buffers are reused
     pool = [Observable(ctx, n, empty, empty, np.zeros(0), precision=precision, eps=eps_fwd, max_terms=max_terms_fwd)
             for _ in range(max(1, batch))]
+    widened = _widened_gates(circuit, n + TAG_QUBITS) if forward == "batched" else None
     try:
         for t, layer in enumerate(circuit.layers):
             lam = np.asarray(layer.lam, np.float64)
             step = max(1, batch)
+            evolved = {}
             for k0 in range(0, layer.n_gen, step):
                 ks = range(k0, min(k0 + step, layer.n_gen))
-                es = [propagated_error(ctx, circuit, t, k, eps_fwd, max_terms_fwd, precision, into=pool[i])
-                      for i, k in enumerate(ks)]
+                if forward == "batched":
+                    es = []
+                    for i, k in enumerate(ks):
+                        if k not in evolved:
+                            evolved = evolved_errors(ctx, circuit, t, range(k, min(k + (1 << TAG_QUBITS), layer.n_gen)),
+                                                     eps_fwd, precision, widened)
+                        x, z, c = evolved.pop(k)
+                        pool[i].set_terms(x, z, c)
+                        if max_terms_fwd > 0:
+                            pool[i].truncate(0.0, max_terms_fwd)
+                        es.append(pool[i])
+                else:
+                    es = [propagated_error(ctx, circuit, t, k, eps_fwd, max_terms_fwd, precision, into=pool[i])
+                          for i, k in enumerate(ks)]
                 if batch > 1:
                     obs.apply_antinoise_batch(es, [lam[k] for k in ks], batch_order)
                 elif max_products > 0:

@@ -200,9 +200,11 @@ class Server:
                 self._done.append((slot, need, res))
                 self._cv.notify_all()
 
-    def run(self, requests: Sequence, time_scale: float = 1.0) -> List[RequestResult]:
+    def run(self, requests: Sequence, time_scale: float = 1.0,
+            on_done: Optional[Callable[[RequestResult], None]] = None) -> List[RequestResult]:
         """Serve `requests` (objects with `rid`, `arrival_s`, `workload`), arrivals scaled
-        by `time_scale`; returns one result per request in arrival order."""
+        by `time_scale`; returns one result per request in arrival order.  `on_done` is
+        called (on the dispatching thread) with each finished request."""
         reqs = sorted(requests, key=lambda r: r.arrival_s)
         results: Dict[int, RequestResult] = {}
         inboxes = [collections.deque() for _ in range(self.n_slots)]
@@ -221,6 +223,8 @@ class Server:
                         slot, need, res = self._done.pop()
                         self.sched.release(slot, need)
                         pending -= 1
+                        if on_done:
+                            on_done(res)
                     while i < len(reqs) and reqs[i].arrival_s * time_scale <= now:
                         r = reqs[i]
                         res = RequestResult(r.rid, r.arrival_s * time_scale)

@@ -87,3 +87,22 @@ def compare_exports(g, r, thresholds=(), boundary: float = 1e-12, rtol: float = 
     nz = b != 0
     worst = float((err[nz] / np.abs(b[nz])).max()) if nz.any() else 0.0
     return dict(n_gpu=len(gk), n_ref=len(rk), only_gpu=len(only_g), only_ref=len(only_r), worst_rel=worst)
+
+
+def oracle_layer_step(orc, n: int, state, wl, kind: str, m: int):
+    """The reference's version of one layer call of D on the state (x, z, c, ord) exported by the
+    device just before that call.  `kind` is the schedule step the library reported: backward
+    through G_m without noise, the inverse noise N_m^-1 alone, or forward through G_m followed
+    by N_m^-1; the workload's threshold, cap and mode apply as on the device."""
+    x, z, c, o = state
+    r = orc.OracleSum(n, x, z, c, o)
+    layer = wl.circuit.layers[m]
+    kw = dict(eps=wl.eps, max_terms=wl.max_terms, mode=orc.MODES[wl.mode], max_order=wl.max_order)
+    if kind == "backward":
+        r.apply_layer(layer, +1, with_noise=False, **kw)
+    elif kind == "noise":
+        r.apply_layer(layer, -1, with_gates=False, noise_sign=1, **kw)
+    else:
+        r.apply_layer(layer, -1, noise_sign=1, noise_after_gates=True, **kw)
+    return r
+

@@ -25,7 +25,7 @@ import numpy as np
 import pytest
 
 from paper_2606_20441_amd import workloads as W
-from tests.parity import compare_exports
+from tests.parity import compare_exports, oracle_layer_step
 
 pytestmark = pytest.mark.gpu
 
@@ -59,21 +59,6 @@ def orc():
     return oracle
 
 
-def _oracle_step(orc, n, state, wl, kind, m):
-    """The reference's version of one layer call of D, on the device's exported input."""
-    x, z, c, o = state
-    r = orc.OracleSum(n, x, z, c, o)
-    layer = wl.circuit.layers[m]
-    kw = dict(eps=wl.eps, max_terms=wl.max_terms)
-    if kind == "backward":
-        r.apply_layer(layer, +1, with_noise=False, **kw)
-    elif kind == "noise":
-        r.apply_layer(layer, -1, with_gates=False, noise_sign=1, **kw)
-    else:
-        r.apply_layer(layer, -1, noise_sign=1, noise_after_gates=True, **kw)
-    return r
-
-
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("name,kw", [
     ("tfim7x8_pna", dict(steps=10, max_terms=1 << 16)),
@@ -92,7 +77,7 @@ def test_capped_full_schedule_layer_fed(pp, ctx, orc, name, kw):
     t0 = time.time()
 
     def on_layer(step, kind, m, obs):
-        r = _oracle_step(orc, n, state[0], wl, kind, m)
+        r = oracle_layer_step(orc, n, state[0], wl, kind, m)
         got = obs.export()
         ref = r.export()
         st = obs.last_layer_stats()

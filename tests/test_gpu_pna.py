@@ -343,3 +343,130 @@ def test_set_terms_reuses_an_observable(pp, ctx):
         assert reused.as_dict() == fresh.as_dict()
         fresh.destroy()
     reused.destroy()
+
+
+# --------------------------------------------------------------------------------------
+# Large E' (more than 4096 terms): pairs decoded on the device, expansions in chunks, pair
+# magnitudes sorted on the device; forward propagation of a layer's errors in one batch.
+# --------------------------------------------------------------------------------------
+def test_antinoise_large_eprime(pp, ctx, orc):
+    """An exact update with |E'| = 4100 (over eight million pairs) against the reference's
+    plain double sum over all ordered pairs."""
+    from tests.parity import compare_exports
+    n = 56
+    o = W.random_pauli_sum(n, 1, seed=71)
+    e = W.random_pauli_arrays(n, 4100, seed=72, density=0.25)
+    e.c = e.c * 0.01
+    lam = _lam(-0.02)
+    g = pp.Observable.from_sum(ctx, o, eps=1e-12)
+    ge = pp.Observable.from_sum(ctx, e)
+    assert len(ge) > 4096
+    log(f"antinoise |E'| = {len(ge)}")
+    g.apply_antinoise(ge, lam)
+    r = orc.OracleSum.from_sum(o)
+    r.antinoise(orc.OracleSum.from_sum(e), orc.antinoise_q(lam))
+    r.truncate(1e-12, 0)
+    rep = compare_exports(g.export(), r.export(), thresholds=[1e-12], context="large E'")
+    log(f"  {rep}")
+    assert abs(g.expectation() - r.expectation()) < 1e-10
+    g.destroy()
+    ge.destroy()
+
+
+def test_antinoise_chunked_expansion_is_linear(pp, ctx):
+    """When |O| (1 + K(K-1)/2) exceeds one slab the library expands O a chunk of terms at a
+    time; the map is linear in O, so the result must equal the sum of the updates of two
+    halves of O, each small enough for one slab.  E' holds 4100 of the 4^7 Paulis on seven
+    qubits, so every product lands on few strings and the result stays small."""
+    n = 56
+    rng = np.random.default_rng(83)
+    labels = rng.choice(4 ** 7, 4100, replace=False)
+    ex = np.zeros((4100, 1), np.uint64)
+    ez = np.zeros((4100, 1), np.uint64)
+    for q in range(7):
+        d = (labels >> (2 * q)) & 3
+        ex[:, 0] |= (d & 1).astype(np.uint64) << np.uint64(q)
+        ez[:, 0] |= (d >> 1).astype(np.uint64) << np.uint64(q)
+    e = W.PauliSum(n, ex, ez, 0.01 * rng.standard_normal(4100))
+    o = W.random_pauli_sum(n, 24, seed=81)
+    lam = _lam(-0.01)
+    ge = pp.Observable.from_sum(ctx, e)
+    assert len(ge) == 4100 and 24 * (1 + 4100 * 4099 // 2) > (1 << 27)
+    whole = pp.Observable.from_sum(ctx, o)
+    whole.apply_antinoise(ge, lam)
+    halves = {}
+    for part in (slice(0, 12), slice(12, 24)):
+        sub = W.PauliSum(n, o.x[part], o.z[part], o.c[part])
+        h = pp.Observable.from_sum(ctx, sub)
+        h.apply_antinoise(ge, lam)
+        for k, v in h.as_dict().items():
+            halves[k] = halves.get(k, 0.0) + v
+        h.destroy()
+    halves = {k: v for k, v in halves.items() if v != 0.0}
+    rep = compare_sums(whole.as_dict(), halves, rtol=1e-12, atol=1e-15, context="chunked vs halves")
+    log(f"  chunked expansion: {rep}")
+    whole.destroy()
+    ge.destroy()
+
+
+def test_antinoise_topk_large_eprime(pp, ctx, orc):
+    """A product-limited update with |E'| = 4300 (pair magnitudes sorted on the device)."""
+    n = 56
+    o = W.random_pauli_sum(n, 2, seed=91, allow_duplicates=False)
+    e = W.random_pauli_arrays(n, 4300, seed=92, density=0.25)
+    e.c = e.c * 0.01
+    lam = _lam(-0.03)
+    kmax = 200_000
+    g = pp.Observable.from_sum(ctx, o)
+    ge = pp.Observable.from_sum(ctx, e)
+    assert len(ge) > 4096
+    g.apply_antinoise_topk(ge, lam, kmax)
+    r = orc.OracleSum.from_sum(o)
+    r.antinoise_topk(orc.OracleSum.from_sum(e), orc.antinoise_q(lam), kmax)
+    rep = compare_sums(g.as_dict(), r.as_dict(), context="top-k large E'")
+    log(f"  {rep}")
+    assert abs(g.expectation() - r.expectation()) < 1e-10
+    g.destroy()
+    ge.destroy()
+
+
+@pytest.mark.parametrize("name,kw,eps,cap,eps_fwd,cap_fwd,kmax", [
+    ("tfim3x3", dict(steps=2), 1e-5, 0, 1e-4, 0, 0),
+    ("tfim3x3", dict(steps=2), 1e-5, 200, 1e-4, 12, 0),
+    ("tfim3x3", dict(steps=2), 1e-6, 0, 1e-5, 40, 0),
+    ("tfim7x8_pna", dict(steps=1), 1e-5, 0, 1e-4, 0, 0),
+    ("tfim8x16", dict(steps=1), 1e-4, 0, 1e-4, 0, 0),
+])
+def test_pna_batched_forward(pp, ctx, orc, name, kw, eps, cap, eps_fwd, cap_fwd, kmax):
+    """A layer's errors carried forward together (each tagged on extra qubits), each E' cut
+    to its cap_fwd largest terms once before it is absorbed, against the reference walking
+    one generator at a time with the same cut."""
+    wl = W.named_workload(name, **kw)
+    log(f"pna batched forward {name} {kw} eps={eps} cap={cap} eps_fwd={eps_fwd} cap_fwd={cap_fwd} kmax={kmax}")
+    g = pp.pna(ctx, wl.circuit, wl.observable, eps=eps, max_terms=cap, eps_fwd=eps_fwd, max_terms_fwd=cap_fwd,
+               max_products=kmax, forward="batched")
+    r = orc.pna(wl.circuit, wl.observable, eps=eps, max_terms=cap, eps_fwd=eps_fwd, max_terms_fwd=cap_fwd,
+                max_products=kmax, fwd_cap="final")
+    ref = r.as_dict()
+    th = [eps] + ([cap_cut(ref)] if cap else [])
+    rep = compare_sums(g.as_dict(), ref, thresholds=th, context=f"batched forward {name}")
+    eg, eo = g.expectation(), r.expectation()
+    log(f"  {rep}; <O~> {eg!r} vs {eo!r}")
+    assert abs(eg - eo) < 1e-10
+    g.destroy()
+
+
+def test_evolved_errors_batch_equals_one_by_one(pp, ctx):
+    """The batched forward propagation gives each generator's E' exactly as propagating it
+    alone does (threshold per term, no cap)."""
+    wl = W.named_workload("tfim7x8_pna", steps=2)
+    circ = wl.circuit
+    t = 1
+    ks = list(range(0, circ.layers[t].n_gen, 7))
+    got = pp.evolved_errors(ctx, circ, t, ks, eps_fwd=1e-4)
+    for k in ks:
+        one = pp.propagated_error(ctx, circ, t, k, 1e-4)
+        x, z, c = got[k]
+        mine = {(tuple(int(v) for v in x[i]), tuple(int(v) for v in z[i]), 0): float(c[i]) for i in range(len(c))}
+        compare_sums(mine, one.as_dict(), rtol=0.0, atol=0.0, context=f"E' of generator {k}")
+        one.destroy()

@@ -7,6 +7,8 @@ import time
 import numpy as np
 import pytest
 
+from tests.parity import compare_exports, oracle_layer_step
+
 from paper_2606_20441_amd import serve, workloads as W
 
 
@@ -124,15 +126,42 @@ def test_serving_alone_equals_mix_and_oracle():
     finally:
         mix.close()
     assert mix.sched.peak_running > 1
-    for r in reqs:
-        a, m = ra[r.rid], rm[r.rid]
-        assert a.status == "ok" and m.status == "ok", (a.message, m.message)
-        assert a.n_terms == m.n_terms
-        assert a.expectation == m.expectation        # deterministic kernels: bit-identical
-        wl = r.workload
-        if wl.precision == "f64":
-            eo = oracle.run_workload(wl).expectation()
-            assert abs(a.expectation - eo) < 1e-10, (r.rid, a.expectation, eo)
+    from paper_2606_20441_amd import pp
+    ctx = pp.Context(0)
+    try:
+        for r in reqs:
+            a, m = ra[r.rid], rm[r.rid]
+            assert a.status == "ok" and m.status == "ok", (a.message, m.message)
+            assert a.n_terms == m.n_terms
+            assert a.expectation == m.expectation        # deterministic kernels: bit-identical
+            wl = r.workload
+            if wl.precision != "f64":
+                continue
+            # The same request through the library directly, with the reference fed the
+            # device's terms before every layer call (the two round the noise products in a
+            # different order, so an unfed walk may put a term within an ulp of the threshold
+            # or of a cut on different sides): every call term by term, and the end result
+            # equal to the served one bit for bit.
+            state = [None]
+            n = wl.circuit.n_qubits
+            g0 = pp.Observable.from_sum(ctx, wl.observable, eps=wl.eps, max_terms=wl.max_terms)
+            state[0] = g0.export()
+            g0.destroy()
+
+            def on_layer(step, kind, mm, obs, wl=wl, n=n, state=state, rid=r.rid):
+                ref = oracle_layer_step(oracle, n, state[0], wl, kind, mm)
+                got = obs.export()
+                rr = ref.export()
+                cut = float(np.abs(rr[2]).min()) if len(rr[2]) else 0.0
+                compare_exports(got, rr, thresholds=[wl.eps, cut], context=f"request {rid} call {step}")
+                assert abs(obs.expectation() - ref.expectation()) < 1e-10
+                state[0] = got
+
+            d = pp.run_workload(ctx, wl, on_layer=on_layer)
+            assert d.expectation() == a.expectation, (r.rid, d.expectation(), a.expectation)
+            d.destroy()
+    finally:
+        ctx.close()
 
 
 @pytest.mark.gpu
@@ -148,3 +177,32 @@ def test_serving_oom_fails_alone():
     assert out[reqs[1].rid].status == "oom"
     assert all(out[r.rid].status == "ok" for r in reqs if r.rid != reqs[1].rid)
     assert srv.sched.reserved == 0
+
+
+@pytest.mark.gpu
+def test_serving_budget_defers_on_device():
+    """The HBM budget binds on the device: with room for two reservations, four slots and
+    six requests arriving at once, at most two run together; each later request is admitted
+    only when an earlier one has finished and returned its memory; every result equals the
+    same request served alone."""
+    reqs = _small_stream(6, seed=21)
+    need = 1 << 30                                      # the reservation floor of these requests
+    assert all(serve.reservation_bytes(r.workload) == need for r in reqs)
+    srv = serve.Server(n_slots=4, hbm_budget_bytes=int(2.5 * need))
+    try:
+        out = srv.run(reqs, time_scale=0.0)
+    finally:
+        srv.close()
+    assert all(r.status == "ok" for r in out), [r.message for r in out]
+    assert srv.sched.peak_running == 2 and srv.sched.peak_reserved == 2 * need
+    by_admit = sorted(out, key=lambda r: r.admitted)
+    for k, r in enumerate(by_admit[2:], start=2):
+        # two reservations at most: someone admitted earlier had finished by then
+        assert any(o.finished <= r.admitted + 1e-6 for o in by_admit[:k]), r.rid
+    alone = serve.Server(n_slots=1, hbm_budget_bytes=200 * 10**9)
+    try:
+        ra = {r.rid: r for r in alone.run(reqs, time_scale=0.0)}
+    finally:
+        alone.close()
+    for r in out:
+        assert r.expectation == ra[r.rid].expectation and r.n_terms == ra[r.rid].n_terms
