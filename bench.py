@@ -46,11 +46,13 @@ def run_gpu(ctx, wl, precision, steps, warmup, layers_verbose=False, progress=Fa
 
     def one(verbose=False):
         upd = [0]
+        io = [0]
         t_layer = [time.perf_counter()]
 
         def on_layer(step, phase, m, obs):
             st = obs.last_layer_stats()
             upd[0] += st["n_in"]
+            io[0] += st["n_in"] + st["n_out"]
             if verbose:
                 now = time.perf_counter()
                 log(f"  {step:3d} {phase:8s} m={m:2d} in={st['n_in']:>10d} out={st['n_out']:>10d} "
@@ -62,29 +64,37 @@ def run_gpu(ctx, wl, precision, steps, warmup, layers_verbose=False, progress=Fa
         e = obs.expectation()
         n = len(obs)
         obs.destroy()
-        return upd[0], e, n
+        return upd[0], e, n, io[0]
 
     for i in range(warmup):
+        tw = time.perf_counter()
         one(verbose=layers_verbose and i == 0)
+        log(f"   warmup propagation {i + 1}/{warmup}: {1e3 * (time.perf_counter() - tw):.1f} ms")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     total_upd = 0
+    total_io = 0
     res = None
-    for _ in range(steps):
-        u, e, n = one(verbose=progress)
+    for i in range(steps):
+        u, e, n, q = one(verbose=progress)
         total_upd += u
+        total_io += q
         res = (e, n)
+        log(f"   timed propagation {i + 1}/{steps} done at {1e3 * (time.perf_counter() - t0):.1f} ms")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     # per-kernel HIP-event timing on the library's stream, in one extra step of its own (the
     # event records and byte counters are kept out of the timed steps above)
     ctx.timing_read(reset=True)
     ctx.timing(True)
-    one()
+    ts = time.perf_counter()
+    one(verbose=progress)
     torch.cuda.synchronize()
+    log(f"   statistics propagation (HIP events on every launch): {1e3 * (time.perf_counter() - ts):.1f} ms")
     ctx.timing(False)
     kstats = ctx.timing_read(reset=True)
-    return dict(seconds=t1 - t0, updates=total_upd, expectation=res[0], terms=res[1], kernels=kstats)
+    return dict(seconds=t1 - t0, updates=total_upd, layer_terms_io=total_io, expectation=res[0], terms=res[1],
+                kernels=kstats)
 
 
 def kernel_source_hash() -> str:
@@ -96,8 +106,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel: str, precision: str):
-    """HBM bytes per launch recorded for `kernel` at `precision`, or None when absent or stale."""
+def recorded_traffic(workload: str, kernel: str, precision: str):
+    """HBM bytes per launch recorded for `kernel` at `precision` on `workload`, or None when
+    absent or stale (kernel sources changed since the counters were taken)."""
     try:
         with open(TRAFFIC_FILE) as fh:
             text = fh.read()
@@ -105,11 +116,13 @@ def recorded_traffic(kernel: str, precision: str):
         return None
     src = kernel_source_hash()
     for line in text.splitlines():
-        # machine-readable lines: "traffic: <kernel> <precision> <bytes per launch> <source hash>"
+        # machine-readable lines:
+        #   "traffic: <workload> <kernel> <precision> <bytes per launch> <source hash>"
         if line.startswith("traffic:"):
             parts = line.split()
-            if len(parts) == 5 and parts[1] == kernel and parts[2] == precision and parts[4] == src:
-                return float(parts[3])
+            if (len(parts) == 6 and parts[1] == workload and parts[2] == kernel and parts[3] == precision
+                    and parts[5] == src):
+                return float(parts[4])
     return None
 
 
@@ -146,34 +159,41 @@ def copy_ceiling(nbytes: int = 1 << 30, reps: int = 5) -> float:
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
-def roofline(kstats, term_bytes, precision="f64", copy_gbs=None):
+def roofline(kstats, workload, precision="f64", copy_gbs=None):
+    """The dominant kernel (largest device time) against the HBM roofline.
+
+    `achieved` counts the algorithmic bytes of the work unit: a layer call reads its input
+    terms once and writes its output terms once, (N_in + N_out) B.  A kernel that applies one
+    gate per pass over the whole array is charged 1/G of its layer's bytes per pass (G gates
+    in that layer call); per-gate re-reads are overhead.  The per-pass rate (every pass
+    counted as one read and one write of what it handled) is reported beside it as
+    `pass_gbs`, and the counted DRAM traffic (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a
+    plain copy's counters) as `traffic` per launch."""
     timed = [k for k in kstats if k["total_ms"] > 0]
     total = sum(k["total_ms"] for k in timed)
     dom = max(timed, key=lambda k: k["total_ms"])
-    fused = next((k for k in timed if k["name"] == "layer_fused_wave"), None)
-    pick = dom
-    avg_ms = pick["total_ms"] / pick["launches"]
-    per_launch_bytes = pick["algo_bytes"] / pick["launches"]
-    achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    traffic = recorded_traffic(pick["name"], precision)
-    out = {"bound": "hbm", "kernel": pick["name"], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+    avg_ms = dom["total_ms"] / dom["launches"]
+    layer_bytes = dom["layer_bytes"] / dom["launches"]
+    pass_bytes = dom["algo_bytes"] / dom["launches"]
+    achieved = layer_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    pass_gbs = pass_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    traffic = recorded_traffic(workload, dom["name"], precision)
+    out = {"bound": "hbm", "kernel": dom["name"], "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
            "traffic": None if traffic is None else round(traffic),
-           "algo_bytes_per_launch": round(per_launch_bytes),
-           "share_of_device_time": round(pick["total_ms"] / total, 3),
-           "avg_launch_ms": round(avg_ms, 4), "launches": pick["launches"]}
+           "algo_bytes_per_launch": round(layer_bytes),
+           "avg_launch_ms": round(avg_ms, 4), "launches": dom["launches"],
+           "share_of_device_time": round(dom["total_ms"] / total, 3),
+           "pass_bytes_per_launch": round(pass_bytes), "pass_gbs": round(pass_gbs, 1),
+           "pass_frac": round(pass_gbs / HBM_PEAK_GBS, 4)}
     if traffic is not None and avg_ms > 0:
         tg = traffic / (avg_ms * 1e-3) / 1e9   # counted DRAM bytes per second
         out["traffic_gbs"] = round(tg, 1)
         out["traffic_frac"] = round(tg / HBM_PEAK_GBS, 4)
+        out["traffic_over_pass_bytes"] = round(traffic / pass_bytes, 3) if pass_bytes else None
     if copy_gbs:
         out["copy_ceiling_gbs"] = round(copy_gbs, 1)
-        out["frac_of_copy"] = round(achieved / copy_gbs, 4)
-    if fused is not None and fused is not pick:
-        f_ms = fused["total_ms"] / fused["launches"]
-        f_ach = fused["algo_bytes"] / fused["launches"] / (f_ms * 1e-3) / 1e9
-        out["layer_fused_wave"] = {"achieved": round(f_ach, 1), "frac": round(f_ach / HBM_PEAK_GBS, 4),
-                              "avg_launch_ms": round(f_ms, 4), "share_of_device_time": round(fused["total_ms"] / total, 3)}
+        out["pass_frac_of_copy"] = round(pass_gbs / copy_gbs, 4)
     return out
 
 
@@ -197,6 +217,46 @@ def noisy_check(ctx, wl, precision):
     obs.destroy()
     log(f"   noisy evaluation: Tr[O~ rho_noisy] = {v!r} in {1e3 * dt:.1f} ms ({upd[0] / dt:.4g} term-updates/s)")
     return {"value": v, "ms": round(1e3 * dt, 3), "term_updates_per_s": round(upd[0] / dt, 1), "terms_out": n}
+
+
+def pna_walk(ctx, steps: int, eps: float, cap: int, eps_fwd: float, cap_fwd: int, kmax: int,
+             forward: str = "batched"):
+    """One propagated-noise-absorption walk (Section I.A) on the headline lattice, angles
+    and noise at `steps` Trotter steps: every generator's error carried forward through the
+    later gates (a layer's errors together, forward="batched"; threshold eps_fwd, each E'
+    cut to its cap_fwd largest terms before it is absorbed), then absorbed into O one update
+    per generator, E' O E' limited to its kmax most significant products when kmax > 0
+    (Appendix B), O thresholded at eps and capped at `cap` after every update.  Timed whole,
+    uninstrumented, with one progress line per layer."""
+    import torch
+    from paper_2606_20441_amd import pp, workloads as W
+    wl = W.named_workload("tfim7x8_pna", steps=steps)
+    circ = wl.circuit
+    n_maps = sum(l.n_gen for l in circ.layers)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seen = {"t": -1}
+
+    def on_map(t, k, obs):
+        if t != seen["t"] and k == circ.layers[t].n_gen - 1:
+            seen["t"] = t
+            log(f"   PNA walk: layer {t + 1}/{len(circ.layers)} absorbed at {time.perf_counter() - t0:.1f} s, "
+                f"|O| = {len(obs)}")
+
+    g = pp.pna(ctx, circ, wl.observable, eps=eps, max_terms=cap, eps_fwd=eps_fwd, max_terms_fwd=cap_fwd,
+               max_products=kmax, forward=forward, on_map=on_map)
+    v = g.expectation()
+    n_out = len(g)
+    g.destroy()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    res = {"workload": f"tfim7x8_pna at {steps} Trotter steps: 56q, {len(circ.layers)} layers, {n_maps} maps; "
+                       f"K_O {cap or 'none'}, eps {eps:g}; K_E {cap_fwd or 'none'}, forward eps {eps_fwd:g}, "
+                       f"{forward} forward propagation; products per map {kmax or 'all'}",
+           "maps": n_maps, "ms": round(1e3 * dt, 1), "maps_per_s": round(n_maps / dt, 1), "expectation": v,
+           "terms_out": n_out}
+    log(f"   PNA walk: {n_maps} maps in {dt:.1f} s ({n_maps / dt:.0f} maps/s), <O~> = {v!r}, {n_out} terms")
+    return res
 
 
 def pna_check(ctx, cpu: bool, prefix_maps: int = 300, topk=(), batches=()):
@@ -312,9 +372,9 @@ def sine_order_check(ctx, wl, orders):
     return out
 
 
-def cpu_baseline(wl, budget_s=15.0):
-    """The FP64 CPU reference (single thread) on a bounded prefix of the same propagation:
-    layer calls in the same order until the time budget is spent."""
+def _cpu_sample(wl, budget_s):
+    """The FP64 CPU reference (one thread) on a bounded prefix of the propagation: layer calls
+    in the same order until the time budget is spent.  Returns (term-updates, seconds, calls)."""
     from oracle import oracle
     c = wl.circuit
     M = len(c.layers)
@@ -340,9 +400,53 @@ def cpu_baseline(wl, budget_s=15.0):
         prev, last = last, time.perf_counter() - t_call
         upd += n_in
         done += 1
-    dt = time.perf_counter() - t0
-    return {"value": round(upd / dt, 1), "unit": "term-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {done} of {len(calls)} layer calls of the same propagation ({upd} term-updates, {dt:.1f} s)"}
+    return upd, time.perf_counter() - t0, done, len(calls)
+
+
+def _host_cpu():
+    """Host CPU facts for the report: logical CPUs, CPUs this process may run on, model."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = os.cpu_count() or 1
+    return {"nproc": os.cpu_count(), "allowed_cpus": allowed, "model": model}
+
+
+def cpu_baseline(wl, workload, max_terms, budget_s=15.0, workers=16):
+    """The oracle as it stands (single-threaded C++) on the host's cores: `workers` processes
+    (the machine's CPU share, at most the CPUs this process may use), each running the same
+    bounded prefix of the propagation at once; the value is their summed term-updates over
+    the wall time of the set.  One worker's own rate is reported beside it."""
+    import subprocess
+    host = _host_cpu()
+    p = max(1, min(workers, host["allowed_cpus"]))
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-worker", "--workload", workload,
+           "--cpu-budget", str(budget_s), "--trotter-steps", str(len(wl.circuit.layers) // 2)]
+    if max_terms is not None:
+        cmd += ["--max-terms", str(max_terms)]
+    t0 = time.perf_counter()
+    procs = [subprocess.Popen(cmd, stdout=subprocess.PIPE, text=True) for _ in range(p)]
+    outs = [json.loads(pr.communicate()[0].strip().splitlines()[-1]) for pr in procs]
+    wall = time.perf_counter() - t0
+    if any(pr.returncode for pr in procs):
+        raise RuntimeError("a CPU reference worker failed")
+    upd = sum(o["updates"] for o in outs)
+    one = outs[0]
+    return {"value": round(upd / wall, 1), "unit": "term-updates/s", "cores": p, "kind": "oracle",
+            "sample": f"{p} concurrent single-threaded oracle processes, each the first {one['calls']} of "
+                      f"{one['of']} layer calls of the same propagation ({one['updates']} term-updates, "
+                      f"{one['seconds']:.1f} s); {upd} term-updates in {wall:.1f} s wall",
+            "single_thread_value": round(one["updates"] / one["seconds"], 1),
+            "host": host}
 
 
 def run_serving(n_requests: int, rate_hz: float, n_slots: int, warmup: int):
@@ -351,8 +455,16 @@ def run_serving(n_requests: int, rate_hz: float, n_slots: int, warmup: int):
     from paper_2606_20441_amd import serve, workloads as W
     reqs = W.serving_stream(n_requests + warmup, rate_hz=rate_hz)
     srv = serve.Server(n_slots=n_slots, hbm_budget_bytes=200 * 10**9)
+    done = [0]
+
+    def on_done(res):
+        done[0] += 1
+        if done[0] % 10 == 0 or done[0] == len(reqs):
+            log(f"   served {done[0]}/{len(reqs)} (last: request {res.rid}, {res.status}, "
+                f"latency {1e3 * res.latency:.0f} ms)")
+
     try:
-        out = srv.run(reqs)
+        out = srv.run(reqs, on_done=on_done)
     finally:
         srv.close()
     measured = [r for r in out if r.rid >= warmup]
@@ -372,6 +484,7 @@ def main():
     ap.add_argument("--layers", action="store_true", help="print per-layer counts of the first warmup step")
     ap.add_argument("--progress", action="store_true", help="print per-layer counts of the timed steps too")
     ap.add_argument("--max-terms", type=int, default=None, help="override the workload's cap")
+    ap.add_argument("--trotter-steps", type=int, default=None, help="override the workload's Trotter steps")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-noisy-check", action="store_true",
                     help="skip propagating O~ back through the noisy circuit")
@@ -379,18 +492,45 @@ def main():
     ap.add_argument("--pna-only", action="store_true", help="run only the propagated-noise-absorption leg")
     ap.add_argument("--pna-topk", default="", help="comma-separated product limits for extra PNA walks")
     ap.add_argument("--pna-batch", default="", help="comma-separated C:order pairs for batched PNA walks")
+    ap.add_argument("--pna-walk", action="store_true",
+                    help="run only one PNA walk with the --pna-* settings below and print its JSON")
+    ap.add_argument("--pna-steps", type=int, default=10)
+    ap.add_argument("--pna-eps", type=float, default=1e-5)
+    ap.add_argument("--pna-cap", type=int, default=1 << 16, help="K_O: terms kept in O after every update")
+    ap.add_argument("--pna-eps-fwd", type=float, default=1e-4)
+    ap.add_argument("--pna-fwd-cap", type=int, default=256, help="K_E: terms kept in each evolved error")
+    ap.add_argument("--pna-kmax", type=int, default=1 << 18, help="most significant products per update (0: all)")
+    ap.add_argument("--pna-forward", default="each", choices=["batched", "each"],
+                    help="each: every error alone, K_E after every non-Clifford gate; batched: 256 "
+                         "errors of a layer together, K_E once at the end")
     ap.add_argument("--sine-orders", default="", help="comma-separated CPT-order limits: run only the "
                     "workload in the sine-order mode for each")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="concurrent CPU reference processes (the box's CPU share)")
+    ap.add_argument("--cpu-worker", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--serve-requests", type=int, default=30,
                     help="measured requests of the serving stream per arrival rate (0: skip it)")
     ap.add_argument("--serve-rates", default="200,0.5",
                     help="arrival rates (req/s): the configured one and one the device sustains")
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving stream (--serve-requests measured after --serve-warmup, "
+                         "at each of --serve-rates) and print its JSON")
     ap.add_argument("--serve-warmup", type=int, default=10)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration) and exit")
     args = ap.parse_args()
+    if args.cpu_worker:
+        # one CPU reference process of the baseline (no GPU use): prints its sample as JSON
+        from paper_2606_20441_amd import workloads as W
+        over = {} if args.max_terms is None else {"max_terms": args.max_terms}
+        if args.trotter_steps is not None:
+            over["steps"] = args.trotter_steps
+        wl = W.named_workload(args.workload, **over)
+        u, dt, done, of = _cpu_sample(wl, args.cpu_budget)
+        print(json.dumps({"updates": u, "seconds": dt, "calls": done, "of": of}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
@@ -406,11 +546,32 @@ def main():
         copy_probe(args.copy_probe)
         return
     pp.lib()
-    wl = W.named_workload(args.workload, **({} if args.max_terms is None else {"max_terms": args.max_terms}))
+    over = {} if args.max_terms is None else {"max_terms": args.max_terms}
+    if args.trotter_steps is not None:
+        over["steps"] = args.trotter_steps
+    wl = W.named_workload(args.workload, **over)
     ctx = pp.Context(0)
     if args.sine_orders:
         so = sine_order_check(ctx, wl, [int(v) for v in args.sine_orders.split(",") if v])
         print(json.dumps({"sine_order": so, "workload": args.workload}), flush=True)
+        ctx.close()
+        return
+    if args.serve_only:
+        out = []
+        for rate in [float(r) for r in args.serve_rates.split(",") if r]:
+            log(f"== serving: {args.serve_requests} requests after {args.serve_warmup} at {rate:g}/s, "
+                f"{args.serve_slots} slots")
+            t0 = time.perf_counter()
+            res = run_serving(args.serve_requests, rate, args.serve_slots, args.serve_warmup)
+            res["wall_s"] = round(time.perf_counter() - t0, 1)
+            out.append(res)
+            log(f"   {res}")
+        print(json.dumps({"serving": out}), flush=True)
+        return
+    if args.pna_walk:
+        res = pna_walk(ctx, args.pna_steps, args.pna_eps, args.pna_cap, args.pna_eps_fwd, args.pna_fwd_cap,
+                       args.pna_kmax, args.pna_forward)
+        print(json.dumps({"pna_walk": res}), flush=True)
         ctx.close()
         return
     if args.pna_only:
@@ -429,7 +590,8 @@ def main():
         r = run_gpu(ctx, wl, prec, args.steps, args.warmup, layers_verbose=args.layers, progress=args.progress)
         tb = 16 * Wd + (8 if prec == "f64" else 4) + (1 if wl.mode == "error_order" else 0)
         r["term_bytes"] = tb
-        r["roofline"] = roofline(r["kernels"], tb, prec, copy_gbs)
+        r["roofline"] = roofline(r["kernels"], args.workload, prec, copy_gbs)
+        r["step_algo_gbs"] = tb * r["layer_terms_io"] / r["seconds"] / 1e9
         results[prec] = r
         log(f"   {r['updates'] / r['seconds']:.4g} term-updates/s, {1e3 * r['seconds'] / args.steps:.1f} ms/step, "
             f"<O> = {r['expectation']!r}, {r['terms']} terms")
@@ -444,7 +606,7 @@ def main():
     r = results[main_prec]
     value = r["updates"] / r["seconds"]
     line = {
-        "metric": "Pauli-term updates/s (56q TFIM noise-canceling propagation)",
+        "metric": "Pauli-term updates/s + HBM GB/s (56q TFIM, FP64 vs FP32); p50/p99 latency",
         "value": round(value, 1),
         "unit": "term-updates/s",
         "n_gpus": 1,
@@ -462,6 +624,9 @@ def main():
                    "terms_out": r["terms"], "expectation": r["expectation"],
                    "term_updates_per_step": r["updates"] // args.steps, "parallelism": "1 GPU"},
         "roofline": r["roofline"],
+        "step_algo": {"gbs": round(r["step_algo_gbs"], 2), "frac": round(r["step_algo_gbs"] / HBM_PEAK_GBS, 5),
+                      "bytes_per_step": int(r["term_bytes"] * r["layer_terms_io"] / args.steps),
+                      "note": "sum over the layer calls of (N_in + N_out) x term bytes, over ms_per_step"},
     }
     if noisy is not None:
         line["noisy_evaluation"] = noisy
@@ -474,6 +639,7 @@ def main():
                          "speedup_vs_f64": round(r["seconds"] / f["seconds"], 3),
                          "expectation": f["expectation"],
                          "abs_err_vs_f64_gpu": abs(f["expectation"] - r["expectation"]),
+                         "step_algo_gbs": round(f["step_algo_gbs"], 2),
                          "roofline": f["roofline"]}
     if args.serve_requests > 0:
         line["serving"] = []
@@ -484,7 +650,7 @@ def main():
             log(f"   {res}")
     if not args.no_cpu:
         log("== CPU reference sample")
-        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
+        line["cpu_baseline"] = cpu_baseline(wl, args.workload, args.max_terms, args.cpu_budget, args.cpu_workers)
     print(json.dumps(line), flush=True)
 
 
