@@ -220,14 +220,17 @@ def noisy_check(ctx, wl, precision):
 
 
 def pna_walk(ctx, steps: int, eps: float, cap: int, eps_fwd: float, cap_fwd: int, kmax: int,
-             forward: str = "batched"):
+             forward: str = "batched", weights: bool = False):
     """One propagated-noise-absorption walk (Section I.A) on the headline lattice, angles
     and noise at `steps` Trotter steps: every generator's error carried forward through the
     later gates (a layer's errors together, forward="batched"; threshold eps_fwd, each E'
     cut to its cap_fwd largest terms before it is absorbed), then absorbed into O one update
     per generator, E' O E' limited to its kmax most significant products when kmax > 0
     (Appendix B), O thresholded at eps and capped at `cap` after every update.  Timed whole,
-    uninstrumented, with one progress line per layer."""
+    uninstrumented, with one progress line per layer.  weights=True also reads every E' back
+    and reports how much of its unit weight (sum of c^2; conjugation by the later gates keeps
+    it at 1) the forward threshold and cap removed; that read-back is inside the timing."""
+    import numpy as np
     import torch
     from paper_2606_20441_amd import pp, workloads as W
     wl = W.named_workload("tfim7x8_pna", steps=steps)
@@ -237,14 +240,27 @@ def pna_walk(ctx, steps: int, eps: float, cap: int, eps_fwd: float, cap_fwd: int
     t0 = time.perf_counter()
     seen = {"t": -1}
 
+    lost = {"sum": 0.0, "max": 0.0, "n": 0}
+
     def on_map(t, k, obs):
         if t != seen["t"] and k == circ.layers[t].n_gen - 1:
             seen["t"] = t
+            extra = ""
+            if weights:
+                extra = (f", E' weight lost: mean {lost['sum'] / max(1, lost['n']):.2e}, "
+                         f"max {lost['max']:.2e}")
             log(f"   PNA walk: layer {t + 1}/{len(circ.layers)} absorbed at {time.perf_counter() - t0:.1f} s, "
-                f"|O| = {len(obs)}")
+                f"|O| = {len(obs)}, <O~> = {obs.expectation():.6g}{extra}")
+
+    def on_error(t, k, e):
+        c = e.export()[2]
+        d = 1.0 - float(np.dot(c, c))
+        lost["sum"] += d
+        lost["max"] = max(lost["max"], d)
+        lost["n"] += 1
 
     g = pp.pna(ctx, circ, wl.observable, eps=eps, max_terms=cap, eps_fwd=eps_fwd, max_terms_fwd=cap_fwd,
-               max_products=kmax, forward=forward, on_map=on_map)
+               max_products=kmax, forward=forward, on_map=on_map, on_error=on_error if weights else None)
     v = g.expectation()
     n_out = len(g)
     g.destroy()
@@ -255,6 +271,8 @@ def pna_walk(ctx, steps: int, eps: float, cap: int, eps_fwd: float, cap_fwd: int
                        f"{forward} forward propagation; products per map {kmax or 'all'}",
            "maps": n_maps, "ms": round(1e3 * dt, 1), "maps_per_s": round(n_maps / dt, 1), "expectation": v,
            "terms_out": n_out}
+    if weights:
+        res["eprime_weight_lost"] = {"mean": lost["sum"] / max(1, lost["n"]), "max": lost["max"]}
     log(f"   PNA walk: {n_maps} maps in {dt:.1f} s ({n_maps / dt:.0f} maps/s), <O~> = {v!r}, {n_out} terms")
     return res
 
@@ -503,6 +521,8 @@ def main():
     ap.add_argument("--pna-forward", default="each", choices=["batched", "each"],
                     help="each: every error alone, K_E after every non-Clifford gate; batched: 256 "
                          "errors of a layer together, K_E once at the end")
+    ap.add_argument("--pna-weights", action="store_true",
+                    help="read every evolved error back and report the weight its truncation removed")
     ap.add_argument("--sine-orders", default="", help="comma-separated CPT-order limits: run only the "
                     "workload in the sine-order mode for each")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -570,7 +590,7 @@ def main():
         return
     if args.pna_walk:
         res = pna_walk(ctx, args.pna_steps, args.pna_eps, args.pna_cap, args.pna_eps_fwd, args.pna_fwd_cap,
-                       args.pna_kmax, args.pna_forward)
+                       args.pna_kmax, args.pna_forward, args.pna_weights)
         print(json.dumps({"pna_walk": res}), flush=True)
         ctx.close()
         return

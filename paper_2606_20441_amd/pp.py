@@ -513,7 +513,7 @@ def evolved_errors(ctx: Context, circuit, t: int, ks, eps_fwd: float = 0.0, prec
 
 def pna(ctx: Context, circuit, observable, eps: float = 0.0, max_terms: int = 0, eps_fwd: float = 0.0,
         max_terms_fwd: int = 0, precision: str = "f64", on_map=None, max_products: int = 0, batch: int = 1,
-        batch_order: int = 1, forward: str = "batched") -> Observable:
+        batch_order: int = 1, forward: str = "batched", on_error=None) -> Observable:
     """Propagated noise absorption (Section I.A).
 
     With C_noisy = N_M G_M .. N_1 G_1, inserting N_t^{-1} N_t after every G_t and carrying
@@ -530,7 +530,8 @@ def pna(ctx: Context, circuit, observable, eps: float = 0.0, max_terms: int = 0,
     propagation (evolved_errors), with the threshold eps_fwd after every non-Clifford gate;
     each E' is then cut to its max_terms_fwd largest terms once, on the device, before it is
     absorbed.  forward="each" propagates every generator on its own with eps_fwd and the
-    max_terms_fwd cap after every non-Clifford gate.
+    max_terms_fwd cap after every non-Clifford gate.  on_error(t, k, e) sees every evolved
+    error E' (an Observable) just before it is absorbed.
     """
     if forward not in ("batched", "each"):
         raise ValueError("forward must be 'batched' or 'each'")
@@ -562,6 +563,9 @@ def pna(ctx: Context, circuit, observable, eps: float = 0.0, max_terms: int = 0,
                 else:
                     es = [propagated_error(ctx, circuit, t, k, eps_fwd, max_terms_fwd, precision, into=pool[i])
                           for i, k in enumerate(ks)]
+                if on_error:
+                    for k, e in zip(ks, es):
+                        on_error(t, k, e)
                 if batch > 1:
                     obs.apply_antinoise_batch(es, [lam[k] for k in ks], batch_order)
                 elif max_products > 0:
