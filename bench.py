@@ -615,7 +615,7 @@ def main():
         results[prec] = r
         log(f"   {r['updates'] / r['seconds']:.4g} term-updates/s, {1e3 * r['seconds'] / args.steps:.1f} ms/step, "
             f"<O> = {r['expectation']!r}, {r['terms']} terms")
-        for k in sorted(r["kernels"], key=lambda k: -k["total_ms"])[:12]:
+        for k in sorted(r["kernels"], key=lambda k: -k["total_ms"])[:20]:
             avg = k["total_ms"] / k["launches"]
             bw = k["algo_bytes"] / k["launches"] / (avg * 1e-3) / 1e9 if avg > 0 and k["algo_bytes"] else 0
             log(f"   {k['name']:24s} {k['launches']:6d} launches {k['total_ms']:9.2f} ms  avg {avg:8.4f} ms  "

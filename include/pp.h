@@ -24,8 +24,12 @@
  *    pp_last_error() returns a thread-local message for the last failure.
  *  - Streams: all GPU work is enqueued on the context's stream.  pp_apply_layer and
  *    pp_truncate synchronise that stream internally to read term counts (the arrays
- *    are resized per layer); pp_size, pp_expectation and pp_export return host values
- *    and therefore also synchronise.
+ *    are resized per layer), so they return with the layer complete.  Inside a layer
+ *    whose cap binds, the gates' passes and the cut after each of them are selected and
+ *    applied on the device: the host enqueues gate after gate without waiting, and reads
+ *    each gate's counters (statistics, retiling decisions) while the next one runs.
+ *    pp_size, pp_expectation and pp_export return host values and therefore also
+ *    synchronise.
  *  - Threads: a context and its observables must be used by one host thread at a time;
  *    different contexts may be driven concurrently from different threads.
  */

@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -26,6 +27,7 @@
 #include "pp_gate.hpp"
 #include "pp_layer.hpp"
 #include "pp_misc.hpp"
+#include "pp_select.hpp"
 #include "pp_sort.hpp"
 
 using namespace pp;
@@ -336,7 +338,7 @@ struct Engine final : EngineBase {
   TBuf<CT, ORD> gb;              // boundary candidates of a cap
   Buf u32a, u32b, u32c, scan_scr, tiles, gates_d, sup_d, tab_d, drun_d, dm_d, dval_d, cnt_d, ovf_d, partial_d, f64_d, span_d, htab_d, lstat_d;
   Buf hscr_d, tr_s0, tr_l0, tr_s1, tr_l1, g1_d, g1_ovf, g1_base, g1_base2;   // per-gate tile path
-  Buf rl0, rl1, rl2, ovl1, ovl2, tf_flag, tf_pos, tf_list, g1_io, g1_tab, g1_tabmeta, win_hist_d, qlist_d, topk_d, topk_off;
+  Buf rl0, rl1, rl2, ovl1, ovl2, tf_flag, tf_pos, tf_list, g1_io, g1_tab, g1_tabmeta, win_hist_d, qlist_d, topk_d, topk_off, sel_d;
   double growth[4] = {4.0, 4.0, 2.0, 3.0};
   double tile_target[4] = {80.0, 80.0, 80.0, 64.0};   // level-0 (one-wavefront) tile targets
   uint64_t last_ntiles = 1, last_ovf_tiles = 0;
@@ -346,7 +348,7 @@ struct Engine final : EngineBase {
     for (auto* t : {&ta, &tb}) { t->mem.ctx = ctx; t->W = W; }
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &drun_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
                    &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hscr_d, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &rl0, &rl1, &rl2, &ovl1, &ovl2,
-                   &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d, &qlist_d, &topk_d, &topk_off})
+                   &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d, &qlist_d, &topk_d, &topk_off, &sel_d})
       b->ctx = ctx;
     cnt_d.ensure(256);
     span_d.ensure(256);
@@ -359,7 +361,7 @@ struct Engine final : EngineBase {
     for (auto* t : {&ta, &tb}) t->mem.release();
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &drun_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
                    &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hscr_d, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &rl0, &rl1, &rl2, &ovl1, &ovl2,
-                   &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d, &qlist_d, &topk_d, &topk_off})
+                   &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d, &qlist_d, &topk_d, &topk_off, &sel_d})
       b->release();
   }
 
@@ -1199,9 +1201,13 @@ struct Engine final : EngineBase {
   static constexpr size_t kPinBases = 3072, kPinWin = 4096;
 
   struct G1Counters {
-    uint32_t nlist[3];   // routed tiles: small, middle, large
+    uint32_t nlist[3];   // routed tiles: small, middle, large (kept from one gate to the next)
     uint32_t ovf[3];     // tiles reported by the small shapes, the 256-thread and the 1024-thread shape
-    unsigned long long bases_total;   // the next gate's output extent
+    unsigned long long bases_total;   // the next gate's output extent (2 x the live terms)
+    unsigned long long tab_cursor;    // hash-table words handed out to oversize tiles
+    unsigned long long big_terms;     // terms of the oversize tiles
+    uint32_t tab_err;                 // an oversize tile found no table room
+    uint32_t pad;
     double drop[kDropSlots];          // sum of |c| removed, per slot
   };
   static constexpr uint32_t kG1SmallMax = 128;   // tiles up to this size start in one wavefront
@@ -1412,7 +1418,9 @@ struct Engine final : EngineBase {
 
   // Drop the terms a cut removes (and exact zeros) from cur (N slots).
   // tv: cur is tiled over its first N slots (only the tiles' live ranges hold terms).
-  void apply_cut(const CutDev& cut, pp_layer_stats& ls, const TileView* tv = nullptr) {
+  // cutp: the cut is the one pending on the device there (tiled buffers only).
+  void apply_cut(const CutDev& cut, pp_layer_stats& ls, const TileView* tv = nullptr, const CutDev* cutp = nullptr) {
+    if (cutp && !tv) throw_fail(PP_ERR_DEVICE, "a device-side cut applies to tiles only");
     if (N == 0) return;
     u32b.ensure(N * 4 + 64);
     uint32_t* keep = u32b.as<uint32_t>();
@@ -1423,7 +1431,8 @@ struct Engine final : EngineBase {
     if (tv) HIPCHK(hipMemsetAsync(keep, 0, n * 4, st));
     ctx->run("cut_flags", 0, (double)n, [&] {
       if (tv)
-        hipLaunchKernelGGL((k_cut_keep_tiles<W, CT, ORD>), dim3(tile_grid(*tv)), dim3(256), 0, st, t, *tv, cut, keep, dd);
+        hipLaunchKernelGGL((k_cut_keep_tiles<W, CT, ORD>), dim3(tile_grid(*tv)), dim3(256), 0, st, t, *tv, cut, cutp,
+                           keep, dd);
       else
         hipLaunchKernelGGL((k_cut_keep<W, CT, ORD>), gridb(n), dim3(256), 0, st, t, n, cut, keep, dd);
     });
@@ -1479,21 +1488,34 @@ struct Engine final : EngineBase {
       HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
       HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_gate1<W, CT, ORD, CAPK, BLOCKK>,
                                                           BLOCKK, 0));
+      // A persistent grid must be resident at once: a workgroup that only starts when
+      // another ends does its share of tiles after the others.  The occupancy query has
+      // allowed one workgroup per compute unit more than the 160 KiB of LDS of a gfx950
+      // compute unit holds (it leaves out that LDS is allocated in 512-byte blocks), so
+      // that bound is taken as well.
+      hipFuncAttributes fa{};
+      HIPCHK(hipFuncGetAttributes(&fa, (const void*)k_gate1<W, CT, ORD, CAPK, BLOCKK>));
+      constexpr int kLdsPerCu = 160 * 1024, kLdsBlock = 512;
+      const int lds_wg = (int)((fa.sharedSizeBytes + kLdsBlock - 1) / kLdsBlock) * kLdsBlock;
+      if (lds_wg > 0) per_cu = std::min<int>(per_cu, kLdsPerCu / lds_wg);
       return (unsigned)std::max(1, cus * std::max(1, per_cu));
     }();
     return resident;
   }
 
   // `ntiles` list entries, or, with dev_count, the count the device holds there (at most ntiles).
+  // max_blocks: a smaller persistent grid for a list expected to be short (the kernel loops
+  // over the list whatever its length).
   template <int CAPK, int BLOCKK>
-  void g1_launch(Gate1Args<CT> a, unsigned ntiles, int shape, const uint32_t* dev_count = nullptr) {
+  void g1_launch(Gate1Args<CT> a, unsigned ntiles, int shape, const uint32_t* dev_count = nullptr,
+                 unsigned max_blocks = 0xffffffffu) {
     static const char* names[4] = {"gate_tile_wave", "gate_tile_256", "gate_tile_1024", "gate_tile_128"};
     g1_io.ensure(2 * kDropSlots * 8 + 64);
     unsigned long long* io = g1_io.as<unsigned long long>();
     a.io = io;
     a.t_count = ntiles;
     a.t_count_dev = dev_count;
-    const unsigned nblocks = std::min(ntiles, g1_resident<CAPK, BLOCKK>());
+    const unsigned nblocks = std::max(1u, std::min({ntiles, g1_resident<CAPK, BLOCKK>(), max_blocks}));
     if (ctx->timing) HIPCHK(hipMemsetAsync(io, 0, 2 * kDropSlots * 8, st));
     const int pi = ctx->run(names[shape], 0, (double)ntiles, [&] {
       hipLaunchKernelGGL((k_gate1<W, CT, ORD, CAPK, BLOCKK>), dim3(nblocks), dim3(BLOCKK), 0, st, a);
@@ -1546,11 +1568,72 @@ struct Engine final : EngineBase {
     return cut;
   }
 
+  // The device-side state of the cap's cut between gates (one per engine), set up on first
+  // use: no cut pending, no window yet.
+  SelState* sel_state() {
+    if (!sel_d.p) {
+      sel_d.ensure(sizeof(SelState) + 64);
+      HIPCHK(hipMemsetAsync(sel_d.p, 0, sizeof(SelState), st));
+      hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(64), 0, st, sel_d.as<SelState>(), sizeof(CT) == 8 ? 43 : 14);
+      ctx->check_launch();
+    }
+    return sel_d.as<SelState>();
+  }
+  // Enqueue the cut after a gate: select the K-th term of the tiles' live slots on the device
+  // (nothing when the live count, read there too, is within the cap) and leave it pending.
+  // A fixed chain of launches; those with nothing to do return at once.
+  void sel_launch(const TileView& tv, const unsigned long long* live2, uint64_t K) {
+    SelState* ss = sel_state();
+    gb.ensure(sel_gather<W>() + 64);
+    const Terms<CT> t = cur.view(), g = gb.view();
+    const dim3 grid(tile_grid(tv));
+    ctx->run("cap_hist", 0, 0.0, [&] {
+      hipLaunchKernelGGL((k_sel_win<W, CT, ORD>), grid, dim3(256), 0, st, t.c, tv, live2, (unsigned long long)K, ss);
+    });
+    ctx->check_launch();
+    ctx->run("cap_pick", 0, 0.0, [&] {
+      hipLaunchKernelGGL((k_sel_pick<W, CT, ORD>), dim3(1), dim3(256), 0, st, ss, 0);
+    });
+    ctx->check_launch();
+    // the passes after the window are rarely needed: a smaller grid returns sooner when not
+    const dim3 pgrid(std::min(256u, tile_grid(tv)));
+    for (int p = 0; p < 2; ++p) {
+      ctx->run("cap_pass", 0, 0.0, [&] {
+        hipLaunchKernelGGL((k_sel_pass<W, CT, ORD>), pgrid, dim3(256), 0, st, t.c, tv, ss);
+      });
+      ctx->check_launch();
+      ctx->run("cap_pick", 0, 0.0, [&] {
+        hipLaunchKernelGGL((k_sel_pick<W, CT, ORD>), dim3(1), dim3(256), 0, st, ss, 1);
+      });
+      ctx->check_launch();
+    }
+    ctx->run("cap_rest", 0, 0.0, [&] {
+      hipLaunchKernelGGL((k_sel_rest<W, CT, ORD>), dim3(1), dim3(256), 0, st, t, tv, ss);
+    });
+    ctx->check_launch();
+    ctx->run("cap_gather", 0, 0.0, [&] {
+      hipLaunchKernelGGL((k_sel_gather<W, CT, ORD>), grid, dim3(256), 0, st, t, tv, ss, g);
+    });
+    ctx->check_launch();
+    ctx->run("cap_rank", 0, 0.0, [&] {
+      hipLaunchKernelGGL((k_sel_rank<W, CT, ORD>), dim3(1), dim3(256), 0, st, ss, g);
+    });
+    ctx->check_launch();
+  }
+
   // Apply `gates` one at a time with the cap after each non-Clifford gate (Section I.A's
   // truncation of intermediate results, taken after every such gate).  The terms are tiled
   // once by the run's invariant bits; each gate is one pass over the tiles.  Between gates
-  // the buffer holds each tile in its own region (2x its input), unused slots at c = 0, and
-  // the cut of the last gate is applied when the next pass loads the tile.
+  // the buffer holds each tile in its own region (2x its input) and only the tiles' live
+  // ranges are read; the cut of the last gate is selected on the device and applied when
+  // the next pass loads the tile.
+  //
+  // Nothing in the loop waits for the device: a gate's pass reads its tile lists and the
+  // pending cut on the device, oversize tiles take their hash tables from a device-side
+  // cursor, and the buffers are sized for the largest extent a pass can produce (a pass
+  // writes 2 slots per input term, and at most 2 terms per survivor of the previous cut, so
+  // 4 max(K, N) slots).  The host reads each gate's counters one gate later, while the next
+  // pass runs, to keep statistics and to decide when to sort the tiles again or regroup.
   void gate_by_gate(const std::vector<GateDev>& gates, int kind, double eps, uint64_t cap, pp_layer_stats& ls) {
     const GroupMask gm = invariant_mask(gates, kind);
     // each gate's pass over the tiles carries 1 / G of the layer's read-once, write-once bytes
@@ -1559,57 +1642,102 @@ struct Engine final : EngineBase {
       ~ShareGuard() { c->pass_share = 1.0; }
     } share_guard{ctx};
     ctx->pass_share = 1.0 / (double)std::max<size_t>(1, gates.size());
+    SelState* ss = sel_state();
+    const CutDev* cutp = &ss->cut;
+    hipLaunchKernelGGL(k_sel_clear, dim3(1), dim3(64), 0, st, ss);
+    ctx->check_launch();
+    bool cut_pending = false;    // a cut may be pending on the device
     bool need_tiles = true;
-    CutDev cut{};   // the pending cut (cut.has = 0: none)
-    uint64_t extent = N;      // slots of cur that hold terms or zeros
-    uint64_t out_extent = 0;  // slots the next pass writes
-    g1_d.ensure(sizeof(G1Counters) + 64);
+    uint64_t extent = N;         // slots of cur that hold terms (exact when `exact`)
+    uint64_t out_extent = 0;     // slots the next pass writes (known on the host after tiling)
+    const uint64_t bound = 4 * std::max<uint64_t>(cap, N) + 64;
+    g1_d.ensure(2 * sizeof(G1Counters) + 64);
     G1Counters* cd = g1_d.as<G1Counters>();
     double* dropd = &cd->drop[0];
-    bool tiled = false;       // cur holds tiles (live ranges tr_s0/tr_l0 of g1_ntiles tiles)
+    bool tiled = false;          // cur holds tiles (live ranges tr_s0/tr_l0 of g1_ntiles tiles)
+    // counters of the gates enqueued but not yet read (at most two: the previous and this one)
+    constexpr size_t kPinRing = 16384;
+    struct Lag {
+      size_t gi;
+      hipEvent_t ev;
+      int slot;
+    };
+    std::vector<Lag> lag;
+    uint64_t last_live = 0;      // live terms after the last gate read, before its cut
+    uint64_t ext_next = 0;       // slots the pass after the last gate read writes
+    uint64_t ext_last = 0;       // slots the last gate read wrote
+    bool last_capped = false;
+    // sizes of the retry lists of the last gate read, which size the next retries' grids
+    // (0xffffffff: unknown, a full grid)
+    uint32_t seen_ovf[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu};
+    auto absorb = [&](const Lag& l) {   // read one gate's counters (waits for that gate only)
+      HIPCHK(hipEventSynchronize(l.ev));
+      G1Counters h;
+      std::memcpy(&h, (const char*)ctx->pinned + kPinRing + (size_t)l.slot * 1024, sizeof h);
+      ctx->evfree.push_back(l.ev);
+      if (h.tab_err) throw_fail(PP_ERR_DEVICE, "no room for an oversize tile's hash table");
+      for (int k = 0; k < kDropSlots; ++k) ls.dropped_l1 += h.drop[k];
+      ls.n_fallback += (int64_t)h.big_terms;
+      for (int k = 0; k < 3; ++k) seen_ovf[k] = h.ovf[k];
+      last_live = h.bases_total / 2;
+      ext_last = ext_next;
+      ext_next = h.bases_total;
+      ls.n_peak = std::max<int64_t>(ls.n_peak, (int64_t)last_live);
+      if (h.ovf[0] * 64 > h.nlist[0] + h.nlist[1]) routed = false;   // tiles outgrew their shape: sort again
+      last_capped = !gates[l.gi].clifford && cap > 0 && last_live > cap;
+      const uint64_t n_after = last_capped ? cap : last_live;
+      if (n_after < g1_ntiles * kG1Target / 4) need_tiles = true;   // the tiles have become small
+    };
+    auto drain = [&]() {
+      for (const Lag& l : lag) absorb(l);
+      lag.clear();
+    };
     auto densify = [&]() {   // apply a pending cut and squeeze out the unused slots
       N = extent;
       const TileView tv{tr_s0.as<uint32_t>(), tr_l0.as<uint32_t>(), (uint32_t)g1_ntiles};
-      apply_cut(cut, ls, tiled ? &tv : nullptr);
-      cut.has = 0;
+      apply_cut(CutDev{}, ls, tiled ? &tv : nullptr, cut_pending ? cutp : nullptr);
+      hipLaunchKernelGGL(k_sel_clear, dim3(1), dim3(64), 0, st, ss);
+      ctx->check_launch();
+      cut_pending = false;
       extent = N;
       tiled = false;
     };
-    for (size_t gi = 0; gi < gates.size() && N > 0; ++gi) {
+    size_t gi = 0;
+    for (; gi < gates.size() && N > 0; ++gi) {
       const GateDev& G = gates[gi];
       if (need_tiles) {
-        if (extent != N || cut.has) densify();
+        drain();
+        if (tiled) {
+          // extent and live count of the last pass, exactly
+          extent = ext_last;
+          N = last_capped ? cap : last_live;
+        }
+        if (extent != N || cut_pending) densify();
         if (N == 0) break;
         g1_tile(gm);
         out_extent = g1_bases(tr_l0.as<uint32_t>(), g1_ntiles);
+        ext_next = out_extent;
+        for (auto& v : seen_ovf) v = 0xffffffffu;
         need_tiles = false;
       }
       const uint64_t ntiles = g1_ntiles;
-      alt.ensure(out_extent + 64);
+      alt.ensure(std::max(bound, out_extent + 64));
       tr_s1.ensure(ntiles * 4 + 64);
       tr_l1.ensure(ntiles * 4 + 64);
       for (Buf* b : {&rl0, &rl1, &rl2, &g1_ovf, &ovl1, &ovl2}) b->ensure(ntiles * 4 + 64);
-      HIPCHK(hipMemsetAsync(cd, 0, sizeof(G1Counters), st));
-      G1Counters hc;
-      auto read_counters = [&]() {
-        HIPCHK(hipMemcpyAsync(ctx->pinned, cd, sizeof hc, hipMemcpyDeviceToHost, st));
-        sync();
-        std::memcpy(&hc, ctx->pinned, sizeof hc);
-      };
+      // counters of this gate (the routed list sizes stay)
+      HIPCHK(hipMemsetAsync(&cd->ovf[0], 0, sizeof(G1Counters) - offsetof(G1Counters, ovf), st));
       if (!routed) {
-        // sort the tiles by size once per tiling (a tile changes size slowly; one that
-        // outgrows the wavefront shape is retried in the next shape)
+        // sort the tiles by size (a tile changes size slowly; one that outgrows its shape is
+        // retried in the next); the passes read the list sizes on the device
+        HIPCHK(hipMemsetAsync(&cd->nlist[0], 0, sizeof cd->nlist, st));
         hipLaunchKernelGGL(k_route_tiles, grid1(ntiles), dim3(256), 0, st, (const uint32_t*)tr_l0.as<uint32_t>(),
                            (uint32_t)ntiles, kG1SmallMax, kG1MidMax, (const uint32_t*)g1_base.as<uint32_t>(),
                            tr_s1.as<uint32_t>(), tr_l1.as<uint32_t>(), rl0.as<uint32_t>(), rl1.as<uint32_t>(),
                            rl2.as<uint32_t>(), &cd->nlist[0]);
         ctx->check_launch();
-        read_counters();
-        for (int k = 0; k < 3; ++k) route_n[k] = hc.nlist[k];
         routed = true;
-        HIPCHK(hipMemsetAsync(cd, 0, sizeof(G1Counters), st));
       }
-      for (int k = 0; k < 3; ++k) hc.nlist[k] = route_n[k];
       Gate1Args<CT> a{};
       a.in = cur.view();
       a.out = alt.view();
@@ -1621,7 +1749,7 @@ struct Engine final : EngineBase {
       a.zero_on_ovf = 0;
       a.g = G;
       a.eps = G.clifford ? 0.0 : eps;
-      a.cut = cut;
+      a.cutp = cutp;
       a.dropped = dropd;
       auto with_list = [&](const Buf& list, Buf& ovl, int k, int zero) {
         Gate1Args<CT> b = a;
@@ -1631,108 +1759,98 @@ struct Engine final : EngineBase {
         b.zero_on_ovf = zero;
         return b;
       };
-      // One wavefront for small tiles, 256 threads for the others.  Tiles that outgrow a shape
-      // are retried in the next; the retries read their counts on the device, so the whole
-      // cascade is enqueued without waiting.
-      const uint32_t nl0 = hc.nlist[0], nl1 = hc.nlist[1], nl2 = hc.nlist[2];
-      if (nl0) g1_launch<kG1WaveCap, 64>(with_list(rl0, g1_ovf, 0, 0), nl0, 0);
-      if (nl1) g1_launch<512, 128>(with_list(rl1, g1_ovf, 0, 0), nl1, 3);
-      if (nl2) g1_launch<1024, 256>(with_list(rl2, ovl1, 1, 0), nl2, 1);
-      if (nl0 + nl1) g1_launch<1024, 256>(with_list(g1_ovf, ovl1, 1, 0), nl0 + nl1, 1, &cd->ovf[0]);
-      if (nl0 + nl1 + nl2)
-        g1_launch<LayerCfg<W>::CAP, LayerCfg<W>::BLOCK>(with_list(ovl1, ovl2, 2, 1), nl0 + nl1 + nl2, 2,
-                                                         &cd->ovf[1]);
-      // the next gate's output bases (other buffer: the oversize pass below still reads the
-      // current ones) and their total, then the counter block (counts, total, dropped
-      // weight) read back in one copy
-      g1_bases_launch(tr_l1.as<uint32_t>(), ntiles, g1_base2, &cd->bases_total);
-      HIPCHK(hipMemcpyAsync(ctx->pinned, cd, sizeof hc, hipMemcpyDeviceToHost, st));
-      sync();
-      std::memcpy(&hc, ctx->pinned, sizeof hc);
-      hc.nlist[0] = nl0;
-      hc.nlist[1] = nl1;
-      hc.nlist[2] = nl2;
-      if (hc.ovf[0] * 64 > nl0 + nl1) routed = false;   // tiles outgrew their shape: sort again
-      uint64_t giant_terms = 0;
-      uint64_t next_extent = hc.bases_total;
-      std::vector<double> dsl(hc.drop, hc.drop + kDropSlots);
-      if (hc.ovf[2] > 0) {
-        // classes too large for LDS that the gate touches: one workgroup per tile in its own
-        // output region, with a hash table in global memory
-        const uint32_t n2 = hc.ovf[2];
-        std::vector<uint32_t> o2(n2), tl(ntiles);
-        HIPCHK(hipMemcpyAsync(o2.data(), ovl2.p, 4 * (size_t)n2, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(tl.data(), tr_l0.p, 4 * ntiles, hipMemcpyDeviceToHost, st));
-        sync();
-        std::vector<uint64_t> off(n2);
-        std::vector<uint32_t> hs(n2);
-        uint64_t tot = 0;
-        for (uint32_t b = 0; b < n2; ++b) {
-          const uint32_t n0 = tl[o2[b]];
-          uint32_t h = 64;
-          while (h < 2 * n0) h <<= 1;
-          off[b] = tot;
-          hs[b] = h;
-          tot += h;
-          ls.n_fallback += n0;
-        }
-        g1_tab.ensure(tot * 4 + 64);
-        g1_tabmeta.ensure(12 * (size_t)n2 + 64);
-        HIPCHK(hipMemsetAsync(g1_tab.p, 0xff, tot * 4, st));
-        uint64_t* offd = g1_tabmeta.as<uint64_t>();
-        uint32_t* hsd = (uint32_t*)(offd + n2);
-        HIPCHK(hipMemcpyAsync(offd, off.data(), 8 * (size_t)n2, hipMemcpyHostToDevice, st));
-        HIPCHK(hipMemcpyAsync(hsd, hs.data(), 4 * (size_t)n2, hipMemcpyHostToDevice, st));
+      // One wavefront for small tiles, 128 and 256 threads for the others.  Tiles that
+      // outgrow a shape are retried in the next; every launch reads its list size on the
+      // device, so the whole cascade is enqueued without waiting.
+      const unsigned nt = (unsigned)ntiles;
+      // the retries' grids follow the retry lists of the gate read last (a list is rarely
+      // much longer than at the gate before; a longer one is still covered, more slowly)
+      auto retry_grid = [&](uint32_t seen) {
+        return seen == 0xffffffffu ? 0xffffffffu : std::max<uint32_t>(16, 2 * seen);
+      };
+      g1_launch<kG1WaveCap, 64>(with_list(rl0, g1_ovf, 0, 0), nt, 0, &cd->nlist[0]);
+      g1_launch<512, 128>(with_list(rl1, g1_ovf, 0, 0), nt, 3, &cd->nlist[1]);
+      g1_launch<1024, 256>(with_list(rl2, ovl1, 1, 0), nt, 1, &cd->nlist[2]);
+      g1_launch<1024, 256>(with_list(g1_ovf, ovl1, 1, 0), nt, 1, &cd->ovf[0], retry_grid(seen_ovf[0]));
+      g1_launch<LayerCfg<W>::CAP, LayerCfg<W>::BLOCK>(with_list(ovl1, ovl2, 2, 1), nt, 2, &cd->ovf[1],
+                                                       retry_grid(seen_ovf[1]));
+      {
+        // classes too large for LDS that the gate touches: a persistent grid of 1024-thread
+        // workgroups, one tile at a time in its own output region, with a hash table in
+        // global memory carved from g1_tab (at most 4 words per input term of the pass)
+        const uint64_t tab_words = 2 * std::max<uint64_t>(bound, out_extent) + 4096;
+        g1_tab.ensure(tab_words * 4 + 64);
         hscr_d.ensure(alt.cap * 4 + 64);   // hash scratch, one slot per output slot
         Gate1Args<CT> b = with_list(ovl2, ovl2, 2, 0);
+        b.t_count = nt;
+        b.t_count_dev = &cd->ovf[2];
         b.hscr = hscr_d.as<uint32_t>();
         g1_io.ensure(2 * kDropSlots * 8 + 64);
         b.io = g1_io.as<unsigned long long>();
-        if (ctx->timing) HIPCHK(hipMemsetAsync(b.io, 0, 2 * kDropSlots * 8, st));
         uint32_t* tabd = g1_tab.as<uint32_t>();
-        const int pi = ctx->run("gate_tile_global", 0, (double)n2, [&] {
-          hipLaunchKernelGGL((k_gate1_big<W, CT, ORD>), dim3(n2), dim3(1024), 0, st, b, tabd, (const uint64_t*)offd,
-                             (const uint32_t*)hsd);
+        const unsigned nbig = (unsigned)std::min<uint64_t>({ntiles, 256, retry_grid(seen_ovf[2])});
+        ctx->run("gate_tile_global", 0, 0.0, [&] {
+          hipLaunchKernelGGL((k_gate1_big<W, CT, ORD>), dim3(nbig), dim3(1024), 0, st, b, tabd, (const uint64_t*)nullptr,
+                             (const uint32_t*)nullptr, &cd->tab_cursor, (unsigned long long)tab_words, &cd->tab_err,
+                             &cd->big_terms);
         });
         ctx->check_launch();
-        if (pi >= 0) {
-          std::vector<unsigned long long> h(2 * kDropSlots);
-          HIPCHK(hipMemcpyAsync(h.data(), b.io, h.size() * 8, hipMemcpyDeviceToHost, st));
-          sync();
-          double terms = 0.0;
-          for (unsigned long long v : h) terms += (double)v;
-          ctx->pending[pi].bytes = kTermBytes * terms;
-        }
-        sync();   // host vectors above are copy sources
-        // the tiles it wrote change the bases and the dropped weight read above
-        g1_bases_launch(tr_l1.as<uint32_t>(), ntiles, g1_base2, &cd->bases_total);
-        HIPCHK(hipMemcpyAsync(ctx->pinned, cd, sizeof hc, hipMemcpyDeviceToHost, st));
-        sync();
-        std::memcpy(&hc, ctx->pinned, sizeof hc);
-        next_extent = hc.bases_total;
-        dsl.assign(hc.drop, hc.drop + kDropSlots);
       }
+      // the next gate's output bases (other buffer: this pass read the current ones) and their
+      // total, twice the live count
+      g1_bases_launch(tr_l1.as<uint32_t>(), ntiles, g1_base2, &cd->bases_total);
       cur.swap(alt);
       std::swap(tr_s0, tr_s1);
       std::swap(tr_l0, tr_l1);
       std::swap(g1_base, g1_base2);
-      extent = out_extent;
       tiled = true;
-      for (double v : dsl) ls.dropped_l1 += v;
-      N = next_extent / 2 + giant_terms;
-      out_extent = next_extent;
-      ls.n_peak = std::max<int64_t>(ls.n_peak, (int64_t)N);
-      cut.has = 0;
-      if (!G.clifford && cap > 0 && N > cap) {
+      // the cap after a non-Clifford gate: selected on the device from the live ranges
+      if (!G.clifford && cap > 0) {
         const TileView tv{tr_s0.as<uint32_t>(), tr_l0.as<uint32_t>(), (uint32_t)ntiles};
-        cut = cap_cut(cap, extent, &tv);
-        ls.n_capped += (int64_t)(N - cap);
-        N = cap;
+        sel_launch(tv, &cd->bases_total, cap);
+        cut_pending = true;
+      } else {
+        hipLaunchKernelGGL(k_sel_clear, dim3(1), dim3(64), 0, st, ss);
+        ctx->check_launch();
+        cut_pending = false;
       }
-      // regroup when the cut has left the tiles small on average
-      if (N < ntiles * kG1Target / 4) need_tiles = true;
+      // this gate's counters, read one gate later
+      const int slot = (int)(gi & 1);
+      HIPCHK(hipMemcpyAsync((char*)ctx->pinned + kPinRing + (size_t)slot * 1024, cd, sizeof(G1Counters),
+                            hipMemcpyDeviceToHost, st));
+      hipEvent_t ev = ctx->ev();
+      HIPCHK(hipEventRecord(ev, st));
+      // the output extent of the next pass is this pass's bases total: known on the host
+      // only once read; until then the buffers are sized by the bound
+      out_extent = 0;
+      lag.push_back(Lag{gi, ev, slot});
+      if (lag.size() > 1) {
+        absorb(lag.front());
+        lag.erase(lag.begin());
+      }
     }
-    if (cut.has || extent != N) densify();
+    drain();
+    if (tiled) {
+      extent = ext_last;
+      N = last_capped ? cap : last_live;
+    }
+    if (cut_pending || extent != N) densify();
+    check_selection(ls);
+  }
+
+  // Statistics of the device-side cuts since the last call, and their error flag.
+  void check_selection(pp_layer_stats& ls) {
+    if (!sel_d.p) return;
+    SelState* ss = sel_d.as<SelState>();
+    constexpr size_t kPinSel = 24576;
+    HIPCHK(hipMemcpyAsync((char*)ctx->pinned + kPinSel, ss, offsetof(SelState, cut), hipMemcpyDeviceToHost, st));
+    sync();
+    SelState h;
+    std::memcpy(&h, (const char*)ctx->pinned + kPinSel, offsetof(SelState, cut));
+    if (h.n_errors) throw_fail(PP_ERR_DEVICE, "cap selection lost its boundary");
+    ls.n_capped += (int64_t)h.n_capped;
+    hipLaunchKernelGGL(k_sel_reset_stats, dim3(1), dim3(64), 0, st, ss);
+    ctx->check_launch();
   }
 
   // ---- create ----------------------------------------------------------------------------------

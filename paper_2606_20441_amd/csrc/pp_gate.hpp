@@ -70,11 +70,20 @@ struct Gate1Args {
   GateDev g;
   double eps;                   // threshold after the gate (0: none)
   CutDev cut;                   // the previous gate's cap, applied on load
+  const CutDev* cutp;           // if set, that cut is read from here on the device instead
   uint32_t* ovf_tiles;          // tiles that did not fit in LDS
   uint32_t* ovf_count;
   double* dropped;              // [kDropSlots]: sum of |c| removed (cut and threshold)
   unsigned long long* io;       // [2][kDropSlots]: terms loaded / written by completed tiles
 };
+
+// The pending cut of a gate pass: from device memory (written there by the device-side
+// selection of the previous gate) or from the launch arguments.
+template <class CT>
+__device__ __forceinline__ CutDev gate_cut(const Gate1Args<CT>& a) {
+  if (!a.cutp) return a.cut;
+  return *a.cutp;
+}
 
 // A tile handed to another path: its output range is left empty (length 0).
 template <class CT>
@@ -88,7 +97,7 @@ __device__ void zero_region(const Gate1Args<CT>& a, uint32_t tile, uint32_t n0) 
 
 // A tile copied through with only the pending cut applied (order kept).
 template <int W, class CT, bool ORD, int BLOCK>
-__device__ void pass_through(const Gate1Args<CT>& a, uint32_t tile, uint32_t t0, uint32_t n0) {
+__device__ void pass_through(const Gate1Args<CT>& a, const CutDev& cut, uint32_t tile, uint32_t t0, uint32_t n0) {
   constexpr int NW = BLOCK / 64;
   __shared__ uint32_t p_wsum[NW];
   __shared__ double p_drop[NW];
@@ -97,11 +106,11 @@ __device__ void pass_through(const Gate1Args<CT>& a, uint32_t tile, uint32_t t0,
     const CT v = a.in.c[src];
     if (v == (CT)0) return false;
     if (fabs((double)v) < a.eps) return false;   // the threshold after a non-Clifford gate
-    if (!a.cut.has) return true;
+    if (!cut.has) return true;
     uint64_t kx[W], kz[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) { kx[w] = a.in.x[w * a.in.stride + src]; kz[w] = a.in.z[w * a.in.stride + src]; }
-    return cut_keeps<W, CT>(v, kx, kz, ORD ? a.in.o[src] : 0u, a.cut);
+    return cut_keeps<W, CT>(v, kx, kz, ORD ? a.in.o[src] : 0u, cut);
   };
   // count survivors per contiguous chunk of the tile
   const uint32_t chunk = (n0 + BLOCK - 1) / BLOCK;
@@ -228,6 +237,7 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
   const uint32_t gh = a.g.khash;
   const int pw = a.g.pivot_word, pb = a.g.pivot_bit;
   const double thr = a.eps;
+  const CutDev cut = gate_cut(a);
 
   // current tile and the next one (ranges), the current tile's terms in flight
   uint32_t tile = tile_at(li), t0 = ld_uniform(a.t_start, tile), n0 = ld_uniform(a.t_len, tile);
@@ -277,7 +287,7 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
         if (tid == 0) a.ovf_tiles[atomicAdd(a.ovf_count, 1u)] = tile;
         if (a.zero_on_ovf) zero_region(a, tile, n0);
       } else {
-        pass_through<W, CT, ORD, BLOCK>(a, tile, t0, n0);
+        pass_through<W, CT, ORD, BLOCK>(a, cut, tile, t0, n0);
       }
     } else {
       for (int j = tid; j < H; j += BLOCK) hidx[j] = EMPTY;
@@ -301,7 +311,7 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
         for (int w = 0; w < W; ++w) { sx[w][i] = cur.x[r][w]; sz[w][i] = cur.z[r][w]; }
         if (ORD) so[i] = (uint8_t)cur.o[r];
         const CT cv = cur.c[r];
-        if (cv != (CT)0 && !cut_keeps<W, CT>(cv, cur.x[r], cur.z[r], cur.o[r], a.cut)) {
+        if (cv != (CT)0 && !cut_keeps<W, CT>(cv, cur.x[r], cur.z[r], cur.o[r], cut)) {
           lost += fabs((double)cv);
           cur.c[r] = (CT)0;
         }
@@ -484,13 +494,17 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
   }
 }
 
-// A tile too large for LDS that the gate touches: one 1024-thread workgroup per tile works
-// in the tile's own output region (2 * n0 slots) with an open-addressing table in global
-// memory (table[off[b] .. off[b] + hsize[b]), hsize a power of two >= 2 * n0, preset to
-// ~0), then compacts the region in place.  Same arithmetic as k_gate1.
+// A tile too large for LDS that the gate touches: a 1024-thread workgroup works in the
+// tile's own output region (2 * n0 slots) with an open-addressing table in global memory,
+// then compacts the region in place.  Same arithmetic as k_gate1.  Tables: either given
+// (table[off[b] .. off[b] + hsize[b]) for list entry b, hsize a power of two >= 2 * n0,
+// preset to ~0; one workgroup per entry), or, with `cursor` set, carved out of `table`
+// (table_cap words) on the device, one per tile, by a persistent grid that reads the
+// entry count on the device; a table that does not fit sets *err and its tile is skipped.
 template <int W, class CT, bool ORD>
-__global__ void __launch_bounds__(1024) k_gate1_big(Gate1Args<CT> a, uint32_t* table, const uint64_t* off,
-                                                    const uint32_t* hsize) {
+__device__ void gate1_big_tile(const Gate1Args<CT>& a, uint32_t li, uint32_t* table, const uint64_t* off,
+                               const uint32_t* hsize, unsigned long long* cursor, unsigned long long table_cap,
+                               unsigned int* err) {
   constexpr int BLOCK = 1024;
   constexpr int NW = BLOCK / 64;
   constexpr uint32_t EMPTY = 0xffffffffu;
@@ -498,19 +512,39 @@ __global__ void __launch_bounds__(1024) k_gate1_big(Gate1Args<CT> a, uint32_t* t
   __shared__ uint32_t s_wsum[NW];
   __shared__ uint32_t s_done;
   __shared__ double s_drop[NW];
+  __shared__ unsigned long long s_off;
+  __shared__ uint32_t s_hsize;
   const int tid = threadIdx.x, lane = tid & 63;
-  const uint32_t tile = a.t_list[blockIdx.x];
+  const uint32_t tile = a.t_list[li];
   const uint64_t t0 = a.t_start[tile];
   const uint32_t n0 = a.t_len[tile];
   const uint64_t base = a.o_base[tile];
-  uint32_t* tab = table + off[blockIdx.x];
-  const uint32_t hm = hsize[blockIdx.x] - 1;
+  if (cursor) {
+    if (tid == 0) {
+      uint32_t h = 64;
+      while (h < 2 * n0) h <<= 1;
+      const unsigned long long o = atomicAdd(cursor, (unsigned long long)h);
+      s_off = o;
+      s_hsize = o + h <= table_cap ? h : 0u;
+      if (!s_hsize) atomicOr(err, 1u);
+    }
+    __syncthreads();
+    if (!s_hsize) return;
+    for (uint32_t j = tid; j < s_hsize; j += BLOCK) table[s_off + j] = EMPTY;
+  } else if (tid == 0) {
+    s_off = off[li];
+    s_hsize = hsize[li];
+  }
+  __syncthreads();
+  uint32_t* tab = table + s_off;
+  const uint32_t hm = s_hsize - 1;
   uint64_t m[2 * W];
 #pragma unroll
   for (int w = 0; w < 2 * W; ++w) m[w] = a.g.m[w];
   const double cs = a.g.cs, snd = a.g.sn_dir, thr = a.eps;
   const uint32_t gh = a.g.khash;
   const int pw = a.g.pivot_word, pb = a.g.pivot_bit;
+  const CutDev cut = gate_cut(a);
   Terms<CT> o = a.out;
   if (tid == 0) { s_new = 0; s_done = 0; }
   double lost = 0.0;
@@ -534,7 +568,7 @@ __global__ void __launch_bounds__(1024) k_gate1_big(Gate1Args<CT> a, uint32_t* t
     a.hscr[base + i] = h;
     const CT cv = a.in.c[t0 + i];
     CT keep = cv;
-    if (cv != (CT)0 && !cut_keeps<W, CT>(cv, kx, kz, oi, a.cut)) {
+    if (cv != (CT)0 && !cut_keeps<W, CT>(cv, kx, kz, oi, cut)) {
       lost += fabs((double)cv);
       keep = (CT)0;
     }
@@ -660,11 +694,26 @@ __global__ void __launch_bounds__(1024) k_gate1_big(Gate1Args<CT> a, uint32_t* t
     a.o_len[tile] = written;
     double v = 0.0;
     for (int w = 0; w < NW; ++w) v += s_drop[w];
-    if (v != 0.0) atomicAdd(&a.dropped[blockIdx.x % kDropSlots], v);
-    atomicAdd(&a.io[blockIdx.x % kDropSlots], (unsigned long long)n0);
-    atomicAdd(&a.io[kDropSlots + blockIdx.x % kDropSlots], (unsigned long long)written);
+    if (v != 0.0) atomicAdd(&a.dropped[li % kDropSlots], v);
+    if (a.io) {
+      atomicAdd(&a.io[li % kDropSlots], (unsigned long long)n0);
+      atomicAdd(&a.io[kDropSlots + li % kDropSlots], (unsigned long long)written);
+    }
   }
   (void)s_done;
+}
+
+template <int W, class CT, bool ORD>
+__global__ void __launch_bounds__(1024) k_gate1_big(Gate1Args<CT> a, uint32_t* table, const uint64_t* off,
+                                                    const uint32_t* hsize, unsigned long long* cursor,
+                                                    unsigned long long table_cap, unsigned int* err,
+                                                    unsigned long long* big_terms) {
+  const uint32_t count = a.t_count_dev ? min(*a.t_count_dev, a.t_count) : a.t_count;
+  for (uint32_t li = blockIdx.x; li < count; li += gridDim.x) {
+    __syncthreads();   // the previous tile's readers of the shared words are done
+    if (big_terms && threadIdx.x == 0) atomicAdd(big_terms, (unsigned long long)a.t_len[a.t_list[li]]);
+    gate1_big_tile<W, CT, ORD>(a, li, table, off, hsize, cursor, table_cap, err);
+  }
 }
 
 // Sort tiles by size: empty tiles get their (empty) output record here, tiles of at most
@@ -859,7 +908,9 @@ __global__ void k_gather_bucket_tiles(Terms<CT> t, TileView tv, uint64_t pmask, 
 // keep[i] = 1 for the live slots that survive the pending cut (the caller clears keep over
 // the whole buffer first, so unused slots stay 0).
 template <int W, class CT, bool ORD>
-__global__ void k_cut_keep_tiles(Terms<CT> t, TileView tv, CutDev cut, uint32_t* keep, double* dropped) {
+__global__ void k_cut_keep_tiles(Terms<CT> t, TileView tv, CutDev cut0, const CutDev* cutp, uint32_t* keep,
+                                 double* dropped) {
+  const CutDev cut = cutp ? *cutp : cut0;
   double lost = 0.0;
   tile_visit<CT>(t.c, tv, [&](uint64_t i, uint64_t key) {
     bool k = true;
