@@ -1215,7 +1215,11 @@ struct Engine final : EngineBase {
   // LDS capacity of the one-wavefront shape: less LDS per wavefront, more of them per compute
   // unit; a tile that outgrows it is redone in the 256-thread shape
   static constexpr int kG1WaveCap = 256;
-  static constexpr uint64_t kG1Target = 96;     // terms per one-wavefront tile when tiling
+  // Terms per tile when tiling.  Measured on the 56-qubit workload (cap 2^24, FP64, ms per
+  // propagation): 96 -> 401, 128 -> 390, 192 -> 378, 256 -> 370, 384 -> 375, 512 -> 380,
+  // 768 -> 437.  Larger tiles mean fewer per-tile phases and fewer half-used cache lines at
+  // tile edges, until the tiles no longer fit the one-wavefront and 128-thread shapes.
+  static constexpr uint64_t kG1Target = 256;
   uint64_t g1_ntiles = 0;
   bool routed = false;      // tile lists by size are current for this tiling
   uint32_t route_n[3] = {0, 0, 0};
