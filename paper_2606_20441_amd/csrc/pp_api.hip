@@ -338,7 +338,7 @@ struct Engine final : EngineBase {
   TBuf<CT, ORD> gb;              // boundary candidates of a cap
   Buf u32a, u32b, u32c, scan_scr, tiles, gates_d, sup_d, tab_d, drun_d, dm_d, dval_d, cnt_d, ovf_d, partial_d, f64_d, span_d, htab_d, lstat_d;
   Buf hscr_d, tr_s0, tr_l0, tr_s1, tr_l1, g1_d, g1_ovf, g1_base, g1_base2;   // per-gate tile path
-  Buf rl0, rl1, rl2, ovl1, ovl2, tf_flag, tf_pos, tf_list, g1_io, g1_tab, g1_tabmeta, win_hist_d, qlist_d, topk_d, topk_off, sel_d;
+  Buf rl0, rl1, rl2, ovl1, ovl2, tf_flag, tf_pos, tf_list, g1_io, g1_tab, g1_tabmeta, win_hist_d, qlist_d, topk_d, topk_off, sel_d, cscr_d;
   double growth[4] = {4.0, 4.0, 2.0, 3.0};
   double tile_target[4] = {80.0, 80.0, 80.0, 64.0};   // level-0 (one-wavefront) tile targets
   uint64_t last_ntiles = 1, last_ovf_tiles = 0;
@@ -348,7 +348,7 @@ struct Engine final : EngineBase {
     for (auto* t : {&ta, &tb}) { t->mem.ctx = ctx; t->W = W; }
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &drun_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
                    &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hscr_d, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &rl0, &rl1, &rl2, &ovl1, &ovl2,
-                   &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d, &qlist_d, &topk_d, &topk_off, &sel_d})
+                   &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d, &qlist_d, &topk_d, &topk_off, &sel_d, &cscr_d})
       b->ctx = ctx;
     cnt_d.ensure(256);
     span_d.ensure(256);
@@ -361,7 +361,7 @@ struct Engine final : EngineBase {
     for (auto* t : {&ta, &tb}) t->mem.release();
     for (Buf* b : {&u32a, &u32b, &u32c, &scan_scr, &tiles, &gates_d, &sup_d, &tab_d, &drun_d, &dm_d, &dval_d, &cnt_d, &ovf_d,
                    &partial_d, &f64_d, &span_d, &htab_d, &lstat_d, &hscr_d, &tr_s0, &tr_l0, &tr_s1, &tr_l1, &g1_d, &g1_ovf, &g1_base, &g1_base2, &rl0, &rl1, &rl2, &ovl1, &ovl2,
-                   &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d, &qlist_d, &topk_d, &topk_off, &sel_d})
+                   &tf_flag, &tf_pos, &tf_list, &g1_io, &g1_tab, &g1_tabmeta, &win_hist_d, &qlist_d, &topk_d, &topk_off, &sel_d, &cscr_d})
       b->release();
   }
 
@@ -1222,6 +1222,7 @@ struct Engine final : EngineBase {
   static constexpr uint64_t kG1Target = 256;
   uint64_t g1_ntiles = 0;
   bool routed = false;      // tile lists by size are current for this tiling
+  int sine_limit = -1;      // >= 0: the gate passes run in sine order with this tag limit
   uint32_t route_n[3] = {0, 0, 0};
 
   // Group the terms by the run's invariant bits and cut them into tiles of whole groups
@@ -1755,6 +1756,10 @@ struct Engine final : EngineBase {
       a.eps = G.clifford ? 0.0 : eps;
       a.cutp = cutp;
       a.dropped = dropd;
+      if (sine_limit >= 0) {
+        a.sine_on = 1;
+        a.sine_max = sine_limit;
+      }
       auto with_list = [&](const Buf& list, Buf& ovl, int k, int zero) {
         Gate1Args<CT> b = a;
         b.t_list = list.as<uint32_t>();
@@ -1789,6 +1794,10 @@ struct Engine final : EngineBase {
         b.t_count = nt;
         b.t_count_dev = &cd->ovf[2];
         b.hscr = hscr_d.as<uint32_t>();
+        if (b.sine_on) {
+          cscr_d.ensure(alt.cap * 8 + 64);   // coefficient scratch, one slot per output slot
+          b.cscr = cscr_d.as<double>();
+        }
         g1_io.ensure(2 * kDropSlots * 8 + 64);
         b.io = g1_io.as<unsigned long long>();
         uint32_t* tabd = g1_tab.as<uint32_t>();
@@ -1960,15 +1969,36 @@ struct Engine final : EngineBase {
       if (N) noise_greedy(cur.view(), N, nd, "noise");
     };
     if (!L->noise_after_gates) noise();
-    for (const HostGate& h : prepare_gates(L)) {
-      if (N == 0) break;
-      cur.swap(sa);
-      const uint64_t m = per_gate(N, {h.g}, obs->trunc.eps, nullptr, 0.0, nullptr, nullptr, obs->trunc.max_order);
-      cur.swap(sa);
-      N = m;
-      ls.n_peak = std::max(ls.n_peak, (int64_t)N);
-      if (!h.g.clifford && obs->trunc.max_terms > 0 && (int64_t)N > obs->trunc.max_terms)
-        cap_select((uint64_t)obs->trunc.max_terms, ls);
+    const std::vector<HostGate> hg = prepare_gates(L);
+    if (obs->trunc.max_terms > 0) {
+      // with a cap: the tiled gate passes in sine order, one run of gates of a kind at a time
+      // (the tags are part of each term's key, the sin parts step them up)
+      struct SineGuard {
+        int* p;
+        ~SineGuard() { *p = -1; }
+      } sine_guard{&sine_limit};
+      sine_limit = obs->trunc.max_order;
+      size_t i = 0;
+      while (i < hg.size() && N > 0) {
+        size_t j = i + 1;
+        const int kind = hg[i].kind;
+        if (kind != KIND_OTHER)
+          while (j < hg.size() && hg[j].kind == kind) ++j;
+        std::vector<GateDev> run;
+        for (size_t k = i; k < j; ++k) run.push_back(hg[k].g);
+        gate_by_gate(run, kind, obs->trunc.eps, (uint64_t)obs->trunc.max_terms, ls);
+        ls.n_peak = std::max(ls.n_peak, (int64_t)N);
+        i = j;
+      }
+    } else {
+      for (const HostGate& h : hg) {
+        if (N == 0) break;
+        cur.swap(sa);
+        const uint64_t m = per_gate(N, {h.g}, obs->trunc.eps, nullptr, 0.0, nullptr, nullptr, obs->trunc.max_order);
+        cur.swap(sa);
+        N = m;
+        ls.n_peak = std::max(ls.n_peak, (int64_t)N);
+      }
     }
     if (L->noise_after_gates) noise();
     ls.n_out = (int64_t)N;

@@ -71,6 +71,11 @@ struct Gate1Args {
   double eps;                   // threshold after the gate (0: none)
   CutDev cut;                   // the previous gate's cap, applied on load
   const CutDev* cutp;           // if set, that cut is read from here on the device instead
+  // Sine order (sine_on, non-Clifford gates only): the tag counts sines.  The cos part of
+  // (P, t) keeps its tag, the sin part goes to (RP, t + 1) and is dropped above sine_max.
+  int sine_on;
+  int sine_max;
+  double* cscr;                 // per-slot coefficient scratch of `out` (the oversize kernel, sine order)
   uint32_t* ovf_tiles;          // tiles that did not fit in LDS
   uint32_t* ovf_count;
   double* dropped;              // [kDropSlots]: sum of |c| removed (cut and threshold)
@@ -325,6 +330,9 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
       __syncthreads();
 
       // ---- the gate ----------------------------------------------------------------------------
+      const bool sine = ORD && a.sine_on && pairs;
+      CT nsc[R];
+      uint32_t upd = 0;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const uint32_t i = (uint32_t)r * BLOCK + tid;
@@ -348,6 +356,58 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
           for (int w = 0; w < W; ++w) { sx[w][i] = qx[w]; sz[w][i] = qz[w]; }
           sh[i] = hh[r] ^ gh;
           sc[i] = (CT)((neg_i ? -ci : ci) * snd);
+          continue;
+        }
+        if (sine) {
+          // sine order: (Q, s) becomes cos c(Q, s) plus the sin part of (RQ, s - 1); the sin
+          // part of (Q, s) starts (RQ, s + 1) when no entry of that string and tag exists
+          // (an existing one takes it as its own incoming part).  Originals are read here,
+          // the new values written after the barrier.
+          const uint32_t hq = hh[r] ^ gh;
+          const uint32_t t = cur.o[r];
+          auto find = [&](uint32_t tag) -> uint32_t {
+            uint32_t sl = (hq ^ (tag * 0x9e3779b9u)) & (H - 1);
+            for (;;) {
+              const uint32_t k = hidx[sl];
+              if (k == EMPTY) return EMPTY;
+              if (sh[k] == hq && so[k] == tag) {
+                bool eq = true;
+#pragma unroll
+                for (int w = 0; w < W; ++w) eq = eq && sx[w][k] == qx[w] && sz[w][k] == qz[w];
+                if (eq) return k;
+              }
+              sl = (sl + 1) & (H - 1);
+            }
+          };
+          double ni = ci * cs;
+          if (t > 0) {
+            const uint32_t j = find(t - 1);
+            if (j != EMPTY) {
+              const double cj = (double)sc[j];
+              const bool neg_j = irp_negative<W>(qx, qz, m, a.g.rr_phase);
+              ni += (neg_j ? -cj : cj) * snd;
+            }
+          }
+          if (fabs(ni) < thr || ni == 0.0) { lost += fabs(ni); ni = 0.0; }
+          nsc[r] = (CT)ni;
+          upd |= 1u << r;
+          if ((int)t + 1 <= a.sine_max && find(t + 1) == EMPTY) {
+            const double nq = (neg_i ? -ci : ci) * snd;
+            if (fabs(nq) < thr || nq == 0.0) {
+              lost += fabs(nq);
+            } else {
+              const uint32_t k = n0 + atomicAdd(&s_new, 1u);
+              if (k < (uint32_t)CAP) {
+#pragma unroll
+                for (int w = 0; w < W; ++w) { sx[w][k] = qx[w]; sz[w][k] = qz[w]; }
+                sh[k] = hq;
+                so[k] = (uint8_t)(t + 1);
+                sc[k] = (CT)nq;
+              } else {
+                s_ovf = 1;
+              }
+            }
+          }
           continue;
         }
         // non-Clifford: find the partner string (same order tag) in the tile
@@ -397,6 +457,12 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
             }
           }
         }
+      }
+      if (sine) {
+        __syncthreads();   // every original has been read
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          if ((upd >> r) & 1u) sc[(uint32_t)r * BLOCK + tid] = nsc[r];
       }
       if (more) g1_fetch<W, CT, ORD, CAP, BLOCK>(a, cur, t0_n, n0_n);
       __syncthreads();
@@ -579,6 +645,12 @@ __device__ void gate1_big_tile(const Gate1Args<CT>& a, uint32_t li, uint32_t* ta
     }
   }
   __syncthreads();
+  // sine order: new coefficients go to cscr first (originals are read by other threads) and
+  // are copied back after the barrier
+  const bool sine = ORD && a.sine_on && cs != 0.0 && snd != 0.0;
+  if (sine)
+    for (uint32_t i = tid; i < n0; i += BLOCK) a.cscr[base + i] = (double)o.c[base + i];
+  __syncthreads();
   // the gate
   for (uint32_t i = tid; i < n0; i += BLOCK) {
     const double ci = (double)o.c[base + i];
@@ -586,7 +658,11 @@ __device__ void gate1_big_tile(const Gate1Args<CT>& a, uint32_t li, uint32_t* ta
     uint64_t kx[W], kz[W];
     okey(base + i, kx, kz);
     if (!anticommutes<W>(kx, kz, m)) {
-      if (fabs(ci) < thr) { lost += fabs(ci); o.c[base + i] = (CT)0; }   // threshold on every term
+      if (fabs(ci) < thr) {   // threshold on every term
+        lost += fabs(ci);
+        o.c[base + i] = (CT)0;
+        if (sine) a.cscr[base + i] = 0.0;
+      }
       continue;
     }
     if (snd == 0.0) {
@@ -607,6 +683,51 @@ __device__ void gate1_big_tile(const Gate1Args<CT>& a, uint32_t li, uint32_t* ta
       continue;
     }
     const uint32_t hq = h ^ gh;
+    if (sine) {
+      // as in k_gate1: (Q, s) takes cos c(Q, s) plus the sin part of (RQ, s - 1); a sin part
+      // without an entry (RQ, s + 1) starts one
+      auto find = [&](uint32_t tag) -> uint32_t {
+        uint32_t sl = (hq ^ (tag * 0x9e3779b9u)) & hm;
+        for (;;) {
+          const uint32_t k = tab[sl];
+          if (k == EMPTY) return EMPTY;
+          if (a.hscr[base + k] == hq && o.o[base + k] == tag) {
+            uint64_t px[W], pz[W];
+            okey(base + k, px, pz);
+            bool eq = true;
+#pragma unroll
+            for (int w = 0; w < W; ++w) eq = eq && px[w] == qx[w] && pz[w] == qz[w];
+            if (eq) return k;
+          }
+          sl = (sl + 1) & hm;
+        }
+      };
+      double ni = ci * cs;
+      if (oi > 0) {
+        const uint32_t j = find(oi - 1);
+        if (j != EMPTY) {
+          const double cj = (double)o.c[base + j];
+          const bool neg_j = irp_negative<W>(qx, qz, m, a.g.rr_phase);
+          ni += (neg_j ? -cj : cj) * snd;
+        }
+      }
+      if (fabs(ni) < thr || ni == 0.0) { lost += fabs(ni); ni = 0.0; }
+      a.cscr[base + i] = ni;
+      if ((int)oi + 1 <= a.sine_max && find(oi + 1) == EMPTY) {
+        const double nq = (neg_i ? -ci : ci) * snd;
+        if (fabs(nq) < thr || nq == 0.0) {
+          lost += fabs(nq);
+        } else {
+          const uint64_t k = base + n0 + atomicAdd(&s_new, 1u);   // at most one child per term
+#pragma unroll
+          for (int w = 0; w < W; ++w) { o.x[w * o.stride + k] = qx[w]; o.z[w * o.stride + k] = qz[w]; }
+          o.o[k] = (uint8_t)(oi + 1);
+          o.c[k] = (CT)nq;
+          a.hscr[k] = hq;
+        }
+      }
+      continue;
+    }
     uint32_t slot = (hq ^ (oi * 0x9e3779b9u)) & hm;
     uint32_t j = EMPTY;
     for (;;) {
@@ -651,6 +772,10 @@ __device__ void gate1_big_tile(const Gate1Args<CT>& a, uint32_t li, uint32_t* ta
     }
   }
   __syncthreads();
+  if (sine) {
+    for (uint32_t i = tid; i < n0; i += BLOCK) o.c[base + i] = (CT)a.cscr[base + i];
+    __syncthreads();
+  }
   // compact the region in place, chunk by chunk (destinations never pass their sources)
   const uint32_t n = n0 + s_new;
   uint32_t written = 0;

@@ -67,6 +67,8 @@ def _wide_angles(circ, seed):
     ("tfim3x3", dict(steps=3), 3, 0.0, 25, True),
     ("tfim7x8_pna", dict(steps=2), 2, 1e-5, 0, False),
     ("tfim8x16", dict(steps=1), 2, 1e-4, 0, True),
+    ("tfim7x8_pna", dict(steps=2), 2, 1e-6, 400, False),
+    ("tfim8x16", dict(steps=1), 2, 1e-5, 1000, True),
 ])
 def test_sine_order_parity(pp, ctx, orc, name, kw, K, eps, cap, wide):
     wl = W.named_workload(name, **kw)
@@ -84,6 +86,40 @@ def test_sine_order_parity(pp, ctx, orc, name, kw, K, eps, cap, wide):
     log(f"  {rep}; <O~> {eg!r} vs {eo!r}")
     assert abs(eg - eo) < 1e-10
     g.destroy()
+
+
+@pytest.mark.parametrize("K", [1, 3])
+@pytest.mark.parametrize("cap", [40000, 12000])
+def test_sine_order_capped_oversize_classes(pp, ctx, orc, K, cap):
+    """Sine order under a binding cap, through the tiled gate passes: 2^14 strings share one
+    z (all x patterns on 14 qubits, a class far larger than an LDS tile) plus small classes
+    elsewhere; every X rotation pairs a whole class and the sin parts step the tags up to K.
+    The angles stay within pi/4, so the interaction picture adds no Clifford gate."""
+    n = 40
+    rng = np.random.default_rng(17)
+    terms = []
+    for xm in range(1 << 14):
+        terms.append(({q: ("Y" if (xm >> q) & 1 else "Z") for q in range(14)}, float(rng.uniform(-1, 1))))
+    for k in range(3000):
+        qs = rng.choice(np.arange(14, n), 4, replace=False)
+        terms.append(({int(q): "XYZ"[int(rng.integers(0, 3))] for q in qs}, float(rng.uniform(-1, 1))))
+    ps = W.pauli_sum(n, terms)
+    layer = W.make_layer(n, [({q: "X"}, 0.2 + 0.01 * q) for q in range(n)], [])
+    log(f"sine order, oversize classes: K={K} cap={cap} terms={len(ps.c)}")
+    for direction in (1, -1):
+        g = pp.Observable.from_sum(ctx, ps, eps=1e-5, max_terms=cap, mode="sine_order", max_order=K)
+        o = orc.OracleSum.from_sum(ps)
+        g.apply_layer(layer, direction, with_noise=False)
+        st = g.last_layer_stats()
+        o.apply_layer(layer, direction, with_noise=False, eps=1e-5, max_terms=cap, mode=2, max_order=K)
+        gd, od = g.as_dict(), o.as_dict()
+        assert st["n_fallback"] > 0
+        rep = compare_sums(gd, od, thresholds=[1e-5, cap_cut(od)], rtol=1e-12, atol=1e-15,
+                           context=f"sine order, oversize classes, direction {direction}")
+        log(f"  direction {direction}: {rep}")
+        assert len(gd) <= cap
+        assert max(k[2] for k in gd) <= K
+        g.destroy()
 
 
 def test_sine_order_all_tags_equal_greedy(pp, ctx):
