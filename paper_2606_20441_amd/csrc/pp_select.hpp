@@ -8,7 +8,7 @@
 // and returns at once when it has nothing to do:
 //  * k_sel_win: reads the live count the gate pass left on the device (nothing more to do
 //    when the sum is within the cap), then a histogram of the |c| keys over a window of 2048
-//    bins around the previous cut;
+//    bins around the previous cut (before the first cut: one bin per octave, every key);
 //  * k_sel_pick (one workgroup): the bin holding the K-th term, or, when the window missed
 //    it, the passes start from the top bits;
 //  * twice k_sel_pass + k_sel_pick: 13 more bits of |c|, while the bucket of the K-th term
@@ -26,6 +26,13 @@
 
 namespace pp {
 
+// Window bins start at 2^shift keys and narrow by one bit after each cut whose window bucket
+// was still too large to gather, down to 2^min_shift.  A window that misses the cut widens by
+// two bits; if that miss also left the two passes short, so that the one-workgroup sweeps had
+// to finish the job (FP64 keys of a large sum), the wider window becomes the new floor: such
+// a miss costs far more than the passes a narrow window saves.
+constexpr int kSelMinShift = 4;
+
 // Candidates ranked in LDS: (8 + 16 W + 1) bytes each.
 template <int W>
 constexpr uint32_t sel_gather() { return W == 1 ? 4096u : (W == 2 ? 2048u : 1024u); }
@@ -41,6 +48,8 @@ struct SelState {
   unsigned long long hint_key;   // |c| key of the last cut
   int hint_valid;
   int hint_shift;                // window bins of 2^hint_shift keys
+  int min_shift;                 // the narrowest bins the window may take
+  int missed;                    // the window of the current cut missed it
   // one cut
   unsigned long long K;          // the cap
   int active;                    // 1: the sum exceeds the cap and a cut is being selected
@@ -147,6 +156,22 @@ __device__ __forceinline__ void sel_fix(SelState* ss, int word, int shift, int b
   ss->done = count <= G;
 }
 
+// The window of the first histogram: 2048 bins of 2^sh keys from lo, around the previous cut
+// (returns true), or, before the first cut, over every key (bins of one octave of |c|).
+template <class CT>
+__device__ __forceinline__ bool sel_window(const SelState* ss, int& sh, unsigned long long& lo) {
+  constexpr int KB = sizeof(CT) == 8 ? 63 : 31;
+  if (!ss->hint_valid) {
+    sh = KB - 11;
+    lo = 0ULL;
+    return false;
+  }
+  sh = ss->hint_shift;
+  const unsigned long long hk = ss->hint_key, half = 1024ULL << sh;
+  lo = hk > half ? ((hk - half) >> sh) << sh : 0ULL;
+  return true;
+}
+
 // The pick after the window histogram (stage 0) or after a pass (stage 1), by one
 // workgroup.  lh: LDS for the bins (2049 at stage 0, kSelBins at stage 1).
 __device__ __forceinline__ unsigned int sel_hist_at(const SelState* ss, int b) { return ss->hist[b]; }
@@ -158,10 +183,10 @@ __device__ void sel_pick(SelState* ss, int stage, unsigned long long K, unsigned
   const int tid = threadIdx.x;
   if (stage == 0) {
     bool hit = false;
-    if (ss->hint_valid) {
-      const int sh = ss->hint_shift;
-      const unsigned long long hk = ss->hint_key, half = 1024ULL << sh;
-      const unsigned long long lo = hk > half ? ((hk - half) >> sh) << sh : 0ULL;
+    {
+      int sh;
+      unsigned long long lo;
+      const bool hinted = sel_window<CT>(ss, sh, lo);
       for (int b = tid; b < 2049; b += 256) lh[b] = sel_hist_at(ss, b);
       __syncthreads();
       unsigned long long need = K;
@@ -178,9 +203,10 @@ __device__ void sel_pick(SelState* ss, int stage, unsigned long long K, unsigned
           ss->pm[0] = ~0ULL << sh;
           ss->hi = sh;
           ss->done = count <= G;
-          if (count > G && ss->hint_shift > 4) ss->hint_shift -= 1;   // finer bins next time
+          if (hinted && count > G && ss->hint_shift > ss->min_shift) ss->hint_shift -= 1;   // finer bins next time
         } else {
           ss->n_misses += 1;
+          ss->missed = 1;
           ss->hint_shift = min(ss->hint_shift + 2, KB - kSelBits);   // a wider window next time
         }
       }
@@ -231,15 +257,15 @@ __global__ void __launch_bounds__(256) k_sel_win(const CT* c, TileView tv, const
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ss->active = 1;
+    ss->missed = 0;
     ss->K = K;
     ss->gcount = 0;
     ss->n_capped += n_live - K;
     ss->n_cuts += 1;
   }
-  if (!ss->hint_valid) return;   // no window yet: the passes start from the top
-  const int sh = ss->hint_shift;
-  const unsigned long long hk = ss->hint_key, half = 1024ULL << sh;
-  const unsigned long long lo = hk > half ? ((hk - half) >> sh) << sh : 0ULL;
+  int sh;
+  unsigned long long lo;
+  sel_window<CT>(ss, sh, lo);
   for (int b = threadIdx.x; b < 2049; b += 256) h[b] = 0;
   __syncthreads();
   uint32_t above = 0;   // most keys lie above a window near the cut: counted in a register
@@ -298,7 +324,10 @@ __global__ void __launch_bounds__(256) k_sel_rest(Terms<CT> t, TileView tv, SelS
   __shared__ unsigned int lh[kSelBins];
   __shared__ unsigned long long lsum[256];
   if (ss->active != 1 || ss->done) return;
-  if (threadIdx.x == 0) ss->n_rest += 1;
+  if (threadIdx.x == 0) {
+    ss->n_rest += 1;
+    if (ss->missed) ss->min_shift = max(ss->min_shift, ss->hint_shift);   // never that narrow again
+  }
   for (;;) {
     __syncthreads();
     const int word = ss->word;
@@ -460,6 +489,8 @@ __global__ void k_sel_init(SelState* ss, int shift) {
     ss->hint_valid = 0;
     ss->hint_key = 0;
     ss->hint_shift = shift;
+    ss->min_shift = kSelMinShift;
+    ss->missed = 0;
     ss->active = 0;
     ss->cut.has = 0;
   }
