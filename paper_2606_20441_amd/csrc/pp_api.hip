@@ -1602,11 +1602,13 @@ struct Engine final : EngineBase {
     ctx->check_launch();
     // the passes after the window are rarely needed: a smaller grid returns sooner when not
     const dim3 pgrid(std::min(256u, tile_grid(tv)));
+    // the pick after the second pass runs at the start of k_sel_rest
     for (int p = 0; p < 2; ++p) {
       ctx->run("cap_pass", 0, 0.0, [&] {
         hipLaunchKernelGGL((k_sel_pass<W, CT, ORD>), pgrid, dim3(256), 0, st, t.c, tv, ss);
       });
       ctx->check_launch();
+      if (p == 1) break;
       ctx->run("cap_pick", 0, 0.0, [&] {
         hipLaunchKernelGGL((k_sel_pick<W, CT, ORD>), dim3(1), dim3(256), 0, st, ss, 1);
       });
@@ -1730,8 +1732,12 @@ struct Engine final : EngineBase {
       tr_s1.ensure(ntiles * 4 + 64);
       tr_l1.ensure(ntiles * 4 + 64);
       for (Buf* b : {&rl0, &rl1, &rl2, &g1_ovf, &ovl1, &ovl2}) b->ensure(ntiles * 4 + 64);
-      // counters of this gate (the routed list sizes stay)
-      HIPCHK(hipMemsetAsync(&cd->ovf[0], 0, sizeof(G1Counters) - offsetof(G1Counters, ovf), st));
+      // counters of this gate (the routed list sizes stay), cleared by one small kernel (a
+      // memset of this unaligned range is split into three fills)
+      static_assert((sizeof(G1Counters) - offsetof(G1Counters, ovf)) % 4 == 0, "counter words");
+      hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, (uint32_t*)&cd->ovf[0],
+                         (uint64_t)((sizeof(G1Counters) - offsetof(G1Counters, ovf)) / 4), 0u);
+      ctx->check_launch();
       if (!routed) {
         // sort the tiles by size (a tile changes size slowly; one that outgrows its shape is
         // retried in the next); the passes read the list sizes on the device

@@ -11,10 +11,11 @@
 //    bins around the previous cut (before the first cut: one bin per octave, every key);
 //  * k_sel_pick (one workgroup): the bin holding the K-th term, or, when the window missed
 //    it, the passes start from the top bits;
-//  * twice k_sel_pass + k_sel_pick: 13 more bits of |c|, while the bucket of the K-th term
-//    holds more than a few thousand terms;
-//  * k_sel_rest (one workgroup): whatever is left, in the rare case it is not done: more
-//    bits of |c|, then the canonical key words, which split a bucket of exactly equal |c|;
+//  * twice k_sel_pass, each followed by a pick of its bin: 13 more bits of |c|, while the
+//    bucket of the K-th term holds more than a few thousand terms;
+//  * k_sel_rest (one workgroup): the pick after the second pass, then whatever is left, in
+//    the rare case it is not done: more bits of |c|, then the canonical key words, which
+//    split a bucket of exactly equal |c|;
 //  * k_sel_gather: the bucket's terms;
 //  * k_sel_rank (one workgroup): sorts them in LDS in the cut order and writes the K-th as
 //    the pending cut, which the next gate pass reads from device memory.
@@ -315,14 +316,16 @@ __global__ void __launch_bounds__(256) k_sel_pick(SelState* ss, int stage) {
   }
 }
 
-// One 256-thread workgroup finishing a selection the passes left undone (a bucket of exactly
-// equal |c|, split by the strings): each further pass is a sweep of all tiles by this one
-// workgroup.
+// One 256-thread workgroup: the pick after the last pass, then whatever that leaves undone
+// (a bucket of exactly equal |c|, split by the strings, or low bits of |c| after a window
+// that missed): each further pass is a sweep of all tiles by this one workgroup.
 template <int W, class CT, bool ORD>
 __global__ void __launch_bounds__(256) k_sel_rest(Terms<CT> t, TileView tv, SelState* ss) {
   constexpr int NWORDS = 2 * W + 1 + (ORD ? 1 : 0);
   __shared__ unsigned int lh[kSelBins];
   __shared__ unsigned long long lsum[256];
+  sel_pick<W, CT, ORD>(ss, 1, 0ULL, lh, lsum);
+  __syncthreads();   // the pick's state, written by thread 0, is read by every thread below
   if (ss->active != 1 || ss->done) return;
   if (threadIdx.x == 0) {
     ss->n_rest += 1;
