@@ -1257,15 +1257,16 @@ struct Engine final : EngineBase {
     const uint64_t nb = cdiv(ntiles, kSortTile);
     ctx->run("scan", 0, (double)ntiles, [&] {
       if (nb == 1) {
-        hipLaunchKernelGGL(k_bases_apply, dim3(1), dim3(kSortBlock), 0, st, len, ntiles, (const uint32_t*)nullptr, b,
-                           total);
+        hipLaunchKernelGGL(k_bases_apply, dim3(1), dim3(kSortBlock), 0, st, len, ntiles, (const uint32_t*)nullptr, 0,
+                           b, total);
       } else {
         scan_scr.ensure(scan_scratch_words(nb) * 4 + nb * 4 + 256);
         uint32_t* sums = scan_scr.as<uint32_t>();
         hipLaunchKernelGGL(k_bases_sums, dim3((unsigned)nb), dim3(kSortBlock), 0, st, len, ntiles, sums);
-        exclusive_scan_u32(sums, nb, sums + nb + 64, st);
+        const int raw = nb <= kBasesRawMax;   // few blocks: each adds up the sums before it
+        if (!raw) exclusive_scan_u32(sums, nb, sums + nb + 64, st);
         hipLaunchKernelGGL(k_bases_apply, dim3((unsigned)nb), dim3(kSortBlock), 0, st, len, ntiles,
-                           (const uint32_t*)sums, b, total);
+                           (const uint32_t*)sums, raw, b, total);
       }
     });
     ctx->check_launch();

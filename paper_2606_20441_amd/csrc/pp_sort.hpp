@@ -88,7 +88,10 @@ __global__ void __launch_bounds__(kSortBlock) k_scan_apply(uint32_t* data, uint6
 }
 
 // Output-region bases of tiles: out[t] = exclusive prefix of 2 * len[t], and *total = the
-// sum of 2 * len (tiles of kSortTile; sums scanned in between like exclusive_scan_u32).
+// sum of 2 * len.  Blocks of kSortTile entries: k_bases_sums writes each block's sum.  With
+// few blocks (raw_sums = 1) each block of k_bases_apply adds up the sums of the blocks
+// before it itself, so no scan of the sums runs in between; otherwise the sums have been
+// scanned like exclusive_scan_u32 and each block reads its own.
 __global__ void __launch_bounds__(kSortBlock) k_bases_sums(const uint32_t* len, uint64_t n, uint32_t* sums) {
   __shared__ uint32_t tmp[kSortBlock / 64];
   const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
@@ -102,8 +105,10 @@ __global__ void __launch_bounds__(kSortBlock) k_bases_sums(const uint32_t* len, 
   if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
+constexpr uint32_t kBasesRawMax = 1024;   // most blocks whose sums k_bases_apply adds up itself
+
 __global__ void __launch_bounds__(kSortBlock) k_bases_apply(const uint32_t* len, uint64_t n, const uint32_t* sums,
-                                                            uint32_t* out, unsigned long long* total) {
+                                                            int raw_sums, uint32_t* out, unsigned long long* total) {
   __shared__ uint32_t tmp[kSortBlock / 64];
   const uint64_t base = (uint64_t)blockIdx.x * kSortTile + (uint64_t)threadIdx.x * kSortItems;
   uint32_t v[kSortItems];
@@ -115,7 +120,14 @@ __global__ void __launch_bounds__(kSortBlock) k_bases_apply(const uint32_t* len,
     s += v[k];
   }
   uint32_t ex = block_exclusive_scan<kSortBlock>(s, tmp, (uint32_t*)nullptr);
-  if (sums) ex += sums[blockIdx.x];
+  if (sums && raw_sums) {   // uniform: the barriers of the scan below are reached by every thread
+    uint32_t p = 0, before = 0;
+    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kSortBlock) p += sums[b];
+    block_exclusive_scan<kSortBlock>(p, tmp, &before);
+    ex += before;
+  } else if (sums) {
+    ex += sums[blockIdx.x];
+  }
 #pragma unroll
   for (int k = 0; k < kSortItems; ++k) {
     const uint64_t i = base + k;
