@@ -216,6 +216,13 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
   static_assert(H > CAP && (H & (H - 1)) == 0 && R * BLOCK == CAP, "tile shape");
   constexpr int NW = BLOCK / 64;
   constexpr uint32_t EMPTY = 0xffffffffu;
+  // Table slot of a (string hash, order tag): the top bits of a multiplicative mix, which
+  // depend on every bit of the key.  (The strings of a class differ in a few bits, and the
+  // low bits of their linear hashes are correlated.)
+  constexpr int HB = __builtin_ctz((unsigned)H);
+  auto slot_of = [](uint32_t h, uint32_t o) -> uint32_t {
+    return ((h ^ (o * 0x9e3779b9u)) * 0x85ebca6bu) >> (32 - HB);
+  };
   __shared__ uint64_t sx[W][CAP];
   __shared__ uint64_t sz[W][CAP];
   __shared__ CT sc[CAP];
@@ -323,7 +330,7 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
         sh[i] = hh[r];
         sc[i] = cur.c[r];
         if (pairs && an[r] && cur.c[r] != (CT)0) {
-          uint32_t slot = (hh[r] ^ (cur.o[r] * 0x9e3779b9u)) & (H - 1);
+          uint32_t slot = slot_of(hh[r], cur.o[r]);
           while (atomicCAS(&hidx[slot], EMPTY, i) != EMPTY) slot = (slot + 1) & (H - 1);
         }
       }
@@ -366,7 +373,7 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
           const uint32_t hq = hh[r] ^ gh;
           const uint32_t t = cur.o[r];
           auto find = [&](uint32_t tag) -> uint32_t {
-            uint32_t sl = (hq ^ (tag * 0x9e3779b9u)) & (H - 1);
+            uint32_t sl = slot_of(hq, tag);
             for (;;) {
               const uint32_t k = hidx[sl];
               if (k == EMPTY) return EMPTY;
@@ -412,7 +419,7 @@ __global__ void __launch_bounds__(BLOCK) k_gate1(Gate1Args<CT> a) {
         }
         // non-Clifford: find the partner string (same order tag) in the tile
         const uint32_t hq = hh[r] ^ gh;
-        uint32_t slot = (hq ^ (cur.o[r] * 0x9e3779b9u)) & (H - 1);
+        uint32_t slot = slot_of(hq, cur.o[r]);
         uint32_t j = EMPTY;
         for (;;) {
           const uint32_t k = hidx[slot];
