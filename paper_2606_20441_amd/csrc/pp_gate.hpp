@@ -611,6 +611,11 @@ __device__ void gate1_big_tile(const Gate1Args<CT>& a, uint32_t li, uint32_t* ta
   __syncthreads();
   uint32_t* tab = table + s_off;
   const uint32_t hm = s_hsize - 1;
+  const int hb = __builtin_ctz(s_hsize);   // the table has 2^hb slots (hb >= 6)
+  // slot of a (string hash, order tag): the top bits of a multiplicative mix, as in k_gate1
+  auto bslot = [hb](uint32_t hh, uint32_t o) -> uint32_t {
+    return ((hh ^ (o * 0x9e3779b9u)) * 0x85ebca6bu) >> (32 - hb);
+  };
   uint64_t m[2 * W];
 #pragma unroll
   for (int w = 0; w < 2 * W; ++w) m[w] = a.g.m[w];
@@ -647,7 +652,7 @@ __device__ void gate1_big_tile(const Gate1Args<CT>& a, uint32_t li, uint32_t* ta
     }
     o.c[base + i] = keep;
     if (keep != (CT)0) {
-      uint32_t slot = (h ^ (oi * 0x9e3779b9u)) & hm;
+      uint32_t slot = bslot(h, oi);
       while (atomicCAS(&tab[slot], EMPTY, i) != EMPTY) slot = (slot + 1) & hm;
     }
   }
@@ -694,7 +699,7 @@ __device__ void gate1_big_tile(const Gate1Args<CT>& a, uint32_t li, uint32_t* ta
       // as in k_gate1: (Q, s) takes cos c(Q, s) plus the sin part of (RQ, s - 1); a sin part
       // without an entry (RQ, s + 1) starts one
       auto find = [&](uint32_t tag) -> uint32_t {
-        uint32_t sl = (hq ^ (tag * 0x9e3779b9u)) & hm;
+        uint32_t sl = bslot(hq, tag);
         for (;;) {
           const uint32_t k = tab[sl];
           if (k == EMPTY) return EMPTY;
@@ -735,7 +740,7 @@ __device__ void gate1_big_tile(const Gate1Args<CT>& a, uint32_t li, uint32_t* ta
       }
       continue;
     }
-    uint32_t slot = (hq ^ (oi * 0x9e3779b9u)) & hm;
+    uint32_t slot = bslot(hq, oi);
     uint32_t j = EMPTY;
     for (;;) {
       const uint32_t k = tab[slot];

@@ -268,10 +268,14 @@ __global__ void __launch_bounds__(BLOCK) k_layer(LayerArgs<CT> a) {
     return;
   }
 
-  // Slot = low bits of the full hash, fingerprint = its high 16 bits (kept in the slot so
-  // most probes are resolved without reading the stored key).
+  // Slot = the top bits of a multiplicative mix of the full hash (the strings of a tile's
+  // classes differ in a few bits, and the low bits of their linear hashes are correlated),
+  // fingerprint = its high 16 bits (kept in the slot so most probes are resolved without
+  // reading the stored key).
+  static_assert((H & (H - 1)) == 0, "table size");
+  constexpr int HB = __builtin_ctz((unsigned)H);
   auto full_hash = [](uint32_t hs, uint32_t o) -> uint32_t { return ORD ? hs ^ ord_hash(o) : hs; };
-  auto slot_of = [](uint32_t fh) -> uint32_t { return fh & (uint32_t)(H - 1); };
+  auto slot_of = [](uint32_t fh) -> uint32_t { return (fh * 0x85ebca6bu) >> (32 - HB); };
   auto fp_of = [](uint32_t fh) -> uint32_t { return fh >> 16; };
   auto same_key = [&](uint32_t idx, const uint64_t* kx, const uint64_t* kz, uint32_t o) -> bool {
     bool eq = true;
