@@ -70,11 +70,13 @@ typedef enum { PP_F64 = 0, PP_F32_KAHAN = 1 } pp_precision;
  * kappa = k + 2p of the Euclid appendix (k steps and p bubbles, one sine per step): the
  * sin child of a non-Clifford rotation gets tag + 1 and is dropped above max_order
  * (0..250), Clifford rotations do not count, the noise rescales as in PP_MODE_GREEDY, and
- * terms merge by (string, tag).  Every gate takes the per-gate sort-and-merge path.
- * pp_apply_layer writes each layer in the Clifford interaction picture of the Euclid
- * appendix before propagating: a rotation by theta becomes the exact Clifford rotation by
- * the nearest multiple k pi/2 followed by one by the residual theta - k pi/2 (at most pi/4,
- * so every counted sine is at most 1/sqrt 2); whole turns are dropped.  <O~> sums all tags.
+ * terms merge by (string, tag).  With max_terms > 0 the gates of a layer go through the
+ * tiled gate passes with the cap's cut on the device, as in PP_MODE_GREEDY; without a cap,
+ * through the per-gate sort-and-merge path.  pp_apply_layer writes each layer in the
+ * Clifford interaction picture of the Euclid appendix before propagating: a rotation by
+ * theta becomes the exact Clifford rotation by the nearest multiple k pi/2 followed by one
+ * by the residual theta - k pi/2 (at most pi/4, so every counted sine is at most
+ * 1/sqrt 2); whole turns are dropped.  <O~> sums all tags.
  * The Euclid appendix expands D over every gate of C_ideal, the first layer's included, so
  * a caller building D in this mode keeps the G_1^dag G_1 pair. */
 typedef enum { PP_MODE_GREEDY = 0, PP_MODE_ERROR_ORDER = 1, PP_MODE_SINE_ORDER = 2 } pp_mode;
