@@ -11,7 +11,7 @@
 //    bins around the previous cut (before the first cut: one bin per octave, every key);
 //  * k_sel_pick (one workgroup): the bin holding the K-th term, or, when the window missed
 //    it, the passes start from the top bits;
-//  * twice k_sel_pass, each followed by a pick of its bin: 13 more bits of |c|, while the
+//  * twice k_sel_pass, each followed by a pick of its bin: 15 more bits of |c|, while the
 //    bucket of the K-th term holds more than a few thousand terms;
 //  * k_sel_rest (one workgroup): the pick after the second pass, then whatever is left, in
 //    the rare case it is not done: more bits of |c|, then the canonical key words, which
@@ -41,7 +41,7 @@ constexpr uint32_t sel_gather() { return W == 1 ? 4096u : (W == 2 ? 2048u : 1024
 // Words of the composite key: 0 = |c| key (larger first), 1..W = x words W-1..0, W+1..2W =
 // z words W-1..0, 2W+1 = order tag (smaller first for all but word 0).
 constexpr int kSelWords = 2 * PP_MAXW + 2;
-constexpr int kSelBits = 13;                 // bits per pass after the window
+constexpr int kSelBits = 15;                 // bits per pass after the window (128 KiB of LDS)
 constexpr int kSelBins = 1 << kSelBits;
 
 struct SelState {
@@ -284,7 +284,7 @@ __global__ void __launch_bounds__(256) k_sel_win(const CT* c, TileView tv, const
     if (h[b]) atomicAdd(&ss->hist[b], h[b]);
 }
 
-// The next 13 bits of |c| inside the bucket, while the bucket is large.
+// The next kSelBits bits of |c| inside the bucket, while the bucket is large.
 template <int W, class CT, bool ORD>
 __global__ void __launch_bounds__(256) k_sel_pass(const CT* c, TileView tv, SelState* ss) {
   __shared__ unsigned int h[kSelBins];
